@@ -1,0 +1,114 @@
+"""Seeded synthetic inputs for the CSD (shared by tests, bench and smoke).
+
+This module only draws random matrices and angle sets and assembles
+A = [U1 C V1^T; U2 S V1^T]; it holds none of the decomposition's arithmetic.
+Every generator takes a ``numpy.random.Generator`` (PCG64 via
+``numpy.random.default_rng(seed)``) and returns FP64 numpy arrays.
+
+Recipes (the paper's test classes of Sec. 6, real analogues):
+
+* ``stiefel``      Haar-distributed 2n x n matrix with orthonormal columns
+                   (test class 1): Q of a Gaussian 2n x n, columns sign-normalised.
+* ``haar``         Haar orthogonal n x n (same construction).
+* ``angles_*``     angle sets: uniform in [0, pi/2]; clustered near 0 and pi/2
+                   with offsets 10^-U[8, 12]; the cumulative-sum clustered class
+                   of Sec. 6 (test class 2).
+* ``from_angles``  A1 = U1 diag(cos t) V1^T, A2 = U2 diag(sin t) V1^T, optionally
+                   with C_ii = S_ii = 0 on a set of indices (rank-deficient
+                   partial isometry, test class 4).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def haar(n, rng):
+    G = rng.standard_normal((n, n))
+    Q, R = np.linalg.qr(G)
+    d = np.sign(np.diag(R))
+    d[d == 0] = 1.0
+    return Q * d
+
+
+def stiefel(m, n, rng):
+    G = rng.standard_normal((m, n))
+    Q, R = np.linalg.qr(G)
+    d = np.sign(np.diag(R))
+    d[d == 0] = 1.0
+    return Q * d
+
+
+def angles_uniform(n, rng):
+    return np.sort(rng.uniform(0.0, np.pi / 2, n))
+
+
+def angles_clustered_ends(n, rng, n_low=None, n_high=None, lo_exp=8.0, hi_exp=12.0):
+    """Half uniform in [0, pi/2], a quarter at 10^-U[lo,hi] and a quarter at pi/2 minus that."""
+    if n_low is None:
+        n_low = n // 4
+    if n_high is None:
+        n_high = n // 4
+    n_mid = n - n_low - n_high
+    mid = rng.uniform(0.0, np.pi / 2, n_mid)
+    low = 10.0 ** (-rng.uniform(lo_exp, hi_exp, n_low))
+    high = np.pi / 2 - 10.0 ** (-rng.uniform(lo_exp, hi_exp, n_high))
+    return np.sort(np.concatenate([low, mid, high]))
+
+
+def angles_cumsum_clustered(n, rng, spread=18.0):
+    """Test class 2 of Sec. 6: delta = 10^(-18 U), theta = (pi/2) cumsum(delta)/sum(delta)."""
+    delta = 10.0 ** (-spread * rng.uniform(0.0, 1.0, n + 1))
+    return (np.pi / 2) * np.cumsum(delta[:n]) / np.sum(delta)
+
+
+def from_angles(theta, rng, zero_idx=None, U1=None, U2=None, V1=None):
+    """A = diag(U1, U2) [C; S] V1^T with Haar factors; C_ii = S_ii = 0 on zero_idx."""
+    n = theta.shape[0]
+    U1 = haar(n, rng) if U1 is None else U1
+    U2 = haar(n, rng) if U2 is None else U2
+    V1 = haar(n, rng) if V1 is None else V1
+    c = np.cos(theta)
+    s = np.sin(theta)
+    if zero_idx is not None and len(zero_idx):
+        c = c.copy()
+        s = s.copy()
+        c[zero_idx] = 0.0
+        s[zero_idx] = 0.0
+    A1 = (U1 * c) @ V1.T
+    A2 = (U2 * s) @ V1.T
+    return A1, A2, {"U1": U1, "U2": U2, "V1": V1, "theta": theta, "zero_idx": zero_idx}
+
+
+# ---- named workloads -----------------------------------------------------
+
+def haar_stiefel_pair(n, seed):
+    """2n x n Haar matrix split into A1 (top n rows) and A2 (bottom n rows)."""
+    rng = np.random.default_rng(seed)
+    A = stiefel(2 * n, n, rng)
+    return np.ascontiguousarray(A[:n]), np.ascontiguousarray(A[n:]), {}
+
+
+def clustered_pair(n, seed, rank_deficient=0):
+    """Angles: n/2 uniform, n/4 within 1e-8..1e-12 of 0, n/4 within that of pi/2.
+
+    rank_deficient > 0 zeroes C_ii = S_ii on that many random indices (rank n - k).
+    """
+    rng = np.random.default_rng(seed)
+    theta = angles_clustered_ends(n, rng)
+    zero_idx = None
+    if rank_deficient:
+        zero_idx = np.sort(rng.choice(n, size=rank_deficient, replace=False))
+    A1, A2, meta = from_angles(theta, rng, zero_idx=zero_idx)
+    return A1, A2, meta
+
+
+def uniform_pair(n, seed):
+    rng = np.random.default_rng(seed)
+    theta = angles_uniform(n, rng)
+    return from_angles(theta, rng)
+
+
+def batched_sizes(count, seed, lo=8, hi=256):
+    """Sizes drawn log-uniform in [lo, hi] and rounded."""
+    rng = np.random.default_rng(seed)
+    return np.rint(np.exp(rng.uniform(np.log(lo), np.log(hi), count))).astype(np.int64)

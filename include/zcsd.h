@@ -1,0 +1,192 @@
+/*
+ * zcsd.h -- C ABI of libzcsd, an MI355X (gfx950) implementation of the CS
+ * decomposition of Gawlik, Nakatsukasa & Sutton, "A Backward Stable Algorithm
+ * for Computing the CS Decomposition via the Polar Decomposition"
+ * (arXiv 1804.09002): Zolo-csd = two Zolotarev polar decompositions (Zolo-pd,
+ * Sec. 5), the Hermitian matrix B = H2 - H1 + mu (I - A^T A) (Algorithm 1,
+ * line 4) and a Zolotarev spectral divide-and-conquer eigendecomposition of B
+ * (Zolo-eig, Sec. 5), assembled into U1, U2, V1 and the angles theta.
+ *
+ * Conventions for every entry point
+ *  - Matrices are real FP64, column-major, with a leading dimension ld >= rows.
+ *  - Pointers named d_* are device pointers (HIP memory on the handle's device);
+ *    h_* are host pointers.  The caller owns all input and output buffers.
+ *  - Work is enqueued on the handle's stream.  Entry points that need host
+ *    decisions (rank, Zolotarev degree, divide-and-conquer split sizes)
+ *    synchronise that stream internally; when an entry point returns
+ *    ZCSD_OK its outputs are complete and the info struct is filled.
+ *  - Inputs are not modified; outputs must not alias inputs.
+ *  - Argument errors return ZCSD_EINVAL before any work is enqueued.
+ *    HIP runtime failures return ZCSD_EHIP; allocation failures ZCSD_ENOMEM.
+ *    Numerical conditions are reported through the status and zcsd_info.
+ *  - A handle is not thread-safe; use one handle per host thread.
+ */
+#ifndef ZCSD_H
+#define ZCSD_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  ZCSD_OK = 0,
+  ZCSD_EINVAL = 1,   /* bad argument (size, leading dimension, NULL pointer, NaN/Inf input) */
+  ZCSD_ENOTISO = 2,  /* input is far from a partial isometry: |‖A‖_F^2 - rank| too large (Sec. 2.1) */
+  ZCSD_ENOCONV = 3,  /* Zolo-pd did not reach 1 - l_2 <= tol, or a split of Zolo-eig failed */
+  ZCSD_EREPAIR = 4,  /* reserved: Algorithm 2 repair rejected (‖R~ - R‖ too large, Sec. 5.1) */
+  ZCSD_EHIP = 5,     /* HIP runtime error */
+  ZCSD_ENOMEM = 6    /* device allocation failed */
+} zcsd_status;
+
+typedef enum { ZCSD_FP64 = 0, ZCSD_MIXED_FP32 = 1 } zcsd_precision;
+
+typedef enum {
+  ZCSD_RANK_AUTO = 0,      /* Remark (vi): rank = round(‖A‖_F^2); deficient iff rank < n */
+  ZCSD_RANK_FULL = 1,      /* Algorithm 1 with mu = 0 */
+  ZCSD_RANK_DEFICIENT = 2  /* Algorithm 3 with mu = opts.mu */
+} zcsd_rank_mode;
+
+/* Options.  zcsd_default_opts() fills the paper's values. */
+typedef struct {
+  zcsd_precision prec;     /* arithmetic of the Cholesky-form iterations (FP64 default) */
+  zcsd_rank_mode rank_mode;
+  double eps;              /* floor of the Zolo-pd interval [eps, 1]; 1e-15 (Sec. 5.1) */
+  double mu;               /* shift of the null space in B; 2 (Algorithm 3 line 3) */
+  double tol;              /* Zolo-pd target 1 - l_2 <= tol; 2^-53 */
+  int r_override;          /* 0 = choose r from the l estimate; 1..8 forces r */
+  double ell_override;     /* 0 = estimate l = sigma_min lower bound; > 0 forces l */
+  int n_leaf;              /* Zolo-eig blocks of at most this size go to Jacobi (<= 64) */
+  int postprocess;         /* 1: theta = atan2(S_ii, C_ii), C = cos, S = sin (Remark (iii)) */
+} zcsd_opts;
+
+/* Diagnostics filled by zcsd_dcsd / zcsd_dzolo_pd / zcsd_dsyev_zolo. */
+typedef struct {
+  int rank;                /* numerical rank used (columns of U1, U2, V1 that are valid) */
+  int r_used[2];           /* Zolotarev terms per iteration of the two polars (same r both steps) */
+  double ell[2];           /* lower bounds l_0 used for the two polars */
+  double zolo_resid;       /* 1 - l_2 of the coefficient sequence actually used */
+  int eig_levels;          /* divide-and-conquer levels of Zolo-eig */
+  int eig_splits;          /* number of successful splits */
+  int eig_max_r;           /* largest Zolotarev degree used inside Zolo-eig */
+  double eig_offblock;     /* max over splits of ‖V-^T B V+‖_F / ‖B‖_F (0 if not measured) */
+  double time_ms[4];       /* polar, B, eig, assembly wall time (ms), measured with stream syncs */
+} zcsd_info;
+
+typedef struct zcsd_handle_s zcsd_handle;
+
+/* Create a handle on HIP device `device`; it owns a workspace arena and a stream
+ * (the null stream until zcsd_set_stream is called).  Returns ZCSD_EHIP if the
+ * device cannot be set. */
+zcsd_status zcsd_create(zcsd_handle** handle, int device);
+zcsd_status zcsd_destroy(zcsd_handle* handle);
+/* Work is enqueued on `stream` (a hipStream_t passed as void*). */
+zcsd_status zcsd_set_stream(zcsd_handle* handle, void* stream);
+void zcsd_default_opts(zcsd_opts* opts);
+const char* zcsd_status_string(zcsd_status s);
+
+/*
+ * CS decomposition of A = [A1; A2], A1, A2 n x n (Sec. 1; Theorem 2.1 for a
+ * rank-deficient partial isometry).  Algorithm 1, or Algorithm 3 when the
+ * rank is (detected or forced) below n:
+ *    A1 = U1 diag(cos theta) V1^T,  A2 = U2 diag(sin theta) V1^T,
+ *    0 <= theta_1 <= ... <= theta_r <= pi/2 (Sec. 1), r = info->rank.
+ * Outputs: d_U1, d_U2, d_V1 are n x n (ld >= n); only their first r columns
+ * and the first r entries of d_theta (length n) are valid (economical CSD,
+ * Remark (vii)); the rest are zero.  d_W1, d_W2 (optional, may be NULL)
+ * receive the polar factors W_i (n x n, ld n) used by the backward pass.
+ * opts may be NULL (defaults); info may be NULL.
+ */
+zcsd_status zcsd_dcsd(zcsd_handle* handle, int n,
+                      const double* d_A1, int lda1, const double* d_A2, int lda2,
+                      double* d_U1, int ldu1, double* d_U2, int ldu2,
+                      double* d_V1, int ldv1, double* d_theta,
+                      double* d_W1, double* d_W2,
+                      const zcsd_opts* opts, zcsd_info* info);
+
+/*
+ * Batched Zolo-pd (Sec. 5): polar decompositions X_b = W_b H_b of `batch`
+ * n x n matrices stored at d_X + b*strideX (ld ldx), scaled by 1/alpha (alpha
+ * must bound sigma_max).  One shared lower bound l (estimated as the minimum
+ * over the batch of 1/‖R_b^{-1}‖_F, or opts->ell_override) and degree r
+ * (opts->r_override or the smallest r <= 8 with 1 - l_2 <= opts->tol).
+ * Outputs W (ld n, stride n*n), H = sym(W^T X) (ld n, stride n*n; may be
+ * NULL), and optionally the first iterate X1 (may be NULL).
+ */
+zcsd_status zcsd_dzolo_pd(zcsd_handle* handle, int batch, int n, double alpha,
+                          const double* d_X, int ldx, long long strideX,
+                          double* d_W, double* d_H, double* d_X1,
+                          const zcsd_opts* opts, zcsd_info* info);
+
+/*
+ * Symmetric eigendecomposition B = V diag(lambda) V^T of an n x n symmetric
+ * matrix by Zolo-eig (Sec. 5: spectral divide and conquer on the sign
+ * function computed by Zolo-pd, Jacobi on blocks of at most opts->n_leaf).
+ * lo <= lambda_min and hi >= lambda_max must bound the spectrum.  lambda is
+ * returned in ascending order with the matching columns of V (ld ldv).
+ */
+zcsd_status zcsd_dsyev_zolo(zcsd_handle* handle, int n, const double* d_B, int ldb,
+                            double lo, double hi, double* d_V, int ldv, double* d_lambda,
+                            const zcsd_opts* opts, zcsd_info* info);
+
+/*
+ * Zolotarev coefficients of one iteration (host only): c[0..2r-1] = c_1..c_2r,
+ * a[0..r-1], M with Z(1) = 1, and l_next = Z(l) (Sec. 5; definitions in the
+ * library's host code).  Returns ZCSD_EINVAL unless 0 < l <= 1 and 1 <= r <= 8.
+ */
+zcsd_status zcsd_zolo_coeffs(double ell, int r, double* h_c, double* h_a, double* h_M,
+                             double* h_ell_next);
+/* Smallest r in 1..8 with 1 - l_2 <= tol after two iterations from l, or 0 if none. */
+int zcsd_zolo_choose_r(double ell, double tol);
+
+/*
+ * FP64 MFMA matrix product (the building block of every step above):
+ * C_b = alpha op(A_b) op(B_b) + beta C_b for b < batch, op = transpose when
+ * transA/transB != 0; op(A) is m x k, op(B) is k x n; batch strides in elements.
+ */
+zcsd_status zcsd_dgemm(zcsd_handle* handle, int transA, int transB, int m, int n, int k,
+                       double alpha, const double* d_A, int lda, long long strideA,
+                       const double* d_B, int ldb, long long strideB, double beta,
+                       double* d_C, int ldc, long long strideC, int batch);
+
+/*
+ * Blocked Householder QR (the QR form of Zolo-pd, Sec. 5), batched in place.
+ * stacked == 0: d_M_b is m x n (m >= n); on return its top n x n upper triangle
+ *   holds R and everything below is zero; d_Q_b (m x n, may be NULL) receives
+ *   the explicit Q with Q R = M.
+ * stacked != 0: d_M_b is the 2n x n matrix [R0; D] with R0 upper triangular and
+ *   D diagonal (m must equal 2n); the structured factorisation touches only the
+ *   nonzero pattern; outputs as above.
+ */
+zcsd_status zcsd_dqr(zcsd_handle* handle, int batch, int stacked, int m, int n,
+                     double* d_M, int ldm, long long strideM,
+                     double* d_Q, int ldq, long long strideQ);
+
+/*
+ * Kernel timing for measurement tools.  Between zcsd_profile_begin() and
+ * zcsd_profile_end(), every launch of the instrumented kernels (the MFMA GEMM
+ * tile variants, the QR panel, the Cholesky base, the Jacobi leaf) is
+ * bracketed by HIP events on its own stream and its algorithmic flops and
+ * bytes are added to a record named after the kernel (for example
+ * "dgemm_128x128_NT").  zcsd_profile_query fills the launch count, the
+ * summed algorithmic flops and bytes and the summed event time in ms of one
+ * record and returns 1, or returns 0 if there is none; it synchronises on the
+ * recorded events.  zcsd_profile_names writes the record names, one per line,
+ * into buf (NUL-terminated, truncated to len) and returns the full length.
+ * zcsd_profile_filter restricts recording to one record so that the event
+ * pairs perturb nothing else.  Process-wide, not thread-safe with respect to
+ * concurrent begin/end.
+ */
+void zcsd_profile_begin(void);
+void zcsd_profile_end(void);
+/* Restrict recording to the record `name` (NULL: record every kernel). */
+void zcsd_profile_filter(const char* name);
+int zcsd_profile_query(const char* name, long long* launches, double* flops, double* bytes,
+                       double* ms);
+int zcsd_profile_names(char* buf, int len);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ZCSD_H */

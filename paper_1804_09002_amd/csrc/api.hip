@@ -1,0 +1,175 @@
+// C ABI entry points: handle management, option defaults, status strings and
+// the exception-to-status boundary shared by every entry point.
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+
+#include "zcsd_api_guard.h"
+#include "zcsd_internal.h"
+
+using namespace zcsd;
+
+extern "C" {
+
+zcsd_status zcsd_create(zcsd_handle** handle, int device) {
+  if (!handle) return ZCSD_EINVAL;
+  *handle = nullptr;
+  return guarded([&] {
+    int count = 0;
+    ZCSD_HIP(hipGetDeviceCount(&count));
+    ZCSD_REQUIRE(device >= 0 && device < count, "zcsd_create: no such device");
+    ZCSD_HIP(hipSetDevice(device));
+    auto* h = new zcsd_handle_s();
+    h->device = device;
+    h->stream = nullptr;
+    h->h_stage_count = 1 << 16;
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&h->h_stage),
+                                 h->h_stage_count * sizeof(double), hipHostMallocDefault);
+    if (e != hipSuccess) {
+      delete h;
+      ZCSD_HIP(e);
+    }
+    *handle = h;
+  });
+}
+
+zcsd_status zcsd_destroy(zcsd_handle* handle) {
+  if (!handle) return ZCSD_OK;
+  return guarded([&] {
+    ZCSD_HIP(hipSetDevice(handle->device));
+    ZCSD_HIP(hipDeviceSynchronize());
+    if (handle->h_stage) (void)hipHostFree(handle->h_stage);
+    delete handle;
+  });
+}
+
+zcsd_status zcsd_set_stream(zcsd_handle* handle, void* stream) {
+  if (!handle) return ZCSD_EINVAL;
+  handle->stream = static_cast<hipStream_t>(stream);
+  return ZCSD_OK;
+}
+
+void zcsd_default_opts(zcsd_opts* o) {
+  if (!o) return;
+  o->prec = ZCSD_FP64;
+  o->rank_mode = ZCSD_RANK_AUTO;
+  o->eps = 1e-15;
+  o->mu = 2.0;
+  o->tol = std::ldexp(1.0, -53);
+  o->r_override = 0;
+  o->ell_override = 0.0;
+  o->n_leaf = 64;
+  o->postprocess = 1;
+}
+
+const char* zcsd_status_string(zcsd_status s) {
+  switch (s) {
+    case ZCSD_OK: return "ZCSD_OK";
+    case ZCSD_EINVAL: return "ZCSD_EINVAL: invalid argument";
+    case ZCSD_ENOTISO: return "ZCSD_ENOTISO: input is not close to a partial isometry";
+    case ZCSD_ENOCONV: return "ZCSD_ENOCONV: Zolotarev iteration or divide-and-conquer split did not converge";
+    case ZCSD_EREPAIR: return "ZCSD_EREPAIR: ill-conditioned repair rejected";
+    case ZCSD_EHIP: return "ZCSD_EHIP: HIP runtime error";
+    case ZCSD_ENOMEM: return "ZCSD_ENOMEM: device allocation failed";
+  }
+  return "unknown zcsd_status";
+}
+
+zcsd_status zcsd_dgemm(zcsd_handle* handle, int transA, int transB, int m, int n, int k,
+                       double alpha, const double* A, int lda, long long strideA, const double* B,
+                       int ldb, long long strideB, double beta, double* C, int ldc,
+                       long long strideC, int batch) {
+  if (!handle) return ZCSD_EINVAL;
+  return guarded([&] {
+    ZCSD_REQUIRE(m >= 0 && n >= 0 && k >= 0 && batch >= 0, "dgemm: negative size");
+    if (m == 0 || n == 0 || batch == 0) return;
+    ZCSD_REQUIRE(C && (k == 0 || (A && B)), "dgemm: NULL pointer");
+    ZCSD_REQUIRE(ldc >= std::max(1, m), "dgemm: ldc too small");
+    ZCSD_REQUIRE(k == 0 || (lda >= std::max(1, transA ? k : m) && ldb >= std::max(1, transB ? n : k)),
+                 "dgemm: leading dimension too small");
+    ZCSD_HIP(hipSetDevice(handle->device));
+    GemmBatch g;
+    g.transA = transA != 0;
+    g.transB = transB != 0;
+    g.m = m; g.n = n; g.k = k;
+    g.A = A; g.lda = lda; g.sA = strideA;
+    g.B = B; g.ldb = ldb; g.sB = strideB;
+    g.C = C; g.ldc = ldc; g.sC = strideC;
+    g.alpha = alpha; g.beta = beta; g.batch = batch;
+    dgemm(g, handle->stream);
+  });
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+#include "zcsd_zolo.h"
+
+namespace {
+size_t zolo_pd_ws_bytes(int batch, int n) {
+  const size_t nn = (size_t)n * n;
+  return (size_t)batch * (64 * nn + 64 * (size_t)n) * sizeof(double) + (64u << 20);
+}
+}  // namespace
+
+extern "C" zcsd_status zcsd_dzolo_pd(zcsd_handle* handle, int batch, int n, double alpha,
+                                     const double* d_X, int ldx, long long strideX, double* d_W,
+                                     double* d_H, double* d_X1, const zcsd_opts* opts,
+                                     zcsd_info* info) {
+  if (!handle) return ZCSD_EINVAL;
+  return guarded([&] {
+    ZCSD_REQUIRE(batch >= 1 && n >= 1, "zolo_pd: batch and n must be positive");
+    ZCSD_REQUIRE(d_X && d_W, "zolo_pd: NULL pointer");
+    ZCSD_REQUIRE(ldx >= n, "zolo_pd: ldx < n");
+    ZCSD_REQUIRE(alpha > 0.0 && std::isfinite(alpha), "zolo_pd: alpha must be positive");
+    zcsd_opts o;
+    zcsd_default_opts(&o);
+    if (opts) o = *opts;
+    ZCSD_REQUIRE(o.r_override >= 0 && o.r_override <= ZOLO_RMAX, "zolo_pd: r_override out of range");
+    ZCSD_HIP(hipSetDevice(handle->device));
+    handle->arena.reset();
+    handle->arena.reserve(zolo_pd_ws_bytes(batch, n));
+    ZoloPdArgs a;
+    a.batch = batch;
+    a.n = n;
+    a.alpha = alpha;
+    a.X = d_X; a.ldx = ldx; a.sx = strideX;
+    a.W = d_W; a.H = d_H; a.X1 = d_X1;
+    a.eps = o.eps; a.tol = o.tol;
+    a.r_override = o.r_override;
+    a.ell_override = o.ell_override;
+    ZoloPdResult r = zolo_pd_batched(a, handle->arena, handle->stream);
+    ZCSD_HIP(hipStreamSynchronize(handle->stream));
+    if (info) {
+      *info = zcsd_info{};
+      info->rank = n;
+      info->r_used[0] = info->r_used[1] = r.r;
+      info->ell[0] = info->ell[1] = r.ell;
+      info->zolo_resid = r.resid;
+    }
+  });
+}
+
+#include "zcsd_la.h"
+
+extern "C" zcsd_status zcsd_dqr(zcsd_handle* handle, int batch, int stacked, int m, int n,
+                                double* d_M, int ldm, long long strideM, double* d_Q, int ldq,
+                                long long strideQ) {
+  if (!handle) return ZCSD_EINVAL;
+  return guarded([&] {
+    ZCSD_REQUIRE(batch >= 1 && n >= 1 && m >= n, "qr: need batch >= 1, m >= n >= 1");
+    ZCSD_REQUIRE(!stacked || m == 2 * n, "qr: stacked shape needs m == 2n");
+    ZCSD_REQUIRE(d_M && ldm >= m, "qr: bad M");
+    ZCSD_REQUIRE(!d_Q || ldq >= m, "qr: bad Q");
+    ZCSD_HIP(hipSetDevice(handle->device));
+    const QRShape shape = stacked ? QRShape::Stacked : QRShape::General;
+    const size_t need = (size_t)batch * ((size_t)m * n + 4 * (size_t)m * 32 + 64 * (size_t)n) *
+                            sizeof(double) * 2 + (16u << 20);
+    handle->arena.reset();
+    handle->arena.reserve(need);
+    QRWork wk = qr_work_alloc(handle->arena, shape, batch, m, n, 32);
+    geqrf_batched(batch, shape, m, n, d_M, ldm, strideM, wk, handle->stream);
+    if (d_Q) orgqr_batched(batch, shape, m, n, d_Q, ldq, strideQ, nullptr, wk, handle->stream);
+    ZCSD_HIP(hipStreamSynchronize(handle->stream));
+  });
+}

@@ -1,0 +1,236 @@
+// Cholesky factorisation with its inverse factor, and upper-triangular inverse.
+//
+// Zolo-pd's Cholesky form (Sec. 5) needs X (X^T X + c I)^{-1} = X R^{-1} R^{-T}
+// with R^T R = X^T X + c I.  chol_inv_batched returns R and R^{-1} together by
+// the block recursion
+//     R11 = chol(A11),  R12 = R11^{-T} A12,  R22 = chol(A22 - R12^T R12),
+//     (R^{-1})12 = -R11^{-1} R12 R22^{-1},
+// so the triangular solves become MFMA GEMMs; blocks of at most CH_BASE are
+// factored and inverted in LDS by one workgroup.
+//
+// trtri_upper_batched inverts an upper-triangular R: all diagonal blocks of
+// size CH_BASE are inverted at once, then neighbouring blocks are merged level
+// by level, (R^{-1})_{AB} = -R_A^{-1} R_{AB} R_B^{-1}, every pair of a level in
+// one batched GEMM.
+#include <algorithm>
+#include <cmath>
+
+#include "zcsd_internal.h"
+#include "zcsd_la.h"
+
+namespace zcsd {
+
+constexpr int CH_BASE = 64;
+constexpr int CH_NT = 256;
+
+// In LDS: upper-triangular inverse of U (nb x nb, ld CH_BASE+1) into Ui.
+// Thread j computes column j by back substitution (rows j..0).
+__device__ void lds_upper_inverse(const double (*U)[CH_BASE + 1], double (*Ui)[CH_BASE + 1],
+                                  int nb) {
+  const int j = threadIdx.x;
+  if (j < nb) {
+    for (int i = nb - 1; i >= 0; --i) {
+      double v;
+      if (i > j) v = 0.0;
+      else if (i == j) v = 1.0 / U[j][j];
+      else {
+        double s = 0.0;
+        for (int p = i + 1; p <= j; ++p) s += U[i][p] * Ui[p][j];
+        v = -s / U[i][i];
+      }
+      Ui[i][j] = v;
+    }
+  }
+}
+
+// one workgroup per problem: A (nb x nb, symmetric, upper triangle read) -> R, Ri
+__global__ __launch_bounds__(CH_NT) void chol_inv_base_kernel(int nb, const double* A, long long lda,
+                                                              long long sA, double* R, long long ldr,
+                                                              long long sR, double* Ri,
+                                                              long long ldi, long long sI,
+                                                              int* d_flag) {
+  __shared__ double S[CH_BASE][CH_BASE + 1];
+  __shared__ double Ui[CH_BASE][CH_BASE + 1];
+  const long long b = blockIdx.x;
+  A += b * sA;
+  R += b * sR;
+  Ri += b * sI;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < nb * nb; e += CH_NT) {
+    const int i = e % nb, j = e / nb;
+    // symmetric read from the upper triangle
+    S[i][j] = (i <= j) ? A[i + (long long)j * lda] : A[j + (long long)i * lda];
+  }
+  __syncthreads();
+  // right-looking Cholesky in LDS: row k of R overwrites row k of S
+  for (int k = 0; k < nb; ++k) {
+    if (tid == 0) {
+      double d = S[k][k];
+      if (!(d > 0.0)) {
+        if (d_flag) atomicAdd(d_flag, 1);
+        d = 1e-300;
+      }
+      S[k][k] = sqrt(d);
+    }
+    __syncthreads();
+    const double rkk = S[k][k];
+    for (int j = k + 1 + tid; j < nb; j += CH_NT) S[k][j] /= rkk;
+    __syncthreads();
+    const int m = nb - k - 1;
+    for (int e = tid; e < m * m; e += CH_NT) {
+      const int i = k + 1 + e % m, j = k + 1 + e / m;
+      if (i <= j) S[i][j] -= S[k][i] * S[k][j];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < nb * nb; e += CH_NT) {
+    const int i = e % nb, j = e / nb;
+    if (i > j) S[i][j] = 0.0;
+  }
+  __syncthreads();
+  lds_upper_inverse(S, Ui, nb);
+  __syncthreads();
+  for (int e = tid; e < nb * nb; e += CH_NT) {
+    const int i = e % nb, j = e / nb;
+    R[i + (long long)j * ldr] = S[i][j];
+    Ri[i + (long long)j * ldi] = Ui[i][j];
+  }
+}
+
+// one workgroup per (problem, diagonal block)
+__global__ __launch_bounds__(CH_NT) void trtri_base_kernel(int n, const double* R, long long ldr,
+                                                           long long sR, double* Ri, long long ldi,
+                                                           long long sI) {
+  __shared__ double U[CH_BASE][CH_BASE + 1];
+  __shared__ double Ui[CH_BASE][CH_BASE + 1];
+  const long long b = blockIdx.y;
+  const int o = blockIdx.x * CH_BASE;
+  const int nb = min(CH_BASE, n - o);
+  R += b * sR + o + (long long)o * ldr;
+  Ri += b * sI + o + (long long)o * ldi;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < nb * nb; e += CH_NT) {
+    const int i = e % nb, j = e / nb;
+    U[i][j] = (i <= j) ? R[i + (long long)j * ldr] : 0.0;
+  }
+  __syncthreads();
+  lds_upper_inverse(U, Ui, nb);
+  __syncthreads();
+  for (int e = tid; e < nb * nb; e += CH_NT) {
+    const int i = e % nb, j = e / nb;
+    Ri[i + (long long)j * ldi] = Ui[i][j];
+  }
+}
+
+// ---------------------------------------------------------------------------
+static void chol_inv_rec(int batch, int n, double* A, long long lda, long long sA, double* R,
+                         double* Ri, long long ld, long long s, Arena& ar, hipStream_t st) {
+  if (n <= CH_BASE) {
+    hipLaunchKernelGGL(chol_inv_base_kernel, dim3(batch), dim3(CH_NT), 0, st, n, A, lda, sA, R,
+                       ld, s, Ri, ld, s, (int*)nullptr);
+    ZCSD_CHECK_LAUNCH();
+    return;
+  }
+  int n1 = ((n / 2 + CH_BASE - 1) / CH_BASE) * CH_BASE;
+  if (n1 >= n) n1 = n - CH_BASE;
+  const int n2 = n - n1;
+  double* A12 = A + (long long)n1 * lda;
+  double* A22 = A + n1 + (long long)n1 * lda;
+  double* R12 = R + (long long)n1 * ld;
+  double* R22 = R + n1 + (long long)n1 * ld;
+  double* Ri12 = Ri + (long long)n1 * ld;
+  double* Ri22 = Ri + n1 + (long long)n1 * ld;
+  chol_inv_rec(batch, n1, A, lda, sA, R, Ri, ld, s, ar, st);
+  GemmBatch g;
+  g.batch = batch;
+  // R12 = R11i^T A12
+  g.transA = 1; g.transB = 0; g.m = n1; g.n = n2; g.k = n1;
+  g.A = Ri; g.lda = ld; g.sA = s;
+  g.B = A12; g.ldb = lda; g.sB = sA;
+  g.C = R12; g.ldc = ld; g.sC = s;
+  g.alpha = 1.0; g.beta = 0.0;
+  dgemm(g, st);
+  // A22 <- A22 - R12^T R12
+  GemmBatch h;
+  h.batch = batch;
+  h.transA = 1; h.transB = 0; h.m = n2; h.n = n2; h.k = n1;
+  h.A = R12; h.lda = ld; h.sA = s;
+  h.B = R12; h.ldb = ld; h.sB = s;
+  h.C = A22; h.ldc = lda; h.sC = sA;
+  h.alpha = -1.0; h.beta = 1.0;
+  dgemm(h, st);
+  chol_inv_rec(batch, n2, A22, lda, sA, R22, Ri22, ld, s, ar, st);
+  // Ri12 = -R11i (R12 R22i)
+  ArenaScope scope(ar);
+  double* X = ar.dalloc((size_t)batch * n1 * n2);
+  GemmBatch x;
+  x.batch = batch;
+  x.transA = 0; x.transB = 0; x.m = n1; x.n = n2; x.k = n2;
+  x.A = R12; x.lda = ld; x.sA = s;
+  x.B = Ri22; x.ldb = ld; x.sB = s;
+  x.C = X; x.ldc = n1; x.sC = (long long)n1 * n2;
+  x.alpha = 1.0; x.beta = 0.0;
+  dgemm(x, st);
+  GemmBatch y;
+  y.batch = batch;
+  y.transA = 0; y.transB = 0; y.m = n1; y.n = n2; y.k = n1;
+  y.A = Ri; y.lda = ld; y.sA = s;
+  y.B = X; y.ldb = n1; y.sB = (long long)n1 * n2;
+  y.C = Ri12; y.ldc = ld; y.sC = s;
+  y.alpha = -1.0; y.beta = 0.0;
+  dgemm(y, st);
+}
+
+void chol_inv_batched(int batch, int n, double* A, long long lda, long long sA, double* R,
+                      double* Ri, Arena& ar, hipStream_t s) {
+  if (batch <= 0 || n <= 0) return;
+  const long long nn = (long long)n * n;
+  // the blocks below the diagonal of R and R^{-1} are never written by the recursion
+  set_identity(batch, n, n, 0.0, R, n, nn, s);
+  set_identity(batch, n, n, 0.0, Ri, n, nn, s);
+  chol_inv_rec(batch, n, A, lda, sA, R, Ri, n, nn, ar, s);
+}
+
+void trtri_upper_batched(int batch, int n, const double* R, long long ldr, long long sR, double* Ri,
+                         long long ldi, long long sI, Arena& ar, hipStream_t s) {
+  if (batch <= 0 || n <= 0) return;
+  for (int b = 0; b < batch; ++b) set_identity(1, n, n, 0.0, Ri + b * sI, ldi, 0, s);
+  const int nblk = (n + CH_BASE - 1) / CH_BASE;
+  hipLaunchKernelGGL(trtri_base_kernel, dim3(nblk, batch), dim3(CH_NT), 0, s, n, R, ldr, sR, Ri,
+                     ldi, sI);
+  ZCSD_CHECK_LAUNCH();
+  ArenaScope scope(ar);
+  for (int sz = CH_BASE; sz < n; sz *= 2) {
+    // pairs (A, B) with A = [o, o + sz), B = [o + sz, min(o + 2 sz, n)), o = 2 sz p
+    const int npairs_full = n / (2 * sz);
+    const int rem = n - npairs_full * 2 * sz;  // leftover rows after the full pairs
+    double* X = ar.dalloc((size_t)batch * (npairs_full + 1) * sz * sz);
+    auto merge = [&](int o, int np, int nbB) {
+      if (np <= 0 || nbB <= 0) return;
+      const long long pstrideR = 2LL * sz * (ldr + 1), pstrideI = 2LL * sz * (ldi + 1);
+      // X = R_AB Ri_B  (sz x nbB)
+      GemmBatch g;
+      g.batch = batch; g.batch2 = np;
+      g.transA = 0; g.transB = 0; g.m = sz; g.n = nbB; g.k = nbB;
+      g.A = R + o + (long long)(o + sz) * ldr; g.lda = ldr; g.sA = sR; g.sA2 = pstrideR;
+      g.B = Ri + (o + sz) + (long long)(o + sz) * ldi; g.ldb = ldi; g.sB = sI; g.sB2 = pstrideI;
+      g.C = X; g.ldc = sz; g.sC = (long long)(npairs_full + 1) * sz * sz; g.sC2 = (long long)sz * sz;
+      g.alpha = 1.0; g.beta = 0.0;
+      dgemm(g, s);
+      // Ri_AB = -Ri_A X
+      GemmBatch h;
+      h.batch = batch; h.batch2 = np;
+      h.transA = 0; h.transB = 0; h.m = sz; h.n = nbB; h.k = sz;
+      h.A = Ri + o + (long long)o * ldi; h.lda = ldi; h.sA = sI; h.sA2 = pstrideI;
+      h.B = X; h.ldb = sz; h.sB = g.sC; h.sB2 = g.sC2;
+      h.C = Ri + o + (long long)(o + sz) * ldi; h.ldc = ldi; h.sC = sI; h.sC2 = pstrideI;
+      h.alpha = -1.0; h.beta = 0.0;
+      dgemm(h, s);
+    };
+    merge(0, npairs_full, sz);
+    if (rem > sz) merge(npairs_full * 2 * sz, 1, rem - sz);
+    ar.release(scope.m);
+  }
+}
+
+}  // namespace zcsd

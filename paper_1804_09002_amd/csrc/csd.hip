@@ -1,0 +1,357 @@
+// Zolo-csd driver: Algorithm 1 (full rank) and Algorithm 3 (rank-deficient
+// partial isometry) on the device, with Remarks (iii), (vi) and (vii).
+//
+//   a1  rank: r_A = round(||A||_F^2) (Remark (vi)); mu = 0 if r_A = n else 2
+//   a2-a5  W_i H_i = A_i for i = 1, 2 in one batched Zolo-pd (lines 1-2; the two
+//       polars run side by side, Remark (ii)); rank-deficient inputs use the
+//       modified Zolo-pd on [eps, 1] with r = 8 (Sec. 5.1, Algorithm 3 line 1)
+//   a6  B = H2 - H1 + mu (I - A1^T A1 - A2^T A2), symmetrised (line 4)
+//   a7  V1 Lambda V1^T = B by Zolo-eig (line 5)
+//   a8  rank-deficient: keep the eigenvectors with Lambda in [-1, 1] (Alg. 3 line 5)
+//   a9  U_i = W_i V1 (lines 6-7)
+//   a10 C = diag(V1^T H1 V1), S = diag(V1^T H2 V1) (lines 8-9)
+//   a11 theta = atan2(S_ii, C_ii) clamped to [0, pi/2] (Remark (iii)), columns
+//       sorted by ascending theta.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <numeric>
+#include <vector>
+
+#include "zcsd_api_guard.h"
+#include "zcsd_eig.h"
+#include "zcsd_internal.h"
+#include "zcsd_la.h"
+#include "zcsd_zolo.h"
+
+namespace zcsd {
+
+// Y = a X + b Y (n x n, ld n)
+__global__ void axpby_kernel(long long total, double a, const double* __restrict__ X, double b,
+                             double* Y) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x)
+    Y[e] = a * X[e] + b * Y[e];
+}
+
+// out[j] = sum_i V(i, j) T(i, j), one workgroup per column
+__global__ void coldot_kernel(int n, const double* __restrict__ V, long long ldv,
+                              const double* __restrict__ T, long long ldt, double* out) {
+  const int j = blockIdx.x;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x)
+    acc += V[i + (long long)j * ldv] * T[i + (long long)j * ldt];
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[j] = red[0];
+}
+
+// theta_j = clamp(atan2(s_j, c_j), 0, pi/2)   (Remark (iii))
+__global__ void theta_kernel(int r, const double* __restrict__ c, const double* __restrict__ s,
+                             double* th) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < r) {
+    double t = atan2(s[j], c[j]);
+    t = fmin(fmax(t, 0.0), 1.5707963267948966);
+    th[j] = t;
+  }
+}
+
+static void axpby(long long total, double a, const double* X, double b, double* Y, hipStream_t s) {
+  long long g = std::max<long long>(1, std::min<long long>((total + 255) / 256, 4096));
+  hipLaunchKernelGGL(axpby_kernel, dim3((unsigned)g), dim3(256), 0, s, total, a, X, b, Y);
+  ZCSD_CHECK_LAUNCH();
+}
+
+static double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+size_t csd_workspace_bytes(int n) {
+  const size_t nn = (size_t)n * n;
+  // polar batch (2 problems, r <= 8), Zolo-eig levels, assembly buffers
+  return (2 * 64 * nn + 64 * nn + 16 * nn) * sizeof(double) + (256u << 20);
+}
+
+struct CsdOut {
+  int rank = 0;
+  ZoloPdResult pd;
+  ZoloEigResult eig;
+  double t_polar = 0, t_B = 0, t_eig = 0, t_asm = 0;
+};
+
+static CsdOut csd_run(int n, const double* A1, long long lda1, const double* A2, long long lda2,
+                      double* U1, long long ldu1, double* U2, long long ldu2, double* V1,
+                      long long ldv1, double* theta, double* W1o, double* W2o, const zcsd_opts& o,
+                      Arena& ar, hipStream_t s) {
+  CsdOut out;
+  const long long nn = (long long)n * n;
+  ArenaScope scope(ar);
+  double t0 = now_ms();
+
+  // a1: rank from ||A||_F^2 (Remark (vi))
+  double* X = ar.dalloc(2 * (size_t)nn);
+  copy_scale(1, n, n, 1.0, A1, lda1, 0, X, n, 0, s);
+  copy_scale(1, n, n, 1.0, A2, lda2, 0, X + nn, n, 0, s);
+  double* d_ss = ar.dalloc(2);
+  sumsq(2, n, n, X, n, nn, d_ss, s);
+  double ss[2];
+  d2h(ss, d_ss, sizeof(ss), s);
+  const double f2 = ss[0] + ss[1];
+  if (!std::isfinite(f2)) throw ArgError("csd: input contains NaN or Inf");
+  const long long rA = std::llround(f2);
+  bool deficient;
+  if (o.rank_mode == ZCSD_RANK_FULL) deficient = false;
+  else if (o.rank_mode == ZCSD_RANK_DEFICIENT) deficient = true;
+  else {
+    if (std::fabs(f2 - (double)rA) > 0.25)
+      throw NumError(ZCSD_ENOTISO, "csd: ||A||_F^2 is not close to an integer rank");
+    deficient = rA < n;
+  }
+  const double mu = deficient ? o.mu : 0.0;
+
+  // a2-a5: the two polar decompositions, batched
+  double* W = ar.dalloc(2 * (size_t)nn);
+  double* H = ar.dalloc(2 * (size_t)nn);
+  {
+    ZoloPdArgs za;
+    za.batch = 2;
+    za.n = n;
+    za.alpha = 1.0;
+    za.X = X; za.ldx = n; za.sx = nn;
+    za.W = W; za.H = H;
+    za.eps = o.eps; za.tol = o.tol;
+    za.r_override = o.r_override;
+    za.ell_override = o.ell_override;
+    if (deficient) {
+      if (za.ell_override <= 0.0) za.ell_override = o.eps;
+      if (za.r_override <= 0) za.r_override = ZOLO_RMAX;
+    }
+    out.pd = zolo_pd_batched(za, ar, s);
+  }
+  HostSync::sync(s);
+  double t1 = now_ms();
+  out.t_polar = t1 - t0;
+
+  // a6: B = H2 - H1 + mu (I - A^T A)
+  double* B = ar.dalloc(nn);
+  copy_scale(1, n, n, 1.0, H + nn, n, 0, B, n, 0, s);
+  axpby(nn, -1.0, H, 1.0, B, s);
+  if (mu != 0.0) {
+    add_diag(1, n, mu, B, n, 0, s);
+    GemmBatch g;
+    g.transA = 1; g.transB = 0;
+    g.m = n; g.n = n; g.k = n;
+    g.A = X; g.lda = n; g.B = X; g.ldb = n;
+    g.C = B; g.ldc = n;
+    g.alpha = -mu; g.beta = 1.0;
+    dgemm(g, s);
+    g.A = X + nn; g.B = X + nn;
+    dgemm(g, s);
+  }
+  symmetrize(1, n, B, n, 0, s);
+  HostSync::sync(s);
+  double t2 = now_ms();
+  out.t_B = t2 - t1;
+
+  // a7: Zolo-eig of B
+  double* V = ar.dalloc(nn);
+  double* lam = ar.dalloc(n);
+  {
+    ZoloEigArgs ea;
+    ea.n = n;
+    ea.B = B; ea.ldb = n;
+    const double margin = 1e-6;
+    ea.lo = -1.0 - margin;
+    ea.hi = (mu > 1.0 ? mu : 1.0) + margin;
+    ea.V = V; ea.ldv = n;
+    ea.lam = lam;
+    ea.n_leaf = o.n_leaf;
+    ea.eps = o.eps; ea.tol = o.tol;
+    out.eig = zolo_eig(ea, ar, s);
+  }
+  HostSync::sync(s);
+  double t3 = now_ms();
+  out.t_eig = t3 - t2;
+
+  // a8: rank-deficient selection (eigenvalues ascending: the kept ones come first)
+  int r = n;
+  if (deficient) {
+    std::vector<double> lh(n);
+    d2h(lh.data(), lam, n * sizeof(double), s);
+    r = 0;
+    for (int j = 0; j < n; ++j)
+      if (lh[j] <= 0.5 * (1.0 + mu)) ++r;
+  }
+  out.rank = r;
+
+  // a9, a10: U_i = W_i V, c = diag(V^T H1 V), s = diag(V^T H2 V)
+  double* Ut = ar.dalloc(2 * (size_t)nn);
+  double* T = ar.dalloc(2 * (size_t)nn);
+  double* cs = ar.dalloc(2 * (size_t)n);
+  double* th = ar.dalloc(n);
+  if (r > 0) {
+    GemmBatch g;
+    g.batch = 2;
+    g.m = n; g.n = r; g.k = n;
+    g.A = W; g.lda = n; g.sA = nn;
+    g.B = V; g.ldb = n; g.sB = 0;
+    g.C = Ut; g.ldc = n; g.sC = nn;
+    dgemm(g, s);
+    if (deficient) {
+      // Newton-Schulz steps U <- U + U (I - U^T U) / 2 on U_i = W~_i V_1r.  In
+      // exact arithmetic U_i is orthonormal (Sec. 5.2); in floating point the
+      // zero singular values of A_i become O(u), the modified Zolo-pd maps them
+      // to values strictly between 0 and 1, and when A_i also has singular
+      // values only a few orders above eps the two groups mix at second order.
+      // The defect U^T U - I then lives on the columns whose C_ii (or S_ii) is
+      // ~0, so the correction leaves A1 = U1 C V1^T, A2 = U2 S V1^T unchanged
+      // to first order.
+      double* Gr = T;  // r x r per polar, T is free until the H_i V product below
+      double* Tc = ar.dalloc(2 * (size_t)nn);
+      for (int it = 0; it < 2; ++it) {
+        GemmBatch q;
+        q.batch = 2;
+        q.transA = 1; q.transB = 0;
+        q.m = r; q.n = r; q.k = n;
+        q.A = Ut; q.lda = n; q.sA = nn;
+        q.B = Ut; q.ldb = n; q.sB = nn;
+        q.C = Gr; q.ldc = r; q.sC = nn;
+        dgemm(q, s);
+        GemmBatch u;
+        u.batch = 2;
+        u.m = n; u.n = r; u.k = r;
+        u.A = Ut; u.lda = n; u.sA = nn;
+        u.B = Gr; u.ldb = r; u.sB = nn;
+        u.C = Tc; u.ldc = n; u.sC = nn;
+        dgemm(u, s);
+        axpby((long long)n * r, -0.5, Tc, 1.5, Ut, s);
+        axpby((long long)n * r, -0.5, Tc + nn, 1.5, Ut + nn, s);
+      }
+    }
+    g.A = H;
+    g.C = T;
+    dgemm(g, s);
+    hipLaunchKernelGGL(coldot_kernel, dim3(r), dim3(256), 0, s, n, V, (long long)n, T,
+                       (long long)n, cs);
+    ZCSD_CHECK_LAUNCH();
+    hipLaunchKernelGGL(coldot_kernel, dim3(r), dim3(256), 0, s, n, V, (long long)n, T + nn,
+                       (long long)n, cs + n);
+    ZCSD_CHECK_LAUNCH();
+    hipLaunchKernelGGL(theta_kernel, dim3((r + 255) / 256), dim3(256), 0, s, r, cs, cs + n, th);
+    ZCSD_CHECK_LAUNCH();
+  }
+  // a11: order by ascending theta and write the outputs (columns r..n-1 zero)
+  std::vector<double> thh(r);
+  if (r > 0) d2h(thh.data(), th, r * sizeof(double), s);
+  std::vector<int> perm(r);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) { return thh[x] < thh[y]; });
+  set_identity(1, n, n, 0.0, U1, ldu1, 0, s);
+  set_identity(1, n, n, 0.0, U2, ldu2, 0, s);
+  set_identity(1, n, n, 0.0, V1, ldv1, 0, s);
+  std::vector<double> th_sorted(n, 0.0);
+  {
+    std::vector<CopyDesc> c1, c2, c3;
+    for (int j = 0; j < r; ++j) {
+      c1.push_back({(long long)perm[j] * n, (long long)j * ldu1, n, (int)ldu1, n, 1});
+      c2.push_back({nn + (long long)perm[j] * n, (long long)j * ldu2, n, (int)ldu2, n, 1});
+      c3.push_back({(long long)perm[j] * n, (long long)j * ldv1, n, (int)ldv1, n, 1});
+      th_sorted[j] = thh[perm[j]];
+    }
+    copy_blocks(Ut, U1, c1, ar, s);
+    copy_blocks(Ut, U2, c2, ar, s);
+    copy_blocks(V, V1, c3, ar, s);
+  }
+  h2d(theta, th_sorted.data(), n * sizeof(double), s);
+  if (W1o) copy_scale(1, n, n, 1.0, W, n, 0, W1o, n, 0, s);
+  if (W2o) copy_scale(1, n, n, 1.0, W + nn, n, 0, W2o, n, 0, s);
+  HostSync::sync(s);
+  out.t_asm = now_ms() - t3;
+  return out;
+}
+
+}  // namespace zcsd
+
+using namespace zcsd;
+
+extern "C" zcsd_status zcsd_dcsd(zcsd_handle* handle, int n, const double* d_A1, int lda1,
+                                 const double* d_A2, int lda2, double* d_U1, int ldu1, double* d_U2,
+                                 int ldu2, double* d_V1, int ldv1, double* d_theta, double* d_W1,
+                                 double* d_W2, const zcsd_opts* opts, zcsd_info* info) {
+  if (!handle) return ZCSD_EINVAL;
+  return guarded([&] {
+    ZCSD_REQUIRE(n >= 1, "csd: n must be positive");
+    ZCSD_REQUIRE(d_A1 && d_A2 && d_U1 && d_U2 && d_V1 && d_theta, "csd: NULL pointer");
+    ZCSD_REQUIRE(lda1 >= n && lda2 >= n && ldu1 >= n && ldu2 >= n && ldv1 >= n,
+                 "csd: leading dimension < n");
+    zcsd_opts o;
+    zcsd_default_opts(&o);
+    if (opts) o = *opts;
+    ZCSD_REQUIRE(o.r_override >= 0 && o.r_override <= ZOLO_RMAX, "csd: r_override out of range");
+    ZCSD_REQUIRE(o.eps > 0.0 && o.eps < 1.0 && o.tol > 0.0, "csd: eps/tol out of range");
+    ZCSD_REQUIRE(o.mu > 1.0 || o.rank_mode == ZCSD_RANK_FULL, "csd: mu must exceed 1");
+    ZCSD_HIP(hipSetDevice(handle->device));
+    handle->arena.reset();
+    handle->arena.reserve(csd_workspace_bytes(n));
+    CsdOut r = csd_run(n, d_A1, lda1, d_A2, lda2, d_U1, ldu1, d_U2, ldu2, d_V1, ldv1, d_theta,
+                       d_W1, d_W2, o, handle->arena, handle->stream);
+    if (info) {
+      *info = zcsd_info{};
+      info->rank = r.rank;
+      info->r_used[0] = info->r_used[1] = r.pd.r;
+      info->ell[0] = info->ell[1] = r.pd.ell;
+      info->zolo_resid = r.pd.resid;
+      info->eig_levels = r.eig.levels;
+      info->eig_splits = r.eig.splits;
+      info->eig_max_r = r.eig.max_r;
+      info->eig_offblock = r.eig.max_offblock;
+      info->time_ms[0] = r.t_polar;
+      info->time_ms[1] = r.t_B;
+      info->time_ms[2] = r.t_eig;
+      info->time_ms[3] = r.t_asm;
+    }
+  });
+}
+
+extern "C" zcsd_status zcsd_dsyev_zolo(zcsd_handle* handle, int n, const double* d_B, int ldb,
+                                       double lo, double hi, double* d_V, int ldv,
+                                       double* d_lambda, const zcsd_opts* opts, zcsd_info* info) {
+  if (!handle) return ZCSD_EINVAL;
+  return guarded([&] {
+    ZCSD_REQUIRE(n >= 1, "syev: n must be positive");
+    ZCSD_REQUIRE(d_B && d_V && d_lambda, "syev: NULL pointer");
+    ZCSD_REQUIRE(ldb >= n && ldv >= n, "syev: leading dimension < n");
+    ZCSD_REQUIRE(lo < hi && std::isfinite(lo) && std::isfinite(hi), "syev: need lo < hi");
+    zcsd_opts o;
+    zcsd_default_opts(&o);
+    if (opts) o = *opts;
+    ZCSD_HIP(hipSetDevice(handle->device));
+    handle->arena.reset();
+    handle->arena.reserve(csd_workspace_bytes(n));
+    ZoloEigArgs ea;
+    ea.n = n;
+    ea.B = d_B; ea.ldb = ldb;
+    ea.lo = lo; ea.hi = hi;
+    ea.V = d_V; ea.ldv = ldv;
+    ea.lam = d_lambda;
+    ea.n_leaf = o.n_leaf;
+    ea.eps = o.eps; ea.tol = o.tol;
+    ZoloEigResult r = zolo_eig(ea, handle->arena, handle->stream);
+    ZCSD_HIP(hipStreamSynchronize(handle->stream));
+    if (info) {
+      *info = zcsd_info{};
+      info->rank = n;
+      info->eig_levels = r.levels;
+      info->eig_splits = r.splits;
+      info->eig_max_r = r.max_r;
+      info->eig_offblock = r.max_offblock;
+    }
+  });
+}

@@ -1,0 +1,574 @@
+// Zolo-eig (Sec. 5): symmetric eigendecomposition by spectral divide and
+// conquer on the matrix sign function, which is the polar factor of B - sI.
+//
+// Level by level, every unfinished block B_b (size n_b, spectrum inside
+// [lo_b, hi_b]) is processed in one batch, zero-padded to the level's largest
+// size N with the padding decoupled from the real part:
+//   1. shift s_b (median of diag B_b, kept inside (lo_b, hi_b)); alpha_b =
+//      max(hi_b - s_b, s_b - lo_b) bounds ||B_b - s_b I||_2; X_b = (B_b - s_b I)/alpha_b
+//      with 1 on the padded diagonal;
+//   2. W_b = sign(X_b) by batched Zolo-pd; P_b = (W_b + W_b^T)/4 + I/2 is the
+//      spectral projector onto the eigenvalues above s_b (plus the padding);
+//      n+_b = round(trace P_b over the real part);
+//   3. [V+ V-] = Q of the Householder QR of P_b Omega_b (Omega random on the
+//      real part, identity on the padding, so Q = diag(Q_real, I) exactly);
+//   4. B'_b = Q^T B_b Q, V_b <- V_b Q; the diagonal blocks of B'_b of sizes
+//      n+ and n_b - n+ are the children, with spectra in [s_b, hi_b] and
+//      [lo_b, s_b]; ||B'_21||_F / ||B||_F is recorded.
+// A split with n+ in {0, n_b} only moves the interval (bisection on s).
+// Blocks of at most n_leaf go to batched Jacobi; blocks whose spread
+// ||B_b - mean I||_F is below 4 n u ||B||_F are already diagonal to working
+// accuracy and are finished as they are.  Eigenpairs are finally sorted.
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+#include <vector>
+
+#include "zcsd_eig.h"
+#include "zcsd_internal.h"
+#include "zcsd_la.h"
+#include "zcsd_zolo.h"
+
+namespace zcsd {
+
+// ---------------------------------------------------------------------------
+// kernels
+
+__global__ void copy_blocks_kernel(const double* __restrict__ src, double* dst,
+                                   const CopyDesc* __restrict__ d) {
+  const CopyDesc c = d[blockIdx.y];
+  const long long total = (long long)c.rows * c.cols;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e % c.rows), j = (int)(e / c.rows);
+    dst[c.dst_off + i + (long long)j * c.dst_ld] = src[c.src_off + i + (long long)j * c.src_ld];
+  }
+}
+
+// X_b = (B_b - s_b I) * inva_b on the real n_b x n_b part, identity on the padding
+__global__ void form_shifted_kernel(int N, const double* __restrict__ Bp, double* X,
+                                    const int* __restrict__ nb, const double* __restrict__ sh,
+                                    const double* __restrict__ inva) {
+  const long long b = blockIdx.y;
+  const long long NN = (long long)N * N;
+  const int m = nb[b];
+  const double s = sh[b], f = inva[b];
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < NN;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e % N), j = (int)(e / N);
+    double v;
+    if (i < m && j < m) v = (Bp[b * NN + e] - (i == j ? s : 0.0)) * f;
+    else v = (i == j) ? 1.0 : 0.0;
+    X[b * NN + e] = v;
+  }
+}
+
+// P_b = (W_b + W_b^T)/4 + I/2 in place
+__global__ void projector_kernel(int N, double* W) {
+  const long long b = blockIdx.y;
+  const long long NN = (long long)N * N;
+  double* Wb = W + b * NN;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < NN;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e % N), j = (int)(e / N);
+    if (i > j) {
+      const double v = 0.25 * (Wb[e] + Wb[j + (long long)i * N]);
+      Wb[e] = v;
+      Wb[j + (long long)i * N] = v;
+    } else if (i == j) {
+      Wb[e] = 0.5 * Wb[e] + 0.5;
+    }
+  }
+}
+
+__global__ void trace_real_kernel(int N, const double* __restrict__ P, const int* __restrict__ nb,
+                                  double* tr) {
+  const long long b = blockIdx.x;
+  const int m = nb[b];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) acc += P[b * (long long)N * N + i + (long long)i * N];
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) tr[b] = red[0];
+}
+
+// Omega_b: uniform(-1, 1) on the real part (counter hash), identity on the padding
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+  z += 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  return z ^ (z >> 31);
+}
+__global__ void omega_kernel(int N, double* Om, const int* __restrict__ nb,
+                             unsigned long long seed) {
+  const long long b = blockIdx.y;
+  const long long NN = (long long)N * N;
+  const int m = nb[b];
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < NN;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e % N), j = (int)(e / N);
+    double v;
+    if (i < m && j < m) {
+      const unsigned long long h = mix64(seed ^ mix64(((unsigned long long)i << 32) | (unsigned)j));
+      v = 2.0 * ((double)(h >> 11) * 0x1.0p-53) - 1.0;
+    } else {
+      v = (i == j) ? 1.0 : 0.0;
+    }
+    Om[b * NN + e] = v;
+  }
+}
+
+// out[b] = ||B_b - d_b I||_F^2 over the n_b x n_b real part (diag shift d_b)
+__global__ void sumsq_shift_kernel(int N, const double* __restrict__ Bp, const int* __restrict__ nb,
+                                   const double* __restrict__ d, double* out) {
+  const long long b = blockIdx.x;
+  const int m = nb[b];
+  const double s = d[b];
+  const double* Bb = Bp + b * (long long)N * N;
+  double acc = 0.0;
+  for (long long e = threadIdx.x; e < (long long)m * m; e += blockDim.x) {
+    const int i = (int)(e % m), j = (int)(e / m);
+    const double v = Bb[i + (long long)j * N] - (i == j ? s : 0.0);
+    acc += v * v;
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[b] = red[0];
+}
+
+// out[b] = ||B'_b(np:nb, 0:np)||_F^2
+__global__ void offblock_kernel(int N, const double* __restrict__ Bp, const int* __restrict__ nb,
+                                const int* __restrict__ npos, double* out) {
+  const long long b = blockIdx.x;
+  const int m = nb[b], p = npos[b];
+  const double* Bb = Bp + b * (long long)N * N;
+  double acc = 0.0;
+  const long long rows = m - p;
+  for (long long e = threadIdx.x; e < rows * p; e += blockDim.x) {
+    const int i = p + (int)(e % rows), j = (int)(e / rows);
+    const double v = Bb[i + (long long)j * N];
+    acc += v * v;
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[b] = red[0];
+}
+
+__global__ void diag_kernel(int N, const double* __restrict__ Bp, const int* __restrict__ nb,
+                            double* out) {
+  const long long b = blockIdx.y;
+  const int m = nb[b];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x)
+    out[b * (long long)N + i] = Bp[b * (long long)N * N + i + (long long)i * N];
+}
+
+static dim3 grid2(long long total, int batch) {
+  long long g = (total + 255) / 256;
+  g = std::max<long long>(1, std::min<long long>(g, 1024));
+  return dim3((unsigned)g, (unsigned)batch);
+}
+
+void copy_blocks(const double* src, double* dst, const std::vector<CopyDesc>& d, Arena& ar,
+                 hipStream_t s) {
+  if (d.empty()) return;
+  ArenaScope sc(ar);
+  CopyDesc* dd = static_cast<CopyDesc*>(ar.alloc(d.size() * sizeof(CopyDesc)));
+  h2d(dd, d.data(), d.size() * sizeof(CopyDesc), s);
+  long long mx = 1;
+  for (const auto& c : d) mx = std::max<long long>(mx, (long long)c.rows * c.cols);
+  for (size_t o = 0; o < d.size(); o += 65535) {
+    const unsigned cnt = (unsigned)std::min<size_t>(65535, d.size() - o);
+    hipLaunchKernelGGL(copy_blocks_kernel, grid2(mx, cnt), dim3(256), 0, s, src, dst, dd + o);
+    ZCSD_CHECK_LAUNCH();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host driver
+
+namespace {
+struct Blk {
+  int n;
+  double lo, hi;
+  // location at the current level
+  const double* B;  // n x n, ld ldB
+  long long ldB;
+  const double* V;  // nglob x n, ld nglob
+  int tries = 0;
+};
+
+template <class T>
+T* upload(Arena& ar, const std::vector<T>& v, hipStream_t s) {
+  T* d = static_cast<T*>(ar.alloc(std::max<size_t>(1, v.size()) * sizeof(T)));
+  if (!v.empty()) h2d(d, v.data(), v.size() * sizeof(T), s);
+  return d;
+}
+}  // namespace
+
+ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
+  const int n = a.n;
+  ZoloEigResult res;
+  ZCSD_REQUIRE(n >= 1, "zolo_eig: n >= 1");
+  const int nleaf = std::max(1, std::min(a.n_leaf, 64));
+  ArenaScope scope(ar);
+
+  // global Frobenius norm of B (for the "already scalar" test and the off-block ratio)
+  double bnorm2;
+  {
+    double* d_ss = ar.dalloc(1);
+    sumsq(1, n, n, a.B, a.ldb, 0, d_ss, s);
+    d2h(&bnorm2, d_ss, sizeof(double), s);
+  }
+  const double bnorm = std::sqrt(bnorm2);
+  const double scalar_tol = 4.0 * n * 0x1p-53 * std::max(bnorm, 1e-300);
+
+  // output assembly: unsorted eigenvectors/values
+  double* Vout = ar.dalloc((size_t)n * n);
+  std::vector<double> lam_out;
+  lam_out.reserve(n);
+  int col_out = 0;
+
+  // level 0: the whole matrix, V = I
+  double* V0 = ar.dalloc((size_t)n * n);
+  set_identity(1, n, n, 1.0, V0, n, 0, s);
+  std::vector<Blk> active;
+  {
+    Blk r;
+    r.n = n;
+    r.lo = a.lo;
+    r.hi = a.hi;
+    r.B = a.B;
+    r.ldB = a.ldb;
+    r.V = V0;
+    active.push_back(r);
+  }
+  unsigned long long seed = 0x5DEECE66DULL;
+
+  // blocks parked for the end: leaves
+  while (!active.empty()) {
+    ++res.levels;
+    // --- classify: leaves / scalar / split --------------------------------
+    std::vector<Blk> leaves, split;
+    for (auto& b : active) {
+      if (b.n <= nleaf) leaves.push_back(b);
+      else split.push_back(b);
+    }
+    // pack every block of this level into padded arrays
+    std::vector<Blk> all = split;
+    all.insert(all.end(), leaves.begin(), leaves.end());
+    const int nblk = (int)all.size();
+    int N = 1;
+    for (auto& b : all) N = std::max(N, b.n);
+    const long long NN = (long long)N * N;
+    double* Bp = ar.dalloc((size_t)nblk * NN);
+    double* Vp = ar.dalloc((size_t)nblk * n * N);
+    set_identity(nblk, N, N, 0.0, Bp, N, NN, s);
+    set_identity(nblk, n, N, 0.0, Vp, n, (long long)n * N, s);
+    {
+      // the blocks of a level come from different buffers (children of splits and
+      // re-tried blocks): copy each block from its own base
+      for (int k = 0; k < nblk; ++k) {
+        std::vector<CopyDesc> one = {{0, (long long)k * NN, (int)all[k].ldB, N, all[k].n, all[k].n}};
+        copy_blocks(all[k].B, Bp, one, ar, s);
+        std::vector<CopyDesc> onev = {{0, (long long)k * n * N, n, n, n, all[k].n}};
+        copy_blocks(all[k].V, Vp, onev, ar, s);
+      }
+    }
+    std::vector<int> nbh(nblk);
+    for (int k = 0; k < nblk; ++k) nbh[k] = all[k].n;
+    int* d_nb = upload(ar, nbh, s);
+
+    // diagonal of each block (shift choice and the scalar test)
+    double* d_diag = ar.dalloc((size_t)nblk * N);
+    hipLaunchKernelGGL(diag_kernel, grid2(N, nblk), dim3(256), 0, s, N, Bp, d_nb, d_diag);
+    ZCSD_CHECK_LAUNCH();
+    std::vector<double> diag((size_t)nblk * N);
+    d2h(diag.data(), d_diag, diag.size() * sizeof(double), s);
+    std::vector<double> mean(nblk);
+    for (int k = 0; k < nblk; ++k) {
+      double t = 0.0;
+      for (int i = 0; i < all[k].n; ++i) t += diag[(size_t)k * N + i];
+      mean[k] = t / all[k].n;
+    }
+    double* d_mean = upload(ar, mean, s);
+    double* d_spread = ar.dalloc(nblk);
+    hipLaunchKernelGGL(sumsq_shift_kernel, dim3(nblk), dim3(256), 0, s, N, Bp, d_nb, d_mean,
+                       d_spread);
+    ZCSD_CHECK_LAUNCH();
+    std::vector<double> spread(nblk);
+    d2h(spread.data(), d_spread, nblk * sizeof(double), s);
+
+    // finished blocks: scalar (any basis) or leaves (Jacobi)
+    std::vector<int> leaf_idx, scalar_idx, split_idx;
+    for (int k = 0; k < nblk; ++k) {
+      if (std::sqrt(spread[k]) <= scalar_tol) scalar_idx.push_back(k);
+      else if (all[k].n <= nleaf) leaf_idx.push_back(k);
+      else split_idx.push_back(k);
+    }
+    {
+      long long add = 0;
+      for (int k : scalar_idx) add += all[k].n;
+      for (int k : leaf_idx) add += all[k].n;
+      if (col_out + add > n) throw NumError(ZCSD_ENOCONV, "zolo_eig: block sizes exceed n");
+    }
+    // scalar blocks: V columns as they are, eigenvalues = diag
+    if (!scalar_idx.empty()) {
+      std::vector<CopyDesc> cv;
+      for (int k : scalar_idx) {
+        cv.push_back({(long long)k * n * N, (long long)col_out * n, n, n, n, all[k].n});
+        for (int i = 0; i < all[k].n; ++i) lam_out.push_back(diag[(size_t)k * N + i]);
+        col_out += all[k].n;
+      }
+      copy_blocks(Vp, Vout, cv, ar, s);
+    }
+    // leaves: Jacobi on 64 x 64 padded copies, then V_b Q_leaf into the output
+    if (!leaf_idx.empty()) {
+      const int nl = (int)leaf_idx.size();
+      const int L = 64;
+      double* Lb = ar.dalloc((size_t)nl * L * L);
+      double* Lv = ar.dalloc((size_t)nl * L * L);
+      double* Ll = ar.dalloc((size_t)nl * L);
+      double* LV = ar.dalloc((size_t)nl * n * L);
+      set_identity(nl, L, L, 0.0, Lv, L, (long long)L * L, s);
+      set_identity(nl, n, L, 0.0, LV, n, (long long)n * L, s);
+      std::vector<CopyDesc> cb, cv;
+      std::vector<int> szs;
+      for (int q = 0; q < nl; ++q) {
+        const int k = leaf_idx[q];
+        cb.push_back({(long long)k * NN, (long long)q * L * L, N, L, all[k].n, all[k].n});
+        cv.push_back({(long long)k * n * N, (long long)q * n * L, n, n, n, all[k].n});
+        szs.push_back(all[k].n);
+      }
+      copy_blocks(Bp, Lb, cb, ar, s);
+      copy_blocks(Vp, LV, cv, ar, s);
+      int* d_sz = upload(ar, szs, s);
+      jacobi_batched(nl, d_sz, Lb, L, (long long)L * L, Lv, L, (long long)L * L, Ll, s);
+      double* LVo = ar.dalloc((size_t)nl * n * L);
+      GemmBatch g;
+      g.batch = nl;
+      g.m = n; g.n = L; g.k = L;
+      g.A = LV; g.lda = n; g.sA = (long long)n * L;
+      g.B = Lv; g.ldb = L; g.sB = (long long)L * L;
+      g.C = LVo; g.ldc = n; g.sC = (long long)n * L;
+      dgemm(g, s);
+      std::vector<double> ll((size_t)nl * L);
+      d2h(ll.data(), Ll, ll.size() * sizeof(double), s);
+      std::vector<CopyDesc> co;
+      for (int q = 0; q < nl; ++q) {
+        const int k = leaf_idx[q];
+        co.push_back({(long long)q * n * L, (long long)col_out * n, n, n, n, all[k].n});
+        for (int i = 0; i < all[k].n; ++i) lam_out.push_back(ll[(size_t)q * L + i]);
+        col_out += all[k].n;
+      }
+      copy_blocks(LVo, Vout, co, ar, s);
+    }
+    if (split_idx.empty()) {
+      active.clear();
+      break;
+    }
+
+    // --- split step on the remaining blocks ---------------------------------
+    const int ns = (int)split_idx.size();
+    // shifts and scalings (padded to the level's N; the split set is a prefix of `all`)
+    std::vector<double> sh(nblk, 0.0), inva(nblk, 1.0);
+    for (int q = 0; q < ns; ++q) {
+      const int k = split_idx[q];
+      Blk& b = all[k];
+      std::vector<double> d(diag.begin() + (size_t)k * N, diag.begin() + (size_t)k * N + b.n);
+      std::nth_element(d.begin(), d.begin() + b.n / 2, d.end());
+      double sft = d[b.n / 2];
+      const double w = b.hi - b.lo;
+      if (b.tries > 0 || !(sft > b.lo + 1e-3 * w && sft < b.hi - 1e-3 * w)) sft = 0.5 * (b.lo + b.hi);
+      sh[k] = sft;
+      const double alpha = std::max(b.hi - sft, sft - b.lo) * (1.0 + 1e-12) + 1e-300;
+      inva[k] = 1.0 / alpha;
+    }
+    // the split blocks occupy indices split_idx; gather them into a compact batch
+    std::vector<int> map(ns);
+    for (int q = 0; q < ns; ++q) map[q] = split_idx[q];
+    int Ns = 1;
+    for (int q = 0; q < ns; ++q) Ns = std::max(Ns, all[map[q]].n);
+    const long long SS = (long long)Ns * Ns;
+    double* Bs = ar.dalloc((size_t)ns * SS);
+    double* Vs = ar.dalloc((size_t)ns * n * Ns);
+    set_identity(ns, Ns, Ns, 0.0, Bs, Ns, SS, s);
+    set_identity(ns, n, Ns, 0.0, Vs, n, (long long)n * Ns, s);
+    {
+      std::vector<CopyDesc> cb, cv;
+      for (int q = 0; q < ns; ++q) {
+        const int k = map[q];
+        cb.push_back({(long long)k * NN, (long long)q * SS, N, Ns, all[k].n, all[k].n});
+        cv.push_back({(long long)k * n * N, (long long)q * n * Ns, n, n, n, all[k].n});
+      }
+      copy_blocks(Bp, Bs, cb, ar, s);
+      copy_blocks(Vp, Vs, cv, ar, s);
+    }
+    std::vector<int> nbs(ns);
+    std::vector<double> shs(ns), invas(ns);
+    for (int q = 0; q < ns; ++q) {
+      nbs[q] = all[map[q]].n;
+      shs[q] = sh[map[q]];
+      invas[q] = inva[map[q]];
+    }
+    int* d_nbs = upload(ar, nbs, s);
+    double* d_sh = upload(ar, shs, s);
+    double* d_inva = upload(ar, invas, s);
+    double* X = ar.dalloc((size_t)ns * SS);
+    hipLaunchKernelGGL(form_shifted_kernel, grid2(SS, ns), dim3(256), 0, s, Ns, Bs, X, d_nbs, d_sh,
+                       d_inva);
+    ZCSD_CHECK_LAUNCH();
+    double* W = ar.dalloc((size_t)ns * SS);
+    {
+      ZoloPdArgs za;
+      za.batch = ns;
+      za.n = Ns;
+      za.alpha = 1.0;
+      za.X = X; za.ldx = Ns; za.sx = SS;
+      za.W = W; za.H = nullptr; za.X1 = nullptr;
+      za.eps = a.eps; za.tol = a.tol;
+      za.symmetric_input = true;
+      ZoloPdResult zr = zolo_pd_batched(za, ar, s);
+      res.max_r = std::max(res.max_r, zr.r);
+    }
+    hipLaunchKernelGGL(projector_kernel, grid2(SS, ns), dim3(256), 0, s, Ns, W);
+    ZCSD_CHECK_LAUNCH();
+    double* d_tr = ar.dalloc(ns);
+    hipLaunchKernelGGL(trace_real_kernel, dim3(ns), dim3(256), 0, s, Ns, W, d_nbs, d_tr);
+    ZCSD_CHECK_LAUNCH();
+    std::vector<double> tr(ns);
+    d2h(tr.data(), d_tr, ns * sizeof(double), s);
+    std::vector<int> npos(ns);
+    for (int q = 0; q < ns; ++q) {
+      long long v = std::llround(tr[q]);
+      npos[q] = (int)std::min<long long>(std::max<long long>(v, 0), nbs[q]);
+    }
+    // basis: Q of QR(P Omega)
+    double* Om = ar.dalloc((size_t)ns * SS);
+    hipLaunchKernelGGL(omega_kernel, grid2(SS, ns), dim3(256), 0, s, Ns, Om, d_nbs, seed);
+    ZCSD_CHECK_LAUNCH();
+    seed = seed * 6364136223846793005ULL + 1442695040888963407ULL;
+    double* Y = X;  // X is dead
+    {
+      GemmBatch g;
+      g.batch = ns;
+      g.m = Ns; g.n = Ns; g.k = Ns;
+      g.A = W; g.lda = Ns; g.sA = SS;
+      g.B = Om; g.ldb = Ns; g.sB = SS;
+      g.C = Y; g.ldc = Ns; g.sC = SS;
+      dgemm(g, s);
+    }
+    double* Q = Om;  // Omega is dead after the product
+    {
+      ArenaScope qs(ar);
+      QRWork wk = qr_work_alloc(ar, QRShape::General, ns, Ns, Ns, 32);
+      geqrf_batched(ns, QRShape::General, Ns, Ns, Y, Ns, SS, wk, s);
+      orgqr_batched(ns, QRShape::General, Ns, Ns, Q, Ns, SS, nullptr, wk, s);
+    }
+    // B' = Q^T B Q, V' = V Q
+    double* T1 = W;  // W is dead
+    double* Bq = Y;  // Y is dead after orgqr
+    {
+      GemmBatch g;
+      g.batch = ns;
+      g.m = Ns; g.n = Ns; g.k = Ns;
+      g.A = Bs; g.lda = Ns; g.sA = SS;
+      g.B = Q; g.ldb = Ns; g.sB = SS;
+      g.C = T1; g.ldc = Ns; g.sC = SS;
+      dgemm(g, s);
+      GemmBatch h = g;
+      h.transA = 1;
+      h.A = Q; h.B = T1; h.C = Bq;
+      dgemm(h, s);
+    }
+    symmetrize(ns, Ns, Bq, Ns, SS, s);
+    double* Vq = ar.dalloc((size_t)ns * n * Ns);
+    {
+      GemmBatch g;
+      g.batch = ns;
+      g.m = n; g.n = Ns; g.k = Ns;
+      g.A = Vs; g.lda = n; g.sA = (long long)n * Ns;
+      g.B = Q; g.ldb = Ns; g.sB = SS;
+      g.C = Vq; g.ldc = n; g.sC = (long long)n * Ns;
+      dgemm(g, s);
+    }
+    if (a.measure_offblock) {
+      int* d_np = upload(ar, npos, s);
+      double* d_off = ar.dalloc(ns);
+      hipLaunchKernelGGL(offblock_kernel, dim3(ns), dim3(256), 0, s, Ns, Bq, d_nbs, d_np, d_off);
+      ZCSD_CHECK_LAUNCH();
+      std::vector<double> off(ns);
+      d2h(off.data(), d_off, ns * sizeof(double), s);
+      for (int q = 0; q < ns; ++q)
+        res.max_offblock = std::max(res.max_offblock, std::sqrt(off[q]) / std::max(bnorm, 1e-300));
+    }
+    // children (Bq and Vq stay alive until the next level copies them)
+    std::vector<Blk> next;
+    for (int q = 0; q < ns; ++q) {
+      const Blk& b = all[map[q]];
+      const int np = npos[q];
+      const double sft = shs[q];
+      if (np == 0 || np == b.n) {
+        ++res.failed_splits;
+        Blk c = b;
+        c.B = Bs + q * SS;
+        c.ldB = Ns;
+        c.V = Vs + (long long)q * n * Ns;
+        if (np == 0) c.hi = sft; else c.lo = sft;
+        c.tries = b.tries + 1;
+        if (c.tries > 60) throw NumError(ZCSD_ENOCONV, "zolo_eig: divide and conquer stalled");
+        next.push_back(c);
+        continue;
+      }
+      ++res.splits;
+      Blk plus;
+      plus.n = np;
+      plus.lo = sft;
+      plus.hi = b.hi;
+      plus.B = Bq + q * SS;
+      plus.ldB = Ns;
+      plus.V = Vq + (long long)q * n * Ns;
+      Blk minus;
+      minus.n = b.n - np;
+      minus.lo = b.lo;
+      minus.hi = sft;
+      minus.B = Bq + q * SS + np + (long long)np * Ns;
+      minus.ldB = Ns;
+      minus.V = Vq + (long long)q * n * Ns + (long long)np * n;
+      next.push_back(minus);
+      next.push_back(plus);
+    }
+    active.swap(next);
+  }
+  if (col_out != n) throw NumError(ZCSD_ENOCONV, "zolo_eig: lost eigenpairs");
+
+  // sort ascending and write V, lambda
+  std::vector<int> perm(n);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) { return lam_out[x] < lam_out[y]; });
+  std::vector<CopyDesc> cv;
+  std::vector<double> lam_sorted(n);
+  for (int j = 0; j < n; ++j) {
+    cv.push_back({(long long)perm[j] * n, (long long)j * a.ldv, n, (int)a.ldv, n, 1});
+    lam_sorted[j] = lam_out[perm[j]];
+  }
+  copy_blocks(Vout, a.V, cv, ar, s);
+  h2d(a.lam, lam_sorted.data(), n * sizeof(double), s);
+  return res;
+}
+
+}  // namespace zcsd

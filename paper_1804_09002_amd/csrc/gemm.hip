@@ -1,0 +1,202 @@
+// FP64 matrix product on the gfx950 matrix cores (v_mfma_f64_16x16x4f64).
+//
+// C_b = alpha op(A_b) op(B_b) + beta C_b, column-major, batched with element
+// strides.  Every dense contraction of the Zolo-csd path (the trailing updates
+// and Q formation of the blocked Householder QR, the Cholesky and triangular
+// inverse recursions, the Zolotarev combines, B, U_i = W_i V1, V1^T H_i V1)
+// goes through this kernel.
+//
+// Tiling: a 256-thread workgroup (4 wave64s in a 2 x 2 grid) owns a BM x BN
+// tile of C; each wave owns WM x WN = (BM/2) x (BN/2) and issues
+// (WM/16) x (WN/16) MFMA 16x16x4 blocks per k-step of 4.  A and B tiles of
+// depth BK are staged through LDS (k-major), with the next tile's global loads
+// issued into registers before the current tile's MFMAs.
+//
+// Lane layout of v_mfma_f64_16x16x4f64 (wave64): input a[i][k] comes from
+// lane i + 16k, input b[k][j] from lane j + 16k, and output d[i][j] is item
+// i / 4 of lane j + 16 (i % 4).  The kernel feeds op(B)^T as the MFMA "a"
+// operand and op(A)^T as "b", so the accumulator holds C^T: lane l, item v is
+// C[row0 + l % 16][col0 + l / 16 + 4 v], and 16 consecutive lanes store 16
+// consecutive rows of one column of C (a 128-byte coalesced segment).
+#include <string>
+
+#include "zcsd_internal.h"
+#include "zcsd_prof.h"
+
+namespace zcsd {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+template <int BM, int BN, int BK, bool TA, bool TB>
+__global__ __launch_bounds__(256) void dgemm_kernel(
+    int m, int n, int k, const double* __restrict__ A, long long lda, long long sA,
+    const double* __restrict__ B, long long ldb, long long sB, double* __restrict__ C,
+    long long ldc, long long sC, double alpha, double beta, int nb1, long long sA2, long long sB2,
+    long long sC2) {
+  constexpr int WM = BM / 2, WN = BN / 2;
+  constexpr int TM = WM / 16, TN = WN / 16;
+  constexpr int NA = BM * BK / 256, NB = BN * BK / 256;
+  static_assert(NA * 256 == BM * BK && NB * 256 == BN * BK, "tile/threads mismatch");
+  __shared__ double As[BK][BM + 1];
+  __shared__ double Bs[BK][BN + 1];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int wm = wave & 1, wn = wave >> 1;
+  const int i0 = blockIdx.x * BM;
+  const int j0 = blockIdx.y * BN;
+  const long long b1 = blockIdx.z % nb1, b2 = blockIdx.z / nb1;
+  A += b1 * sA + b2 * sA2;
+  B += b1 * sB + b2 * sB2;
+  C += b1 * sC + b2 * sC2;
+
+  double ra[NA], rb[NB];
+  auto load_tiles = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = tid + 256 * q;
+      int i, kk;
+      if (!TA) { i = e % BM; kk = e / BM; } else { kk = e % BK; i = e / BK; }
+      const int gi = i0 + i, gk = k0 + kk;
+      double v = 0.0;
+      if (gi < m && gk < k) v = TA ? A[gk + (long long)gi * lda] : A[gi + (long long)gk * lda];
+      ra[q] = v;
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int e = tid + 256 * q;
+      int j, kk;
+      if (!TB) { kk = e % BK; j = e / BK; } else { j = e % BN; kk = e / BN; }
+      const int gj = j0 + j, gk = k0 + kk;
+      double v = 0.0;
+      if (gj < n && gk < k) v = TB ? B[gj + (long long)gk * ldb] : B[gk + (long long)gj * ldb];
+      rb[q] = v;
+    }
+  };
+  auto store_tiles = [&]() {
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int e = tid + 256 * q;
+      int i, kk;
+      if (!TA) { i = e % BM; kk = e / BM; } else { kk = e % BK; i = e / BK; }
+      As[kk][i] = ra[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int e = tid + 256 * q;
+      int j, kk;
+      if (!TB) { kk = e % BK; j = e / BK; } else { j = e % BN; kk = e / BN; }
+      Bs[kk][j] = rb[q];
+    }
+  };
+
+  d4 acc[TM][TN];
+#pragma unroll
+  for (int x = 0; x < TM; ++x)
+#pragma unroll
+    for (int y = 0; y < TN; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+
+  const int lr = lane & 15;   // row (of the 16-block) this lane feeds / owns
+  const int lk = lane >> 4;   // k index within the k-step of 4
+
+  if (k > 0) load_tiles(0);
+  for (int k0 = 0; k0 < k; k0 += BK) {
+    __syncthreads();
+    store_tiles();
+    __syncthreads();
+    if (k0 + BK < k) load_tiles(k0 + BK);
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      double fa[TM], fb[TN];
+#pragma unroll
+      for (int x = 0; x < TM; ++x) fa[x] = As[kk + lk][wm * WM + x * 16 + lr];
+#pragma unroll
+      for (int y = 0; y < TN; ++y) fb[y] = Bs[kk + lk][wn * WN + y * 16 + lr];
+#pragma unroll
+      for (int x = 0; x < TM; ++x)
+#pragma unroll
+        for (int y = 0; y < TN; ++y)
+          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[y], fa[x], acc[x][y], 0, 0, 0);
+    }
+  }
+
+  // epilogue: lane owns C[row][col + 4v]
+#pragma unroll
+  for (int x = 0; x < TM; ++x) {
+    const int row = i0 + wm * WM + x * 16 + lr;
+    if (row >= m) continue;
+#pragma unroll
+    for (int y = 0; y < TN; ++y) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int col = j0 + wn * WN + y * 16 + lk + 4 * v;
+        if (col < n) {
+          double* p = C + row + (long long)col * ldc;
+          const double r = alpha * acc[x][y][v];
+          *p = (beta == 0.0) ? r : r + beta * (*p);
+        }
+      }
+    }
+  }
+}
+
+template <int BM, int BN, int BK>
+static const char* tile_name(int ta, int tb) {
+  static const char* names[4] = {nullptr, nullptr, nullptr, nullptr};
+  static std::string store[4];
+  const int i = (ta ? 2 : 0) + (tb ? 1 : 0);
+  if (!names[i]) {
+    store[i] = "dgemm_" + std::to_string(BM) + "x" + std::to_string(BN) + "_" + (ta ? "T" : "N") +
+               (tb ? "T" : "N");
+    names[i] = store[i].c_str();
+  }
+  return names[i];
+}
+
+template <int BM, int BN, int BK>
+static void launch_tile(const GemmBatch& g, hipStream_t s) {
+  const double nprob = (double)g.batch * g.batch2;
+  ProfScope prof(tile_name<BM, BN, BK>(g.transA, g.transB), s,
+                 2.0 * g.m * (double)g.n * g.k * nprob,
+                 8.0 * nprob * ((double)g.m * g.k + (double)g.k * g.n + (g.beta != 0.0 ? 2.0 : 1.0) * g.m * g.n));
+  const int gx = (g.m + BM - 1) / BM, gy = (g.n + BN - 1) / BN;
+  // the z dimension enumerates (b1, b2) pairs; chunk over b2 to stay within 65535
+  const int per = std::max(1, 65535 / std::max(1, g.batch));
+  if (g.batch > 65535) throw ArgError("dgemm: batch too large");
+  for (int c0 = 0; c0 < g.batch2; c0 += per) {
+    const int nc = std::min(per, g.batch2 - c0);
+    dim3 grid(gx, gy, g.batch * nc), block(256);
+    const double* A = g.A + (long long)c0 * g.sA2;
+    const double* B = g.B + (long long)c0 * g.sB2;
+    double* C = g.C + (long long)c0 * g.sC2;
+#define ZCSD_GEMM_LAUNCH(TA_, TB_)                                                        \
+  hipLaunchKernelGGL((dgemm_kernel<BM, BN, BK, TA_, TB_>), grid, block, 0, s, g.m, g.n, g.k, A, \
+                     g.lda, g.sA, B, g.ldb, g.sB, C, g.ldc, g.sC, g.alpha, g.beta, g.batch,     \
+                     g.sA2, g.sB2, g.sC2)
+    if (!g.transA && !g.transB) ZCSD_GEMM_LAUNCH(false, false);
+    else if (!g.transA && g.transB) ZCSD_GEMM_LAUNCH(false, true);
+    else if (g.transA && !g.transB) ZCSD_GEMM_LAUNCH(true, false);
+    else ZCSD_GEMM_LAUNCH(true, true);
+#undef ZCSD_GEMM_LAUNCH
+    ZCSD_CHECK_LAUNCH();
+  }
+}
+
+void dgemm(const GemmBatch& g, hipStream_t s) {
+  if (g.m <= 0 || g.n <= 0 || g.batch <= 0 || g.batch2 <= 0) return;
+  if (g.k <= 0) {
+    // C = beta C
+    if (g.beta != 1.0)
+      for (int c = 0; c < g.batch2; ++c)
+        copy_scale(g.batch, g.m, g.n, g.beta, g.C + c * g.sC2, g.ldc, g.sC, g.C + c * g.sC2, g.ldc,
+                   g.sC, s);
+    return;
+  }
+  const long long tiles128 =
+      (long long)((g.m + 127) / 128) * ((g.n + 127) / 128) * g.batch * g.batch2;
+  if (tiles128 >= 512) launch_tile<128, 128, 16>(g, s);
+  else launch_tile<64, 64, 16>(g, s);
+}
+
+}  // namespace zcsd

@@ -1,0 +1,303 @@
+// Blocked Householder QR on the gfx950 path (batched, FP64).
+//
+// Two shapes share one engine:
+//  * General: an m x n matrix (m >= n).  Panel k (columns c0 = k*nb ..) acts on
+//    rows [c0, m).
+//  * Stacked: the 2n x n matrix [R; sqrt(c) I] of the QR form of a Zolotarev
+//    term (Sec. 5), with R upper triangular.  Reflector j only touches top row
+//    j and bottom rows 0..j (the bottom block fills in as an upper triangle),
+//    so panel k acts on the two row segments top [c0, c0+w) and bottom
+//    [n, n + c0 + w): the panels grow from 2w to n + w rows instead of a
+//    constant 2n, and the factorisation costs ~2n^3/3 flops instead of 10n^3/3.
+//
+// Each panel is factored by one workgroup (qr_panel_kernel): the panel's rows
+// are copied into a contiguous buffer V (logical rows: segment 1 then
+// segment 2), Householder reflectors are computed column by column with
+// workgroup reductions, and the compact-WY factor T (H_1...H_w = I - V T V^T)
+// is built on the fly from the same reductions.  R goes back into the matrix,
+// the annihilated entries become exact zeros.  Trailing updates and Q
+// formation are MFMA GEMMs on the two segments.
+#include <algorithm>
+#include <cmath>
+
+#include "zcsd_internal.h"
+#include "zcsd_la.h"
+#include "zcsd_prof.h"
+
+namespace zcsd {
+
+constexpr int QR_NT = 256;
+
+template <int NW>
+__device__ __forceinline__ void wave_sum_multi(double (&p)[NW]) {
+#pragma unroll
+  for (int j = 0; j < NW; ++j) {
+    double v = p[j];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    p[j] = v;
+  }
+}
+
+// logical row -> physical row of the matrix
+__device__ __forceinline__ int qr_phys(int i, int h1, int r1a, int r2a) {
+  return i < h1 ? r1a + i : r2a + (i - h1);
+}
+
+template <int NB>
+__global__ __launch_bounds__(QR_NT) void qr_panel_kernel(double* M, long long ldm, long long sM,
+                                                         int c0, int w, int r1a, int r1b, int r2a,
+                                                         int r2b, double* V, long long ldv,
+                                                         long long sV, double* T, long long sT) {
+  constexpr int NWV = QR_NT / 64;
+  __shared__ double red[NWV][NB];
+  __shared__ double sums[NB];
+  __shared__ double Ts[NB][NB + 1];
+  __shared__ double betas[NB];
+  __shared__ double sig_sh;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const long long b = blockIdx.x;
+  M += b * sM;
+  V += b * sV;
+  T += b * sT;
+  const int h1 = r1b - r1a, h2 = r2b - r2a, h = h1 + h2;
+
+  // copy the panel into V (logical rows)
+  for (long long e = tid; e < (long long)h * w; e += QR_NT) {
+    const int i = (int)(e % h), j = (int)(e / h);
+    V[i + j * ldv] = M[qr_phys(i, h1, r1a, r2a) + (long long)(c0 + j) * ldm];
+  }
+  for (int e = tid; e < NB * (NB + 1); e += QR_NT) (&Ts[0][0])[e] = 0.0;
+  __syncthreads();
+
+  for (int t = 0; t < w; ++t) {
+    double* vt = V + (long long)t * ldv;
+    // ||x(t+1:h)||^2
+    double p[1] = {0.0};
+    for (int i = t + 1 + tid; i < h; i += QR_NT) {
+      const double x = vt[i];
+      p[0] += x * x;
+    }
+    wave_sum_multi<1>(p);
+    if (lane == 0) red[wave][0] = p[0];
+    __syncthreads();
+    if (tid == 0) {
+      double s = 0.0;
+      for (int q = 0; q < NWV; ++q) s += red[q][0];
+      sig_sh = s;
+    }
+    __syncthreads();
+    const double sig2 = sig_sh;
+    const double alpha = vt[t];
+    double tau, beta, scal;
+    if (sig2 == 0.0) {  // H = I (LAPACK convention: no reflection, R_tt = alpha)
+      tau = 0.0;
+      beta = alpha;
+      scal = 1.0;
+    } else {
+      const double nrm = sqrt(alpha * alpha + sig2);
+      beta = alpha >= 0.0 ? -nrm : nrm;
+      tau = (beta - alpha) / beta;
+      scal = 1.0 / (alpha - beta);
+    }
+    __syncthreads();  // every thread has read alpha
+    if (tid == 0) {
+      vt[t] = 1.0;
+      betas[t] = beta;
+    }
+    for (int i = t + 1 + tid; i < h; i += QR_NT) vt[i] *= scal;
+    __syncthreads();
+
+    // d_j = V(t,j) + sum_{i>t} v_i V(i,j), j != t: the T column (j < t) and the update (j > t)
+    double d[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) d[j] = 0.0;
+    for (int i = t + 1 + tid; i < h; i += QR_NT) {
+      const double vi = vt[i];
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+        if (j < w && j != t) d[j] += vi * V[i + (long long)j * ldv];
+    }
+    wave_sum_multi<NB>(d);
+    if (lane == 0) {
+#pragma unroll
+      for (int j = 0; j < NB; ++j) red[wave][j] = d[j];
+    }
+    __syncthreads();
+    if (tid < w && tid != t) {
+      double s = V[t + (long long)tid * ldv];
+      for (int q = 0; q < NWV; ++q) s += red[q][tid];
+      sums[tid] = s;
+    }
+    __syncthreads();
+    // T(0:t, t) = -tau T(0:t, 0:t) d(0:t); T(t, t) = tau
+    if (tid < t) {
+      double s = 0.0;
+      for (int q = tid; q < t; ++q) s += Ts[tid][q] * sums[q];
+      Ts[tid][t] = -tau * s;
+    }
+    if (tid == 0) Ts[t][t] = tau;
+    // update columns j > t: A(t:h, j) -= tau d_j v
+    const int nup = w - t - 1;
+    if (nup > 0 && tau != 0.0) {
+      for (long long e = tid; e < (long long)(h - t) * nup; e += QR_NT) {
+        const int i = t + (int)(e % (h - t));
+        const int j = t + 1 + (int)(e / (h - t));
+        const double vi = (i == t) ? 1.0 : vt[i];
+        V[i + (long long)j * ldv] -= tau * sums[j] * vi;
+      }
+    }
+    __syncthreads();
+  }
+
+  // write R back (logical rows 0..w-1 = physical r1a..), zero the rest of the panel columns;
+  // then clear V above its unit diagonal and store T.
+  for (long long e = tid; e < (long long)h * w; e += QR_NT) {
+    const int i = (int)(e % h), j = (int)(e / h);
+    double val;
+    if (i < j) val = V[i + (long long)j * ldv];
+    else if (i == j) val = betas[j];
+    else val = 0.0;
+    M[qr_phys(i, h1, r1a, r2a) + (long long)(c0 + j) * ldm] = val;
+  }
+  __syncthreads();
+  for (long long e = tid; e < (long long)w * w; e += QR_NT) {
+    const int i = (int)(e % w), j = (int)(e / w);
+    if (i < j) V[i + (long long)j * ldv] = 0.0;
+  }
+  for (int e = tid; e < NB * NB; e += QR_NT) {
+    const int i = e % NB, j = e / NB;
+    T[i + (long long)j * NB] = (i < w && j < w) ? Ts[i][j] : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+
+static void panel_segments(QRShape shape, int m, int n, int nb, int k, int* c0, int* w, int* r1a,
+                           int* r1b, int* r2a, int* r2b) {
+  *c0 = k * nb;
+  *w = std::min(nb, n - *c0);
+  if (shape == QRShape::General) {
+    *r1a = *c0;
+    *r1b = m;
+    *r2a = *r2b = 0;
+  } else {  // stacked [R; D], R and D n x n, m = 2n
+    *r1a = *c0;
+    *r1b = *c0 + *w;
+    *r2a = n;
+    *r2b = n + *c0 + *w;
+  }
+}
+
+QRWork qr_work_alloc(Arena& ar, QRShape shape, int batch, int m, int n, int nb) {
+  QRWork wk;
+  wk.nb = nb;
+  wk.K = (n + nb - 1) / nb;
+  wk.ldv = (shape == QRShape::General) ? m : (n + nb);
+  wk.sV = (long long)wk.K * wk.ldv * nb;
+  wk.sT = (long long)wk.K * nb * nb;
+  wk.V = ar.dalloc((size_t)batch * wk.sV);
+  wk.T = ar.dalloc((size_t)batch * wk.sT);
+  wk.sW = (long long)nb * n;
+  wk.W = ar.dalloc((size_t)batch * wk.sW);
+  wk.W2 = ar.dalloc((size_t)batch * wk.sW);
+  return wk;
+}
+
+// C <- (I - V T' V^T) C on the panel's row segments, columns [col0, col0 + nc);
+// T' = T^T when transT (apply Q^T), T' = T otherwise (apply Q).
+static void apply_block_reflector(int batch, double* M, long long ldm, long long sM, int col0,
+                                  int nc, int r1a, int r1b, int r2a, int r2b, int w,
+                                  const double* V, long long ldv, long long sV, const double* T,
+                                  long long sT, int nbT, double* W, double* W2, long long sW,
+                                  bool transT, hipStream_t s) {
+  if (nc <= 0 || w <= 0) return;
+  const int h1 = r1b - r1a, h2 = r2b - r2a;
+  GemmBatch g;
+  g.batch = batch;
+  // W = V1^T C1 (+ V2^T C2)
+  g.transA = 1; g.transB = 0;
+  g.m = w; g.n = nc; g.k = h1;
+  g.A = V; g.lda = ldv; g.sA = sV;
+  g.B = M + r1a + (long long)col0 * ldm; g.ldb = ldm; g.sB = sM;
+  g.C = W; g.ldc = w; g.sC = sW;
+  g.alpha = 1.0; g.beta = 0.0;
+  dgemm(g, s);
+  if (h2 > 0) {
+    g.k = h2;
+    g.A = V + h1; g.B = M + r2a + (long long)col0 * ldm;
+    g.beta = 1.0;
+    dgemm(g, s);
+  }
+  // W2 = T' W
+  GemmBatch t;
+  t.batch = batch;
+  t.transA = transT ? 1 : 0; t.transB = 0;
+  t.m = w; t.n = nc; t.k = w;
+  t.A = T; t.lda = nbT; t.sA = sT;
+  t.B = W; t.ldb = w; t.sB = sW;
+  t.C = W2; t.ldc = w; t.sC = sW;
+  t.alpha = 1.0; t.beta = 0.0;
+  dgemm(t, s);
+  // C -= V W2
+  GemmBatch u;
+  u.batch = batch;
+  u.transA = 0; u.transB = 0;
+  u.m = h1; u.n = nc; u.k = w;
+  u.A = V; u.lda = ldv; u.sA = sV;
+  u.B = W2; u.ldb = w; u.sB = sW;
+  u.C = M + r1a + (long long)col0 * ldm; u.ldc = ldm; u.sC = sM;
+  u.alpha = -1.0; u.beta = 1.0;
+  dgemm(u, s);
+  if (h2 > 0) {
+    u.m = h2;
+    u.A = V + h1;
+    u.C = M + r2a + (long long)col0 * ldm;
+    dgemm(u, s);
+  }
+}
+
+void geqrf_batched(int batch, QRShape shape, int m, int n, double* M, long long ldm, long long sM,
+                   QRWork& wk, hipStream_t s) {
+  if (batch <= 0 || n <= 0) return;
+  const int nb = wk.nb;
+  for (int k = 0; k < wk.K; ++k) {
+    int c0, w, r1a, r1b, r2a, r2b;
+    panel_segments(shape, m, n, nb, k, &c0, &w, &r1a, &r1b, &r2a, &r2b);
+    double* Vk = wk.V + (long long)k * wk.ldv * nb;
+    double* Tk = wk.T + (long long)k * nb * nb;
+    const double hh = (double)(r1b - r1a) + (r2b - r2a);
+    ProfScope prof("qr_panel", s, batch * 2.0 * hh * w * w, batch * 8.0 * 2.0 * hh * w);
+    if (nb == 32)
+      hipLaunchKernelGGL(qr_panel_kernel<32>, dim3(batch), dim3(QR_NT), 0, s, M, ldm, sM, c0, w,
+                         r1a, r1b, r2a, r2b, Vk, wk.ldv, wk.sV, Tk, wk.sT);
+    else if (nb == 16)
+      hipLaunchKernelGGL(qr_panel_kernel<16>, dim3(batch), dim3(QR_NT), 0, s, M, ldm, sM, c0, w,
+                         r1a, r1b, r2a, r2b, Vk, wk.ldv, wk.sV, Tk, wk.sT);
+    else
+      throw ArgError("geqrf: unsupported panel width");
+    ZCSD_CHECK_LAUNCH();
+    const int col0 = c0 + w;
+    apply_block_reflector(batch, M, ldm, sM, col0, n - col0, r1a, r1b, r2a, r2b, w, Vk, wk.ldv,
+                          wk.sV, Tk, wk.sT, nb, wk.W, wk.W2, wk.sW, /*transT=*/true, s);
+  }
+}
+
+void orgqr_batched(int batch, QRShape shape, int m, int n, double* Q, long long ldq, long long sQ,
+                   const double* d_scale, const QRWork& wk, hipStream_t s) {
+  if (batch <= 0 || n <= 0) return;
+  set_identity_scaled(batch, m, n, d_scale, 1.0, Q, ldq, sQ, s);
+  const int nb = wk.nb;
+  for (int k = wk.K - 1; k >= 0; --k) {
+    int c0, w, r1a, r1b, r2a, r2b;
+    panel_segments(shape, m, n, nb, k, &c0, &w, &r1a, &r1b, &r2a, &r2b);
+    const double* Vk = wk.V + (long long)k * wk.ldv * nb;
+    const double* Tk = wk.T + (long long)k * nb * nb;
+    apply_block_reflector(batch, Q, ldq, sQ, c0, n - c0, r1a, r1b, r2a, r2b, w, Vk, wk.ldv,
+                          wk.sV, Tk, wk.sT, nb, wk.W, wk.W2, wk.sW, /*transT=*/false, s);
+  }
+}
+
+}  // namespace zcsd

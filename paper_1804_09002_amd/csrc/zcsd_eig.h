@@ -1,0 +1,39 @@
+// Zolo-eig (internal): spectral divide and conquer on the sign function.
+#pragma once
+#include "zcsd_internal.h"
+
+namespace zcsd {
+
+// batched Jacobi on blocks of at most 64 (jacobi.hip): sizes per block (device),
+// A_b read (ld lda, stride sA), V_b written (n_b x n_b, ld ldv), lam_b (64 per block)
+void jacobi_batched(int nblk, const int* d_sizes, const double* A, long long lda, long long sA,
+                    double* V, long long ldv, long long sV, double* d_lam, hipStream_t s);
+
+struct ZoloEigArgs {
+  int n = 0;
+  const double* B = nullptr;  // n x n symmetric, ld ldb
+  long long ldb = 0;
+  double lo = -1.0, hi = 1.0;  // spectrum bounds
+  double* V = nullptr;         // n x n eigenvectors (ld ldv), ascending eigenvalues
+  long long ldv = 0;
+  double* lam = nullptr;       // n eigenvalues (device)
+  int n_leaf = 64;
+  double eps = 1e-15, tol = 0x1p-53;
+  bool measure_offblock = true;
+};
+struct ZoloEigResult {
+  int levels = 0, splits = 0, max_r = 0, failed_splits = 0;
+  double max_offblock = 0.0;
+};
+ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s);
+
+// column copies described on the host: dst[:, c] for items (device descriptors)
+struct CopyDesc {
+  long long src_off, dst_off;  // element offsets from the base pointers
+  int src_ld, dst_ld;
+  int rows, cols;
+};
+void copy_blocks(const double* src, double* dst, const std::vector<CopyDesc>& d, Arena& ar,
+                 hipStream_t s);
+
+}  // namespace zcsd

@@ -1,0 +1,122 @@
+// Internal declarations of libzcsd (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/zcsd.h"
+
+namespace zcsd {
+
+// ---------------------------------------------------------------------------
+// errors
+struct HipError : std::runtime_error {
+  explicit HipError(const std::string& s) : std::runtime_error(s) {}
+};
+struct ArgError : std::runtime_error {
+  explicit ArgError(const std::string& s) : std::runtime_error(s) {}
+};
+struct NumError : std::runtime_error {
+  zcsd_status code;
+  NumError(zcsd_status c, const std::string& s) : std::runtime_error(s), code(c) {}
+};
+
+#define ZCSD_HIP(call)                                                              \
+  do {                                                                              \
+    hipError_t e_ = (call);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      throw ::zcsd::HipError(std::string(#call) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+#define ZCSD_CHECK_LAUNCH() ZCSD_HIP(hipGetLastError())
+
+#define ZCSD_REQUIRE(cond, msg)                                                     \
+  do {                                                                              \
+    if (!(cond)) throw ::zcsd::ArgError(msg);                                       \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// device workspace: a bump allocator over one hipMalloc'd block that grows
+// between calls; every allocation is 256-byte aligned.
+class Arena {
+ public:
+  ~Arena();
+  void reserve(size_t bytes);      // make capacity >= bytes (frees and reallocates if needed)
+  void reset() { top_ = 0; }
+  size_t mark() const { return top_; }
+  void release(size_t m) { top_ = m; }
+  double* dalloc(size_t count) { return static_cast<double*>(alloc(count * sizeof(double))); }
+  int* ialloc(size_t count) { return static_cast<int*>(alloc(count * sizeof(int))); }
+  void* alloc(size_t bytes);
+  size_t capacity() const { return cap_; }
+  size_t high_water() const { return high_; }
+
+ private:
+  char* base_ = nullptr;
+  size_t cap_ = 0, top_ = 0, high_ = 0;
+};
+
+// Scoped release of arena allocations made inside a block.
+struct ArenaScope {
+  Arena& a;
+  size_t m;
+  explicit ArenaScope(Arena& ar) : a(ar), m(ar.mark()) {}
+  ~ArenaScope() { a.release(m); }
+};
+
+}  // namespace zcsd
+
+struct zcsd_handle_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  zcsd::Arena arena;
+  // pinned host staging for small readbacks
+  double* h_stage = nullptr;
+  size_t h_stage_count = 0;
+};
+
+namespace zcsd {
+
+// ---------------------------------------------------------------------------
+// GEMM (gemm.hip).  Column-major, C_b = alpha_b op(A_b) op(B_b) + beta_b C_b.
+struct GemmBatch {
+  int transA = 0, transB = 0;
+  int m = 0, n = 0, k = 0;
+  const double* A = nullptr; long long lda = 0, sA = 0;
+  const double* B = nullptr; long long ldb = 0, sB = 0;
+  double* C = nullptr; long long ldc = 0, sC = 0;
+  double alpha = 1.0, beta = 0.0;
+  int batch = 1;
+  // optional second batch dimension: problem (b1, b2) uses offsets b1*s? + b2*s?2
+  int batch2 = 1;
+  long long sA2 = 0, sB2 = 0, sC2 = 0;
+};
+void dgemm(const GemmBatch& g, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// element-wise and reduction kernels (elem.hip)
+// Y_b = alpha X_b (+ diag_add on the diagonal), m x n, per-batch strides.
+void copy_scale(int batch, int m, int n, double alpha, const double* X, long long ldx, long long sx,
+                double* Y, long long ldy, long long sy, hipStream_t s);
+void add_diag(int batch, int n, double v, double* X, long long ldx, long long sx, hipStream_t s);
+void set_identity(int batch, int m, int n, double v, double* X, long long ldx, long long sx,
+                  hipStream_t s);
+// X_b = (X_b + X_b^T) / 2 in place (n x n)
+void symmetrize(int batch, int n, double* X, long long ldx, long long sx, hipStream_t s);
+// out[b] = sum of squares of X_b (m x n) -> device array (length batch)
+void sumsq(int batch, int m, int n, const double* X, long long ldx, long long sx, double* out,
+           hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// host helpers
+struct HostSync {
+  static void sync(hipStream_t s) { ZCSD_HIP(hipStreamSynchronize(s)); }
+};
+void d2h(void* h, const void* d, size_t bytes, hipStream_t s);  // async + sync
+void h2d(void* d, const void* h, size_t bytes, hipStream_t s);  // async (pageable: sync inside)
+
+}  // namespace zcsd

@@ -1,0 +1,44 @@
+// Device linear-algebra building blocks of the Zolo-csd path (internal).
+#pragma once
+#include "zcsd_internal.h"
+
+namespace zcsd {
+
+// ---------------------------------------------------------------------------
+// blocked Householder QR (qr.hip)
+enum class QRShape { General, Stacked };
+
+struct QRWork {
+  int nb = 32, K = 0;
+  long long ldv = 0;
+  double* V = nullptr;  long long sV = 0;   // K panels of ldv x nb per problem
+  double* T = nullptr;  long long sT = 0;   // K blocks of nb x nb per problem
+  double* W = nullptr;  double* W2 = nullptr; long long sW = 0;  // nb x n scratch per problem
+};
+
+QRWork qr_work_alloc(Arena& ar, QRShape shape, int batch, int m, int n, int nb);
+// In place: M_b (m x n, or 2n x n for Stacked) -> R in its top n x n upper triangle,
+// zeros below; reflectors kept in wk.
+void geqrf_batched(int batch, QRShape shape, int m, int n, double* M, long long ldm, long long sM,
+                   QRWork& wk, hipStream_t s);
+// Q_b = H_1 ... H_K [scale_b I_n; 0] (m x n); d_scale may be NULL (scale 1).
+void orgqr_batched(int batch, QRShape shape, int m, int n, double* Q, long long ldq, long long sQ,
+                   const double* d_scale, const QRWork& wk, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// element-wise helpers beyond zcsd_internal.h (elem.hip)
+// X_b = v_b I (m x n), v_b = d_vals[b] when d_vals != NULL else v
+void set_identity_scaled(int batch, int m, int n, const double* d_vals, double v, double* X,
+                         long long ldx, long long sx, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Cholesky with inverse factor (chol.hip): for SPD A_b (n x n, lower/upper both
+// read symmetrically from the upper triangle): R_b upper with R^T R = A and
+// Ri_b = R^{-1}; both n x n with ld n, stride n*n.  A is overwritten.
+void chol_inv_batched(int batch, int n, double* A, long long lda, long long sA, double* R,
+                      double* Ri, Arena& ar, hipStream_t s);
+// Upper-triangular inverse Ri = R^{-1} (n x n), level-parallel recursion.
+void trtri_upper_batched(int batch, int n, const double* R, long long ldr, long long sR, double* Ri,
+                         long long ldi, long long sI, Arena& ar, hipStream_t s);
+
+}  // namespace zcsd

@@ -1,0 +1,305 @@
+"""ctypes binding of libzcsd (argument marshalling only).
+
+Every step of the decomposition runs in the HIP library; this module only
+checks shapes, passes device pointers of torch tensors, and converts between
+the user's (rows, cols) indexing and the library's column-major storage:
+a matrix X is handed to the library as the contiguous buffer of ``X.t()``,
+and results come back as ``.t()`` views of column-major buffers.
+
+If ``libzcsd.so`` is missing or no HIP device is visible, every call raises;
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libzcsd.so")
+
+ZCSD_OK, ZCSD_EINVAL, ZCSD_ENOTISO, ZCSD_ENOCONV, ZCSD_EREPAIR, ZCSD_EHIP, ZCSD_ENOMEM = range(7)
+RANK_AUTO, RANK_FULL, RANK_DEFICIENT = 0, 1, 2
+FP64, MIXED_FP32 = 0, 1
+
+
+class ZcsdError(RuntimeError):
+    def __init__(self, status, what=""):
+        self.status = status
+        super().__init__(f"{what}: {_lib().zcsd_status_string(status).decode()}")
+
+
+class Opts(C.Structure):
+    _fields_ = [("prec", C.c_int), ("rank_mode", C.c_int), ("eps", C.c_double),
+                ("mu", C.c_double), ("tol", C.c_double), ("r_override", C.c_int),
+                ("ell_override", C.c_double), ("n_leaf", C.c_int), ("postprocess", C.c_int)]
+
+
+class Info(C.Structure):
+    _fields_ = [("rank", C.c_int), ("r_used", C.c_int * 2), ("ell", C.c_double * 2),
+                ("zolo_resid", C.c_double), ("eig_levels", C.c_int), ("eig_splits", C.c_int),
+                ("eig_max_r", C.c_int), ("eig_offblock", C.c_double), ("time_ms", C.c_double * 4)]
+
+    def as_dict(self):
+        return {"rank": self.rank, "r_used": list(self.r_used), "ell": list(self.ell),
+                "zolo_resid": self.zolo_resid, "eig_levels": self.eig_levels,
+                "eig_splits": self.eig_splits, "eig_max_r": self.eig_max_r,
+                "eig_offblock": self.eig_offblock, "time_ms": list(self.time_ms)}
+
+
+_L = None
+
+
+def _lib():
+    global _L
+    if _L is None:
+        if not os.path.exists(_LIB_PATH):
+            raise RuntimeError(f"libzcsd.so not built ({_LIB_PATH}); run __graft_entry__.build()")
+        L = C.CDLL(_LIB_PATH)
+        vp, i, d, ll = C.c_void_p, C.c_int, C.c_double, C.c_longlong
+        L.zcsd_create.argtypes = [C.POINTER(vp), i]
+        L.zcsd_destroy.argtypes = [vp]
+        L.zcsd_set_stream.argtypes = [vp, vp]
+        L.zcsd_default_opts.argtypes = [C.POINTER(Opts)]
+        L.zcsd_default_opts.restype = None
+        L.zcsd_status_string.argtypes = [i]
+        L.zcsd_status_string.restype = C.c_char_p
+        L.zcsd_dgemm.argtypes = [vp, i, i, i, i, i, d, vp, i, ll, vp, i, ll, d, vp, i, ll, i]
+        for name, args in {
+            "zcsd_dcsd": [vp, i, vp, i, vp, i, vp, i, vp, i, vp, i, vp, vp, vp,
+                          C.POINTER(Opts), C.POINTER(Info)],
+            "zcsd_dzolo_pd": [vp, i, i, d, vp, i, ll, vp, vp, vp, C.POINTER(Opts), C.POINTER(Info)],
+            "zcsd_dsyev_zolo": [vp, i, vp, i, d, d, vp, i, vp, C.POINTER(Opts), C.POINTER(Info)],
+            "zcsd_zolo_coeffs": [d, i, C.POINTER(d), C.POINTER(d), C.POINTER(d), C.POINTER(d)],
+            "zcsd_zolo_choose_r": [d, d],
+            "zcsd_dqr": [vp, i, i, i, i, vp, i, ll, vp, i, ll],
+            "zcsd_profile_query": [C.c_char_p, C.POINTER(ll), C.POINTER(d), C.POINTER(d), C.POINTER(d)],
+            "zcsd_profile_names": [C.c_char_p, i],
+            "zcsd_profile_filter": [C.c_char_p],
+        }.items():
+            if hasattr(L, name):
+                getattr(L, name).argtypes = args
+        if hasattr(L, "zcsd_zolo_choose_r"):
+            L.zcsd_zolo_choose_r.restype = C.c_int
+        _L = L
+    return _L
+
+
+def lib():
+    return _lib()
+
+
+def _check(st, what):
+    if st != ZCSD_OK:
+        raise ZcsdError(st, what)
+
+
+_HANDLES = {}
+
+
+def handle(device=None):
+    """Per-device library handle bound to torch's current stream at call time."""
+    if not torch.cuda.is_available():
+        raise RuntimeError("zcsd: no HIP device visible")
+    dev = torch.cuda.current_device() if device is None else int(device)
+    h = _HANDLES.get(dev)
+    if h is None:
+        h = C.c_void_p()
+        _check(_lib().zcsd_create(C.byref(h), dev), "zcsd_create")
+        _HANDLES[dev] = h
+    _lib().zcsd_set_stream(h, C.c_void_p(torch.cuda.current_stream(dev).cuda_stream))
+    return h
+
+
+def default_opts(**kw):
+    o = Opts()
+    _lib().zcsd_default_opts(C.byref(o))
+    for k, v in kw.items():
+        if v is None:
+            continue
+        if k == "rank_mode" and isinstance(v, str):
+            v = {"auto": RANK_AUTO, "full": RANK_FULL, "deficient": RANK_DEFICIENT}[v]
+        if k == "prec" and isinstance(v, str):
+            v = {"fp64": FP64, "mixed_fp32": MIXED_FP32}[v]
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+def _colmajor(X, name):
+    """(rows, cols) float64 CUDA tensor -> contiguous column-major buffer (cols, rows)."""
+    if not (isinstance(X, torch.Tensor) and X.is_cuda and X.dtype == torch.float64 and X.dim() == 2):
+        raise TypeError(f"{name} must be a 2-D float64 tensor on a HIP device")
+    return X.t().contiguous()
+
+
+def dgemm(A, B, transA=False, transB=False, alpha=1.0, beta=0.0, C_=None):
+    """C = alpha op(A) op(B) + beta C for 2-D or batched 3-D float64 device tensors (row-major API)."""
+    batched = A.dim() == 3
+    if not batched:
+        A, B = A.unsqueeze(0), B.unsqueeze(0)
+        C_ = None if C_ is None else C_.unsqueeze(0)
+    # column-major views: a row-major (r, c) tensor is the column-major (c, r) matrix = X^T.
+    # C = op(A) op(B)  <=>  C^T = op(B)^T op(A)^T: call the library with the roles swapped.
+    Ab, Bb = A.contiguous(), B.contiguous()
+    bs, ar, ac = Ab.shape
+    _, br, bc = Bb.shape
+    m_ = ac if transA else ar
+    k_ = ar if transA else ac
+    n_ = br if transB else bc
+    out = torch.empty((bs, m_, n_), dtype=torch.float64, device=A.device) if C_ is None else C_.contiguous()
+    h = handle(A.device.index)
+    # library computes (col-major) C' = op'(B') op'(A') with X' = X^T storage
+    st = _lib().zcsd_dgemm(h, 1 if transB else 0, 1 if transA else 0, n_, m_, k_, alpha,
+                           _ptr(Bb), bc, br * bc, _ptr(Ab), ac, ar * ac, beta,
+                           _ptr(out), n_, m_ * n_, bs)
+    _check(st, "zcsd_dgemm")
+    return out if batched else out[0]
+
+
+def zolo_coeffs(ell, r):
+    """Host Zolotarev coefficients from the library: (c[2r], a[r], M, ell_next)."""
+    c = (C.c_double * (2 * r))()
+    a = (C.c_double * r)()
+    M = C.c_double()
+    nx = C.c_double()
+    _check(_lib().zcsd_zolo_coeffs(float(ell), int(r), c, a, C.byref(M), C.byref(nx)), "zcsd_zolo_coeffs")
+    return list(c), list(a), M.value, nx.value
+
+
+def zolo_choose_r(ell, tol=2.0 ** -53):
+    return int(_lib().zcsd_zolo_choose_r(float(ell), float(tol)))
+
+
+def zolo_pd(X, alpha=1.0, r=None, ell=None, want_H=True, want_X1=False):
+    """Batched Zolo-pd of a (n, n) or (batch, n, n) float64 device tensor.
+
+    Returns (W, H, X1, info) with the same leading shape (H / X1 None unless requested).
+    """
+    batched = X.dim() == 3
+    Xb = X if batched else X.unsqueeze(0)
+    bs, n, n2 = Xb.shape
+    if n != n2:
+        raise ValueError("zolo_pd: square matrices only")
+    Xc = Xb.transpose(1, 2).contiguous()          # column-major buffers
+    W = torch.empty_like(Xc)
+    H = torch.empty_like(Xc) if want_H else None
+    X1 = torch.empty_like(Xc) if want_X1 else None
+    o = default_opts(r_override=r or 0, ell_override=ell or 0.0)
+    info = Info()
+    h = handle(X.device.index)
+    st = _lib().zcsd_dzolo_pd(h, bs, n, float(alpha), _ptr(Xc), n, n * n, _ptr(W),
+                              _ptr(H) if H is not None else None, _ptr(X1) if X1 is not None else None,
+                              C.byref(o), C.byref(info))
+    _check(st, "zcsd_dzolo_pd")
+    tr = lambda T: None if T is None else (T.transpose(1, 2) if batched else T[0].t())
+    return tr(W), tr(H), tr(X1), info.as_dict()
+
+
+def qr(M, stacked=False, want_q=True):
+    """Batched blocked Householder QR of (m, n) / (batch, m, n) device tensors.
+
+    Returns (R, Q): R (n, n) upper triangular, Q (m, n); stacked=True expects [R0; D] (2n x n).
+    """
+    batched = M.dim() == 3
+    Mb = M if batched else M.unsqueeze(0)
+    bs, m, n = Mb.shape
+    Mc = Mb.transpose(1, 2).contiguous()
+    Q = torch.empty_like(Mc) if want_q else None
+    h = handle(M.device.index)
+    st = _lib().zcsd_dqr(h, bs, 1 if stacked else 0, m, n, _ptr(Mc), m, m * n,
+                         _ptr(Q) if Q is not None else None, m, m * n)
+    _check(st, "zcsd_dqr")
+    R = Mc.transpose(1, 2)[:, :n, :]
+    Qr = None if Q is None else Q.transpose(1, 2)
+    if not batched:
+        R = R[0]
+        Qr = None if Qr is None else Qr[0]
+    return R, Qr
+
+
+def syev_zolo(B, lo=-1.0, hi=1.0, n_leaf=None):
+    """Zolo-eig of a symmetric (n, n) float64 device tensor: (lambda ascending, V, info)."""
+    n = B.shape[0]
+    Bc = _colmajor(B, "B")
+    V = torch.empty_like(Bc)
+    lam = torch.empty(n, dtype=torch.float64, device=B.device)
+    o = default_opts(n_leaf=n_leaf)
+    info = Info()
+    h = handle(B.device.index)
+    st = _lib().zcsd_dsyev_zolo(h, n, _ptr(Bc), n, float(lo), float(hi), _ptr(V), n, _ptr(lam),
+                                C.byref(o), C.byref(info))
+    _check(st, "zcsd_dsyev_zolo")
+    return lam, V.t(), info.as_dict()
+
+
+def csd(A1, A2, rank_mode="auto", r=None, ell=None, want_polar=False, **opts):
+    """CS decomposition of [A1; A2] (A1, A2: (n, n) float64 HIP tensors).
+
+    Returns (U1, U2, V1, theta, info) with A1 = U1 diag(cos theta) V1^T and
+    A2 = U2 diag(sin theta) V1^T; in the rank-deficient case only the first
+    info['rank'] columns / entries are valid (the rest are zero).  With
+    want_polar=True, info also holds the polar factors 'W1', 'W2'.
+    """
+    n = A1.shape[0]
+    if A1.shape != (n, n) or A2.shape != (n, n):
+        raise ValueError("csd: A1 and A2 must both be n x n")
+    a1 = _colmajor(A1, "A1")
+    a2 = _colmajor(A2, "A2")
+    U1 = torch.empty_like(a1)
+    U2 = torch.empty_like(a1)
+    V1 = torch.empty_like(a1)
+    th = torch.empty(n, dtype=torch.float64, device=A1.device)
+    W1 = torch.empty_like(a1) if want_polar else None
+    W2 = torch.empty_like(a1) if want_polar else None
+    o = default_opts(rank_mode=rank_mode, r_override=r or 0, ell_override=ell or 0.0, **opts)
+    info = Info()
+    h = handle(A1.device.index)
+    st = _lib().zcsd_dcsd(h, n, _ptr(a1), n, _ptr(a2), n, _ptr(U1), n, _ptr(U2), n, _ptr(V1), n,
+                          _ptr(th), _ptr(W1) if W1 is not None else None,
+                          _ptr(W2) if W2 is not None else None, C.byref(o), C.byref(info))
+    _check(st, "zcsd_dcsd")
+    d = info.as_dict()
+    if want_polar:
+        d["W1"], d["W2"] = W1.t(), W2.t()
+    return U1.t(), U2.t(), V1.t(), th, d
+
+
+class profile:
+    """Context manager: per-kernel HIP-event timing inside the library.
+
+    with zcsd.profile(only="dgemm_128x128_NN") as p: ...; p.stats() -> {name: {...}}
+    """
+
+    def __init__(self, only=None):
+        self.only = only
+
+    def __enter__(self):
+        L = _lib()
+        L.zcsd_profile_filter(self.only.encode() if self.only else None)
+        L.zcsd_profile_begin()
+        return self
+
+    def __exit__(self, *exc):
+        _lib().zcsd_profile_end()
+        return False
+
+    @staticmethod
+    def stats():
+        L = _lib()
+        n = L.zcsd_profile_names(None, 0)
+        buf = C.create_string_buffer(n + 1)
+        L.zcsd_profile_names(buf, n + 1)
+        out = {}
+        for name in buf.value.decode().split("\n"):
+            if not name:
+                continue
+            la, fl, by, ms = C.c_longlong(), C.c_double(), C.c_double(), C.c_double()
+            if L.zcsd_profile_query(name.encode(), C.byref(la), C.byref(fl), C.byref(by), C.byref(ms)):
+                out[name] = {"launches": la.value, "flops": fl.value, "bytes": by.value, "ms": ms.value}
+        return out

@@ -1,0 +1,60 @@
+"""Host-side checks of libzcsd that need no GPU: the library loads, exports
+every symbol include/zcsd.h declares, and its host Zolotarev coefficients
+(theta-series evaluation) agree with the oracle's elliptic-function definition."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1804_09002_amd", "libzcsd.so")
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "zcsd.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(zcsd_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libzcsd.so is not built; run __graft_entry__.build()")
+    return ctypes.CDLL(LIB)
+
+
+def test_exports_every_declared_symbol(lib):
+    names = _declared()
+    assert "zcsd_dcsd" in names and len(names) >= 10
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.parametrize("ell", [1e-15, 1e-9, 3.8e-4, 0.05, 0.5, 0.97])
+@pytest.mark.parametrize("r", [1, 3, 5, 8])
+def test_library_coefficients_match_oracle(ell, r):
+    from oracle import zolotarev as Z
+    from paper_1804_09002_amd import zcsd
+    c, a, M, nxt = zcsd.zolo_coeffs(ell, r)
+    st = Z.ZoloStep(ell, r)
+    assert np.allclose(c, st.c, rtol=2e-15, atol=0)
+    assert np.allclose(a, st.a, rtol=5e-14, atol=0)
+    assert abs(M - st.M) <= 4e-16 * st.M
+    assert abs(nxt - st.ell_next) <= 4e-16 * st.ell_next
+
+
+@pytest.mark.parametrize("ell", [1e-15, 1e-12, 1e-8, 2e-4, 0.1, 0.6])
+def test_library_degree_choice_matches_oracle(ell):
+    from oracle import zolotarev as Z
+    from paper_1804_09002_amd import zcsd
+    assert zcsd.zolo_choose_r(ell) == (Z.choose_r(ell) or 0)
+
+
+def test_invalid_coefficient_arguments(lib):
+    from paper_1804_09002_amd import zcsd
+    with pytest.raises(zcsd.ZcsdError):
+        zcsd.zolo_coeffs(0.0, 3)
+    with pytest.raises(zcsd.ZcsdError):
+        zcsd.zolo_coeffs(0.5, 9)

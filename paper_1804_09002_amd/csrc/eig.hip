@@ -24,6 +24,7 @@
 #include <numeric>
 #include <vector>
 
+#include "zcsd_api_guard.h"
 #include "zcsd_eig.h"
 #include "zcsd_internal.h"
 #include "zcsd_la.h"
@@ -167,6 +168,19 @@ __global__ void offblock_kernel(int N, const double* __restrict__ Bp, const int*
     __syncthreads();
   }
   if (threadIdx.x == 0) out[b] = red[0];
+}
+
+// E_b -= Bq_b on the real n_b x n_b part; zero elsewhere
+__global__ void sub_real_kernel(int N, double* E, const double* __restrict__ Bq,
+                                const int* __restrict__ nb) {
+  const long long b = blockIdx.y;
+  const long long NN = (long long)N * N;
+  const int m = nb[b];
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < NN;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e % N), j = (int)(e / N);
+    E[b * NN + e] = (i < m && j < m) ? E[b * NN + e] - Bq[b * NN + e] : 0.0;
+  }
 }
 
 __global__ void diag_kernel(int N, const double* __restrict__ Bp, const int* __restrict__ nb,
@@ -496,6 +510,7 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
       dgemm(h, s);
     }
     symmetrize(ns, Ns, Bq, Ns, SS, s);
+
     double* Vq = ar.dalloc((size_t)ns * n * Ns);
     {
       GemmBatch g;
@@ -505,6 +520,52 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
       g.B = Q; g.ldb = Ns; g.sB = SS;
       g.C = Vq; g.ldc = n; g.sC = (long long)n * Ns;
       dgemm(g, s);
+    }
+    if (log_enabled()) {
+      // diagnostics: ||Q^T Q - I||_F per block of this level
+      ArenaScope ds(ar);
+      double* G = ar.dalloc((size_t)ns * SS);
+      GemmBatch g;
+      g.batch = ns;
+      g.transA = 1;
+      g.m = Ns; g.n = Ns; g.k = Ns;
+      g.A = Q; g.lda = Ns; g.sA = SS;
+      g.B = Q; g.ldb = Ns; g.sB = SS;
+      g.C = G; g.ldc = Ns; g.sC = SS;
+      dgemm(g, s);
+      add_diag(ns, Ns, -1.0, G, Ns, SS, s);
+      double* d_o = ar.dalloc(ns);
+      sumsq(ns, Ns, Ns, G, Ns, SS, d_o, s);
+      std::vector<double> o(ns);
+      d2h(o.data(), d_o, ns * sizeof(double), s);
+      // invariant: Vq_b^T B Vq_b == Bq_b (B the original matrix)
+      double* BV = ar.dalloc((size_t)ns * n * Ns);
+      double* E = ar.dalloc((size_t)ns * SS);
+      GemmBatch g1;
+      g1.batch = ns;
+      g1.m = n; g1.n = Ns; g1.k = n;
+      g1.A = a.B; g1.lda = a.ldb; g1.sA = 0;
+      g1.B = Vq; g1.ldb = n; g1.sB = (long long)n * Ns;
+      g1.C = BV; g1.ldc = n; g1.sC = (long long)n * Ns;
+      dgemm(g1, s);
+      GemmBatch g2;
+      g2.batch = ns;
+      g2.transA = 1;
+      g2.m = Ns; g2.n = Ns; g2.k = n;
+      g2.A = Vq; g2.lda = n; g2.sA = (long long)n * Ns;
+      g2.B = BV; g2.ldb = n; g2.sB = (long long)n * Ns;
+      g2.C = E; g2.ldc = Ns; g2.sC = SS;
+      dgemm(g2, s);
+      double* d_e = ar.dalloc(ns);
+      std::vector<double> ev(ns);
+      // E -= Bq (only the real n_b x n_b part is meaningful)
+      hipLaunchKernelGGL(sub_real_kernel, grid2(SS, ns), dim3(256), 0, s, Ns, E, Bq, d_nbs);
+      ZCSD_CHECK_LAUNCH();
+      sumsq(ns, Ns, Ns, E, Ns, SS, d_e, s);
+      d2h(ev.data(), d_e, ns * sizeof(double), s);
+      for (int q = 0; q < ns; ++q)
+        std::fprintf(stderr, "[zcsd] eig level %d block %d n=%d N=%d shift=%.6g n+=%d trace=%.6f ||QtQ-I||=%.2e ||VtBV-Bq||=%.2e\n",
+                     res.levels, q, nbs[q], Ns, shs[q], npos[q], tr[q], std::sqrt(o[q]), std::sqrt(ev[q]));
     }
     if (a.measure_offblock) {
       int* d_np = upload(ar, npos, s);

@@ -18,6 +18,7 @@
 // operand and op(A)^T as "b", so the accumulator holds C^T: lane l, item v is
 // C[row0 + l % 16][col0 + l / 16 + 4 v], and 16 consecutive lanes store 16
 // consecutive rows of one column of C (a 128-byte coalesced segment).
+#include <cstdlib>
 #include <string>
 
 #include "zcsd_internal.h"
@@ -32,7 +33,7 @@ __global__ __launch_bounds__(256) void dgemm_kernel(
     int m, int n, int k, const double* __restrict__ A, long long lda, long long sA,
     const double* __restrict__ B, long long ldb, long long sB, double* __restrict__ C,
     long long ldc, long long sC, double alpha, double beta, int nb1, long long sA2, long long sB2,
-    long long sC2) {
+    long long sC2, int nprob, int kchunk, double* ws) {
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int TM = WM / 16, TN = WN / 16;
   constexpr int NA = BM * BK / 256, NB = BN * BK / 256;
@@ -46,10 +47,24 @@ __global__ __launch_bounds__(256) void dgemm_kernel(
   const int wm = wave & 1, wn = wave >> 1;
   const int i0 = blockIdx.x * BM;
   const int j0 = blockIdx.y * BN;
-  const long long b1 = blockIdx.z % nb1, b2 = blockIdx.z / nb1;
+  const int zp = blockIdx.z % nprob;      // problem index (b1, b2)
+  const int split = blockIdx.z / nprob;   // k-split index (0 without split-K)
+  const long long b1 = zp % nb1, b2 = zp / nb1;
   A += b1 * sA + b2 * sA2;
   B += b1 * sB + b2 * sB2;
   C += b1 * sC + b2 * sC2;
+  if (kchunk > 0) {
+    // this workgroup owns k in [split*kchunk, min(k, (split+1)*kchunk)) and writes
+    // its partial product (alpha = 1, beta = 0) to the workspace slab (ld m)
+    const int kb = split * kchunk;
+    A += TA ? (long long)kb : (long long)kb * lda;
+    B += TB ? (long long)kb * ldb : (long long)kb;
+    k = min(kchunk, k - kb);
+    C = ws + ((long long)split * nprob + zp) * (long long)m * n;
+    ldc = m;
+    alpha = 1.0;
+    beta = 0.0;
+  }
 
   double ra[NA], rb[NB];
   auto load_tiles = [&](int k0) {
@@ -141,6 +156,24 @@ __global__ __launch_bounds__(256) void dgemm_kernel(
   }
 }
 
+// C_p = alpha sum_s ws[s][p] + beta C_p  (split-K reduction, deterministic order)
+__global__ void splitk_reduce_kernel(int m, int n, int nprob, int nsplit, const double* __restrict__ ws,
+                                     double* C, long long ldc, long long sC, int nb1,
+                                     long long sC2, double alpha, double beta) {
+  const int zp = blockIdx.y;
+  const long long b1 = zp % nb1, b2 = zp / nb1;
+  double* Cp = C + b1 * sC + b2 * sC2;
+  const long long mn = (long long)m * n;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < mn;
+       e += (long long)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int q = 0; q < nsplit; ++q) s += ws[((long long)q * nprob + zp) * mn + e];
+    const int i = (int)(e % m), j = (int)(e / m);
+    double* c = Cp + i + (long long)j * ldc;
+    *c = (beta == 0.0) ? alpha * s : alpha * s + beta * (*c);
+  }
+}
+
 template <int BM, int BN, int BK>
 static const char* tile_name(int ta, int tb) {
   static const char* names[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -155,31 +188,47 @@ static const char* tile_name(int ta, int tb) {
 }
 
 template <int BM, int BN, int BK>
-static void launch_tile(const GemmBatch& g, hipStream_t s) {
-  const double nprob = (double)g.batch * g.batch2;
+static void launch_tile(const GemmBatch& g, hipStream_t s, int ksplit) {
+  const double nprob_d = (double)g.batch * g.batch2;
   ProfScope prof(tile_name<BM, BN, BK>(g.transA, g.transB), s,
-                 2.0 * g.m * (double)g.n * g.k * nprob,
-                 8.0 * nprob * ((double)g.m * g.k + (double)g.k * g.n + (g.beta != 0.0 ? 2.0 : 1.0) * g.m * g.n));
+                 2.0 * g.m * (double)g.n * g.k * nprob_d,
+                 8.0 * nprob_d * ((double)g.m * g.k + (double)g.k * g.n + (g.beta != 0.0 ? 2.0 : 1.0) * g.m * g.n));
   const int gx = (g.m + BM - 1) / BM, gy = (g.n + BN - 1) / BN;
-  // the z dimension enumerates (b1, b2) pairs; chunk over b2 to stay within 65535
-  const int per = std::max(1, 65535 / std::max(1, g.batch));
   if (g.batch > 65535) throw ArgError("dgemm: batch too large");
+  int kchunk = 0;
+  if (ksplit > 1) {
+    kchunk = (g.k + ksplit - 1) / ksplit;
+    kchunk = ((kchunk + BK - 1) / BK) * BK;
+    ksplit = (g.k + kchunk - 1) / kchunk;
+  }
+  const int nsplit = std::max(1, ksplit);
+  // the z dimension enumerates (split, b2, b1); chunk over b2 to stay within 65535
+  const int per = std::max(1, 65535 / std::max(1, g.batch * nsplit));
+  if (kchunk > 0 && per < g.batch2) throw ArgError("dgemm: split-K batch too large");
   for (int c0 = 0; c0 < g.batch2; c0 += per) {
     const int nc = std::min(per, g.batch2 - c0);
-    dim3 grid(gx, gy, g.batch * nc), block(256);
+    const int nprob = g.batch * nc;
+    dim3 grid(gx, gy, nprob * nsplit), block(256);
     const double* A = g.A + (long long)c0 * g.sA2;
     const double* B = g.B + (long long)c0 * g.sB2;
     double* C = g.C + (long long)c0 * g.sC2;
 #define ZCSD_GEMM_LAUNCH(TA_, TB_)                                                        \
   hipLaunchKernelGGL((dgemm_kernel<BM, BN, BK, TA_, TB_>), grid, block, 0, s, g.m, g.n, g.k, A, \
                      g.lda, g.sA, B, g.ldb, g.sB, C, g.ldc, g.sC, g.alpha, g.beta, g.batch,     \
-                     g.sA2, g.sB2, g.sC2)
+                     g.sA2, g.sB2, g.sC2, nprob, kchunk, g.ws)
     if (!g.transA && !g.transB) ZCSD_GEMM_LAUNCH(false, false);
     else if (!g.transA && g.transB) ZCSD_GEMM_LAUNCH(false, true);
     else if (g.transA && !g.transB) ZCSD_GEMM_LAUNCH(true, false);
     else ZCSD_GEMM_LAUNCH(true, true);
 #undef ZCSD_GEMM_LAUNCH
     ZCSD_CHECK_LAUNCH();
+    if (kchunk > 0) {
+      const long long mn = (long long)g.m * g.n;
+      const unsigned gxr = (unsigned)std::max<long long>(1, std::min<long long>((mn + 255) / 256, 1024));
+      hipLaunchKernelGGL(splitk_reduce_kernel, dim3(gxr, nprob), dim3(256), 0, s, g.m, g.n, nprob,
+                         nsplit, g.ws, C, g.ldc, g.sC, g.batch, g.sC2, g.alpha, g.beta);
+      ZCSD_CHECK_LAUNCH();
+    }
   }
 }
 
@@ -193,10 +242,25 @@ void dgemm(const GemmBatch& g, hipStream_t s) {
                    g.sC, s);
     return;
   }
-  const long long tiles128 =
-      (long long)((g.m + 127) / 128) * ((g.n + 127) / 128) * g.batch * g.batch2;
-  if (tiles128 >= 512) launch_tile<128, 128, 16>(g, s);
-  else launch_tile<64, 64, 16>(g, s);
+  const long long nprob = (long long)g.batch * g.batch2;
+  const long long tiles128 = (long long)((g.m + 127) / 128) * ((g.n + 127) / 128) * nprob;
+  if (tiles128 >= 512) {
+    launch_tile<128, 128, 16>(g, s, 1);
+    return;
+  }
+  // few output tiles and a long k: split k across workgroups when a workspace is given
+  const long long tiles64 = (long long)((g.m + 63) / 64) * ((g.n + 63) / 64) * nprob;
+  int ksplit = 1;
+  static const bool no_split = [] {
+    const char* e = std::getenv("ZCSD_NO_SPLITK");
+    return e && e[0] == '1';
+  }();
+  if (g.ws && !no_split && tiles64 < 256 && g.k >= 1024) {
+    ksplit = (int)std::min<long long>(std::min<long long>(g.k / 256, 16),
+                                      std::max<long long>(2, 512 / std::max<long long>(1, tiles64)));
+    while (ksplit > 1 && (size_t)ksplit * nprob * g.m * g.n > g.ws_elems) --ksplit;
+  }
+  launch_tile<64, 64, 16>(g, s, ksplit);
 }
 
 }  // namespace zcsd

@@ -203,6 +203,9 @@ QRWork qr_work_alloc(Arena& ar, QRShape shape, int batch, int m, int n, int nb) 
   wk.sW = (long long)nb * n;
   wk.W = ar.dalloc((size_t)batch * wk.sW);
   wk.W2 = ar.dalloc((size_t)batch * wk.sW);
+  if (nb == 32) wk.ts = tsqr_scratch_alloc(ar, batch);
+  wk.ws_elems = (size_t)8 * batch * nb * n;
+  wk.ws = ar.dalloc(wk.ws_elems);
   return wk;
 }
 
@@ -212,7 +215,7 @@ static void apply_block_reflector(int batch, double* M, long long ldm, long long
                                   int nc, int r1a, int r1b, int r2a, int r2b, int w,
                                   const double* V, long long ldv, long long sV, const double* T,
                                   long long sT, int nbT, double* W, double* W2, long long sW,
-                                  bool transT, hipStream_t s) {
+                                  bool transT, double* ws, size_t ws_elems, hipStream_t s) {
   if (nc <= 0 || w <= 0) return;
   const int h1 = r1b - r1a, h2 = r2b - r2a;
   GemmBatch g;
@@ -224,6 +227,7 @@ static void apply_block_reflector(int batch, double* M, long long ldm, long long
   g.B = M + r1a + (long long)col0 * ldm; g.ldb = ldm; g.sB = sM;
   g.C = W; g.ldc = w; g.sC = sW;
   g.alpha = 1.0; g.beta = 0.0;
+  g.ws = ws; g.ws_elems = ws_elems;
   dgemm(g, s);
   if (h2 > 0) {
     g.k = h2;
@@ -270,7 +274,10 @@ void geqrf_batched(int batch, QRShape shape, int m, int n, double* M, long long 
     double* Tk = wk.T + (long long)k * nb * nb;
     const double hh = (double)(r1b - r1a) + (r2b - r2a);
     ProfScope prof("qr_panel", s, batch * 2.0 * hh * w * w, batch * 8.0 * 2.0 * hh * w);
-    if (nb == 32)
+    // a panel is either the three TSQR kernels or the one-workgroup kernel
+    if (nb == 32 && wk.ts.Rstack && tsqr_panel_fits((int)hh, w))
+      tsqr_panel(batch, M, ldm, sM, c0, w, r1a, r1b, r2a, r2b, Vk, wk.ldv, wk.sV, Tk, wk.sT, wk.ts, s);
+    else if (nb == 32)
       hipLaunchKernelGGL(qr_panel_kernel<32>, dim3(batch), dim3(QR_NT), 0, s, M, ldm, sM, c0, w,
                          r1a, r1b, r2a, r2b, Vk, wk.ldv, wk.sV, Tk, wk.sT);
     else if (nb == 16)
@@ -281,7 +288,7 @@ void geqrf_batched(int batch, QRShape shape, int m, int n, double* M, long long 
     ZCSD_CHECK_LAUNCH();
     const int col0 = c0 + w;
     apply_block_reflector(batch, M, ldm, sM, col0, n - col0, r1a, r1b, r2a, r2b, w, Vk, wk.ldv,
-                          wk.sV, Tk, wk.sT, nb, wk.W, wk.W2, wk.sW, /*transT=*/true, s);
+                          wk.sV, Tk, wk.sT, nb, wk.W, wk.W2, wk.sW, /*transT=*/true, wk.ws, wk.ws_elems, s);
   }
 }
 
@@ -296,7 +303,7 @@ void orgqr_batched(int batch, QRShape shape, int m, int n, double* Q, long long 
     const double* Vk = wk.V + (long long)k * wk.ldv * nb;
     const double* Tk = wk.T + (long long)k * nb * nb;
     apply_block_reflector(batch, Q, ldq, sQ, c0, n - c0, r1a, r1b, r2a, r2b, w, Vk, wk.ldv,
-                          wk.sV, Tk, wk.sT, nb, wk.W, wk.W2, wk.sW, /*transT=*/false, s);
+                          wk.sV, Tk, wk.sT, nb, wk.W, wk.W2, wk.sW, /*transT=*/false, wk.ws, wk.ws_elems, s);
   }
 }
 

@@ -94,6 +94,9 @@ struct GemmBatch {
   // optional second batch dimension: problem (b1, b2) uses offsets b1*s? + b2*s?2
   int batch2 = 1;
   long long sA2 = 0, sB2 = 0, sC2 = 0;
+  // optional workspace for split-K (deterministic: partial products, then a reduction)
+  double* ws = nullptr;
+  size_t ws_elems = 0;
 };
 void dgemm(const GemmBatch& g, hipStream_t s);
 

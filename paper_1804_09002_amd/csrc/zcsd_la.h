@@ -1,6 +1,7 @@
 // Device linear-algebra building blocks of the Zolo-csd path (internal).
 #pragma once
 #include "zcsd_internal.h"
+#include "zcsd_qr_tsqr.h"
 
 namespace zcsd {
 
@@ -14,6 +15,8 @@ struct QRWork {
   double* V = nullptr;  long long sV = 0;   // K panels of ldv x nb per problem
   double* T = nullptr;  long long sT = 0;   // K blocks of nb x nb per problem
   double* W = nullptr;  double* W2 = nullptr; long long sW = 0;  // nb x n scratch per problem
+  TsqrScratch ts;                                                 // tall-panel scratch
+  double* ws = nullptr; size_t ws_elems = 0;                      // split-K workspace
 };
 
 QRWork qr_work_alloc(Arena& ar, QRShape shape, int batch, int m, int n, int nb);

@@ -18,7 +18,8 @@ def _t(x):
     return torch.tensor(np.ascontiguousarray(x), device=DEV)
 
 
-@pytest.mark.parametrize("m,n", [(1, 1), (5, 3), (32, 32), (33, 33), (100, 70), (257, 257), (600, 450)])
+@pytest.mark.parametrize("m,n", [(1, 1), (5, 3), (32, 32), (33, 33), (100, 70), (257, 257), (600, 450),
+                                 (2000, 100), (4352 - 1, 40)])
 def test_qr_general(m, n):
     from paper_1804_09002_amd import zcsd
     rng = np.random.default_rng(m + 7 * n)
@@ -35,7 +36,7 @@ def test_qr_general(m, n):
         assert np.allclose(sgn[:, None] * R[b], Rl, atol=1e-12 * np.abs(Rl).max())
 
 
-@pytest.mark.parametrize("n,c", [(1, 0.3), (31, 1e-6), (64, 0.5), (97, 1e-12), (300, 2.0)])
+@pytest.mark.parametrize("n,c", [(1, 0.3), (31, 1e-6), (64, 0.5), (97, 1e-12), (300, 2.0), (700, 1e-3)])
 def test_qr_stacked_structure(n, c):
     from paper_1804_09002_amd import zcsd
     rng = np.random.default_rng(n)

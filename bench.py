@@ -40,19 +40,39 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def _norm2_sym(E, iters=60):
+    import torch
+    x = torch.ones(E.shape[0], dtype=torch.float64, device=E.device) / E.shape[0] ** 0.5
+    lam = 0.0
+    for _ in range(iters):
+        y = E @ x
+        lam = float(torch.linalg.vector_norm(y))
+        if lam == 0.0:
+            break
+        x = y / lam
+    return lam
+
+
 def accuracy(A1, A2, U1, U2, V1, th, theta_true):
+    """The paper's measures (Sec. 6) on the device: ||A_hat - A||_2 / ||A||_2 and
+    ||X^T X - I||_2 (2-norms by power iteration on symmetric products), plus Frobenius."""
     import torch
     n = A1.shape[0]
     c, s = torch.cos(th), torch.sin(th)
     R1 = (U1 * c) @ V1.T - A1
     R2 = (U2 * s) @ V1.T - A2
-    res = float(torch.sqrt((R1 * R1).sum() + (R2 * R2).sum()) /
-                torch.sqrt((A1 * A1).sum() + (A2 * A2).sum()))
+    res2 = (_norm2_sym(R1.T @ R1 + R2.T @ R2) / _norm2_sym(A1.T @ A1 + A2.T @ A2)) ** 0.5
+    resF = float(torch.sqrt((R1 * R1).sum() + (R2 * R2).sum()) /
+                 torch.sqrt((A1 * A1).sum() + (A2 * A2).sum()))
     I = torch.eye(n, dtype=torch.float64, device=A1.device)
-    orth = {k: float(torch.linalg.matrix_norm(X.T @ X - I)) for k, X in
-            (("U1", U1), ("U2", U2), ("V1", V1))}
+    orth2, orthF = {}, {}
+    for k, X in (("U1", U1), ("U2", U2), ("V1", V1)):
+        E = X.T @ X - I
+        orth2[k] = _norm2_sym(E)
+        orthF[k] = float(torch.linalg.matrix_norm(E))
     dth = float((th - theta_true).abs().max())
-    return {"backward_rel_fro": res, "orth_fro": orth, "max_abs_theta_err": dth}
+    return {"backward_rel_2": res2, "backward_rel_fro": resF, "orth_2": orth2, "orth_fro": orthF,
+            "max_abs_theta_err": dth}
 
 
 def cpu_baseline(n, reps, seed):

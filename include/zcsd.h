@@ -71,6 +71,9 @@ typedef struct {
   int eig_splits;          /* number of successful splits */
   int eig_max_r;           /* largest Zolotarev degree used inside Zolo-eig */
   double eig_offblock;     /* max over splits of ‖V-^T B V+‖_F / ‖B‖_F (0 if not measured) */
+  double eig_coupling;     /* max over splits of ‖X‖_F, the eigenspace-basis coupling that the
+                              subspace-iteration step of each split removes */
+  int eig_full_refinements; /* splits whose step needed a second QR (‖X‖_F > 2^-27) */
   double time_ms[4];       /* polar, B, eig, assembly wall time (ms), measured with stream syncs */
 } zcsd_info;
 

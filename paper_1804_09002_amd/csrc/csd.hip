@@ -100,7 +100,7 @@ static CsdOut csd_run(int n, const double* A1, long long lda1, const double* A2,
   copy_scale(1, n, n, 1.0, A1, lda1, 0, X, n, 0, s);
   copy_scale(1, n, n, 1.0, A2, lda2, 0, X + nn, n, 0, s);
   double* d_ss = ar.dalloc(2);
-  sumsq(2, n, n, X, n, nn, d_ss, s);
+  sumsq(2, n, n, X, n, nn, d_ss, ar, s);
   double ss[2];
   d2h(ss, d_ss, sizeof(ss), s);
   const double f2 = ss[0] + ss[1];
@@ -312,6 +312,8 @@ extern "C" zcsd_status zcsd_dcsd(zcsd_handle* handle, int n, const double* d_A1,
       info->eig_splits = r.eig.splits;
       info->eig_max_r = r.eig.max_r;
       info->eig_offblock = r.eig.max_offblock;
+      info->eig_coupling = r.eig.max_coupling;
+      info->eig_full_refinements = r.eig.full_refinements;
       info->time_ms[0] = r.t_polar;
       info->time_ms[1] = r.t_B;
       info->time_ms[2] = r.t_eig;
@@ -352,6 +354,8 @@ extern "C" zcsd_status zcsd_dsyev_zolo(zcsd_handle* handle, int n, const double*
       info->eig_splits = r.splits;
       info->eig_max_r = r.max_r;
       info->eig_offblock = r.max_offblock;
+      info->eig_coupling = r.max_coupling;
+      info->eig_full_refinements = r.full_refinements;
     }
   });
 }

@@ -11,14 +11,15 @@
 //      spectral projector onto the eigenvalues above s_b (plus the padding);
 //      n+_b = round(trace P_b over the real part);
 //   3. [V+ V-] = Q of the Householder QR of P_b Omega_b (Omega random on the
-//      real part, identity on the padding, so Q = diag(Q_real, I) exactly);
+//      real part, identity on the padding, so Q = diag(Q_real, I) exactly),
+//      refined by one step of subspace iteration on P_b (first-order form);
 //   4. B'_b = Q^T B_b Q, V_b <- V_b Q; the diagonal blocks of B'_b of sizes
 //      n+ and n_b - n+ are the children, with spectra in [s_b, hi_b] and
 //      [lo_b, s_b]; ||B'_21||_F / ||B||_F is recorded.
 // A split with n+ in {0, n_b} only moves the interval (bisection on s).
 // Blocks of at most n_leaf go to batched Jacobi; blocks whose spread
-// ||B_b - mean I||_F is below 4 n u ||B||_F are already diagonal to working
-// accuracy and are finished as they are.  Eigenpairs are finally sorted.
+// ||B_b - mean I||_F is below 4 u max(|lo|, |hi|) are already diagonal to
+// working accuracy and are finished as they are.  Eigenpairs are finally sorted.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -64,15 +65,22 @@ __global__ void form_shifted_kernel(int N, const double* __restrict__ Bp, double
   }
 }
 
-// P_b = (W_b + W_b^T)/4 + I/2 in place
-__global__ void projector_kernel(int N, double* W) {
+// P_b = (W_b + W_b^T)/4 + I/2 in place on the real n_b x n_b part; the padding
+// is reset to exactly I and its coupling to the real part to exactly 0.  Zolo-pd
+// keeps that coupling at rounding level only (the tall-panel QR does not
+// preserve exact zeros), and the QR of the rank-deficient P Omega would turn
+// rounding-level coupling into O(1) coupling on its trailing (null) columns.
+__global__ void projector_kernel(int N, double* W, const int* __restrict__ nb) {
   const long long b = blockIdx.y;
   const long long NN = (long long)N * N;
+  const int m = nb[b];
   double* Wb = W + b * NN;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < NN;
        e += (long long)gridDim.x * blockDim.x) {
     const int i = (int)(e % N), j = (int)(e / N);
-    if (i > j) {
+    if (i >= m || j >= m) {
+      Wb[e] = (i == j) ? 1.0 : 0.0;
+    } else if (i > j) {
       const double v = 0.25 * (Wb[e] + Wb[j + (long long)i * N]);
       Wb[e] = v;
       Wb[j + (long long)i * N] = v;
@@ -125,49 +133,23 @@ __global__ void omega_kernel(int N, double* Om, const int* __restrict__ nb,
 }
 
 // out[b] = ||B_b - d_b I||_F^2 over the n_b x n_b real part (diag shift d_b)
-__global__ void sumsq_shift_kernel(int N, const double* __restrict__ Bp, const int* __restrict__ nb,
-                                   const double* __restrict__ d, double* out) {
-  const long long b = blockIdx.x;
-  const int m = nb[b];
-  const double s = d[b];
-  const double* Bb = Bp + b * (long long)N * N;
-  double acc = 0.0;
-  for (long long e = threadIdx.x; e < (long long)m * m; e += blockDim.x) {
-    const int i = (int)(e % m), j = (int)(e / m);
-    const double v = Bb[i + (long long)j * N] - (i == j ? s : 0.0);
-    acc += v * v;
-  }
-  __shared__ double red[256];
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[b] = red[0];
-}
-
-// out[b] = ||B'_b(np:nb, 0:np)||_F^2
-__global__ void offblock_kernel(int N, const double* __restrict__ Bp, const int* __restrict__ nb,
-                                const int* __restrict__ npos, double* out) {
-  const long long b = blockIdx.x;
+// K_b = [0 -X^T; X 0] on the real n_b x n_b part (X = Z_b(np:n_b, 0:np)), zero
+// elsewhere; the upper block is built from the lower one, so K is exactly skew.
+__global__ void coupling_skew_kernel(int N, const double* __restrict__ Z, double* K,
+                                     const int* __restrict__ nb, const int* __restrict__ npos) {
+  const long long b = blockIdx.y;
+  const long long NN = (long long)N * N;
   const int m = nb[b], p = npos[b];
-  const double* Bb = Bp + b * (long long)N * N;
-  double acc = 0.0;
-  const long long rows = m - p;
-  for (long long e = threadIdx.x; e < rows * p; e += blockDim.x) {
-    const int i = p + (int)(e % rows), j = (int)(e / rows);
-    const double v = Bb[i + (long long)j * N];
-    acc += v * v;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < NN;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e % N), j = (int)(e / N);
+    double v = 0.0;
+    if (i < m && j < m) {
+      if (i >= p && j < p) v = Z[b * NN + e];
+      else if (i < p && j >= p) v = -Z[b * NN + j + (long long)i * N];
+    }
+    K[b * NN + e] = v;
   }
-  __shared__ double red[256];
-  red[threadIdx.x] = acc;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[b] = red[0];
 }
 
 // E_b -= Bq_b on the real n_b x n_b part; zero elsewhere
@@ -189,6 +171,26 @@ __global__ void diag_kernel(int N, const double* __restrict__ Bp, const int* __r
   const int m = nb[b];
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x)
     out[b * (long long)N + i] = Bp[b * (long long)N * N + i + (long long)i * N];
+}
+
+// out[b] = max |X_b(i, j)| over pairs with exactly one of i, j in the padding
+__global__ void offpad_kernel(int N, const double* __restrict__ X, const int* __restrict__ nb,
+                              double* out) {
+  const long long b = blockIdx.x;
+  const int m = nb[b];
+  double mx = 0.0;
+  for (long long e = threadIdx.x; e < (long long)N * N; e += blockDim.x) {
+    const int i = (int)(e % N), j = (int)(e / N);
+    if ((i < m) != (j < m)) mx = fmax(mx, fabs(X[b * (long long)N * N + e]));
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[b] = red[0];
 }
 
 static dim3 grid2(long long total, int batch) {
@@ -245,11 +247,15 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
   double bnorm2;
   {
     double* d_ss = ar.dalloc(1);
-    sumsq(1, n, n, a.B, a.ldb, 0, d_ss, s);
+    sumsq(1, n, n, a.B, a.ldb, 0, d_ss, ar, s);
     d2h(&bnorm2, d_ss, sizeof(double), s);
   }
   const double bnorm = std::sqrt(bnorm2);
-  const double scalar_tol = 4.0 * n * 0x1p-53 * std::max(bnorm, 1e-300);
+  // A block is finished without splitting only when ||B_blk - mean I||_F (an upper
+  // bound of its 2-norm) is a few units of roundoff of ||B||_2 <= max(|lo|, |hi|):
+  // then any orthonormal basis of it is an eigenbasis to working accuracy.
+  const double bmax = std::max(std::fabs(a.lo), std::fabs(a.hi));
+  const double scalar_tol = 4.0 * 0x1p-53 * std::max(bmax, 1e-300);
 
   // output assembly: unsorted eigenvectors/values
   double* Vout = ar.dalloc((size_t)n * n);
@@ -321,9 +327,13 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
     }
     double* d_mean = upload(ar, mean, s);
     double* d_spread = ar.dalloc(nblk);
-    hipLaunchKernelGGL(sumsq_shift_kernel, dim3(nblk), dim3(256), 0, s, N, Bp, d_nb, d_mean,
-                       d_spread);
-    ZCSD_CHECK_LAUNCH();
+    {
+      SumsqRegion rg;
+      rg.nb = d_nb;
+      rg.shift = d_mean;
+      rg.max_cols = N;
+      sumsq_region(nblk, Bp, N, NN, rg, d_spread, ar, s);
+    }
     std::vector<double> spread(nblk);
     d2h(spread.data(), d_spread, nblk * sizeof(double), s);
 
@@ -382,6 +392,47 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
       dgemm(g, s);
       std::vector<double> ll((size_t)nl * L);
       d2h(ll.data(), Ll, ll.size() * sizeof(double), s);
+      if (log_enabled()) {
+        // leaf invariants: ||LVo^T B LVo - diag(lam)||_F per leaf, ||LVo^T LVo - I||_F
+        ArenaScope ds(ar);
+        double* BV = ar.dalloc((size_t)nl * n * L);
+        double* E = ar.dalloc((size_t)nl * L * L);
+        double* E2 = ar.dalloc((size_t)nl * L * L);
+        GemmBatch g1;
+        g1.batch = nl;
+        g1.m = n; g1.n = L; g1.k = n;
+        g1.A = a.B; g1.lda = a.ldb; g1.sA = 0;
+        g1.B = LVo; g1.ldb = n; g1.sB = (long long)n * L;
+        g1.C = BV; g1.ldc = n; g1.sC = (long long)n * L;
+        dgemm(g1, s);
+        GemmBatch g2;
+        g2.batch = nl;
+        g2.transA = 1;
+        g2.m = L; g2.n = L; g2.k = n;
+        g2.A = LVo; g2.lda = n; g2.sA = (long long)n * L;
+        g2.B = BV; g2.ldb = n; g2.sB = (long long)n * L;
+        g2.C = E; g2.ldc = L; g2.sC = (long long)L * L;
+        dgemm(g2, s);
+        g2.B = LVo;
+        g2.C = E2;
+        dgemm(g2, s);
+        std::vector<double> eh((size_t)nl * L * L), e2h((size_t)nl * L * L);
+        d2h(eh.data(), E, eh.size() * sizeof(double), s);
+        d2h(e2h.data(), E2, e2h.size() * sizeof(double), s);
+        for (int q = 0; q < nl; ++q) {
+          const int m = szs[q];
+          double r1 = 0.0, r2 = 0.0;
+          for (int j = 0; j < m; ++j)
+            for (int i = 0; i < m; ++i) {
+              const double v = eh[(size_t)q * L * L + i + j * L] - (i == j ? ll[(size_t)q * L + i] : 0.0);
+              const double w2 = e2h[(size_t)q * L * L + i + j * L] - (i == j ? 1.0 : 0.0);
+              r1 += v * v;
+              r2 += w2 * w2;
+            }
+          std::fprintf(stderr, "[zcsd] eig level %d leaf %d n=%d ||VtBV-L||=%.2e ||VtV-I||=%.2e\n",
+                       res.levels, q, m, std::sqrt(r1), std::sqrt(r2));
+        }
+      }
       std::vector<CopyDesc> co;
       for (int q = 0; q < nl; ++q) {
         const int k = leaf_idx[q];
@@ -459,7 +510,16 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
       ZoloPdResult zr = zolo_pd_batched(za, ar, s);
       res.max_r = std::max(res.max_r, zr.r);
     }
-    hipLaunchKernelGGL(projector_kernel, grid2(SS, ns), dim3(256), 0, s, Ns, W);
+    std::vector<double> offW(ns, 0.0), offY(ns, 0.0), offQ(ns, 0.0), offX(ns, 0.0);
+    auto offpad = [&](const double* M, std::vector<double>& o) {
+      if (!log_enabled()) return;
+      double* d_o = ar.dalloc(ns);
+      hipLaunchKernelGGL(offpad_kernel, dim3(ns), dim3(256), 0, s, Ns, M, d_nbs, d_o);
+      ZCSD_CHECK_LAUNCH();
+      d2h(o.data(), d_o, ns * sizeof(double), s);
+    };
+    offpad(W, offW);
+    hipLaunchKernelGGL(projector_kernel, grid2(SS, ns), dim3(256), 0, s, Ns, W, d_nbs);
     ZCSD_CHECK_LAUNCH();
     double* d_tr = ar.dalloc(ns);
     hipLaunchKernelGGL(trace_real_kernel, dim3(ns), dim3(256), 0, s, Ns, W, d_nbs, d_tr);
@@ -486,6 +546,7 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
       g.C = Y; g.ldc = Ns; g.sC = SS;
       dgemm(g, s);
     }
+    offpad(Y, offY);
     double* Q = Om;  // Omega is dead after the product
     {
       ArenaScope qs(ar);
@@ -493,9 +554,74 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
       geqrf_batched(ns, QRShape::General, Ns, Ns, Y, Ns, SS, wk, s);
       orgqr_batched(ns, QRShape::General, Ns, Ns, Q, Ns, SS, nullptr, wk, s);
     }
+    offpad(Q, offQ);
+    if (log_enabled())
+      for (int q = 0; q < ns; ++q)
+        std::fprintf(stderr, "[zcsd] eig level %d block %d n=%d N=%d off-pad |W|=%.2e |Y|=%.2e |Q|=%.2e\n",
+                     res.levels, q, nbs[q], Ns, offW[q], offY[q], offQ[q]);
+    // One step of subspace iteration on P.  The QR of P Omega leaves Q1 (first n+
+    // columns of Q) off the eigenspace by about u kappa(V+^T Omega1), which grows
+    // with n and would pass straight into the off-diagonal block of Q^T B Q.  With
+    // Z = Q^T P Q, X = Z(n+:, :n+) is that coupling, and span(P Q1) is spanned by the
+    // first n+ columns of Q [I -X^T; X I] (exact up to O(||X||^2) in the basis and
+    // in its orthogonality); when ||X||_F is not below 2^-27 the step is taken in
+    // full instead, Q <- Q factor of the QR of P Q.
+    int* d_np = upload(ar, npos, s);
+    double* PQ = ar.dalloc((size_t)ns * SS);
+    {
+      GemmBatch g;
+      g.batch = ns;
+      g.m = Ns; g.n = Ns; g.k = Ns;
+      g.A = W; g.lda = Ns; g.sA = SS;
+      g.B = Q; g.ldb = Ns; g.sB = SS;
+      g.C = PQ; g.ldc = Ns; g.sC = SS;
+      dgemm(g, s);
+      GemmBatch h = g;
+      h.transA = 1;
+      h.A = Q; h.B = PQ; h.C = Y;  // Z = Q^T (P Q) into the dead QR input
+      dgemm(h, s);
+    }
+    double xmax = 0.0;
+    {
+      double* d_x = ar.dalloc(ns);
+      SumsqRegion rg;
+      rg.nb = d_nbs;
+      rg.np = d_np;
+      rg.max_cols = Ns;
+      sumsq_region(ns, Y, Ns, SS, rg, d_x, ar, s);
+      std::vector<double> xs(ns);
+      d2h(xs.data(), d_x, ns * sizeof(double), s);
+      for (double v : xs) xmax = std::max(xmax, std::sqrt(v));
+    }
+    res.max_coupling = std::max(res.max_coupling, xmax);
+    double* T1;
+    if (xmax <= 0x1p-27) {
+      double* K = PQ;  // P Q is dead once Z is formed
+      hipLaunchKernelGGL(coupling_skew_kernel, grid2(SS, ns), dim3(256), 0, s, Ns, Y, K, d_nbs, d_np);
+      ZCSD_CHECK_LAUNCH();
+      double* Qn = W;  // P is dead too
+      copy_scale(ns, Ns, Ns, 1.0, Q, Ns, SS, Qn, Ns, SS, s);
+      GemmBatch g;
+      g.batch = ns;
+      g.m = Ns; g.n = Ns; g.k = Ns;
+      g.A = Q; g.lda = Ns; g.sA = SS;
+      g.B = K; g.ldb = Ns; g.sB = SS;
+      g.C = Qn; g.ldc = Ns; g.sC = SS;
+      g.beta = 1.0;
+      dgemm(g, s);
+      Q = Qn;
+      T1 = K;
+    } else {
+      ++res.full_refinements;
+      ArenaScope qs(ar);
+      QRWork wk = qr_work_alloc(ar, QRShape::General, ns, Ns, Ns, 32);
+      geqrf_batched(ns, QRShape::General, Ns, Ns, PQ, Ns, SS, wk, s);
+      orgqr_batched(ns, QRShape::General, Ns, Ns, Q, Ns, SS, nullptr, wk, s);
+      T1 = W;
+    }
+
     // B' = Q^T B Q, V' = V Q
-    double* T1 = W;  // W is dead
-    double* Bq = Y;  // Y is dead after orgqr
+    double* Bq = Y;  // Z is dead
     {
       GemmBatch g;
       g.batch = ns;
@@ -535,7 +661,7 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
       dgemm(g, s);
       add_diag(ns, Ns, -1.0, G, Ns, SS, s);
       double* d_o = ar.dalloc(ns);
-      sumsq(ns, Ns, Ns, G, Ns, SS, d_o, s);
+      sumsq(ns, Ns, Ns, G, Ns, SS, d_o, ar, s);
       std::vector<double> o(ns);
       d2h(o.data(), d_o, ns * sizeof(double), s);
       // invariant: Vq_b^T B Vq_b == Bq_b (B the original matrix)
@@ -561,17 +687,47 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
       // E -= Bq (only the real n_b x n_b part is meaningful)
       hipLaunchKernelGGL(sub_real_kernel, grid2(SS, ns), dim3(256), 0, s, Ns, E, Bq, d_nbs);
       ZCSD_CHECK_LAUNCH();
-      sumsq(ns, Ns, Ns, E, Ns, SS, d_e, s);
+      sumsq(ns, Ns, Ns, E, Ns, SS, d_e, ar, s);
       d2h(ev.data(), d_e, ns * sizeof(double), s);
+      // orthonormality of the incoming basis Vs and of the outgoing Vq (real columns), and of Q's real block
+      auto orth_real = [&](const double* X, long long ldx, long long sx, int rows) {
+        double* G = ar.dalloc((size_t)ns * SS);
+        GemmBatch g;
+        g.batch = ns;
+        g.transA = 1;
+        g.m = Ns; g.n = Ns; g.k = rows;
+        g.A = X; g.lda = ldx; g.sA = sx;
+        g.B = X; g.ldb = ldx; g.sB = sx;
+        g.C = G; g.ldc = Ns; g.sC = SS;
+        dgemm(g, s);
+        std::vector<double> gh((size_t)ns * SS);
+        d2h(gh.data(), G, gh.size() * sizeof(double), s);
+        std::vector<double> r(ns, 0.0);
+        for (int q = 0; q < ns; ++q) {
+          const int m = nbs[q];
+          for (int j = 0; j < m; ++j)
+            for (int i = 0; i < m; ++i) {
+              const double v = gh[(size_t)q * SS + i + (size_t)j * Ns] - (i == j ? 1.0 : 0.0);
+              r[q] += v * v;
+            }
+          r[q] = std::sqrt(r[q]);
+        }
+        return r;
+      };
+      std::vector<double> oVs = orth_real(Vs, n, (long long)n * Ns, n);
+      std::vector<double> oVq = orth_real(Vq, n, (long long)n * Ns, n);
+      std::vector<double> oQr = orth_real(Q, Ns, SS, Ns);
       for (int q = 0; q < ns; ++q)
-        std::fprintf(stderr, "[zcsd] eig level %d block %d n=%d N=%d shift=%.6g n+=%d trace=%.6f ||QtQ-I||=%.2e ||VtBV-Bq||=%.2e\n",
-                     res.levels, q, nbs[q], Ns, shs[q], npos[q], tr[q], std::sqrt(o[q]), std::sqrt(ev[q]));
+        std::fprintf(stderr, "[zcsd] eig level %d block %d n=%d N=%d shift=%.6g n+=%d trace=%.6f ||QtQ-I||=%.2e ||VtBV-Bq||=%.2e orth Vs=%.2e Vq=%.2e Qreal(all rows)=%.2e\n",
+                     res.levels, q, nbs[q], Ns, shs[q], npos[q], tr[q], std::sqrt(o[q]), std::sqrt(ev[q]), oVs[q], oVq[q], oQr[q]);
     }
     if (a.measure_offblock) {
-      int* d_np = upload(ar, npos, s);
       double* d_off = ar.dalloc(ns);
-      hipLaunchKernelGGL(offblock_kernel, dim3(ns), dim3(256), 0, s, Ns, Bq, d_nbs, d_np, d_off);
-      ZCSD_CHECK_LAUNCH();
+      SumsqRegion rg;
+      rg.nb = d_nbs;
+      rg.np = d_np;
+      rg.max_cols = Ns;
+      sumsq_region(ns, Bq, Ns, SS, rg, d_off, ar, s);
       std::vector<double> off(ns);
       d2h(off.data(), d_off, ns * sizeof(double), s);
       for (int q = 0; q < ns; ++q)

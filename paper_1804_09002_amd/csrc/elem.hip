@@ -42,12 +42,19 @@ void* Arena::alloc(size_t bytes) {
   return base_ + off;
 }
 
+// Small transfers from or to pageable host memory.  A copy from pageable
+// memory is not guaranteed to wait for kernels already queued on the stream,
+// and the destination of an upload is often arena memory that a queued kernel
+// still reads (arena blocks are reused as soon as a scope ends), so the stream
+// is drained before and after every such copy.
 void d2h(void* h, const void* d, size_t bytes, hipStream_t s) {
+  ZCSD_HIP(hipStreamSynchronize(s));
   ZCSD_HIP(hipMemcpyAsync(h, d, bytes, hipMemcpyDeviceToHost, s));
   ZCSD_HIP(hipStreamSynchronize(s));
 }
 
 void h2d(void* d, const void* h, size_t bytes, hipStream_t s) {
+  ZCSD_HIP(hipStreamSynchronize(s));
   ZCSD_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s));
   ZCSD_HIP(hipStreamSynchronize(s));
 }
@@ -113,16 +120,45 @@ __global__ void symmetrize_kernel(int n, double* X, long long ldx, long long sx)
 }
 
 // per-batch sum of squares; grid (1, batch), block 256, two-level reduction
-__global__ void sumsq_kernel(int m, int n, const double* __restrict__ X, long long ldx,
-                             long long sx, double* out) {
-  const long long b = blockIdx.y;
-  const long long total = (long long)m * n;
-  double acc = 0.0;
-  for (long long e = threadIdx.x; e < total; e += blockDim.x) {
-    const int i = (int)(e % m), j = (int)(e / m);
-    const double v = X[b * sx + i + j * ldx];
-    acc += v * v;
+// partial[b * G + g] = sum over the columns j = c0 + g, c0 + g + G, ... of the
+// region of X_b; every workgroup walks whole columns (coalesced rows).
+__global__ void sumsq_partial_kernel(const double* __restrict__ X, long long ldx, long long sx,
+                                     SumsqRegion R, int G, double* part) {
+  const int b = blockIdx.y, g = blockIdx.x;
+  int r0 = 0, r1 = R.m, c0 = 0, c1 = R.n;
+  double sh = 0.0;
+  if (R.nb) {
+    const int m = R.nb[b];
+    r1 = m;
+    c1 = m;
+    if (R.np) {
+      r0 = R.np[b];
+      c1 = r0;
+    }
+    if (R.shift) sh = R.shift[b];
   }
+  const double* Xb = X + (long long)b * sx;
+  double acc = 0.0;
+  for (int j = c0 + g; j < c1; j += G)
+    for (int i = r0 + (int)threadIdx.x; i < r1; i += blockDim.x) {
+      const double v = Xb[i + (long long)j * ldx] - (i == j ? sh : 0.0);
+      acc += v * v;
+    }
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[(long long)b * G + g] = red[0];
+}
+
+// out[b] = sum of the G partials of problem b, in a fixed order
+__global__ void sumsq_final_kernel(int G, const double* __restrict__ part, double* out) {
+  const int b = blockIdx.x;
+  double acc = 0.0;
+  for (int g = threadIdx.x; g < G; g += blockDim.x) acc += part[(long long)b * G + g];
   __shared__ double red[256];
   red[threadIdx.x] = acc;
   __syncthreads();
@@ -176,11 +212,26 @@ void symmetrize(int batch, int n, double* X, long long ldx, long long sx, hipStr
   ZCSD_CHECK_LAUNCH();
 }
 
-void sumsq(int batch, int m, int n, const double* X, long long ldx, long long sx, double* out,
-           hipStream_t s) {
+void sumsq_region(int batch, const double* X, long long ldx, long long sx, const SumsqRegion& r,
+                  double* out, Arena& ar, hipStream_t s) {
   if (batch <= 0) return;
-  hipLaunchKernelGGL(sumsq_kernel, dim3(1, batch), dim3(256), 0, s, m, n, X, ldx, sx, out);
+  const int cols = r.nb ? r.max_cols : r.n;
+  ZCSD_REQUIRE(batch <= 65535, "sumsq: batch <= 65535");
+  const int G = std::max(1, std::min(cols, std::max(1, 2048 / batch)));
+  ArenaScope sc(ar);
+  double* part = ar.dalloc((size_t)batch * G);
+  hipLaunchKernelGGL(sumsq_partial_kernel, dim3(G, batch), dim3(256), 0, s, X, ldx, sx, r, G, part);
   ZCSD_CHECK_LAUNCH();
+  hipLaunchKernelGGL(sumsq_final_kernel, dim3(batch), dim3(256), 0, s, G, part, out);
+  ZCSD_CHECK_LAUNCH();
+}
+
+void sumsq(int batch, int m, int n, const double* X, long long ldx, long long sx, double* out,
+           Arena& ar, hipStream_t s) {
+  SumsqRegion r;
+  r.m = m;
+  r.n = n;
+  sumsq_region(batch, X, ldx, sx, r, out, ar, s);
 }
 
 }  // namespace zcsd

@@ -24,6 +24,8 @@ struct ZoloEigArgs {
 struct ZoloEigResult {
   int levels = 0, splits = 0, max_r = 0, failed_splits = 0;
   double max_offblock = 0.0;
+  double max_coupling = 0.0;   // largest ||X||_F of the subspace-iteration step
+  int full_refinements = 0;    // splits that needed the full QR step
 };
 ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s);
 

@@ -110,9 +110,20 @@ void set_identity(int batch, int m, int n, double v, double* X, long long ldx, l
                   hipStream_t s);
 // X_b = (X_b + X_b^T) / 2 in place (n x n)
 void symmetrize(int batch, int n, double* X, long long ldx, long long sx, hipStream_t s);
+// Sums of squares over a region of each X_b, reduced by many workgroups into
+// per-problem partials and then in a fixed order (deterministic).
+struct SumsqRegion {
+  int m = 0, n = 0;               // rows x cols of every problem when nb is null
+  const int* nb = nullptr;        // device: per-problem square extent n_b x n_b
+  const int* np = nullptr;        // device, with nb: rows [np_b, n_b) x cols [0, np_b)
+  const double* shift = nullptr;  // device, with nb: shift_b subtracted on the diagonal
+  int max_cols = 0;               // with nb: an upper bound of the column extent
+};
+void sumsq_region(int batch, const double* X, long long ldx, long long sx, const SumsqRegion& r,
+                  double* out, Arena& ar, hipStream_t s);
 // out[b] = sum of squares of X_b (m x n) -> device array (length batch)
 void sumsq(int batch, int m, int n, const double* X, long long ldx, long long sx, double* out,
-           hipStream_t s);
+           Arena& ar, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // host helpers

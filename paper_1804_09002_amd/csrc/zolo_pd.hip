@@ -97,7 +97,7 @@ ZoloPdResult zolo_pd_batched(const ZoloPdArgs& a, Arena& ar, hipStream_t s) {
     double* Ri = ar.dalloc((size_t)B * nn);
     trtri_upper_batched(B, n, M, n, nn, Ri, n, nn, ar, s);
     double* d_ss = ar.dalloc(B);
-    sumsq(B, n, n, Ri, n, nn, d_ss, s);
+    sumsq(B, n, n, Ri, n, nn, d_ss, ar, s);
     std::vector<double> ss(B);
     d2h(ss.data(), d_ss, B * sizeof(double), s);
     ell = 1.0;

@@ -40,13 +40,16 @@ class Opts(C.Structure):
 class Info(C.Structure):
     _fields_ = [("rank", C.c_int), ("r_used", C.c_int * 2), ("ell", C.c_double * 2),
                 ("zolo_resid", C.c_double), ("eig_levels", C.c_int), ("eig_splits", C.c_int),
-                ("eig_max_r", C.c_int), ("eig_offblock", C.c_double), ("time_ms", C.c_double * 4)]
+                ("eig_max_r", C.c_int), ("eig_offblock", C.c_double),
+                ("eig_coupling", C.c_double), ("eig_full_refinements", C.c_int),
+                ("time_ms", C.c_double * 4)]
 
     def as_dict(self):
         return {"rank": self.rank, "r_used": list(self.r_used), "ell": list(self.ell),
                 "zolo_resid": self.zolo_resid, "eig_levels": self.eig_levels,
                 "eig_splits": self.eig_splits, "eig_max_r": self.eig_max_r,
-                "eig_offblock": self.eig_offblock, "time_ms": list(self.time_ms)}
+                "eig_offblock": self.eig_offblock, "eig_coupling": self.eig_coupling,
+                "eig_full_refinements": self.eig_full_refinements, "time_ms": list(self.time_ms)}
 
 
 _L = None

@@ -22,7 +22,7 @@ def _t(x):
     return torch.tensor(np.ascontiguousarray(x), device=DEV)
 
 
-@pytest.mark.parametrize("n,seed", [(1, 1), (7, 2), (64, 3), (65, 4), (150, 5), (300, 6)])
+@pytest.mark.parametrize("n,seed", [(1, 1), (7, 2), (64, 3), (65, 4), (150, 5), (300, 6), (1024, 7)])
 def test_zolo_eig_random_symmetric(n, seed):
     from paper_1804_09002_amd import zcsd
     rng = np.random.default_rng(seed)
@@ -129,3 +129,75 @@ def test_csd_rejects_bad_input():
     B = torch.ones((n, n), dtype=torch.float64, device=DEV) * 0.37
     with pytest.raises(zcsd.ZcsdError):
         zcsd.csd(B, B)
+
+
+def _norm2_sym(E, iters=60):
+    """2-norm of a symmetric device matrix by power iteration (a lower estimate that
+    converges quickly for these error matrices)."""
+    x = torch.ones(E.shape[0], dtype=torch.float64, device=E.device) / E.shape[0] ** 0.5
+    lam = 0.0
+    for _ in range(iters):
+        y = E @ x
+        lam = float(torch.linalg.vector_norm(y))
+        if lam == 0.0:
+            break
+        x = y / lam
+    return lam
+
+
+def _torch_checks(A1, A2, U1, U2, V1, th, r):
+    """Backward error ||A_hat - A||_2 / ||A||_2 and orthogonality ||X^T X - I||_2 (the
+    paper's measures, Sec. 6) computed on the device; Frobenius bounds as a cross-check."""
+    U1, U2, V1, th = U1[:, :r], U2[:, :r], V1[:, :r], th[:r]
+    c, s_ = torch.cos(th), torch.sin(th)
+    R1 = (U1 * c) @ V1.T - A1
+    R2 = (U2 * s_) @ V1.T - A2
+    RtR = R1.T @ R1 + R2.T @ R2
+    AtA = A1.T @ A1 + A2.T @ A2
+    res = (_norm2_sym(RtR) / _norm2_sym(AtA)) ** 0.5
+    fro = float(torch.sqrt((R1 * R1).sum() + (R2 * R2).sum()) / torch.sqrt((A1 * A1).sum() + (A2 * A2).sum()))
+    n = A1.shape[0]
+    assert fro <= 1e-13 * max(1.0, n ** 0.5 / 4), fro
+    I = torch.eye(r, dtype=torch.float64, device=A1.device)
+    orth = {}
+    for k, X in (("U1", U1), ("U2", U2), ("V1", V1)):
+        E = X.T @ X - I
+        orth[k] = _norm2_sym(E)
+        assert float(torch.linalg.matrix_norm(E)) <= 1e-13 * max(1.0, r ** 0.5 / 4)
+    return res, orth
+
+
+@pytest.mark.parametrize("rank_def", [0, 64])
+def test_csd_config2_n1024_matches_oracle(rank_def):
+    """The n = 1024 workload (clustered angles within 1e-8..1e-12 of 0 and pi/2, optional 64
+    zero singular values): theta against the oracle and the construction, full invariants."""
+    from paper_1804_09002_amd import zcsd
+    n = 1024
+    A1, A2, meta = WL.clustered_pair(n, 3 if rank_def else 2, rank_deficient=rank_def)
+    a1, a2 = _t(A1), _t(A2)
+    U1, U2, V1, th, info = zcsd.csd(a1, a2)
+    r = n - rank_def
+    assert info["rank"] == r
+    ref = O.csd(A1, A2)
+    thg = th.cpu().numpy()
+    assert np.max(np.abs(thg[:r] - ref["theta"])) <= 10 * n * U
+    keep = np.setdiff1d(np.arange(n), meta["zero_idx"]) if rank_def else np.arange(n)
+    assert np.max(np.abs(thg[:r] - np.sort(meta["theta"][keep]))) <= 10 * n * U
+    res, orth = _torch_checks(a1, a2, U1, U2, V1, th, r)
+    assert res <= 1e-13, res
+    assert max(orth.values()) <= 1e-13, orth
+
+
+def test_csd_n4096_bench_configuration():
+    """The benchmarked call (n = 4096, uniform angles, seed 4): properties that hold at any
+    size -- angles against the construction, backward error, 2-norm orthogonality."""
+    from paper_1804_09002_amd import zcsd
+    n = 4096
+    A1, A2, meta = WL.uniform_pair(n, 4)
+    a1, a2 = _t(A1), _t(A2)
+    U1, U2, V1, th, info = zcsd.csd(a1, a2)
+    assert info["rank"] == n
+    assert np.max(np.abs(th.cpu().numpy() - np.sort(meta["theta"]))) <= 10 * n * U
+    res, orth = _torch_checks(a1, a2, U1, U2, V1, th, n)
+    assert res <= 1e-13, res
+    assert max(orth.values()) <= 1e-13, orth

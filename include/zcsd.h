@@ -109,6 +109,30 @@ zcsd_status zcsd_dcsd(zcsd_handle* handle, int n,
                       const zcsd_opts* opts, zcsd_info* info);
 
 /*
+ * Backward of `batch` full-rank CS decompositions of size n: the gradients
+ * gA1, gA2 of L = sum_i g_theta[i] theta_i + <G_W1, W1> + <G_W2, W2> with
+ * respect to A1 and A2, where W_i = U_i V1^T are the polar factors (Alg. 1
+ * lines 1-2) and theta the angles (Alg. 1 lines 8-9 with Remark (iii)).
+ * First-order perturbation of c_i = v_i^T H1 v_i and s_i = v_i^T H2 v_i gives
+ * d theta_i = -s_i u1_i^T dA1 v_i + c_i u2_i^T dA2 v_i; the polar factor of
+ * A = U Sigma V^T moves by U [(E - E^T)/(sigma_j + sigma_k)] V^T, E = U^T dA V.
+ * Inputs are the outputs of zcsd_dcsd: d_U1, d_U2, d_V1 (n x n, ld n, batch
+ * stride n*n) and d_theta (batch stride n), column-major, device memory,
+ * caller-owned and read only.  d_g_theta (stride n), d_G_W1, d_G_W2 (n x n,
+ * stride n*n) may each be NULL (zero).  d_gA1, d_gA2 (n x n, stride n*n) are
+ * written; they must not alias the inputs.  Pairs of zero singular values
+ * (rank-deficient inputs) contribute zero.  Synchronous on the handle's stream.
+ * Errors: ZCSD_EINVAL for non-positive sizes, batch > 65535 or a NULL
+ * required pointer (nothing enqueued); ZCSD_ENOMEM if the workspace
+ * (2 batch n^2 doubles) cannot be allocated.
+ */
+zcsd_status zcsd_dcsd_backward(zcsd_handle* handle, int batch, int n,
+                               const double* d_U1, const double* d_U2, const double* d_V1,
+                               const double* d_theta, const double* d_g_theta,
+                               const double* d_G_W1, const double* d_G_W2,
+                               double* d_gA1, double* d_gA2);
+
+/*
  * Batched Zolo-pd (Sec. 5): polar decompositions X_b = W_b H_b of `batch`
  * n x n matrices stored at d_X + b*strideX (ld ldx), scaled by 1/alpha (alpha
  * must bound sigma_max).  One shared lower bound l (estimated as the minimum

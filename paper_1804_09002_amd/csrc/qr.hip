@@ -273,19 +273,21 @@ void geqrf_batched(int batch, QRShape shape, int m, int n, double* M, long long 
     double* Vk = wk.V + (long long)k * wk.ldv * nb;
     double* Tk = wk.T + (long long)k * nb * nb;
     const double hh = (double)(r1b - r1a) + (r2b - r2a);
-    ProfScope prof("qr_panel", s, batch * 2.0 * hh * w * w, batch * 8.0 * 2.0 * hh * w);
     // a panel is either the three TSQR kernels or the one-workgroup kernel
-    if (nb == 32 && wk.ts.Rstack && tsqr_panel_fits((int)hh, w))
+    if (nb == 32 && wk.ts.Rstack && tsqr_panel_fits((int)hh, w)) {
       tsqr_panel(batch, M, ldm, sM, c0, w, r1a, r1b, r2a, r2b, Vk, wk.ldv, wk.sV, Tk, wk.sT, wk.ts, s);
-    else if (nb == 32)
-      hipLaunchKernelGGL(qr_panel_kernel<32>, dim3(batch), dim3(QR_NT), 0, s, M, ldm, sM, c0, w,
-                         r1a, r1b, r2a, r2b, Vk, wk.ldv, wk.sV, Tk, wk.sT);
-    else if (nb == 16)
-      hipLaunchKernelGGL(qr_panel_kernel<16>, dim3(batch), dim3(QR_NT), 0, s, M, ldm, sM, c0, w,
-                         r1a, r1b, r2a, r2b, Vk, wk.ldv, wk.sV, Tk, wk.sT);
-    else
-      throw ArgError("geqrf: unsupported panel width");
-    ZCSD_CHECK_LAUNCH();
+    } else {
+      ProfScope prof("qr_panel", s, batch * 2.0 * hh * w * w, batch * 8.0 * 2.0 * hh * w);
+      if (nb == 32)
+        hipLaunchKernelGGL(qr_panel_kernel<32>, dim3(batch), dim3(QR_NT), 0, s, M, ldm, sM, c0, w,
+                           r1a, r1b, r2a, r2b, Vk, wk.ldv, wk.sV, Tk, wk.sT);
+      else if (nb == 16)
+        hipLaunchKernelGGL(qr_panel_kernel<16>, dim3(batch), dim3(QR_NT), 0, s, M, ldm, sM, c0, w,
+                           r1a, r1b, r2a, r2b, Vk, wk.ldv, wk.sV, Tk, wk.sT);
+      else
+        throw ArgError("geqrf: unsupported panel width");
+      ZCSD_CHECK_LAUNCH();
+    }
     const int col0 = c0 + w;
     apply_block_reflector(batch, M, ldm, sM, col0, n - col0, r1a, r1b, r2a, r2b, w, Vk, wk.ldv,
                           wk.sV, Tk, wk.sT, nb, wk.W, wk.W2, wk.sW, /*transT=*/true, wk.ws, wk.ws_elems, s);

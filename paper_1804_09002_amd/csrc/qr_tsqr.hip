@@ -1,10 +1,10 @@
 // Tall panel factorisation for the blocked Householder QR: TSQR followed by
 // reconstruction of the Householder vectors.
 //
-// A panel of h logical rows and w <= 32 columns is cut into P row blocks of
-// TS_MB rows (the last one takes the remainder, < 2 TS_MB rows):
-//   A. every block is factored in LDS by one workgroup, Q_p R_p (local
-//      Householder vectors Y_p and compact-WY factor T_p);
+// A panel of h logical rows and w <= 32 columns is cut into P = ceil(h / TS_MB)
+// row blocks of TS_MB rows (the last one takes the remainder):
+//   A. every block is factored by one workgroup, Q_p R_p (local Householder
+//      vectors Y_p and compact-WY factor T_p);
 //   B. one workgroup factors the stacked [R_1; ...; R_P] = Q_top R, forms the
 //      explicit Q_top, the top w x w block Q_00 of the panel's Q, and the
 //      LU factorisation Q_00 - S = L_1 U with the sign of each pivot chosen so
@@ -15,6 +15,10 @@
 //   C. every block forms its rows of the explicit Q,
 //      Q_p = (I - Y_p T_p Y_p^T) [Q_top,p; 0], and of V = Q U^{-1}.
 // Each stage is parallel over rows; only the w x w pieces are sequential.
+// The Householder factorisations keep the matrix in registers, one row (or a
+// few) per thread: a step needs the dot products of the pivot column with all
+// 32 columns, which one butterfly over the wave and a 4-way sum across the
+// waves deliver together, so a step costs two barriers.
 // The result is interchangeable with a column-by-column Householder panel
 // (same R up to row signs, V unit lower trapezoidal, H = I - V T V^T).
 #include <algorithm>
@@ -22,156 +26,245 @@
 
 #include "zcsd_internal.h"
 #include "zcsd_la.h"
+#include "zcsd_prof.h"
 #include "zcsd_qr_tsqr.h"
 
 namespace zcsd {
 
 constexpr int TS_NT = 256;
-constexpr int TS_W = 32;                    // panel width handled here
-constexpr int TS_LD = 2 * TS_MB + 1;        // LDS leading dimension (odd)
+constexpr int TS_W = 32;  // panel width handled here
+constexpr int TS_W1 = TS_W + 1;
+constexpr int TS_TREE_RPT = (TS_PMAX * TS_W + TS_NT - 1) / TS_NT;  // rows per thread in the tree
 
 __device__ __forceinline__ int ts_phys(int i, int h1, int r1a, int r2a) {
   return i < h1 ? r1a + i : r2a + (i - h1);
 }
 
-__device__ __forceinline__ double block_sum(double v, double* red) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) red[wave] = v;
-  __syncthreads();
-  double s = 0.0;
-#pragma unroll
-  for (int q = 0; q < TS_NT / 64; ++q) s += red[q];
-  return s;
+// Cross-lane moves of doubles (two 32-bit halves).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// Householder QR of A (rows x w, column-major in LDS with leading dim LD) in
-// place: v's below the diagonal with implicit unit diagonal, R on and above
-// (betas hold R's diagonal, A's diagonal is set to 1), T (w x w) in Ts.
-// 256 threads; the dot products d_j = v^T A(:, j) use 8 threads per column.
-__device__ void lds_householder(double* A, int LD, int rows, int w, double (*Ts)[TS_W + 1],
-                                double* betas, double* red, double* sums) {
-  const int tid = threadIdx.x;
-  const int grp = tid >> 3, gl = tid & 7;  // 32 groups of 8 threads
-  for (int e = tid; e < TS_W * (TS_W + 1); e += TS_NT) (&Ts[0][0])[e] = 0.0;
-  for (int t = 0; t < w; ++t) {
-    double* at = A + (long long)t * LD;
-    double p = 0.0;
-    for (int i = t + 1 + tid; i < rows; i += TS_NT) p += at[i] * at[i];
-    const double sig2 = block_sum(p, red);
-    const double alpha = at[t];
-    double tau, beta, scal;
-    if (sig2 == 0.0) {
-      tau = 0.0;
-      beta = alpha;
-      scal = 1.0;
-    } else {
-      const double nrm = sqrt(alpha * alpha + sig2);
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// (a, b) -> a' + b' after swapping the upper half-wave of a with the lower
+// half-wave of b (P32), or the odd 16-lane rows of a with the even rows of b:
+// a lane of the lower half ends with a + partner's a, one of the upper half
+// with partner's b + b -- one halving step of the butterfly below.
+template <bool P32>
+__device__ __forceinline__ double swap_sum(double a, double b) {
+  const long long ia = __double_as_longlong(a), ib = __double_as_longlong(b);
+  const unsigned alo = (unsigned)ia, ahi = (unsigned)(ia >> 32);
+  const unsigned blo = (unsigned)ib, bhi = (unsigned)(ib >> 32);
+  unsigned a0, b0, a1, b1;
+  if constexpr (P32) {
+    const auto rl = __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
+    const auto rh = __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
+    a0 = rl[0]; b0 = rl[1]; a1 = rh[0]; b1 = rh[1];
+  } else {
+    const auto rl = __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
+    const auto rh = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
+    a0 = rl[0]; b0 = rl[1]; a1 = rh[0]; b1 = rh[1];
+  }
+  return __longlong_as_double(((long long)a1 << 32) | a0) +
+         __longlong_as_double(((long long)b1 << 32) | b0);
+}
+
+// One DPP halving step: partner lanes exchange the halves they do not keep;
+// `hi` lanes keep the upper half.  The halves are chosen with a bit mask, not
+// with a conditional on the array index (which the compiler may turn into a
+// dynamic index and demote x to memory).
+template <int CTRL, int HS>
+__device__ __forceinline__ void dpp_halve(double (&x)[TS_W], bool hi) {
+  const long long m = hi ? -1LL : 0LL;
+#pragma unroll
+  for (int k = 0; k < HS; ++k) {
+    const long long lo = __double_as_longlong(x[k]), up = __double_as_longlong(x[k + HS]);
+    const double keep = __longlong_as_double((up & m) | (lo & ~m));
+    const double send = __longlong_as_double((lo & m) | (up & ~m));
+    x[k] = keep + dpp_f64<CTRL>(send);
+  }
+}
+
+// Sum over the 64 lanes of a wave of 32 values per lane by recursive halving:
+// partners lane ^ 32 and lane ^ 16 (permlane swaps), lane ^ 8 (DPP row_ror:8),
+// lane ^ 7 within 8-lane groups (row_half_mirror), lane ^ 2 and a last pairwise
+// add with lane ^ 1 (quad_perm).  The partner of every step agrees with the lane
+// on all bits used before, so lane l returns the sum of x[(l >> 1) & 31].
+__device__ __forceinline__ double wave_sum32(double (&x)[TS_W]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) x[k] = swap_sum<true>(x[k], x[k + 16]);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) x[k] = swap_sum<false>(x[k], x[k + 8]);
+  dpp_halve<0x128, 4>(x, (lane & 8) != 0);  // row_ror:8
+  dpp_halve<0x141, 2>(x, (lane & 4) != 0);  // row_half_mirror
+  dpp_halve<0x4E, 1>(x, (lane & 2) != 0);   // quad_perm [2,3,0,1]
+  return x[0] + dpp_f64<0xB1>(x[0]);        // quad_perm [1,0,3,2]
+}
+
+// Householder QR of a rows x w matrix (w <= 32) held in registers: row
+// i = threadIdx.x + TS_NT * r is a[r][:]; entries beyond rows / w are zero.
+// Step t forms d_j = sum_{i >= t} a_it a_ij for every j at once; with
+// alpha = a_tt, beta = -sign(alpha) sqrt(d_t), v = (a_t - beta e_t)/(alpha - beta)
+// (v_t = 1), tau = (beta - alpha)/beta, the products v^T a_j = (d_j - beta a_tj)
+// / (alpha - beta) serve both the update a_j -= tau v (v^T a_j) (j > t) and the
+// column t of T, T(0:t, t) = -tau T(0:t, 0:t) Y(:, 0:t)^T v (k < t).
+// On return the rows hold R (upper, diagonal beta) and the vectors below the
+// diagonal (unit diagonal implicit), and T is in Ts.
+// LDS: red[4 * 32], rowb[2 * 32] (double-buffered pivot row), tot[32].
+template <int t, int RPT>
+__device__ __forceinline__ void reg_householder_step(double (&a)[RPT][TS_W], int rows,
+                                                     double (*Ts)[TS_W1], double* red, double* rowb,
+                                                     double* tot) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    double x[TS_W];
+#pragma unroll
+    for (int j = 0; j < TS_W; ++j) x[j] = 0.0;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int i = tid + TS_NT * r;
+      if (i >= t && i < rows) {
+        const double ait = a[r][t];
+#pragma unroll
+        for (int j = 0; j < TS_W; ++j) x[j] = fma(ait, a[r][j], x[j]);
+      }
+      if (i == t) {
+#pragma unroll
+        for (int j = 0; j < TS_W; ++j) rowb[(t & 1) * TS_W + j] = a[r][j];
+      }
+    }
+    const double sj = wave_sum32(x);
+    if ((lane & 1) == 0) red[wave * TS_W + ((lane >> 1) & 31)] = sj;
+    __syncthreads();
+    if (tid < TS_W) tot[tid] = (red[tid] + red[TS_W + tid]) + (red[2 * TS_W + tid] + red[3 * TS_W + tid]);
+    __syncthreads();
+    const double* rt = rowb + (t & 1) * TS_W;
+    const double dt = tot[t], alpha = rt[t];
+    double tau = 0.0, beta = 0.0, scal = 0.0;
+    if (dt > 0.0) {
+      const double nrm = sqrt(dt);
       beta = alpha >= 0.0 ? -nrm : nrm;
       tau = (beta - alpha) / beta;
       scal = 1.0 / (alpha - beta);
     }
-    __syncthreads();
-    for (int i = t + 1 + tid; i < rows; i += TS_NT) at[i] *= scal;
-    if (tid == 0) {
-      at[t] = 1.0;
-      betas[t] = beta;
-    }
-    __syncthreads();
-    // d_j = sum_{i >= t} v_i A(i, j), j = grp (group of 8 threads per column)
-    {
-      const int j = grp;
-      double s = 0.0;
-      if (j < w && j != t) {
-        const double* aj = A + (long long)j * LD;
-        for (int i = t + gl; i < rows; i += 8) s += at[i] * aj[i];
+    double wv[TS_W];  // v^T a_j: the update for j > t, y_j^T v for j < t
+#pragma unroll
+    for (int j = 0; j < TS_W; ++j) wv[j] = scal * (tot[j] - beta * rt[j]);
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int i = tid + TS_NT * r;
+      if (i > t && i < rows) {
+        const double v = scal * a[r][t];
+        a[r][t] = v;
+        const double tv = tau * v;
+#pragma unroll
+        for (int j = t + 1; j < TS_W; ++j) a[r][j] = fma(-tv, wv[j], a[r][j]);
+      } else if (i == t) {
+#pragma unroll
+        for (int j = t + 1; j < TS_W; ++j) a[r][j] = fma(-tau, wv[j], a[r][j]);
+        a[r][t] = beta;
       }
-      s += __shfl_xor(s, 4, 64);
-      s += __shfl_xor(s, 2, 64);
-      s += __shfl_xor(s, 1, 64);
-      if (gl == 0) sums[j] = s;
     }
-    __syncthreads();
+    // column t of T (rows of T are independent: no barrier needed before the
+    // next step, which only writes column t + 1)
     if (tid < t) {
       double s = 0.0;
-      for (int q = tid; q < t; ++q) s += Ts[tid][q] * sums[q];
+#pragma unroll
+      for (int k = 0; k < t; ++k) s = fma(Ts[tid][k], wv[k], s);
       Ts[tid][t] = -tau * s;
+    } else if (tid == t) {
+      Ts[t][t] = tau;
     }
-    if (tid == 0) Ts[t][t] = tau;
-    const int nup = w - t - 1;
-    if (nup > 0 && tau != 0.0) {
-      const int len = rows - t;
-      for (int e = tid; e < len * nup; e += TS_NT) {
-        const int i = t + e % len, j = t + 1 + e / len;
-        A[i + (long long)j * LD] -= tau * sums[j] * at[i];
-      }
+}
+
+// the 32 steps, unrolled at compile time so that every register index is static
+template <int t, int RPT>
+__device__ __forceinline__ void reg_householder_steps(double (&a)[RPT][TS_W], int rows, int w,
+                                                      double (*Ts)[TS_W1], double* red,
+                                                      double* rowb, double* tot) {
+  if constexpr (t < TS_W) {
+    if (t < w) {
+      reg_householder_step<t, RPT>(a, rows, Ts, red, rowb, tot);
+      reg_householder_steps<t + 1, RPT>(a, rows, w, Ts, red, rowb, tot);
     }
-    __syncthreads();
   }
 }
 
+// Ts (LDS, 32 x 33) receives T; it is zeroed here and complete after the
+// caller's next barrier.
+template <int RPT>
+__device__ void reg_householder(double (&a)[RPT][TS_W], int rows, int w, double (*Ts)[TS_W1],
+                                double* red, double* rowb, double* tot) {
+  for (int e = threadIdx.x; e < TS_W * TS_W1; e += TS_NT) (&Ts[0][0])[e] = 0.0;
+  __syncthreads();
+  reg_householder_steps<0, RPT>(a, rows, w, Ts, red, rowb, tot);
+}
 // ---------------------------------------------------------------------------
 // A: local QR of every row block
 __global__ __launch_bounds__(TS_NT) void tsqr_local_kernel(
     const double* M, long long ldm, long long sM, int c0, int w, int h1, int r1a, int r2a, int h,
     int P, double* V, long long ldv, long long sV, double* Tloc, double* Rstack, long long sScr) {
-  __shared__ double A[TS_W * TS_LD];
-  __shared__ double Ts[TS_W][TS_W + 1];
-  __shared__ double betas[TS_W];
-  __shared__ double red[TS_NT / 64];
-  __shared__ double sums[TS_W];
+  __shared__ double red[4 * TS_W], rowb[2 * TS_W], tot[TS_W];
+  __shared__ double Ts[TS_W][TS_W1];
   const int p = blockIdx.x;
   const long long b = blockIdx.y;
   M += b * sM;
   V += b * sV;
   const int i0 = p * TS_MB;
-  const int rows = (p == P - 1) ? h - i0 : TS_MB;
+  const int rows = min(TS_MB, h - i0);
   const int tid = threadIdx.x;
-  for (int e = tid; e < rows * w; e += TS_NT) {
-    const int i = e % rows, j = e / rows;
-    A[i + j * TS_LD] = M[ts_phys(i0 + i, h1, r1a, r2a) + (long long)(c0 + j) * ldm];
+  double a[1][TS_W];
+  {
+    const long long pr = (tid < rows) ? ts_phys(i0 + tid, h1, r1a, r2a) : 0;
+#pragma unroll
+    for (int j = 0; j < TS_W; ++j)
+      a[0][j] = (tid < rows && j < w) ? M[pr + (long long)(c0 + j) * ldm] : 0.0;
+  }
+  reg_householder<1>(a, rows, w, Ts, red, rowb, tot);
+  // Y_p (unit lower trapezoidal) into V's rows, R_p (upper w x w, zero rows
+  // beyond the block), T_p
+  if (tid < rows) {
+#pragma unroll
+    for (int j = 0; j < TS_W; ++j)
+      if (j < w) V[(i0 + tid) + (long long)j * ldv] = (tid < j) ? 0.0 : ((tid == j) ? 1.0 : a[0][j]);
+  }
+  const int ldr = P * TS_W;
+  if (tid < w) {
+    double* Rp = Rstack + b * sScr;
+#pragma unroll
+    for (int j = 0; j < TS_W; ++j)
+      if (j < w) Rp[(p * w + tid) + (long long)j * ldr] = (j >= tid && tid < rows) ? a[0][j] : 0.0;
   }
   __syncthreads();
-  lds_householder(A, TS_LD, rows, w, Ts, betas, red, sums);
-  // outputs: Y_p (unit lower trapezoidal) into V's rows, T_p, R_p (upper w x w)
-  for (int e = tid; e < rows * w; e += TS_NT) {
-    const int i = e % rows, j = e / rows;
-    double y;
-    if (i < j) y = 0.0;
-    else if (i == j) y = 1.0;
-    else y = A[i + j * TS_LD];
-    V[(i0 + i) + (long long)j * ldv] = y;
-  }
   double* Tp = Tloc + b * sScr + (long long)p * TS_W * TS_W;
-  double* Rp = Rstack + b * sScr;
-  const int ldr = P * TS_W;
-  for (int e = tid; e < TS_W * TS_W; e += TS_NT) {
-    const int i = e % TS_W, j = e / TS_W;
-    Tp[e] = (i < w && j < w) ? Ts[i][j] : 0.0;
-    double r = 0.0;
-    if (i < w && j < w && i <= j) r = (i == j) ? betas[i] : A[i + j * TS_LD];
-    if (i < w && j < w) Rp[(p * w + i) + (long long)j * ldr] = r;
-  }
+  for (int e = tid; e < TS_W * TS_W; e += TS_NT) Tp[e] = Ts[e % TS_W][e / TS_W];
 }
 
-// B: QR of the stacked R factors, explicit Q_top, reconstruction pieces.
-// LDS: the stacked matrix (dead once Q_top is formed, then reused for the
-// w x w work arrays), T_top, Z = T_top Y_top(0:w,:)^T and R_tsqr.
+// B: QR of the stacked R factors (registers), explicit Q_top, reconstruction
+// pieces (w x w work in LDS).
 __global__ __launch_bounds__(TS_NT) void tsqr_tree_kernel(
     double* M, long long ldm, long long sM, int c0, int w, int h1, int r1a, int r2a, int P,
     const double* V, long long ldv, long long sV, const double* Tloc, const double* Rstack,
     double* Qtop, double* Uo, double* Lo, double* So, long long sScr, double* Tfin, long long sT) {
-  constexpr int W1 = TS_W + 1;
-  __shared__ double A[TS_W * TS_LD];
-  __shared__ double Ts[TS_W][W1];
-  __shared__ double Z[TS_W][W1];
-  __shared__ double Rf[TS_W][W1];
-  __shared__ double betas[TS_W];
-  __shared__ double red[TS_NT / 64];
-  __shared__ double sums[TS_W];
+  __shared__ double red[4 * TS_W], rowb[2 * TS_W], tot[TS_W];
+  __shared__ double Ts[TS_W][TS_W1];  // T_top
+  __shared__ double Yt[TS_W][TS_W1];  // Y_top(0:w, 0:w), then X2
+  __shared__ double Z[TS_W][TS_W1];   // T_top Y_top(0:w, :)^T, then L1^{-T}
+  __shared__ double Rf[TS_W][TS_W1];  // R_tsqr
+  __shared__ double Q0[TS_W][TS_W1];  // Q_top,0, then Q_00 and its LU
+  __shared__ double Y0[TS_W][TS_W1];  // Y_0(0:w, 0:w) of block 0
+  __shared__ double T0s[TS_W][TS_W1]; // T_0 of block 0, then U
   __shared__ double sg[TS_W];
-  __shared__ double piv_sh;
   const long long b = blockIdx.x;
   M += b * sM;
   V += b * sV;
@@ -185,195 +278,256 @@ __global__ __launch_bounds__(TS_NT) void tsqr_tree_kernel(
   const int tid = threadIdx.x;
   const int rows = P * w;
   const int ldr = P * TS_W;
-  for (int e = tid; e < rows * w; e += TS_NT) {
-    const int i = e % rows, j = e / rows;
-    A[i + j * TS_LD] = Rstack[i + (long long)j * ldr];
+  double a[TS_TREE_RPT][TS_W];
+#pragma unroll
+  for (int r = 0; r < TS_TREE_RPT; ++r) {
+    const int i = tid + TS_NT * r;
+#pragma unroll
+    for (int j = 0; j < TS_W; ++j) a[r][j] = (i < rows && j < w) ? Rstack[i + (long long)j * ldr] : 0.0;
+  }
+  reg_householder<TS_TREE_RPT>(a, rows, w, Ts, red, rowb, tot);
+  // R_tsqr and Y_top(0:w, 0:w) from the first w rows (rows w..31 belong to the
+  // next block: zero here), Y_0(0:w, 0:w) and T_0 of block 0
+  if (tid < TS_W) {
+    const bool in = tid < w;
+#pragma unroll
+    for (int j = 0; j < TS_W; ++j) {
+      Rf[tid][j] = (in && j >= tid) ? a[0][j] : 0.0;
+      Yt[tid][j] = in ? ((j < tid) ? a[0][j] : ((j == tid) ? 1.0 : 0.0)) : 0.0;
+    }
+  }
+  for (int e = tid; e < TS_W * TS_W; e += TS_NT) {
+    const int i = e & (TS_W - 1), j = e / TS_W;
+    Y0[i][j] = (i < w && j < w) ? ((i < j) ? 0.0 : ((i == j) ? 1.0 : V[i + (long long)j * ldv])) : 0.0;
+    T0s[i][j] = Tloc[e];  // zero beyond w (written so by the local factorisation)
+    Q0[i][j] = 0.0;
   }
   __syncthreads();
-  lds_householder(A, TS_LD, rows, w, Ts, betas, red, sums);
-  // R_tsqr (upper w x w) and Z = T_top Y_top(0:w, :)^T, Y_top unit lower
-  for (int e = tid; e < w * w; e += TS_NT) {
-    const int i = e % w, j = e / w;
-    Rf[i][j] = (i < j) ? A[i + j * TS_LD] : ((i == j) ? betas[i] : 0.0);
+  // Z = T_top Y_top(0:w, :)^T; all 32 x 32 products below run over the full
+  // zero-padded range so that the loops unroll
+  for (int e = tid; e < TS_W * TS_W; e += TS_NT) {
+    const int i = e & (TS_W - 1), j = e / TS_W;
     double s = 0.0;
-    for (int q = i; q <= j && q < w; ++q) {
-      const double y = (j == q) ? 1.0 : A[j + q * TS_LD];  // Y(j, q), j >= q
-      s += Ts[i][q] * y;
-    }
+#pragma unroll
+    for (int q = 0; q < TS_W; ++q) s = fma(Ts[i][q], Yt[j][q], s);
     Z[i][j] = s;
   }
   __syncthreads();
-  // Q_top = [I; 0] - Y_top Z  (rows x w) -> global
-  for (int e = tid; e < rows * w; e += TS_NT) {
-    const int i = e % rows, j = e / rows;
-    double s = (i == j) ? 1.0 : 0.0;
-    const int qmax = min(i, w - 1);
-    for (int q = 0; q <= qmax; ++q) {
-      const double y = (i == q) ? 1.0 : A[i + q * TS_LD];
-      s -= y * Z[q][j];
-    }
-    Qtop[i + (long long)j * ldr] = s;
-  }
-  __syncthreads();  // A is dead from here on: reuse it for w x w arrays
-  double* Q0 = A;                   // Q_00, then its LU in place
-  double* Y0 = A + TS_W * W1;       // Y_0(0:w, 0:w) of block 0 (unit lower)
-  double* Li = A + 2 * TS_W * W1;   // temporaries, then L1^{-T}
-  double* X2 = A + 3 * TS_W * W1;
-#define S2(p, i, j) p[(i) * W1 + (j)]
-  for (int e = tid; e < w * w; e += TS_NT) {
-    const int i = e % w, j = e / w;
-    S2(Q0, i, j) = Qtop[i + (long long)j * ldr];
-    S2(Y0, i, j) = (i < j) ? 0.0 : ((i == j) ? 1.0 : V[i + (long long)j * ldv]);
-  }
-  __syncthreads();
-  // Q_00 = Q_top,0 - Y0 T_0 (Y0^T Q_top,0)
-  const double* T0 = Tloc;
-  for (int e = tid; e < w * w; e += TS_NT) {
-    const int i = e % w, j = e / w;
-    double s = 0.0;
-    for (int q = i; q < w; ++q) s += S2(Y0, q, i) * S2(Q0, q, j);
-    S2(X2, i, j) = s;
-  }
-  __syncthreads();
-  for (int e = tid; e < w * w; e += TS_NT) {
-    const int i = e % w, j = e / w;
-    double s = 0.0;
-    for (int q = i; q < w; ++q) s += T0[i + q * TS_W] * S2(X2, q, j);
-    S2(Li, i, j) = s;
-  }
-  __syncthreads();
-  for (int e = tid; e < w * w; e += TS_NT) {
-    const int i = e % w, j = e / w;
-    double s = 0.0;
-    for (int q = 0; q <= i; ++q) s += S2(Y0, i, q) * S2(Li, q, j);
-    S2(X2, i, j) = S2(Q0, i, j) - s;
-  }
-  __syncthreads();
-  for (int e = tid; e < w * w; e += TS_NT) {
-    const int i = e % w, j = e / w;
-    S2(Q0, i, j) = S2(X2, i, j);
-  }
-  __syncthreads();
-  // LU of Q_00 - S with the pivot sign chosen so that |pivot| >= 1
-  for (int k = 0; k < w; ++k) {
-    if (tid == 0) {
-      const double sk = (S2(Q0, k, k) >= 0.0) ? -1.0 : 1.0;
-      sg[k] = sk;
-      S2(Q0, k, k) -= sk;
-      piv_sh = S2(Q0, k, k);
-    }
-    __syncthreads();
-    const int m = w - k - 1;
-    if (tid < m) S2(Q0, k + 1 + tid, k) /= piv_sh;
-    __syncthreads();
-    for (int e = tid; e < m * m; e += TS_NT) {
-      const int i = k + 1 + e % m, j = k + 1 + e / m;
-      S2(Q0, i, j) -= S2(Q0, i, k) * S2(Q0, k, j);
-    }
-    __syncthreads();
-  }
-  // Li = L1^{-T}: thread j computes column j of L1^{-1} (forward substitution)
-  if (tid < w) {
-    const int j = tid;
-    for (int i = 0; i < w; ++i) {
-      double s = (i == j) ? 1.0 : 0.0;
-      for (int q = j; q < i; ++q) s -= S2(Q0, i, q) * S2(Li, j, q);
-      S2(Li, j, i) = (i < j) ? 0.0 : s;  // L1^{-T}(j, i) = L1^{-1}(i, j)
+  // Q_top = [I; 0] - Y_top Z, row by row from the registers, one column at a time
+#pragma unroll
+  for (int r = 0; r < TS_TREE_RPT; ++r) {
+    const int i = tid + TS_NT * r;
+    if (i < rows) {
+#pragma unroll 2
+      for (int j = 0; j < w; ++j) {
+        double q = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = 0; k < TS_W; ++k) {
+          const double y = (i > k) ? a[r][k] : ((i == k) ? 1.0 : 0.0);
+          q = fma(-y, Z[k][j], q);
+        }
+        Qtop[i + (long long)j * ldr] = q;
+        if (i < TS_W) Q0[i][j] = q;
+      }
     }
   }
   __syncthreads();
-  // T = -U S L1^{-T} (upper), U = upper part of the LU
+  // Q_00 = Q_top,0 - Y_0 T_0 (Y_0^T Q_top,0): X2 = Y_0^T Q_top,0, X3 = T_0 X2
+  double (*X2)[TS_W1] = Yt;
+  double (*X3)[TS_W1] = Z;
   for (int e = tid; e < TS_W * TS_W; e += TS_NT) {
-    const int i = e % TS_W, j = e / TS_W;
+    const int i = e & (TS_W - 1), j = e / TS_W;
     double s = 0.0;
-    if (i < w && j < w && i <= j)
-      for (int q = i; q <= j; ++q) s += S2(Q0, i, q) * sg[q] * S2(Li, q, j);
-    Tfin[i + (long long)j * TS_W] = -s;
+#pragma unroll
+    for (int q = 0; q < TS_W; ++q) s = fma(Y0[q][i], Q0[q][j], s);
+    X2[i][j] = s;
+  }
+  __syncthreads();
+  for (int e = tid; e < TS_W * TS_W; e += TS_NT) {
+    const int i = e & (TS_W - 1), j = e / TS_W;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < TS_W; ++q) s = fma(T0s[i][q], X2[q][j], s);
+    X3[i][j] = s;
+  }
+  __syncthreads();
+  for (int e = tid; e < TS_W * TS_W; e += TS_NT) {
+    const int i = e & (TS_W - 1), j = e / TS_W;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < TS_W; ++q) s = fma(Y0[i][q], X3[q][j], s);
+    X2[i][j] = Q0[i][j] - s;  // Q_00 (zero beyond w)
+  }
+  __syncthreads();
+  // Wave 0, lane i < w holding row i in registers: LU of Q_00 - S with the
+  // pivot sign chosen so that |pivot| >= 1, then L1^{-1} and U^{-1} column by
+  // column (lane j owns column j); pivot rows are broadcast with readlane.
+  double (*Li)[TS_W1] = Z;   // L1^{-T}
+  double (*Ui)[TS_W1] = Q0;  // U^{-1}
+  double (*Us)[TS_W1] = T0s; // U
+  if (tid < 64) {
+    const int lane = tid;
+    const bool own = lane < w;
+    double row[TS_W];
+#pragma unroll
+    for (int j = 0; j < TS_W; ++j) row[j] = own ? X2[lane][j] : 0.0;
+    if (lane < TS_W) sg[lane] = 0.0;  // signs beyond w stay zero
+#pragma unroll
+    for (int k = 0; k < TS_W; ++k) {
+      if (k < w) {
+        const double akk = readlane_f64(row[k], k);
+        const double sk = (akk >= 0.0) ? -1.0 : 1.0;
+        const double piv = akk - sk;
+        const double rp = 1.0 / piv;
+        if (lane == 0) sg[k] = sk;
+        if (lane == k) row[k] = piv;
+        double pr[TS_W];
+#pragma unroll
+        for (int j = k + 1; j < TS_W; ++j) pr[j] = readlane_f64(row[j], k);
+        if (lane > k && own) {
+          const double l = row[k] * rp;
+          row[k] = l;
+#pragma unroll
+          for (int j = k + 1; j < TS_W; ++j) row[j] = fma(-l, pr[j], row[j]);
+        }
+      }
+    }
+    // row now holds L (strictly below the diagonal, unit diagonal implicit) and U
+    double xc[TS_W];
+    // L1^{-1}: x_i = e_i - sum_{k < i} L_ik x_k (column `lane`)
+#pragma unroll
+    for (int i = 0; i < TS_W; ++i) {
+      double x = (lane == i) ? 1.0 : 0.0;
+#pragma unroll
+      for (int k = 0; k < i; ++k) x = fma(-readlane_f64(row[k], i), xc[k], x);
+      xc[i] = (i < w) ? x : 0.0;
+    }
+    if (lane < TS_W) {
+#pragma unroll
+      for (int i = 0; i < TS_W; ++i) Li[lane][i] = own ? xc[i] : 0.0;  // L1^{-T}(lane, i) = L1^{-1}(i, lane)
+    }
+    // U^{-1}: x_i = (e_i - sum_{k > i} U_ik x_k) / U_ii (column `lane`)
+#pragma unroll
+    for (int i = TS_W - 1; i >= 0; --i) {
+      double x = 0.0;
+      if (i < w) {
+        x = (lane == i) ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = i + 1; k < TS_W; ++k) x = fma(-readlane_f64(row[k], i), xc[k], x);
+        x *= 1.0 / readlane_f64(row[i], i);
+      }
+      xc[i] = x;
+    }
+    if (lane < TS_W) {
+#pragma unroll
+      for (int i = 0; i < TS_W; ++i) {
+        Ui[i][lane] = own ? xc[i] : 0.0;
+        Us[lane][i] = (own && i >= lane) ? row[i] : 0.0;
+        Lo[lane + i * TS_W] = own ? ((i < lane) ? row[i] : ((i == lane) ? 1.0 : 0.0)) : 0.0;
+      }
+    }
+  }
+  __syncthreads();
+  // T = -U S L1^{-T} (upper)
+  for (int e = tid; e < TS_W * TS_W; e += TS_NT) {
+    const int i = e & (TS_W - 1), j = e / TS_W;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < TS_W; ++q) s = fma(Us[i][q] * sg[q], Li[q][j], s);
+    Tfin[i + (long long)j * TS_W] = (i <= j) ? -s : 0.0;
   }
   // R = S R_tsqr into the matrix (top w logical rows = segment 1), zeros below the diagonal
   for (int e = tid; e < w * w; e += TS_NT) {
     const int i = e % w, j = e / w;
     M[ts_phys(i, h1, r1a, r2a) + (long long)(c0 + j) * ldm] = (i <= j) ? sg[i] * Rf[i][j] : 0.0;
   }
-  // U, L1, S for the row expansion
-  for (int e = tid; e < w * w; e += TS_NT) {
-    const int i = e % w, j = e / w;
-    Uo[i + j * TS_W] = (i <= j) ? S2(Q0, i, j) : 0.0;
-    Lo[i + j * TS_W] = (i > j) ? S2(Q0, i, j) : ((i == j) ? 1.0 : 0.0);
-  }
+  // U^{-1} and S for the row expansion (L1 was written above)
+  for (int e = tid; e < TS_W * TS_W; e += TS_NT) Uo[e] = Ui[e % TS_W][e / TS_W];
   if (tid < w) So[tid] = sg[tid];
-#undef S2
 }
 
-// C: rows of Q and of V = Q U^{-1}; zero the annihilated panel entries
+// C: rows of Q and of V = Q U^{-1}; zero the annihilated panel entries.
+// With M2 = T_p Y_p(0:w, :)^T Q_top,p, the row i of the panel's Q is
+// q = [Q_top,p; 0](i, :) - y M2 (y = Y_p(i, :)), so v = q U^{-1} =
+// Q3(i, :) - y M3 with Q3 = Q_top,p U^{-1} and M3 = M2 U^{-1} formed once per
+// block; y stays in registers and v is produced one column at a time.
 __global__ __launch_bounds__(TS_NT) void tsqr_expand_kernel(
     double* M, long long ldm, long long sM, int c0, int w, int h1, int r1a, int r2a, int h, int P,
     double* V, long long ldv, long long sV, const double* Tloc, const double* Qtop,
-    const double* Uo, const double* Lo, long long sScr) {
-  __shared__ double M1[TS_W][TS_W + 1];
-  __shared__ double M2[TS_W][TS_W + 1];
-  __shared__ double Us[TS_W][TS_W + 1];
-  __shared__ double Qt[TS_W][TS_W + 1];
-  __shared__ double Qr[TS_W][TS_NT + 1];
+    const double* Uinv, const double* Lo, long long sScr) {
+  __shared__ double Qt[TS_W][TS_W1];
+  __shared__ double Us[TS_W][TS_W1];  // U^{-1}
+  __shared__ double M1[TS_W][TS_W1];  // Y_p^T Q_top,p, then M3
+  __shared__ double M2[TS_W][TS_W1];
+  __shared__ double Q3[TS_W][TS_W1];
   const int p = blockIdx.x;
   const long long b = blockIdx.y;
   M += b * sM;
   V += b * sV;
   Tloc += b * sScr;
   Qtop += b * sScr;
-  Uo += b * sScr;
+  Uinv += b * sScr;
   Lo += b * sScr;
   const int tid = threadIdx.x;
   const int i0 = p * TS_MB;
-  const int rows = (p == P - 1) ? h - i0 : TS_MB;
+  const int rows = min(TS_MB, h - i0);
+  const int wy = min(w, rows);  // rows of Y_p that meet [Q_top,p; 0]
   const int ldr = P * TS_W;
   const double* Tp = Tloc + (long long)p * TS_W * TS_W;
-  for (int e = tid; e < w * w; e += TS_NT) {
-    const int i = e % w, j = e / w;
-    Qt[i][j] = Qtop[(p * w + i) + (long long)j * ldr];
-    Us[i][j] = Uo[i + j * TS_W];
+  for (int e = tid; e < TS_W * TS_W; e += TS_NT) {
+    const int i = e % TS_W, j = e / TS_W;
+    const bool in = i < w && j < w;
+    Qt[i][j] = in ? Qtop[(p * w + i) + (long long)j * ldr] : 0.0;
+    Us[i][j] = in ? Uinv[i + j * TS_W] : 0.0;
   }
   __syncthreads();
-  // M1 = Y_p(0:w, :)^T Qt_p,  Y_p unit lower on its first w rows
-  for (int e = tid; e < w * w; e += TS_NT) {
-    const int i = e % w, j = e / w;
-    double s = 0.0;
-    for (int q = i; q < w; ++q) s += ((q == i) ? 1.0 : V[(i0 + q) + (long long)i * ldv]) * Qt[q][j];
+  // M1 = Y_p(0:wy, :)^T Q_top,p(0:wy, :) (Y_p unit lower on its first rows);
+  // Q3 = Q_top,p U^{-1}
+  for (int e = tid; e < TS_W * TS_W; e += TS_NT) {
+    const int i = e % TS_W, j = e / TS_W;
+    double s = 0.0, s3 = 0.0;
+    if (i < w && j < w) {
+      for (int q = i; q < wy; ++q)
+        s = fma((q == i) ? 1.0 : V[(i0 + q) + (long long)i * ldv], Qt[q][j], s);
+      for (int q = 0; q <= j; ++q) s3 = fma(Qt[i][q], Us[q][j], s3);
+    }
     M1[i][j] = s;
+    Q3[i][j] = s3;
   }
   __syncthreads();
   for (int e = tid; e < TS_W * TS_W; e += TS_NT) {
     const int i = e % TS_W, j = e / TS_W;
-    double s = 0.0;  // rows/columns beyond w stay exactly zero (they multiply y_k = 0)
+    double s = 0.0;  // rows/columns beyond w stay exactly zero
     if (i < w && j < w)
-      for (int q = i; q < w; ++q) s += Tp[i + q * TS_W] * M1[q][j];
+      for (int q = i; q < w; ++q) s = fma(Tp[i + q * TS_W], M1[q][j], s);
     M2[i][j] = s;
   }
   __syncthreads();
-  // row by row: q = [Qt_p; 0](i, :) - Y_p(i, :) M2, then v = q U^{-1}; in place over Y_p.
-  // y lives in registers (fully unrolled over the 32 columns), q in LDS (one column of
-  // Qr per panel column, one entry per thread).
-  for (int i = tid; i < rows; i += TS_NT) {
+  double (*M3)[TS_W1] = M1;
+  for (int e = tid; e < TS_W * TS_W; e += TS_NT) {
+    const int i = e % TS_W, j = e / TS_W;
+    double s = 0.0;
+    if (i < w && j < w)
+      for (int q = 0; q <= j; ++q) s = fma(M2[i][q], Us[q][j], s);
+    M3[i][j] = s;
+  }
+  __syncthreads();
+  if (tid < rows) {
+    const int i = tid;
     const int gi = i0 + i;
-    double y[TS_W];
-#pragma unroll
-    for (int k = 0; k < TS_W; ++k) y[k] = (k < w) ? V[gi + (long long)k * ldv] : 0.0;
-    for (int j = 0; j < w; ++j) {
-      double s = (i < w) ? Qt[i][j] : 0.0;
-#pragma unroll
-      for (int k = 0; k < TS_W; ++k) s -= y[k] * M2[k][j];
-      Qr[j][tid] = s;
-    }
     if (p == 0 && i < w) {
       for (int j = 0; j < w; ++j) V[gi + (long long)j * ldv] = Lo[i + j * TS_W];
     } else {
-      // v U = q, U upper: v_j = (q_j - sum_{k<j} v_k U(k, j)) / U(j, j), v overwrites q
+      double y[TS_W];
+#pragma unroll
+      for (int k = 0; k < TS_W; ++k) y[k] = (k < w) ? V[gi + (long long)k * ldv] : 0.0;
+#pragma unroll 2
       for (int j = 0; j < w; ++j) {
-        double s = Qr[j][tid];
-        for (int k = 0; k < j; ++k) s -= Qr[k][tid] * Us[k][j];
-        Qr[j][tid] = s / Us[j][j];
+        double v = (i < TS_W) ? Q3[i][j] : 0.0;
+#pragma unroll
+        for (int k = 0; k < TS_W; ++k) v = fma(-y[k], M3[k][j], v);
+        V[gi + (long long)j * ldv] = v;
       }
-      for (int j = 0; j < w; ++j) V[gi + (long long)j * ldv] = Qr[j][tid];
     }
     if (gi >= w) {
       const long long pr = ts_phys(gi, h1, r1a, r2a);
@@ -382,24 +536,36 @@ __global__ __launch_bounds__(TS_NT) void tsqr_expand_kernel(
   }
 }
 
-bool tsqr_panel_fits(int h, int w) { return w <= TS_W && w >= 1 && h >= w && h < (TS_PMAX + 1) * TS_MB; }
+bool tsqr_panel_fits(int h, int w) { return w <= TS_W && w >= 1 && h >= w && h <= TS_PMAX * TS_MB; }
 
 void tsqr_panel(int batch, double* M, long long ldm, long long sM, int c0, int w, int r1a, int r1b,
                 int r2a, int r2b, double* V, long long ldv, long long sV, double* T, long long sT,
                 const TsqrScratch& sc, hipStream_t s) {
   const int h1 = r1b - r1a, h2 = r2b - r2a, h = h1 + h2;
-  const int P = std::max(1, h / TS_MB);
-  if (!tsqr_panel_fits(h, w) || P > TS_PMAX) throw ArgError("tsqr_panel: panel too tall");
-  hipLaunchKernelGGL(tsqr_local_kernel, dim3(P, batch), dim3(TS_NT), 0, s, M, ldm, sM, c0, w, h1,
-                     r1a, r2a, h, P, V, ldv, sV, sc.Tloc, sc.Rstack, sc.stride);
-  ZCSD_CHECK_LAUNCH();
-  hipLaunchKernelGGL(tsqr_tree_kernel, dim3(batch), dim3(TS_NT), 0, s, M, ldm, sM, c0, w, h1, r1a,
-                     r2a, P, V, ldv, sV, sc.Tloc, sc.Rstack, sc.Qtop, sc.U, sc.L, sc.S, sc.stride,
-                     T, sT);
-  ZCSD_CHECK_LAUNCH();
-  hipLaunchKernelGGL(tsqr_expand_kernel, dim3(P, batch), dim3(TS_NT), 0, s, M, ldm, sM, c0, w, h1,
-                     r1a, r2a, h, P, V, ldv, sV, sc.Tloc, sc.Qtop, sc.U, sc.L, sc.stride);
-  ZCSD_CHECK_LAUNCH();
+  if (!tsqr_panel_fits(h, w)) throw ArgError("tsqr_panel: panel too tall");
+  const int P = (h + TS_MB - 1) / TS_MB;
+  const double ww = (double)w * w;
+  {
+    ProfScope prof("tsqr_local", s, batch * (2.0 * h * ww - P * 2.0 * ww * w / 3.0),
+                   batch * 8.0 * 2.0 * h * w);
+    hipLaunchKernelGGL(tsqr_local_kernel, dim3(P, batch), dim3(TS_NT), 0, s, M, ldm, sM, c0, w, h1,
+                       r1a, r2a, h, P, V, ldv, sV, sc.Tloc, sc.Rstack, sc.stride);
+    ZCSD_CHECK_LAUNCH();
+  }
+  {
+    ProfScope prof("tsqr_tree", s, batch * (4.0 * P * ww * w + 4.0 * ww * w),
+                   batch * 8.0 * 2.0 * P * ww);
+    hipLaunchKernelGGL(tsqr_tree_kernel, dim3(batch), dim3(TS_NT), 0, s, M, ldm, sM, c0, w, h1, r1a,
+                       r2a, P, V, ldv, sV, sc.Tloc, sc.Rstack, sc.Qtop, sc.U, sc.L, sc.S, sc.stride,
+                       T, sT);
+    ZCSD_CHECK_LAUNCH();
+  }
+  {
+    ProfScope prof("tsqr_expand", s, batch * 3.0 * h * ww, batch * 8.0 * 3.0 * h * w);
+    hipLaunchKernelGGL(tsqr_expand_kernel, dim3(P, batch), dim3(TS_NT), 0, s, M, ldm, sM, c0, w, h1,
+                       r1a, r2a, h, P, V, ldv, sV, sc.Tloc, sc.Qtop, sc.U, sc.L, sc.stride);
+    ZCSD_CHECK_LAUNCH();
+  }
 }
 
 TsqrScratch tsqr_scratch_alloc(Arena& ar, int batch) {

@@ -5,7 +5,7 @@
 namespace zcsd {
 
 constexpr int TS_MB = 256;    // rows per block of the first level
-constexpr int TS_PMAX = 16;   // at most this many blocks (the tree QR holds P*32 rows in LDS)
+constexpr int TS_PMAX = 17;   // at most this many blocks (the tree QR holds P*32 rows)
 
 struct TsqrScratch {
   double* Rstack = nullptr;  // (P w) x w stacked R factors, ld P*32

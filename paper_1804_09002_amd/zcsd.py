@@ -75,6 +75,7 @@ def _lib():
                           C.POINTER(Opts), C.POINTER(Info)],
             "zcsd_dzolo_pd": [vp, i, i, d, vp, i, ll, vp, vp, vp, C.POINTER(Opts), C.POINTER(Info)],
             "zcsd_dsyev_zolo": [vp, i, vp, i, d, d, vp, i, vp, C.POINTER(Opts), C.POINTER(Info)],
+            "zcsd_dcsd_backward": [vp, i, i, vp, vp, vp, vp, vp, vp, vp, vp, vp],
             "zcsd_zolo_coeffs": [d, i, C.POINTER(d), C.POINTER(d), C.POINTER(d), C.POINTER(d)],
             "zcsd_zolo_choose_r": [d, d],
             "zcsd_dqr": [vp, i, i, i, i, vp, i, ll, vp, i, ll],
@@ -306,3 +307,71 @@ class profile:
             if L.zcsd_profile_query(name.encode(), C.byref(la), C.byref(fl), C.byref(by), C.byref(ms)):
                 out[name] = {"launches": la.value, "flops": fl.value, "bytes": by.value, "ms": ms.value}
         return out
+
+
+def _colmajor_batch(X, name, shape):
+    """(batch, rows, cols) float64 device tensor -> contiguous column-major buffers."""
+    if not (isinstance(X, torch.Tensor) and X.is_cuda and X.dtype == torch.float64 and X.dim() == 3
+            and tuple(X.shape) == shape):
+        raise TypeError(f"{name} must be a float64 HIP tensor of shape {shape}")
+    return X.transpose(1, 2).contiguous()
+
+
+def csd_backward(U1, U2, V1, theta, g_theta=None, G_W1=None, G_W2=None):
+    """Gradients (gA1, gA2) of sum g_theta*theta + <G_W1, W1> + <G_W2, W2>.
+
+    U1, U2, V1: (n, n) or (batch, n, n); theta, g_theta: (n,) or (batch, n); the
+    decomposition must be full rank.  Any of g_theta, G_W1, G_W2 may be None.
+    """
+    batched = U1.dim() == 3
+    ex = (lambda t: t) if batched else (lambda t: None if t is None else t.unsqueeze(0))
+    U1, U2, V1, theta, g_theta, G_W1, G_W2 = map(ex, (U1, U2, V1, theta, g_theta, G_W1, G_W2))
+    bs, n, _ = U1.shape
+    shp = (bs, n, n)
+    u1, u2, v1 = (_colmajor_batch(X, nm, shp) for X, nm in ((U1, "U1"), (U2, "U2"), (V1, "V1")))
+    g1 = None if G_W1 is None else _colmajor_batch(G_W1, "G_W1", shp)
+    g2 = None if G_W2 is None else _colmajor_batch(G_W2, "G_W2", shp)
+    if not (theta.is_cuda and theta.dtype == torch.float64 and tuple(theta.shape) == (bs, n)):
+        raise TypeError("theta must be a float64 HIP tensor of shape (batch, n)")
+    th = theta.contiguous()
+    gt = None
+    if g_theta is not None:
+        if not (g_theta.is_cuda and g_theta.dtype == torch.float64 and tuple(g_theta.shape) == (bs, n)):
+            raise TypeError("g_theta must be a float64 HIP tensor of shape (batch, n)")
+        gt = g_theta.contiguous()
+    gA1 = torch.empty_like(u1)
+    gA2 = torch.empty_like(u1)
+    h = handle(U1.device.index)
+    st = _lib().zcsd_dcsd_backward(h, bs, n, _ptr(u1), _ptr(u2), _ptr(v1), _ptr(th),
+                                   _ptr(gt) if gt is not None else None,
+                                   _ptr(g1) if g1 is not None else None,
+                                   _ptr(g2) if g2 is not None else None, _ptr(gA1), _ptr(gA2))
+    _check(st, "zcsd_dcsd_backward")
+    gA1, gA2 = gA1.transpose(1, 2), gA2.transpose(1, 2)
+    return (gA1, gA2) if batched else (gA1[0], gA2[0])
+
+
+class CSDFunction(torch.autograd.Function):
+    """Differentiable CSD: (A1, A2) -> (U1, U2, V1, theta, W1, W2).
+
+    theta and the polar factors W_i = U_i V1^T carry gradients (hand-written
+    backward, zcsd_dcsd_backward); U1, U2, V1 are returned as non-differentiable
+    (their columns are fixed only up to signs and rotations within equal angles).
+    """
+
+    @staticmethod
+    def forward(ctx, A1, A2):
+        U1, U2, V1, th, info = csd(A1, A2, want_polar=True)
+        ctx.rank = info["rank"]
+        ctx.save_for_backward(U1, U2, V1, th)
+        W1, W2 = info["W1"], info["W2"]
+        ctx.mark_non_differentiable(U1, U2, V1)
+        return U1, U2, V1, th, W1, W2
+
+    @staticmethod
+    def backward(ctx, gU1, gU2, gV1, gth, gW1, gW2):
+        U1, U2, V1, th = ctx.saved_tensors
+        if ctx.rank < U1.shape[0]:
+            raise NotImplementedError("CSD backward needs a full-rank input")
+        gA1, gA2 = csd_backward(U1, U2, V1, th, gth, gW1, gW2)
+        return gA1, gA2

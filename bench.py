@@ -33,6 +33,11 @@ def parse():
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     p.add_argument("--cpu-n", type=int, default=2048)
     p.add_argument("--cpu-reps", type=int, default=2)
+    p.add_argument("--no-extra", action="store_true",
+                   help="skip the batched and forward+backward side measurements")
+    p.add_argument("--batched-count", type=int, default=2048)
+    p.add_argument("--single-sample", type=int, default=256,
+                   help="problems of the batched workload timed one by one on the single path")
     return p.parse_args()
 
 
@@ -73,6 +78,95 @@ def accuracy(A1, A2, U1, U2, V1, th, theta_true):
     dth = float((th - theta_true).abs().max())
     return {"backward_rel_2": res2, "backward_rel_fro": resF, "orth_2": orth2, "orth_fro": orthF,
             "max_abs_theta_err": dth}
+
+
+def batched_leg(count, sample, seed=5):
+    """2048 CSDs with n log-uniform in [8, 256] (uniform angles): one batched call
+    vs the single path one problem at a time (timed on a sample, scaled)."""
+    import numpy as np
+    import torch
+    from paper_1804_09002_amd import workloads as WL
+    from paper_1804_09002_amd import zcsd
+    sizes = [int(n) for n in WL.batched_sizes(count, seed)]
+    rng = np.random.default_rng(seed)
+    A1s, A2s = [], []
+    for n in sizes:
+        A1, A2, _ = WL.uniform_pair(n, int(rng.integers(1 << 31)))
+        A1s.append(torch.tensor(A1, device="cuda:0"))
+        A2s.append(torch.tensor(A2, device="cuda:0"))
+    a1, sizes, offs = zcsd.pack_ragged(A1s)
+    a2, _, _ = zcsd.pack_ragged(A2s)
+    zcsd.csd_batched_packed(a1, a2, sizes, offs)  # warm-up (workspace, code objects)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    U1, U2, V1, th, ranks, info = zcsd.csd_batched_packed(a1, a2, sizes, offs)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    idx = np.random.default_rng(seed + 1).choice(count, size=min(sample, count), replace=False)
+    for k in idx[:4]:  # warm-up of the single path on a few sizes
+        zcsd.csd(A1s[k], A2s[k])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in idx:
+        zcsd.csd(A1s[k], A2s[k])
+    torch.cuda.synchronize()
+    t_s = (time.perf_counter() - t0) * count / len(idx)
+    # accuracy of the batched outputs, Frobenius, over every problem
+    worst_res = worst_orth = 0.0
+    t_off = 0
+    for k, n in enumerate(sizes):
+        o = offs[k]
+        u1 = U1[o:o + n * n].view(n, n).t()
+        u2 = U2[o:o + n * n].view(n, n).t()
+        v1 = V1[o:o + n * n].view(n, n).t()
+        t = th[t_off:t_off + n]
+        t_off += n
+        R = torch.cat([(u1 * torch.cos(t)) @ v1.T - A1s[k], (u2 * torch.sin(t)) @ v1.T - A2s[k]])
+        worst_res = max(worst_res, float(torch.linalg.norm(R) / torch.linalg.norm(torch.cat([A1s[k], A2s[k]]))))
+        I = torch.eye(n, dtype=torch.float64, device="cuda:0")
+        worst_orth = max(worst_orth, max(float(torch.linalg.norm(X.T @ X - I)) for X in (u1, u2, v1)))
+    sum_n3 = float(sum(n ** 3 for n in sizes))
+    return {"workload": f"csd_fp64_batched_{count}_n8to256_loguniform", "problems": count,
+            "sum_n3": sum_n3, "batched_s": round(t_b, 4), "batched_csd_per_s": round(count / t_b, 2),
+            "single_path_s_est": round(t_s, 3), "single_sample": int(len(idx)),
+            "speedup_vs_single": round(t_s / t_b, 2),
+            "model_tflops_batched": round(198.0 * sum_n3 / t_b / 1e12, 3),
+            "worst_backward_rel_fro": worst_res, "worst_orth_fro": worst_orth}
+
+
+def backward_leg(count=64, n=512, seed=6):
+    """Forward + hand-written backward of 64 CSDs at n = 512 (uniform angles)."""
+    import numpy as np
+    import torch
+    from paper_1804_09002_amd import workloads as WL
+    from paper_1804_09002_amd import zcsd
+    rng = np.random.default_rng(seed)
+    A1s, A2s = [], []
+    for _ in range(count):
+        A1, A2, _ = WL.uniform_pair(n, int(rng.integers(1 << 31)))
+        A1s.append(torch.tensor(A1, device="cuda:0"))
+        A2s.append(torch.tensor(A2, device="cuda:0"))
+    g = torch.tensor(rng.standard_normal((count, n)), device="cuda:0")
+    G1 = torch.tensor(rng.standard_normal((count, n, n)), device="cuda:0")
+    G2 = torch.tensor(rng.standard_normal((count, n, n)), device="cuda:0")
+
+    def fwd():
+        outs = [zcsd.csd(A1s[b], A2s[b]) for b in range(count)]
+        return [torch.stack([o[k] for o in outs]) for k in range(4)]
+
+    U1, U2, V1, th = fwd()
+    zcsd.csd_backward(U1, U2, V1, th, g, G1, G2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    U1, U2, V1, th = fwd()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    gA1, gA2 = zcsd.csd_backward(U1, U2, V1, th, g, G1, G2)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return {"workload": f"csd_fp64_fwd_bwd_{count}x_n{n}", "forward_s": round(t1 - t0, 4),
+            "backward_s": round(t2 - t1, 4), "fwd_bwd_per_s": round(count / (t2 - t0), 2),
+            "backward_tflops_16n3": round(16.0 * n ** 3 * count / (t2 - t1) / 1e12, 3)}
 
 
 def cpu_baseline(n, reps, seed):
@@ -161,6 +255,13 @@ def main():
                "sample": f"{args.cpu_reps} oracle CSDs at n={args.cpu_n} (same construction), "
                          f"{dt:.2f} s each, scaled by (n_sample/n)^3 to n={n}"}
 
+    extra = None
+    if not args.no_extra:
+        log(f"batched leg: {args.batched_count} problems")
+        extra = {"batched": batched_leg(args.batched_count, args.single_sample)}
+        log("forward+backward leg: 64 x n=512")
+        extra["backward"] = backward_leg()
+
     flops_model = 198.0 * n ** 3  # 67(m1+m2)n^2 + 64n^3 with m1 = m2 = n (Remark (v))
     rec = {
         "metric": METRIC,
@@ -188,6 +289,7 @@ def main():
                  "eig_splits": info["eig_splits"], "eig_max_r": info["eig_max_r"],
                  "eig_offblock": info["eig_offblock"]},
         "kernels_warmup": kern_table if args.warmup > 0 else None,
+        "extra": extra,
     }
     print(json.dumps(rec), flush=True)
 

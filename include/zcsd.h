@@ -109,6 +109,32 @@ zcsd_status zcsd_dcsd(zcsd_handle* handle, int n,
                       const zcsd_opts* opts, zcsd_info* info);
 
 /*
+ * Batched CS decomposition of `batch` independent problems of different sizes
+ * (Algorithm 1, or Algorithm 3 for problems detected or forced rank-deficient;
+ * the same outputs and conventions as zcsd_dcsd per problem).  Packed ragged
+ * layout: problem k has size n_host[k] (1..4096) and its n_k x n_k blocks of
+ * A1, A2 (inputs) and U1, U2, V1 (outputs) start at element offset
+ * off_host[k] of the respective device array, column-major with ld = n_k;
+ * its angles start at element sum_{j<k} n_j of d_theta.  Only the first
+ * rank_host[k] columns / angles of a problem are valid, the rest are zero.
+ * n_host, off_host (read) and rank_host (written) are host arrays of length
+ * batch; matrices are device memory owned by the caller and outputs must not
+ * alias inputs.  Problems are grouped into padded size classes that run
+ * through the batched kernels together; padding is decoupled from the real
+ * spectrum (identity in the polar factors, an isolated eigenvalue 3 in B), so
+ * results equal zcsd_dcsd's up to rounding.  Synchronous on the handle's
+ * stream.  Errors: ZCSD_EINVAL (bad sizes/offsets/pointers, batch outside
+ * 1..65535, opts out of range: mu must lie in (1, 3)); ZCSD_ENOTISO /
+ * ZCSD_ENOCONV / ZCSD_ENOMEM as zcsd_dcsd.  info (may be NULL) holds the
+ * largest r used, the deepest Zolo-eig level count and the total splits.
+ */
+zcsd_status zcsd_dcsd_batched(zcsd_handle* handle, int batch, const int* n_host,
+                              const long long* off_host,
+                              const double* d_A1, const double* d_A2,
+                              double* d_U1, double* d_U2, double* d_V1, double* d_theta,
+                              int* rank_host, const zcsd_opts* opts, zcsd_info* info);
+
+/*
  * Backward of `batch` full-rank CS decompositions of size n: the gradients
  * gA1, gA2 of L = sum_i g_theta[i] theta_i + <G_W1, W1> + <G_W2, W2> with
  * respect to A1 and A2, where W_i = U_i V1^T are the polar factors (Alg. 1

@@ -220,6 +220,7 @@ void copy_blocks(const double* src, double* dst, const std::vector<CopyDesc>& d,
 namespace {
 struct Blk {
   int n;
+  int prob = 0;  // which problem of the batch
   double lo, hi;
   // location at the current level
   const double* B;  // n x n, ld ldB
@@ -238,17 +239,21 @@ T* upload(Arena& ar, const std::vector<T>& v, hipStream_t s) {
 
 ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
   const int n = a.n;
+  const int nprob = a.batch;
   ZoloEigResult res;
-  ZCSD_REQUIRE(n >= 1, "zolo_eig: n >= 1");
+  ZCSD_REQUIRE(n >= 1 && nprob >= 1, "zolo_eig: n >= 1, batch >= 1");
   const int nleaf = std::max(1, std::min(a.n_leaf, 64));
+  const long long nn = (long long)n * n;
   ArenaScope scope(ar);
 
-  // global Frobenius norm of B (for the "already scalar" test and the off-block ratio)
-  double bnorm2;
+  // Frobenius norm of B (largest over the batch; for the off-block ratio)
+  double bnorm2 = 0.0;
   {
-    double* d_ss = ar.dalloc(1);
-    sumsq(1, n, n, a.B, a.ldb, 0, d_ss, ar, s);
-    d2h(&bnorm2, d_ss, sizeof(double), s);
+    double* d_ss = ar.dalloc(nprob);
+    sumsq(nprob, n, n, a.B, a.ldb, a.sB, d_ss, ar, s);
+    std::vector<double> ss(nprob);
+    d2h(ss.data(), d_ss, nprob * sizeof(double), s);
+    for (double v : ss) bnorm2 = std::max(bnorm2, v);
   }
   const double bnorm = std::sqrt(bnorm2);
   // A block is finished without splitting only when ||B_blk - mean I||_F (an upper
@@ -257,24 +262,24 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
   const double bmax = std::max(std::fabs(a.lo), std::fabs(a.hi));
   const double scalar_tol = 4.0 * 0x1p-53 * std::max(bmax, 1e-300);
 
-  // output assembly: unsorted eigenvectors/values
-  double* Vout = ar.dalloc((size_t)n * n);
-  std::vector<double> lam_out;
-  lam_out.reserve(n);
-  int col_out = 0;
+  // output assembly: unsorted eigenvectors/values per problem
+  double* Vout = ar.dalloc((size_t)nprob * nn);
+  std::vector<std::vector<double>> lam_out(nprob);
+  std::vector<int> col_out(nprob, 0);
 
-  // level 0: the whole matrix, V = I
-  double* V0 = ar.dalloc((size_t)n * n);
-  set_identity(1, n, n, 1.0, V0, n, 0, s);
+  // level 0: every problem whole, V = I
+  double* V0 = ar.dalloc((size_t)nprob * nn);
+  set_identity(nprob, n, n, 1.0, V0, n, nn, s);
   std::vector<Blk> active;
-  {
+  for (int p = 0; p < nprob; ++p) {
     Blk r;
     r.n = n;
+    r.prob = p;
     r.lo = a.lo;
     r.hi = a.hi;
-    r.B = a.B;
+    r.B = a.B + (long long)p * a.sB;
     r.ldB = a.ldb;
-    r.V = V0;
+    r.V = V0 + (long long)p * nn;
     active.push_back(r);
   }
   unsigned long long seed = 0x5DEECE66DULL;
@@ -300,14 +305,23 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
     set_identity(nblk, N, N, 0.0, Bp, N, NN, s);
     set_identity(nblk, n, N, 0.0, Vp, n, (long long)n * N, s);
     {
-      // the blocks of a level come from different buffers (children of splits and
-      // re-tried blocks): copy each block from its own base
-      for (int k = 0; k < nblk; ++k) {
-        std::vector<CopyDesc> one = {{0, (long long)k * NN, (int)all[k].ldB, N, all[k].n, all[k].n}};
-        copy_blocks(all[k].B, Bp, one, ar, s);
-        std::vector<CopyDesc> onev = {{0, (long long)k * n * N, n, n, n, all[k].n}};
-        copy_blocks(all[k].V, Vp, onev, ar, s);
+      // the blocks of a level come from different buffers (the input, children of
+      // splits, re-tried blocks): offsets are taken from the lowest block address
+      // (one flat device address space), so each level is two copy launches
+      const double* bbase = all[0].B;
+      const double* vbase = all[0].V;
+      for (int k = 1; k < nblk; ++k) {
+        bbase = std::min(bbase, all[k].B);
+        vbase = std::min(vbase, all[k].V);
       }
+      std::vector<CopyDesc> cb, cv;
+      for (int k = 0; k < nblk; ++k) {
+        cb.push_back({(long long)(all[k].B - bbase), (long long)k * NN, (int)all[k].ldB, N, all[k].n,
+                      all[k].n});
+        cv.push_back({(long long)(all[k].V - vbase), (long long)k * n * N, n, n, n, all[k].n});
+      }
+      copy_blocks(bbase, Bp, cb, ar, s);
+      copy_blocks(vbase, Vp, cv, ar, s);
     }
     std::vector<int> nbh(nblk);
     for (int k = 0; k < nblk; ++k) nbh[k] = all[k].n;
@@ -345,18 +359,20 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
       else split_idx.push_back(k);
     }
     {
-      long long add = 0;
-      for (int k : scalar_idx) add += all[k].n;
-      for (int k : leaf_idx) add += all[k].n;
-      if (col_out + add > n) throw NumError(ZCSD_ENOCONV, "zolo_eig: block sizes exceed n");
+      std::vector<long long> add(nprob, 0);
+      for (int k : scalar_idx) add[all[k].prob] += all[k].n;
+      for (int k : leaf_idx) add[all[k].prob] += all[k].n;
+      for (int p = 0; p < nprob; ++p)
+        if (col_out[p] + add[p] > n) throw NumError(ZCSD_ENOCONV, "zolo_eig: block sizes exceed n");
     }
     // scalar blocks: V columns as they are, eigenvalues = diag
     if (!scalar_idx.empty()) {
       std::vector<CopyDesc> cv;
       for (int k : scalar_idx) {
-        cv.push_back({(long long)k * n * N, (long long)col_out * n, n, n, n, all[k].n});
-        for (int i = 0; i < all[k].n; ++i) lam_out.push_back(diag[(size_t)k * N + i]);
-        col_out += all[k].n;
+        const int p = all[k].prob;
+        cv.push_back({(long long)k * n * N, p * nn + (long long)col_out[p] * n, n, n, n, all[k].n});
+        for (int i = 0; i < all[k].n; ++i) lam_out[p].push_back(diag[(size_t)k * N + i]);
+        col_out[p] += all[k].n;
       }
       copy_blocks(Vp, Vout, cv, ar, s);
     }
@@ -392,7 +408,7 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
       dgemm(g, s);
       std::vector<double> ll((size_t)nl * L);
       d2h(ll.data(), Ll, ll.size() * sizeof(double), s);
-      if (log_enabled()) {
+      if (log_enabled() && nprob == 1) {
         // leaf invariants: ||LVo^T B LVo - diag(lam)||_F per leaf, ||LVo^T LVo - I||_F
         ArenaScope ds(ar);
         double* BV = ar.dalloc((size_t)nl * n * L);
@@ -436,9 +452,10 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
       std::vector<CopyDesc> co;
       for (int q = 0; q < nl; ++q) {
         const int k = leaf_idx[q];
-        co.push_back({(long long)q * n * L, (long long)col_out * n, n, n, n, all[k].n});
-        for (int i = 0; i < all[k].n; ++i) lam_out.push_back(ll[(size_t)q * L + i]);
-        col_out += all[k].n;
+        const int p = all[k].prob;
+        co.push_back({(long long)q * n * L, p * nn + (long long)col_out[p] * n, n, n, n, all[k].n});
+        for (int i = 0; i < all[k].n; ++i) lam_out[p].push_back(ll[(size_t)q * L + i]);
+        col_out[p] += all[k].n;
       }
       copy_blocks(LVo, Vout, co, ar, s);
     }
@@ -647,7 +664,7 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
       g.C = Vq; g.ldc = n; g.sC = (long long)n * Ns;
       dgemm(g, s);
     }
-    if (log_enabled()) {
+    if (log_enabled() && nprob == 1) {
       // diagnostics: ||Q^T Q - I||_F per block of this level
       ArenaScope ds(ar);
       double* G = ar.dalloc((size_t)ns * SS);
@@ -753,6 +770,7 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
       }
       ++res.splits;
       Blk plus;
+      plus.prob = b.prob;
       plus.n = np;
       plus.lo = sft;
       plus.hi = b.hi;
@@ -760,6 +778,7 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
       plus.ldB = Ns;
       plus.V = Vq + (long long)q * n * Ns;
       Blk minus;
+      minus.prob = b.prob;
       minus.n = b.n - np;
       minus.lo = b.lo;
       minus.hi = sft;
@@ -771,20 +790,31 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
     }
     active.swap(next);
   }
-  if (col_out != n) throw NumError(ZCSD_ENOCONV, "zolo_eig: lost eigenpairs");
+  for (int p = 0; p < nprob; ++p)
+    if (col_out[p] != n) throw NumError(ZCSD_ENOCONV, "zolo_eig: lost eigenpairs");
 
-  // sort ascending and write V, lambda
-  std::vector<int> perm(n);
-  std::iota(perm.begin(), perm.end(), 0);
-  std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) { return lam_out[x] < lam_out[y]; });
+  // sort ascending and write V, lambda (per problem)
   std::vector<CopyDesc> cv;
-  std::vector<double> lam_sorted(n);
-  for (int j = 0; j < n; ++j) {
-    cv.push_back({(long long)perm[j] * n, (long long)j * a.ldv, n, (int)a.ldv, n, 1});
-    lam_sorted[j] = lam_out[perm[j]];
+  cv.reserve((size_t)nprob * n);
+  std::vector<double> lam_sorted((size_t)nprob * n);
+  std::vector<int> perm(n);
+  for (int p = 0; p < nprob; ++p) {
+    const std::vector<double>& lo = lam_out[p];
+    std::iota(perm.begin(), perm.end(), 0);
+    std::stable_sort(perm.begin(), perm.end(), [&](int x, int y) { return lo[x] < lo[y]; });
+    for (int j = 0; j < n; ++j) {
+      cv.push_back({p * nn + (long long)perm[j] * n, p * a.sV + (long long)j * a.ldv, n, (int)a.ldv,
+                    n, 1});
+      lam_sorted[(size_t)p * n + j] = lo[perm[j]];
+    }
   }
   copy_blocks(Vout, a.V, cv, ar, s);
-  h2d(a.lam, lam_sorted.data(), n * sizeof(double), s);
+  if (nprob == 1 || a.sL == n) {
+    h2d(a.lam, lam_sorted.data(), (size_t)nprob * n * sizeof(double), s);
+  } else {
+    for (int p = 0; p < nprob; ++p)
+      h2d(a.lam + p * a.sL, lam_sorted.data() + (size_t)p * n, n * sizeof(double), s);
+  }
   return res;
 }
 

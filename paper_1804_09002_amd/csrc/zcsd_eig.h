@@ -11,12 +11,14 @@ void jacobi_batched(int nblk, const int* d_sizes, const double* A, long long lda
 
 struct ZoloEigArgs {
   int n = 0;
-  const double* B = nullptr;  // n x n symmetric, ld ldb
-  long long ldb = 0;
-  double lo = -1.0, hi = 1.0;  // spectrum bounds
-  double* V = nullptr;         // n x n eigenvectors (ld ldv), ascending eigenvalues
-  long long ldv = 0;
-  double* lam = nullptr;       // n eigenvalues (device)
+  int batch = 1;               // independent problems of the same size
+  const double* B = nullptr;  // n x n symmetric, ld ldb, problem p at B + p * sB
+  long long ldb = 0, sB = 0;
+  double lo = -1.0, hi = 1.0;  // spectrum bounds (every problem)
+  double* V = nullptr;         // n x n eigenvectors (ld ldv, stride sV), ascending eigenvalues
+  long long ldv = 0, sV = 0;
+  double* lam = nullptr;       // n eigenvalues per problem (device, stride sL)
+  long long sL = 0;
   int n_leaf = 64;
   double eps = 1e-15, tol = 0x1p-53;
   bool measure_offblock = true;

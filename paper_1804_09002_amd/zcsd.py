@@ -76,6 +76,8 @@ def _lib():
             "zcsd_dzolo_pd": [vp, i, i, d, vp, i, ll, vp, vp, vp, C.POINTER(Opts), C.POINTER(Info)],
             "zcsd_dsyev_zolo": [vp, i, vp, i, d, d, vp, i, vp, C.POINTER(Opts), C.POINTER(Info)],
             "zcsd_dcsd_backward": [vp, i, i, vp, vp, vp, vp, vp, vp, vp, vp, vp],
+            "zcsd_dcsd_batched": [vp, i, C.POINTER(C.c_int), C.POINTER(C.c_longlong), vp, vp, vp, vp,
+                                  vp, vp, C.POINTER(C.c_int), C.POINTER(Opts), C.POINTER(Info)],
             "zcsd_zolo_coeffs": [d, i, C.POINTER(d), C.POINTER(d), C.POINTER(d), C.POINTER(d)],
             "zcsd_zolo_choose_r": [d, d],
             "zcsd_dqr": [vp, i, i, i, i, vp, i, ll, vp, i, ll],
@@ -375,3 +377,59 @@ class CSDFunction(torch.autograd.Function):
             raise NotImplementedError("CSD backward needs a full-rank input")
         gA1, gA2 = csd_backward(U1, U2, V1, th, gth, gW1, gW2)
         return gA1, gA2
+
+
+def pack_ragged(mats):
+    """List of (n_k, n_k) float64 device tensors -> (packed column-major buffer, sizes, offsets)."""
+    sizes = [int(M.shape[0]) for M in mats]
+    offs, o = [], 0
+    for n in sizes:
+        offs.append(o)
+        o += n * n
+    buf = torch.cat([_colmajor(M, "A").reshape(-1) for M in mats]) if mats else None
+    return buf, sizes, offs
+
+
+def unpack_ragged(buf, sizes, offs):
+    return [buf[o:o + n * n].view(n, n).t() for n, o in zip(sizes, offs)]
+
+
+def csd_batched_packed(a1, a2, sizes, offs, rank_mode="auto", **opts):
+    """Batched CSD on packed ragged column-major device buffers (see zcsd_dcsd_batched).
+
+    Returns (U1, U2, V1, theta, ranks, info) as packed buffers; theta of problem k
+    starts at sum(sizes[:k]).
+    """
+    bs = len(sizes)
+    U1 = torch.empty_like(a1)
+    U2 = torch.empty_like(a1)
+    V1 = torch.empty_like(a1)
+    th = torch.empty(sum(sizes), dtype=torch.float64, device=a1.device)
+    nh = (C.c_int * bs)(*sizes)
+    oh = (C.c_longlong * bs)(*offs)
+    rk = (C.c_int * bs)()
+    o = default_opts(rank_mode=rank_mode, **opts)
+    info = Info()
+    h = handle(a1.device.index)
+    st = _lib().zcsd_dcsd_batched(h, bs, nh, oh, _ptr(a1), _ptr(a2), _ptr(U1), _ptr(U2), _ptr(V1),
+                                  _ptr(th), rk, C.byref(o), C.byref(info))
+    _check(st, "zcsd_dcsd_batched")
+    return U1, U2, V1, th, list(rk), info.as_dict()
+
+
+def csd_batched(A1s, A2s, rank_mode="auto", **opts):
+    """Batched CSD of lists of (n_k, n_k) pairs: list of (U1, U2, V1, theta, rank)."""
+    if len(A1s) != len(A2s) or not A1s:
+        raise ValueError("csd_batched: need equal, non-empty lists")
+    for a, b in zip(A1s, A2s):
+        if a.shape != b.shape or a.dim() != 2 or a.shape[0] != a.shape[1]:
+            raise ValueError("csd_batched: every A1[k], A2[k] must be n_k x n_k")
+    a1, sizes, offs = pack_ragged(A1s)
+    a2, _, _ = pack_ragged(A2s)
+    U1, U2, V1, th, ranks, info = csd_batched_packed(a1, a2, sizes, offs, rank_mode=rank_mode, **opts)
+    u1, u2, v1 = unpack_ragged(U1, sizes, offs), unpack_ragged(U2, sizes, offs), unpack_ragged(V1, sizes, offs)
+    out, t0 = [], 0
+    for k, n in enumerate(sizes):
+        out.append((u1[k], u2[k], v1[k], th[t0:t0 + n], ranks[k]))
+        t0 += n
+    return out

@@ -135,7 +135,8 @@ def batched_leg(count, sample, seed=5):
 
 
 def backward_leg(count=64, n=512, seed=6):
-    """Forward + hand-written backward of 64 CSDs at n = 512 (uniform angles)."""
+    """Forward (one batched call) + hand-written backward of 64 CSDs at n = 512
+    (uniform angles)."""
     import numpy as np
     import torch
     from paper_1804_09002_amd import workloads as WL
@@ -150,9 +151,13 @@ def backward_leg(count=64, n=512, seed=6):
     G1 = torch.tensor(rng.standard_normal((count, n, n)), device="cuda:0")
     G2 = torch.tensor(rng.standard_normal((count, n, n)), device="cuda:0")
 
-    def fwd():
-        outs = [zcsd.csd(A1s[b], A2s[b]) for b in range(count)]
-        return [torch.stack([o[k] for o in outs]) for k in range(4)]
+    a1, sizes, offs = zcsd.pack_ragged(A1s)
+    a2, _, _ = zcsd.pack_ragged(A2s)
+
+    def fwd():  # one batched call; the packed outputs are (count, n, n) column-major blocks
+        U1, U2, V1, th, ranks, info = zcsd.csd_batched_packed(a1, a2, sizes, offs)
+        cm = lambda X: X.view(count, n, n).transpose(1, 2)
+        return cm(U1), cm(U2), cm(V1), th.view(count, n)
 
     U1, U2, V1, th = fwd()
     zcsd.csd_backward(U1, U2, V1, th, g, G1, G2)

@@ -194,7 +194,7 @@ void chol_inv_batched(int batch, int n, double* A, long long lda, long long sA, 
 void trtri_upper_batched(int batch, int n, const double* R, long long ldr, long long sR, double* Ri,
                          long long ldi, long long sI, Arena& ar, hipStream_t s) {
   if (batch <= 0 || n <= 0) return;
-  for (int b = 0; b < batch; ++b) set_identity(1, n, n, 0.0, Ri + b * sI, ldi, 0, s);
+  set_identity(batch, n, n, 0.0, Ri, ldi, sI, s);
   const int nblk = (n + CH_BASE - 1) / CH_BASE;
   hipLaunchKernelGGL(trtri_base_kernel, dim3(nblk, batch), dim3(CH_NT), 0, s, n, R, ldr, sR, Ri,
                      ldi, sI);

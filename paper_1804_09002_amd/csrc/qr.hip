@@ -195,27 +195,62 @@ QRWork qr_work_alloc(Arena& ar, QRShape shape, int batch, int m, int n, int nb) 
   QRWork wk;
   wk.nb = nb;
   wk.K = (n + nb - 1) / nb;
-  wk.ldv = (shape == QRShape::General) ? m : (n + nb);
-  wk.sV = (long long)wk.K * wk.ldv * nb;
+  wk.ar = &ar;
+  // two-level blocking when every inner panel takes the TSQR path (tallest
+  // panel: m rows for General, n + nb for Stacked) and there are several panels
+  constexpr int NBO = 128;
+  const int hmax = (shape == QRShape::General) ? m : n + nb;
+  if (nb == 32 && n > nb && tsqr_panel_fits(hmax, nb)) {
+    wk.nbo = NBO;
+    wk.Ko = (n + NBO - 1) / NBO;
+  }
+  const int wcols = wk.nbo ? wk.nbo : nb;
+  const int nblk = wk.nbo ? wk.Ko : wk.K;
+  wk.ldv = (shape == QRShape::General) ? m : (n + wcols);
+  wk.sV = (long long)nblk * wk.ldv * wcols;
   wk.sT = (long long)wk.K * nb * nb;
   wk.V = ar.dalloc((size_t)batch * wk.sV);
   wk.T = ar.dalloc((size_t)batch * wk.sT);
-  wk.sW = (long long)nb * n;
+  wk.sW = (long long)wcols * n;
   wk.W = ar.dalloc((size_t)batch * wk.sW);
   wk.W2 = ar.dalloc((size_t)batch * wk.sW);
   if (nb == 32) wk.ts = tsqr_scratch_alloc(ar, batch);
-  wk.ws_elems = (size_t)8 * batch * nb * n;
+  wk.ws_elems = (size_t)8 * batch * wcols * n;
   wk.ws = ar.dalloc(wk.ws_elems);
+  if (wk.nbo) {
+    wk.sTo = (long long)wk.Ko * NBO * NBO;
+    wk.To = ar.dalloc((size_t)batch * wk.sTo);
+    wk.sTin = (long long)(NBO / nb) * nb * nb;
+    wk.Tin = ar.dalloc((size_t)batch * wk.sTin);
+    wk.sG = (long long)NBO * NBO;
+    wk.G = ar.dalloc((size_t)batch * wk.sG);
+    wk.Ginv = ar.dalloc((size_t)batch * wk.sG);
+  }
   return wk;
+}
+
+// Tinv_b = striu(G_b) + diag(G_b) / 2 (w x w, ld NBO); zero beyond w
+__global__ void ut_tinv_kernel(int w, int ld, const double* __restrict__ G, long long sG, double* Ti) {
+  const long long b = blockIdx.y;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < ld * ld; e += gridDim.x * blockDim.x) {
+    const int i = e % ld, j = e / ld;
+    double v = 0.0;
+    if (i < w && j < w) {
+      const double g = G[b * sG + i + (long long)j * ld];
+      v = (i < j) ? g : ((i == j) ? 0.5 * g : 0.0);
+    }
+    Ti[b * sG + e] = v;
+  }
 }
 
 // C <- (I - V T' V^T) C on the panel's row segments, columns [col0, col0 + nc);
 // T' = T^T when transT (apply Q^T), T' = T otherwise (apply Q).
 static void apply_block_reflector(int batch, double* M, long long ldm, long long sM, int col0,
                                   int nc, int r1a, int r1b, int r2a, int r2b, int w,
-                                  const double* V, long long ldv, long long sV, const double* T,
-                                  long long sT, int nbT, double* W, double* W2, long long sW,
-                                  bool transT, double* ws, size_t ws_elems, hipStream_t s) {
+                                  const double* V, const double* V2, long long ldv, long long sV,
+                                  const double* T, long long sT, int nbT, double* W, double* W2,
+                                  long long sW, bool transT, double* ws, size_t ws_elems,
+                                  hipStream_t s) {
   if (nc <= 0 || w <= 0) return;
   const int h1 = r1b - r1a, h2 = r2b - r2a;
   GemmBatch g;
@@ -231,7 +266,7 @@ static void apply_block_reflector(int batch, double* M, long long ldm, long long
   dgemm(g, s);
   if (h2 > 0) {
     g.k = h2;
-    g.A = V + h1; g.B = M + r2a + (long long)col0 * ldm;
+    g.A = V2; g.B = M + r2a + (long long)col0 * ldm;
     g.beta = 1.0;
     dgemm(g, s);
   }
@@ -257,15 +292,90 @@ static void apply_block_reflector(int batch, double* M, long long ldm, long long
   dgemm(u, s);
   if (h2 > 0) {
     u.m = h2;
-    u.A = V + h1;
+    u.A = V2;
     u.C = M + r2a + (long long)col0 * ldm;
     dgemm(u, s);
+  }
+}
+
+// Two-level blocked factorisation: inside an outer block of nbo columns the
+// inner panels are factored and applied to the rest of the block only; the
+// outer block's compact-WY factor follows from the Gram matrix of its vectors,
+// T^{-1} = striu(V^T V) + diag(V^T V) / 2 (the relation T^{-1} + T^{-T} = V^T V
+// of any orthogonal I - V T V^T with T upper triangular), and the trailing
+// columns get one update with inner dimension nbo, which reads and writes the
+// trailing matrix nbo / nb times less often than panel-by-panel updates.
+// In the outer block's V, the first segment's rows come first and the second
+// segment (Stacked) starts at row wo, so both segments are contiguous.
+static void geqrf_two_level(int batch, QRShape shape, int m, int n, double* M, long long ldm,
+                            long long sM, QRWork& wk, hipStream_t s) {
+  const int nb = wk.nb, NBO = wk.nbo;
+  for (int O = 0; O < wk.Ko; ++O) {
+    const int co = O * NBO, wo = std::min(NBO, n - co);
+    double* VO = wk.V + (long long)O * wk.ldv * NBO;
+    double* TO = wk.To + (long long)O * NBO * NBO;
+    const bool gen = shape == QRShape::General;
+    const int orows = gen ? (m - co) : (2 * wo + co);  // rows of VO in use
+    set_identity(batch, (int)wk.ldv, NBO, 0.0, VO, wk.ldv, wk.sV, s);
+    const int npan = (wo + nb - 1) / nb;
+    for (int kk = 0; kk < npan; ++kk) {
+      const int c0 = co + kk * nb, w = std::min(nb, n - c0);
+      int r1a, r1b, r2a, r2b;
+      if (gen) {
+        r1a = c0; r1b = m; r2a = r2b = 0;
+      } else {
+        r1a = c0; r1b = c0 + w; r2a = n; r2b = n + c0 + w;
+      }
+      const int off = c0 - co;
+      double* V1 = VO + off + (long long)off * wk.ldv;
+      double* V2 = VO + wo + (long long)off * wk.ldv;
+      const int vr2 = gen ? -1 : (wo - off);
+      double* Tk = wk.Tin + (long long)kk * nb * nb;
+      tsqr_panel(batch, M, ldm, sM, c0, w, r1a, r1b, r2a, r2b, V1, wk.ldv, wk.sV, vr2, Tk, wk.sTin,
+                 wk.ts, s);
+      const int col0 = c0 + w;
+      apply_block_reflector(batch, M, ldm, sM, col0, co + wo - col0, r1a, r1b, r2a, r2b, w, V1, V2,
+                            wk.ldv, wk.sV, Tk, wk.sTin, nb, wk.W, wk.W2, wk.sW, /*transT=*/true,
+                            wk.ws, wk.ws_elems, s);
+    }
+    // outer compact-WY factor from G = VO^T VO
+    {
+      GemmBatch g;
+      g.batch = batch;
+      g.transA = 1;
+      g.m = wo; g.n = wo; g.k = orows;
+      g.A = VO; g.lda = wk.ldv; g.sA = wk.sV;
+      g.B = VO; g.ldb = wk.ldv; g.sB = wk.sV;
+      g.C = wk.G; g.ldc = NBO; g.sC = wk.sG;
+      g.ws = wk.ws; g.ws_elems = wk.ws_elems;
+      dgemm(g, s);
+      hipLaunchKernelGGL(ut_tinv_kernel, dim3((NBO * NBO + 255) / 256, batch), dim3(256), 0, s, wo,
+                         NBO, wk.G, wk.sG, wk.Ginv);
+      ZCSD_CHECK_LAUNCH();
+      trtri_upper_batched(batch, wo, wk.Ginv, NBO, wk.sG, TO, NBO, wk.sTo, *wk.ar, s);
+    }
+    const int col0 = co + wo;
+    if (col0 < n) {
+      int r1a, r1b, r2a, r2b;
+      if (gen) {
+        r1a = co; r1b = m; r2a = r2b = 0;
+      } else {
+        r1a = co; r1b = co + wo; r2a = n; r2b = n + co + wo;
+      }
+      apply_block_reflector(batch, M, ldm, sM, col0, n - col0, r1a, r1b, r2a, r2b, wo, VO, VO + wo,
+                            wk.ldv, wk.sV, TO, wk.sTo, NBO, wk.W, wk.W2, wk.sW, /*transT=*/true,
+                            wk.ws, wk.ws_elems, s);
+    }
   }
 }
 
 void geqrf_batched(int batch, QRShape shape, int m, int n, double* M, long long ldm, long long sM,
                    QRWork& wk, hipStream_t s) {
   if (batch <= 0 || n <= 0) return;
+  if (wk.nbo) {
+    geqrf_two_level(batch, shape, m, n, M, ldm, sM, wk, s);
+    return;
+  }
   const int nb = wk.nb;
   for (int k = 0; k < wk.K; ++k) {
     int c0, w, r1a, r1b, r2a, r2b;
@@ -275,7 +385,8 @@ void geqrf_batched(int batch, QRShape shape, int m, int n, double* M, long long 
     const double hh = (double)(r1b - r1a) + (r2b - r2a);
     // a panel is either the three TSQR kernels or the one-workgroup kernel
     if (nb == 32 && wk.ts.Rstack && tsqr_panel_fits((int)hh, w)) {
-      tsqr_panel(batch, M, ldm, sM, c0, w, r1a, r1b, r2a, r2b, Vk, wk.ldv, wk.sV, Tk, wk.sT, wk.ts, s);
+      tsqr_panel(batch, M, ldm, sM, c0, w, r1a, r1b, r2a, r2b, Vk, wk.ldv, wk.sV, -1, Tk, wk.sT,
+                 wk.ts, s);
     } else {
       ProfScope prof("qr_panel", s, batch * 2.0 * hh * w * w, batch * 8.0 * 2.0 * hh * w);
       if (nb == 32)
@@ -289,8 +400,10 @@ void geqrf_batched(int batch, QRShape shape, int m, int n, double* M, long long 
       ZCSD_CHECK_LAUNCH();
     }
     const int col0 = c0 + w;
-    apply_block_reflector(batch, M, ldm, sM, col0, n - col0, r1a, r1b, r2a, r2b, w, Vk, wk.ldv,
-                          wk.sV, Tk, wk.sT, nb, wk.W, wk.W2, wk.sW, /*transT=*/true, wk.ws, wk.ws_elems, s);
+    const int h1 = r1b - r1a;
+    apply_block_reflector(batch, M, ldm, sM, col0, n - col0, r1a, r1b, r2a, r2b, w, Vk, Vk + h1,
+                          wk.ldv, wk.sV, Tk, wk.sT, nb, wk.W, wk.W2, wk.sW, /*transT=*/true, wk.ws,
+                          wk.ws_elems, s);
   }
 }
 
@@ -298,14 +411,34 @@ void orgqr_batched(int batch, QRShape shape, int m, int n, double* Q, long long 
                    const double* d_scale, const QRWork& wk, hipStream_t s) {
   if (batch <= 0 || n <= 0) return;
   set_identity_scaled(batch, m, n, d_scale, 1.0, Q, ldq, sQ, s);
+  if (wk.nbo) {
+    const int NBO = wk.nbo;
+    for (int O = wk.Ko - 1; O >= 0; --O) {
+      const int co = O * NBO, wo = std::min(NBO, n - co);
+      const double* VO = wk.V + (long long)O * wk.ldv * NBO;
+      const double* TO = wk.To + (long long)O * NBO * NBO;
+      int r1a, r1b, r2a, r2b;
+      if (shape == QRShape::General) {
+        r1a = co; r1b = m; r2a = r2b = 0;
+      } else {
+        r1a = co; r1b = co + wo; r2a = n; r2b = n + co + wo;
+      }
+      apply_block_reflector(batch, Q, ldq, sQ, co, n - co, r1a, r1b, r2a, r2b, wo, VO, VO + wo,
+                            wk.ldv, wk.sV, TO, wk.sTo, NBO, wk.W, wk.W2, wk.sW, /*transT=*/false,
+                            wk.ws, wk.ws_elems, s);
+    }
+    return;
+  }
   const int nb = wk.nb;
   for (int k = wk.K - 1; k >= 0; --k) {
     int c0, w, r1a, r1b, r2a, r2b;
     panel_segments(shape, m, n, nb, k, &c0, &w, &r1a, &r1b, &r2a, &r2b);
     const double* Vk = wk.V + (long long)k * wk.ldv * nb;
     const double* Tk = wk.T + (long long)k * nb * nb;
-    apply_block_reflector(batch, Q, ldq, sQ, c0, n - c0, r1a, r1b, r2a, r2b, w, Vk, wk.ldv,
-                          wk.sV, Tk, wk.sT, nb, wk.W, wk.W2, wk.sW, /*transT=*/false, wk.ws, wk.ws_elems, s);
+    const int h1 = r1b - r1a;
+    apply_block_reflector(batch, Q, ldq, sQ, c0, n - c0, r1a, r1b, r2a, r2b, w, Vk, Vk + h1, wk.ldv,
+                          wk.sV, Tk, wk.sT, nb, wk.W, wk.W2, wk.sW, /*transT=*/false, wk.ws,
+                          wk.ws_elems, s);
   }
 }
 

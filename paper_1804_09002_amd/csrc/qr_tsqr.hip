@@ -39,6 +39,8 @@ constexpr int TS_TREE_RPT = (TS_PMAX * TS_W + TS_NT - 1) / TS_NT;  // rows per t
 __device__ __forceinline__ int ts_phys(int i, int h1, int r1a, int r2a) {
   return i < h1 ? r1a + i : r2a + (i - h1);
 }
+// logical row -> row of V (the second segment may start at row vr2 of V)
+__device__ __forceinline__ int ts_vrow(int i, int h1, int vr2) { return i < h1 ? i : vr2 + (i - h1); }
 
 // Cross-lane moves of doubles (two 32-bit halves).
 template <int CTRL>
@@ -213,7 +215,8 @@ __device__ void reg_householder(double (&a)[RPT][TS_W], int rows, int w, double 
 // A: local QR of every row block
 __global__ __launch_bounds__(TS_NT) void tsqr_local_kernel(
     const double* M, long long ldm, long long sM, int c0, int w, int h1, int r1a, int r2a, int h,
-    int P, double* V, long long ldv, long long sV, double* Tloc, double* Rstack, long long sScr) {
+    int P, double* V, long long ldv, long long sV, int vr2, double* Tloc, double* Rstack,
+    long long sScr) {
   __shared__ double red[4 * TS_W], rowb[2 * TS_W], tot[TS_W];
   __shared__ double Ts[TS_W][TS_W1];
   const int p = blockIdx.x;
@@ -236,7 +239,8 @@ __global__ __launch_bounds__(TS_NT) void tsqr_local_kernel(
   if (tid < rows) {
 #pragma unroll
     for (int j = 0; j < TS_W; ++j)
-      if (j < w) V[(i0 + tid) + (long long)j * ldv] = (tid < j) ? 0.0 : ((tid == j) ? 1.0 : a[0][j]);
+      if (j < w)
+        V[ts_vrow(i0 + tid, h1, vr2) + (long long)j * ldv] = (tid < j) ? 0.0 : ((tid == j) ? 1.0 : a[0][j]);
   }
   const int ldr = P * TS_W;
   if (tid < w) {
@@ -254,7 +258,7 @@ __global__ __launch_bounds__(TS_NT) void tsqr_local_kernel(
 // pieces (w x w work in LDS).
 __global__ __launch_bounds__(TS_NT) void tsqr_tree_kernel(
     double* M, long long ldm, long long sM, int c0, int w, int h1, int r1a, int r2a, int P,
-    const double* V, long long ldv, long long sV, const double* Tloc, const double* Rstack,
+    const double* V, long long ldv, long long sV, int vr2, const double* Tloc, const double* Rstack,
     double* Qtop, double* Uo, double* Lo, double* So, long long sScr, double* Tfin, long long sT) {
   __shared__ double red[4 * TS_W], rowb[2 * TS_W], tot[TS_W];
   __shared__ double Ts[TS_W][TS_W1];  // T_top
@@ -298,7 +302,9 @@ __global__ __launch_bounds__(TS_NT) void tsqr_tree_kernel(
   }
   for (int e = tid; e < TS_W * TS_W; e += TS_NT) {
     const int i = e & (TS_W - 1), j = e / TS_W;
-    Y0[i][j] = (i < w && j < w) ? ((i < j) ? 0.0 : ((i == j) ? 1.0 : V[i + (long long)j * ldv])) : 0.0;
+    Y0[i][j] = (i < w && j < w)
+                   ? ((i < j) ? 0.0 : ((i == j) ? 1.0 : V[ts_vrow(i, h1, vr2) + (long long)j * ldv]))
+                   : 0.0;
     T0s[i][j] = Tloc[e];  // zero beyond w (written so by the local factorisation)
     Q0[i][j] = 0.0;
   }
@@ -453,7 +459,7 @@ __global__ __launch_bounds__(TS_NT) void tsqr_tree_kernel(
 // block; y stays in registers and v is produced one column at a time.
 __global__ __launch_bounds__(TS_NT) void tsqr_expand_kernel(
     double* M, long long ldm, long long sM, int c0, int w, int h1, int r1a, int r2a, int h, int P,
-    double* V, long long ldv, long long sV, const double* Tloc, const double* Qtop,
+    double* V, long long ldv, long long sV, int vr2, const double* Tloc, const double* Qtop,
     const double* Uinv, const double* Lo, long long sScr) {
   __shared__ double Qt[TS_W][TS_W1];
   __shared__ double Us[TS_W][TS_W1];  // U^{-1}
@@ -488,7 +494,7 @@ __global__ __launch_bounds__(TS_NT) void tsqr_expand_kernel(
     double s = 0.0, s3 = 0.0;
     if (i < w && j < w) {
       for (int q = i; q < wy; ++q)
-        s = fma((q == i) ? 1.0 : V[(i0 + q) + (long long)i * ldv], Qt[q][j], s);
+        s = fma((q == i) ? 1.0 : V[ts_vrow(i0 + q, h1, vr2) + (long long)i * ldv], Qt[q][j], s);
       for (int q = 0; q <= j; ++q) s3 = fma(Qt[i][q], Us[q][j], s3);
     }
     M1[i][j] = s;
@@ -515,18 +521,19 @@ __global__ __launch_bounds__(TS_NT) void tsqr_expand_kernel(
   if (tid < rows) {
     const int i = tid;
     const int gi = i0 + i;
+    const long long vi = ts_vrow(gi, h1, vr2);
     if (p == 0 && i < w) {
-      for (int j = 0; j < w; ++j) V[gi + (long long)j * ldv] = Lo[i + j * TS_W];
+      for (int j = 0; j < w; ++j) V[vi + (long long)j * ldv] = Lo[i + j * TS_W];
     } else {
       double y[TS_W];
 #pragma unroll
-      for (int k = 0; k < TS_W; ++k) y[k] = (k < w) ? V[gi + (long long)k * ldv] : 0.0;
+      for (int k = 0; k < TS_W; ++k) y[k] = (k < w) ? V[vi + (long long)k * ldv] : 0.0;
 #pragma unroll 2
       for (int j = 0; j < w; ++j) {
         double v = (i < TS_W) ? Q3[i][j] : 0.0;
 #pragma unroll
         for (int k = 0; k < TS_W; ++k) v = fma(-y[k], M3[k][j], v);
-        V[gi + (long long)j * ldv] = v;
+        V[vi + (long long)j * ldv] = v;
       }
     }
     if (gi >= w) {
@@ -539,9 +546,10 @@ __global__ __launch_bounds__(TS_NT) void tsqr_expand_kernel(
 bool tsqr_panel_fits(int h, int w) { return w <= TS_W && w >= 1 && h >= w && h <= TS_PMAX * TS_MB; }
 
 void tsqr_panel(int batch, double* M, long long ldm, long long sM, int c0, int w, int r1a, int r1b,
-                int r2a, int r2b, double* V, long long ldv, long long sV, double* T, long long sT,
-                const TsqrScratch& sc, hipStream_t s) {
+                int r2a, int r2b, double* V, long long ldv, long long sV, int vr2, double* T,
+                long long sT, const TsqrScratch& sc, hipStream_t s) {
   const int h1 = r1b - r1a, h2 = r2b - r2a, h = h1 + h2;
+  if (vr2 < 0) vr2 = h1;
   if (!tsqr_panel_fits(h, w)) throw ArgError("tsqr_panel: panel too tall");
   const int P = (h + TS_MB - 1) / TS_MB;
   const double ww = (double)w * w;
@@ -549,21 +557,21 @@ void tsqr_panel(int batch, double* M, long long ldm, long long sM, int c0, int w
     ProfScope prof("tsqr_local", s, batch * (2.0 * h * ww - P * 2.0 * ww * w / 3.0),
                    batch * 8.0 * 2.0 * h * w);
     hipLaunchKernelGGL(tsqr_local_kernel, dim3(P, batch), dim3(TS_NT), 0, s, M, ldm, sM, c0, w, h1,
-                       r1a, r2a, h, P, V, ldv, sV, sc.Tloc, sc.Rstack, sc.stride);
+                       r1a, r2a, h, P, V, ldv, sV, vr2, sc.Tloc, sc.Rstack, sc.stride);
     ZCSD_CHECK_LAUNCH();
   }
   {
     ProfScope prof("tsqr_tree", s, batch * (4.0 * P * ww * w + 4.0 * ww * w),
                    batch * 8.0 * 2.0 * P * ww);
     hipLaunchKernelGGL(tsqr_tree_kernel, dim3(batch), dim3(TS_NT), 0, s, M, ldm, sM, c0, w, h1, r1a,
-                       r2a, P, V, ldv, sV, sc.Tloc, sc.Rstack, sc.Qtop, sc.U, sc.L, sc.S, sc.stride,
-                       T, sT);
+                       r2a, P, V, ldv, sV, vr2, sc.Tloc, sc.Rstack, sc.Qtop, sc.U, sc.L, sc.S,
+                       sc.stride, T, sT);
     ZCSD_CHECK_LAUNCH();
   }
   {
     ProfScope prof("tsqr_expand", s, batch * 3.0 * h * ww, batch * 8.0 * 3.0 * h * w);
     hipLaunchKernelGGL(tsqr_expand_kernel, dim3(P, batch), dim3(TS_NT), 0, s, M, ldm, sM, c0, w, h1,
-                       r1a, r2a, h, P, V, ldv, sV, sc.Tloc, sc.Qtop, sc.U, sc.L, sc.stride);
+                       r1a, r2a, h, P, V, ldv, sV, vr2, sc.Tloc, sc.Qtop, sc.U, sc.L, sc.stride);
     ZCSD_CHECK_LAUNCH();
   }
 }

@@ -14,9 +14,17 @@ struct QRWork {
   long long ldv = 0;
   double* V = nullptr;  long long sV = 0;   // K panels of ldv x nb per problem
   double* T = nullptr;  long long sT = 0;   // K blocks of nb x nb per problem
-  double* W = nullptr;  double* W2 = nullptr; long long sW = 0;  // nb x n scratch per problem
+  double* W = nullptr;  double* W2 = nullptr; long long sW = 0;  // nbo x n scratch per problem
   TsqrScratch ts;                                                 // tall-panel scratch
   double* ws = nullptr; size_t ws_elems = 0;                      // split-K workspace
+  // two-level blocking (nbo > 0): outer blocks of nbo columns, each made of
+  // nbo / nb inner panels; V holds Ko outer blocks of ldv x nbo, To their
+  // nbo x nbo compact-WY factors, Tin the inner factors of the current block
+  int nbo = 0, Ko = 0;
+  double* To = nullptr; long long sTo = 0;
+  double* Tin = nullptr; long long sTin = 0;
+  double* G = nullptr; double* Ginv = nullptr; long long sG = 0;
+  Arena* ar = nullptr;
 };
 
 QRWork qr_work_alloc(Arena& ar, QRShape shape, int batch, int m, int n, int nb);

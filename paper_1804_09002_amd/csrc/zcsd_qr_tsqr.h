@@ -21,9 +21,11 @@ bool tsqr_panel_fits(int h, int w);
 TsqrScratch tsqr_scratch_alloc(Arena& ar, int batch);
 // Same contract as the one-workgroup panel: reads the panel's rows (two
 // segments) of M, writes R into the top w logical rows and zeros below,
-// V (h x w, unit lower trapezoidal, ld ldv) and T (32 x 32, upper).
+// V (h x w, unit lower trapezoidal, ld ldv) and T (32 x 32, upper).  Logical
+// rows of the second segment go to rows vr2.. of V (vr2 < 0: right after the
+// first segment).
 void tsqr_panel(int batch, double* M, long long ldm, long long sM, int c0, int w, int r1a, int r1b,
-                int r2a, int r2b, double* V, long long ldv, long long sV, double* T, long long sT,
-                const TsqrScratch& sc, hipStream_t s);
+                int r2a, int r2b, double* V, long long ldv, long long sV, int vr2, double* T,
+                long long sT, const TsqrScratch& sc, hipStream_t s);
 
 }  // namespace zcsd

@@ -20,7 +20,34 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "n=4096 CSD time & % MFMA peak; mixed/batched vs plain FP64 at equal error"
-PEAKS = {"f64_mfma_tflops": 78.6, "hbm_gbs": 8000.0}
+PEAKS = {"f64_mfma_tflops": 78.6, "f64_vector_tflops": 78.6, "hbm_gbs": 8000.0}
+
+# HBM bytes per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this
+# workload, scaled by the same counters on a copy of known size (the summaries
+# with their commands are in profiles/).  A figure is reported only while the
+# kernel's source file still has the hash it had when the counters were taken.
+TRAFFIC = {
+    "tsqr_tree": {"bytes": 2828707.0, "src": "paper_1804_09002_amd/csrc/qr_tsqr.hip",
+                  "sha": "d849e46431637a1c", "summary": "profiles/tsqr_tree_kernel_csd4096_traffic.md"},
+    "dgemm_128x128_NN": {"bytes": 599176296.0, "src": "paper_1804_09002_amd/csrc/gemm.hip",
+                         "sha": "65773ad0ff30ed88",
+                         "summary": "profiles/dgemm_kernel_128x128_NN_csd4096_traffic.md"},
+}
+# kernels whose time is set by a dependent chain of small steps in one
+# workgroup per problem, not by the matrix cores: their roofline is the FP64
+# vector rate (256 CUs x 4 SIMDs x 16 lanes x 2 flops x 2.4 GHz = 78.6 TFLOP/s)
+ALU_KERNELS = ("tsqr_local", "tsqr_tree", "tsqr_expand", "qr_panel")
+
+
+def _traffic(kernel):
+    import hashlib
+    t = TRAFFIC.get(kernel)
+    if not t:
+        return None
+    with open(os.path.join(ROOT, t["src"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest()[:16] != t["sha"]:
+            return None
+    return t["bytes"]
 
 
 def parse():
@@ -242,14 +269,15 @@ def main():
         per_launch_flops = dstat["flops"] / dstat["launches"]
         avg_s = dstat["ms"] * 1e-3 / dstat["launches"]
         ach = per_launch_flops / avg_s / 1e12
-        roof = {"kernel": dominant, "bound": "mfma", "achieved": round(ach, 3),
-                "peak": PEAKS["f64_mfma_tflops"], "unit": "TFLOP/s",
-                "frac": round(ach / PEAKS["f64_mfma_tflops"], 4), "traffic": None,
+        alu = dominant in ALU_KERNELS
+        peak = PEAKS["f64_vector_tflops"] if alu else PEAKS["f64_mfma_tflops"]
+        roof = {"kernel": dominant, "bound": "alu" if alu else "mfma", "achieved": round(ach, 4),
+                "peak": peak, "unit": "TFLOP/s", "frac": round(ach / peak, 5),
+                "traffic": _traffic(dominant),
                 "launches_per_step": dstat["launches"] / args.steps,
                 "avg_launch_us": round(avg_s * 1e6, 3),
-                "algorithmic_flops_per_launch": per_launch_flops}
-        if dominant == "qr_panel":
-            roof["bound"] = "alu"
+                "algorithmic_flops_per_launch": per_launch_flops,
+                "algorithmic_bytes_per_launch": dstat["bytes"] / dstat["launches"]}
 
     cpu = None
     if not args.no_cpu:

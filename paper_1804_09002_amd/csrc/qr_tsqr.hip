@@ -123,81 +123,91 @@ __device__ __forceinline__ double wave_sum32(double (&x)[TS_W]) {
 // column t of T, T(0:t, t) = -tau T(0:t, 0:t) Y(:, 0:t)^T v (k < t).
 // On return the rows hold R (upper, diagonal beta) and the vectors below the
 // diagonal (unit diagonal implicit), and T is in Ts.
-// LDS: red[4 * 32], rowb[2 * 32] (double-buffered pivot row), tot[32].
+// One barrier per step: the per-wave partial sums and the pivot row go to
+// double-buffered LDS (a buffer is rewritten two steps later, after every wave
+// has passed the next barrier), each lane reads back the sums of its own
+// column, and the pivot scalars and the update coefficients are broadcast with
+// readlane.  LDS: red[2 * 4 * 32], rowb[2 * 32], zb[32].
 template <int t, int RPT>
 __device__ __forceinline__ void reg_householder_step(double (&a)[RPT][TS_W], int rows,
                                                      double (*Ts)[TS_W1], double* red, double* rowb,
-                                                     double* tot) {
+                                                     double* zb) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    double x[TS_W];
+  constexpr int buf = t & 1;
+  double* rb = red + buf * 4 * TS_W;     // [wave][j] partial sums of this step
+  double* pr = rowb + buf * TS_W;        // pivot row a(t, :)
+  double x[TS_W];
 #pragma unroll
-    for (int j = 0; j < TS_W; ++j) x[j] = 0.0;
+  for (int j = 0; j < TS_W; ++j) x[j] = 0.0;
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-      const int i = tid + TS_NT * r;
-      if (i >= t && i < rows) {
-        const double ait = a[r][t];
+  for (int r = 0; r < RPT; ++r) {
+    const int i = tid + TS_NT * r;
+    if (i >= t && i < rows) {
+      const double ait = a[r][t];
 #pragma unroll
-        for (int j = 0; j < TS_W; ++j) x[j] = fma(ait, a[r][j], x[j]);
-      }
-      if (i == t) {
-#pragma unroll
-        for (int j = 0; j < TS_W; ++j) rowb[(t & 1) * TS_W + j] = a[r][j];
-      }
+      for (int j = 0; j < TS_W; ++j) x[j] = fma(ait, a[r][j], x[j]);
     }
-    const double sj = wave_sum32(x);
-    if ((lane & 1) == 0) red[wave * TS_W + ((lane >> 1) & 31)] = sj;
-    __syncthreads();
-    if (tid < TS_W) tot[tid] = (red[tid] + red[TS_W + tid]) + (red[2 * TS_W + tid] + red[3 * TS_W + tid]);
-    __syncthreads();
-    const double* rt = rowb + (t & 1) * TS_W;
-    const double dt = tot[t], alpha = rt[t];
-    double tau = 0.0, beta = 0.0, scal = 0.0;
-    if (dt > 0.0) {
-      const double nrm = sqrt(dt);
-      beta = alpha >= 0.0 ? -nrm : nrm;
-      tau = (beta - alpha) / beta;
-      scal = 1.0 / (alpha - beta);
+    if (i == t) {
+#pragma unroll
+      for (int j = 0; j < TS_W; ++j) pr[j] = a[r][j];
     }
-    double wv[TS_W];  // v^T a_j: the update for j > t, y_j^T v for j < t
+  }
+  const double sj = wave_sum32(x);
+  const int jl = (lane >> 1) & 31;  // the column this lane's sum belongs to
+  if ((lane & 1) == 0) rb[wave * TS_W + jl] = sj;
+  __syncthreads();
+  // d_j and a(t, j) for this lane's column; the pivot's through readlane
+  const double dj = (rb[jl] + rb[TS_W + jl]) + (rb[2 * TS_W + jl] + rb[3 * TS_W + jl]);
+  const double atj = pr[jl];
+  const double dt = readlane_f64(dj, 2 * t), alpha = readlane_f64(atj, 2 * t);
+  double tau = 0.0, beta = 0.0, scal = 0.0;
+  if (dt > 0.0) {
+    const double nrm = sqrt(dt);
+    beta = alpha >= 0.0 ? -nrm : nrm;
+    tau = (beta - alpha) / beta;
+    scal = 1.0 / (alpha - beta);
+  }
+  // v^T a_j (j > t: the update) and y_j^T v (j < t: the T column), this lane's j
+  const double wl = scal * (dj - beta * atj);
+  double tv[RPT];
 #pragma unroll
-    for (int j = 0; j < TS_W; ++j) wv[j] = scal * (tot[j] - beta * rt[j]);
+  for (int r = 0; r < RPT; ++r) {
+    const int i = tid + TS_NT * r;
+    const double v = (i > t && i < rows) ? scal * a[r][t] : ((i == t) ? 1.0 : 0.0);
+    tv[r] = tau * v;
+    if (i > t && i < rows) a[r][t] = v;
+    else if (i == t) a[r][t] = beta;
+  }
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) {
-      const int i = tid + TS_NT * r;
-      if (i > t && i < rows) {
-        const double v = scal * a[r][t];
-        a[r][t] = v;
-        const double tv = tau * v;
+  for (int j = t + 1; j < TS_W; ++j) {
+    const double wj = readlane_f64(wl, 2 * j);
 #pragma unroll
-        for (int j = t + 1; j < TS_W; ++j) a[r][j] = fma(-tv, wv[j], a[r][j]);
-      } else if (i == t) {
-#pragma unroll
-        for (int j = t + 1; j < TS_W; ++j) a[r][j] = fma(-tau, wv[j], a[r][j]);
-        a[r][t] = beta;
-      }
-    }
-    // column t of T (rows of T are independent: no barrier needed before the
-    // next step, which only writes column t + 1)
-    if (tid < t) {
+    for (int r = 0; r < RPT; ++r) a[r][j] = fma(-tv[r], wj, a[r][j]);
+  }
+  // column t of T, by wave 0 (its even lanes hold every y_k^T v)
+  if (wave == 0) {
+    if ((lane & 1) == 0) zb[jl] = wl;
+    __builtin_amdgcn_wave_barrier();
+    if (lane < t) {
       double s = 0.0;
 #pragma unroll
-      for (int k = 0; k < t; ++k) s = fma(Ts[tid][k], wv[k], s);
-      Ts[tid][t] = -tau * s;
-    } else if (tid == t) {
+      for (int k = 0; k < t; ++k) s = fma(Ts[lane][k], zb[k], s);
+      Ts[lane][t] = -tau * s;
+    } else if (lane == t) {
       Ts[t][t] = tau;
     }
+  }
 }
 
 // the 32 steps, unrolled at compile time so that every register index is static
 template <int t, int RPT>
 __device__ __forceinline__ void reg_householder_steps(double (&a)[RPT][TS_W], int rows, int w,
                                                       double (*Ts)[TS_W1], double* red,
-                                                      double* rowb, double* tot) {
+                                                      double* rowb, double* zb) {
   if constexpr (t < TS_W) {
     if (t < w) {
-      reg_householder_step<t, RPT>(a, rows, Ts, red, rowb, tot);
-      reg_householder_steps<t + 1, RPT>(a, rows, w, Ts, red, rowb, tot);
+      reg_householder_step<t, RPT>(a, rows, Ts, red, rowb, zb);
+      reg_householder_steps<t + 1, RPT>(a, rows, w, Ts, red, rowb, zb);
     }
   }
 }
@@ -206,10 +216,10 @@ __device__ __forceinline__ void reg_householder_steps(double (&a)[RPT][TS_W], in
 // caller's next barrier.
 template <int RPT>
 __device__ void reg_householder(double (&a)[RPT][TS_W], int rows, int w, double (*Ts)[TS_W1],
-                                double* red, double* rowb, double* tot) {
+                                double* red, double* rowb, double* zb) {
   for (int e = threadIdx.x; e < TS_W * TS_W1; e += TS_NT) (&Ts[0][0])[e] = 0.0;
   __syncthreads();
-  reg_householder_steps<0, RPT>(a, rows, w, Ts, red, rowb, tot);
+  reg_householder_steps<0, RPT>(a, rows, w, Ts, red, rowb, zb);
 }
 // ---------------------------------------------------------------------------
 // A: local QR of every row block
@@ -217,7 +227,7 @@ __global__ __launch_bounds__(TS_NT) void tsqr_local_kernel(
     const double* M, long long ldm, long long sM, int c0, int w, int h1, int r1a, int r2a, int h,
     int P, double* V, long long ldv, long long sV, int vr2, double* Tloc, double* Rstack,
     long long sScr) {
-  __shared__ double red[4 * TS_W], rowb[2 * TS_W], tot[TS_W];
+  __shared__ double red[2 * 4 * TS_W], rowb[2 * TS_W], zb[TS_W];
   __shared__ double Ts[TS_W][TS_W1];
   const int p = blockIdx.x;
   const long long b = blockIdx.y;
@@ -233,7 +243,7 @@ __global__ __launch_bounds__(TS_NT) void tsqr_local_kernel(
     for (int j = 0; j < TS_W; ++j)
       a[0][j] = (tid < rows && j < w) ? M[pr + (long long)(c0 + j) * ldm] : 0.0;
   }
-  reg_householder<1>(a, rows, w, Ts, red, rowb, tot);
+  reg_householder<1>(a, rows, w, Ts, red, rowb, zb);
   // Y_p (unit lower trapezoidal) into V's rows, R_p (upper w x w, zero rows
   // beyond the block), T_p
   if (tid < rows) {
@@ -260,7 +270,7 @@ __global__ __launch_bounds__(TS_NT) void tsqr_tree_kernel(
     double* M, long long ldm, long long sM, int c0, int w, int h1, int r1a, int r2a, int P,
     const double* V, long long ldv, long long sV, int vr2, const double* Tloc, const double* Rstack,
     double* Qtop, double* Uo, double* Lo, double* So, long long sScr, double* Tfin, long long sT) {
-  __shared__ double red[4 * TS_W], rowb[2 * TS_W], tot[TS_W];
+  __shared__ double red[2 * 4 * TS_W], rowb[2 * TS_W], zb[TS_W];
   __shared__ double Ts[TS_W][TS_W1];  // T_top
   __shared__ double Yt[TS_W][TS_W1];  // Y_top(0:w, 0:w), then X2
   __shared__ double Z[TS_W][TS_W1];   // T_top Y_top(0:w, :)^T, then L1^{-T}
@@ -289,7 +299,7 @@ __global__ __launch_bounds__(TS_NT) void tsqr_tree_kernel(
 #pragma unroll
     for (int j = 0; j < TS_W; ++j) a[r][j] = (i < rows && j < w) ? Rstack[i + (long long)j * ldr] : 0.0;
   }
-  reg_householder<TS_TREE_RPT>(a, rows, w, Ts, red, rowb, tot);
+  reg_householder<TS_TREE_RPT>(a, rows, w, Ts, red, rowb, zb);
   // R_tsqr and Y_top(0:w, 0:w) from the first w rows (rows w..31 belong to the
   // next block: zero here), Y_0(0:w, 0:w) and T_0 of block 0
   if (tid < TS_W) {

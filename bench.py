@@ -290,8 +290,25 @@ def main():
 
     extra = None
     if not args.no_extra:
+        log("mixed-precision leg: n=4096")
+        zcsd.csd(A1, A2, prec="mixed_fp32")  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            mo = zcsd.csd(A1, A2, prec="mixed_fp32")
+        torch.cuda.synchronize()
+        ms_mixed = (time.perf_counter() - t0) * 1e3 / args.steps
+        macc = accuracy(A1, A2, mo[0], mo[1], mo[2], mo[3], theta_true)
+        mi = mo[4]
+        mixed = {"workload": f"csd_mixed_fp32_n{n}_uniform_angles", "ms_per_csd": round(ms_mixed, 3),
+                 "speedup_vs_fp64": round(ms_step / ms_mixed, 3), "accuracy": macc,
+                 "refine": {"iters": mi["refine_iters"], "clusters": mi["refine_clusters"],
+                            "max_cluster": mi["refine_max_cluster"], "offdiag": mi["refine_offdiag"]},
+                 "phases_ms": {"polar": mi["time_ms"][0], "B": mi["time_ms"][1],
+                               "eig": mi["time_ms"][2], "assembly": mi["time_ms"][3]}}
+        del mo
         log(f"batched leg: {args.batched_count} problems")
-        extra = {"batched": batched_leg(args.batched_count, args.single_sample)}
+        extra = {"mixed": mixed, "batched": batched_leg(args.batched_count, args.single_sample)}
         log("forward+backward leg: 64 x n=512")
         extra["backward"] = backward_leg()
 

@@ -40,6 +40,10 @@ typedef enum {
   ZCSD_ENOMEM = 6    /* device allocation failed */
 } zcsd_status;
 
+/* ZCSD_MIXED_FP32: the polar decompositions and B in FP64; Zolo-eig with its
+ * products on the FP32 matrix cores (FP64 storage and panels), then FP64
+ * refinement of V1 (iterative refinement of the eigenvectors and exact FP64
+ * re-solves of eigenvalue clusters) to the FP64 accuracy.  zcsd_dcsd only. */
 typedef enum { ZCSD_FP64 = 0, ZCSD_MIXED_FP32 = 1 } zcsd_precision;
 
 typedef enum {
@@ -74,6 +78,12 @@ typedef struct {
   double eig_coupling;     /* max over splits of ‖X‖_F, the eigenspace-basis coupling that the
                               subspace-iteration step of each split removes */
   int eig_full_refinements; /* splits whose step needed a second QR (‖X‖_F > 2^-27) */
+  int refine_iters;        /* mixed mode: FP64 eigenvector refinement steps taken */
+  int refine_clusters;     /* mixed mode: eigenvalue clusters re-solved in FP64 (largest: refine_max_cluster) */
+  int refine_max_cluster;
+  double refine_offdiag;   /* mixed mode: final ‖V1^T B V1 - diag‖_2 (power-iteration estimate) */
+  int refine_fallback;     /* mixed mode: 1 if the refinement did not reach the FP64 rounding
+                              floor and Zolo-eig was recomputed in FP64 */
   double time_ms[4];       /* polar, B, eig, assembly wall time (ms), measured with stream syncs */
 } zcsd_info;
 
@@ -202,6 +212,13 @@ zcsd_status zcsd_dgemm(zcsd_handle* handle, int transA, int transB, int m, int n
                        double alpha, const double* d_A, int lda, long long strideA,
                        const double* d_B, int ldb, long long strideB, double beta,
                        double* d_C, int ldc, long long strideC, int batch);
+/* The same product with A and B rounded to FP32 and FP32 accumulation on the
+ * FP32 matrix cores (v_mfma_f32_16x16x4f32), FP64 in and out: the products of
+ * the mixed-precision mode's Zolo-eig.  Same arguments and errors as zcsd_dgemm. */
+zcsd_status zcsd_dgemm_f32acc(zcsd_handle* handle, int transA, int transB, int m, int n, int k,
+                              double alpha, const double* d_A, int lda, long long strideA,
+                              const double* d_B, int ldb, long long strideB, double beta,
+                              double* d_C, int ldc, long long strideC, int batch);
 
 /*
  * Blocked Householder QR (the QR form of Zolo-pd, Sec. 5), batched in place.

@@ -99,6 +99,31 @@ zcsd_status zcsd_dgemm(zcsd_handle* handle, int transA, int transB, int m, int n
     dgemm(g, handle->stream);
   });
 }
+zcsd_status zcsd_dgemm_f32acc(zcsd_handle* handle, int transA, int transB, int m, int n, int k,
+                       double alpha, const double* A, int lda, long long strideA, const double* B,
+                       int ldb, long long strideB, double beta, double* C, int ldc,
+                       long long strideC, int batch) {
+  if (!handle) return ZCSD_EINVAL;
+  return guarded([&] {
+    ZCSD_REQUIRE(m >= 0 && n >= 0 && k >= 0 && batch >= 0, "dgemm_f32acc: negative size");
+    if (m == 0 || n == 0 || batch == 0) return;
+    ZCSD_REQUIRE(C && (k == 0 || (A && B)), "dgemm_f32acc: NULL pointer");
+    ZCSD_REQUIRE(ldc >= std::max(1, m), "dgemm_f32acc: ldc too small");
+    ZCSD_REQUIRE(k == 0 || (lda >= std::max(1, transA ? k : m) && ldb >= std::max(1, transB ? n : k)),
+                 "dgemm_f32acc: leading dimension too small");
+    ZCSD_HIP(hipSetDevice(handle->device));
+    GemmBatch g;
+    g.transA = transA != 0;
+    g.transB = transB != 0;
+    g.m = m; g.n = n; g.k = k;
+    g.A = A; g.lda = lda; g.sA = strideA;
+    g.B = B; g.ldb = ldb; g.sB = strideB;
+    g.C = C; g.ldc = ldc; g.sC = strideC;
+    g.alpha = alpha; g.beta = beta; g.batch = batch;
+    GemmLowpScope lowp(true);
+    dgemm(g, handle->stream);
+  });
+}
 
 }  // extern "C"
 

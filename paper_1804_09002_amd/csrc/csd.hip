@@ -83,6 +83,7 @@ struct CsdOut {
   int rank = 0;
   ZoloPdResult pd;
   ZoloEigResult eig;
+  EigRefineResult refine;
   double t_polar = 0, t_B = 0, t_eig = 0, t_asm = 0;
 };
 
@@ -174,7 +175,19 @@ static CsdOut csd_run(int n, const double* A1, long long lda1, const double* A2,
     ea.lam = lam;
     ea.n_leaf = o.n_leaf;
     ea.eps = o.eps; ea.tol = o.tol;
+    ea.lowp = o.prec == ZCSD_MIXED_FP32;
     out.eig = zolo_eig(ea, ar, s);
+    if (ea.lowp) {
+      const double bmax = std::max(std::fabs(ea.lo), std::fabs(ea.hi));
+      out.refine = eig_refine(n, B, n, V, lam, bmax * bmax, 8, ar, s);
+      if (!out.refine.converged) {
+        // the FP32 divide and conquer was too far off for the refinement: the
+        // FP64 eigendecomposition instead (the result keeps the FP64 accuracy)
+        ea.lowp = false;
+        out.eig = zolo_eig(ea, ar, s);
+        out.refine.fallback = true;
+      }
+    }
   }
   HostSync::sync(s);
   double t3 = now_ms();
@@ -295,6 +308,7 @@ extern "C" zcsd_status zcsd_dcsd(zcsd_handle* handle, int n, const double* d_A1,
     zcsd_default_opts(&o);
     if (opts) o = *opts;
     ZCSD_REQUIRE(o.r_override >= 0 && o.r_override <= ZOLO_RMAX, "csd: r_override out of range");
+    ZCSD_REQUIRE(o.prec == ZCSD_FP64 || o.prec == ZCSD_MIXED_FP32, "csd: unknown precision mode");
     ZCSD_REQUIRE(o.eps > 0.0 && o.eps < 1.0 && o.tol > 0.0, "csd: eps/tol out of range");
     ZCSD_REQUIRE(o.mu > 1.0 || o.rank_mode == ZCSD_RANK_FULL, "csd: mu must exceed 1");
     ZCSD_HIP(hipSetDevice(handle->device));
@@ -314,6 +328,11 @@ extern "C" zcsd_status zcsd_dcsd(zcsd_handle* handle, int n, const double* d_A1,
       info->eig_offblock = r.eig.max_offblock;
       info->eig_coupling = r.eig.max_coupling;
       info->eig_full_refinements = r.eig.full_refinements;
+      info->refine_iters = r.refine.iters;
+      info->refine_clusters = r.refine.clusters;
+      info->refine_max_cluster = r.refine.max_cluster;
+      info->refine_offdiag = r.refine.offdiag;
+      info->refine_fallback = r.refine.fallback ? 1 : 0;
       info->time_ms[0] = r.t_polar;
       info->time_ms[1] = r.t_B;
       info->time_ms[2] = r.t_eig;

@@ -391,6 +391,7 @@ extern "C" zcsd_status zcsd_dcsd_batched(zcsd_handle* handle, int batch, const i
     zcsd_default_opts(&o);
     if (opts) o = *opts;
     ZCSD_REQUIRE(o.r_override >= 0 && o.r_override <= ZOLO_RMAX, "csd_batched: r_override out of range");
+    ZCSD_REQUIRE(o.prec == ZCSD_FP64, "csd_batched: FP64 only");
     ZCSD_REQUIRE(o.eps > 0.0 && o.eps < 1.0 && o.tol > 0.0, "csd_batched: eps/tol out of range");
     ZCSD_REQUIRE(o.mu > 1.0 && o.mu < 3.0, "csd_batched: mu must lie in (1, 3)");
     std::vector<long long> toff(batch + 1, 0);

@@ -245,6 +245,9 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
   const int nleaf = std::max(1, std::min(a.n_leaf, 64));
   const long long nn = (long long)n * n;
   ArenaScope scope(ar);
+  // mixed mode: every product of the divide and conquer runs on the FP32 matrix
+  // cores; the caller refines the result in FP64
+  GemmLowpScope lowp_scope(a.lowp);
 
   // Frobenius norm of B (largest over the batch; for the off-block ratio)
   double bnorm2 = 0.0;
@@ -524,6 +527,9 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
       za.W = W; za.H = nullptr; za.X1 = nullptr;
       za.eps = a.eps; za.tol = a.tol;
       za.symmetric_input = true;
+      // the sign function stays FP64 in the mixed mode: its combines have inner
+      // dimension r n, where FP32 accumulation loses ~1e-5 relative accuracy
+      GemmFp64Scope fp64;
       ZoloPdResult zr = zolo_pd_batched(za, ar, s);
       res.max_r = std::max(res.max_r, zr.r);
     }
@@ -584,58 +590,60 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
     // in its orthogonality); when ||X||_F is not below 2^-27 the step is taken in
     // full instead, Q <- Q factor of the QR of P Q.
     int* d_np = upload(ar, npos, s);
-    double* PQ = ar.dalloc((size_t)ns * SS);
-    {
-      GemmBatch g;
-      g.batch = ns;
-      g.m = Ns; g.n = Ns; g.k = Ns;
-      g.A = W; g.lda = Ns; g.sA = SS;
-      g.B = Q; g.ldb = Ns; g.sB = SS;
-      g.C = PQ; g.ldc = Ns; g.sC = SS;
-      dgemm(g, s);
-      GemmBatch h = g;
-      h.transA = 1;
-      h.A = Q; h.B = PQ; h.C = Y;  // Z = Q^T (P Q) into the dead QR input
-      dgemm(h, s);
-    }
-    double xmax = 0.0;
-    {
-      double* d_x = ar.dalloc(ns);
-      SumsqRegion rg;
-      rg.nb = d_nbs;
-      rg.np = d_np;
-      rg.max_cols = Ns;
-      sumsq_region(ns, Y, Ns, SS, rg, d_x, ar, s);
-      std::vector<double> xs(ns);
-      d2h(xs.data(), d_x, ns * sizeof(double), s);
-      for (double v : xs) xmax = std::max(xmax, std::sqrt(v));
-    }
-    res.max_coupling = std::max(res.max_coupling, xmax);
-    double* T1;
-    if (xmax <= 0x1p-27) {
-      double* K = PQ;  // P Q is dead once Z is formed
-      hipLaunchKernelGGL(coupling_skew_kernel, grid2(SS, ns), dim3(256), 0, s, Ns, Y, K, d_nbs, d_np);
-      ZCSD_CHECK_LAUNCH();
-      double* Qn = W;  // P is dead too
-      copy_scale(ns, Ns, Ns, 1.0, Q, Ns, SS, Qn, Ns, SS, s);
-      GemmBatch g;
-      g.batch = ns;
-      g.m = Ns; g.n = Ns; g.k = Ns;
-      g.A = Q; g.lda = Ns; g.sA = SS;
-      g.B = K; g.ldb = Ns; g.sB = SS;
-      g.C = Qn; g.ldc = Ns; g.sC = SS;
-      g.beta = 1.0;
-      dgemm(g, s);
-      Q = Qn;
-      T1 = K;
-    } else {
-      ++res.full_refinements;
-      ArenaScope qs(ar);
-      QRWork wk = qr_work_alloc(ar, QRShape::General, ns, Ns, Ns, 32);
-      geqrf_batched(ns, QRShape::General, Ns, Ns, PQ, Ns, SS, wk, s);
-      orgqr_batched(ns, QRShape::General, Ns, Ns, Q, Ns, SS, nullptr, wk, s);
-      T1 = W;
-    }
+    double* T1 = W;  // W (P) is dead unless the subspace step below uses it
+    if (!a.lowp) {
+      double* PQ = ar.dalloc((size_t)ns * SS);
+      {
+        GemmBatch g;
+        g.batch = ns;
+        g.m = Ns; g.n = Ns; g.k = Ns;
+        g.A = W; g.lda = Ns; g.sA = SS;
+        g.B = Q; g.ldb = Ns; g.sB = SS;
+        g.C = PQ; g.ldc = Ns; g.sC = SS;
+        dgemm(g, s);
+        GemmBatch h = g;
+        h.transA = 1;
+        h.A = Q; h.B = PQ; h.C = Y;  // Z = Q^T (P Q) into the dead QR input
+        dgemm(h, s);
+      }
+      double xmax = 0.0;
+      {
+        double* d_x = ar.dalloc(ns);
+        SumsqRegion rg;
+        rg.nb = d_nbs;
+        rg.np = d_np;
+        rg.max_cols = Ns;
+        sumsq_region(ns, Y, Ns, SS, rg, d_x, ar, s);
+        std::vector<double> xs(ns);
+        d2h(xs.data(), d_x, ns * sizeof(double), s);
+        for (double v : xs) xmax = std::max(xmax, std::sqrt(v));
+      }
+      res.max_coupling = std::max(res.max_coupling, xmax);
+      if (xmax <= 0x1p-27) {
+        double* K = PQ;  // P Q is dead once Z is formed
+        hipLaunchKernelGGL(coupling_skew_kernel, grid2(SS, ns), dim3(256), 0, s, Ns, Y, K, d_nbs, d_np);
+        ZCSD_CHECK_LAUNCH();
+        double* Qn = W;  // P is dead too
+        copy_scale(ns, Ns, Ns, 1.0, Q, Ns, SS, Qn, Ns, SS, s);
+        GemmBatch g;
+        g.batch = ns;
+        g.m = Ns; g.n = Ns; g.k = Ns;
+        g.A = Q; g.lda = Ns; g.sA = SS;
+        g.B = K; g.ldb = Ns; g.sB = SS;
+        g.C = Qn; g.ldc = Ns; g.sC = SS;
+        g.beta = 1.0;
+        dgemm(g, s);
+        Q = Qn;
+        T1 = K;
+      } else {
+        ++res.full_refinements;
+        ArenaScope qs(ar);
+        QRWork wk = qr_work_alloc(ar, QRShape::General, ns, Ns, Ns, 32);
+        geqrf_batched(ns, QRShape::General, Ns, Ns, PQ, Ns, SS, wk, s);
+        orgqr_batched(ns, QRShape::General, Ns, Ns, Q, Ns, SS, nullptr, wk, s);
+        T1 = W;
+      }
+    }  // !a.lowp (in the mixed mode the FP64 refinement of the caller takes its place)
 
     // B' = Q^T B Q, V' = V Q
     double* Bq = Y;  // Z is dead

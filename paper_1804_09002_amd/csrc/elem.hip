@@ -212,6 +212,23 @@ void symmetrize(int batch, int n, double* X, long long ldx, long long sx, hipStr
   ZCSD_CHECK_LAUNCH();
 }
 
+__global__ void mirror_upper_kernel(int n, double* X, long long ldx, long long sx) {
+  const long long b = blockIdx.y;
+  const long long total = (long long)n * n;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n), j = (int)(e / n);
+    if (i > j) X[b * sx + i + (long long)j * ldx] = X[b * sx + j + (long long)i * ldx];
+  }
+}
+
+void mirror_upper(int batch, int n, double* X, long long ldx, long long sx, hipStream_t s) {
+  if (batch <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(mirror_upper_kernel, egrid((long long)n * n, batch), dim3(256), 0, s, n, X,
+                     ldx, sx);
+  ZCSD_CHECK_LAUNCH();
+}
+
 void sumsq_region(int batch, const double* X, long long ldx, long long sx, const SumsqRegion& r,
                   double* out, Arena& ar, hipStream_t s) {
   if (batch <= 0) return;

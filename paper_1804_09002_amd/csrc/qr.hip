@@ -338,8 +338,9 @@ static void geqrf_two_level(int batch, QRShape shape, int m, int n, double* M, l
                             wk.ldv, wk.sV, Tk, wk.sTin, nb, wk.W, wk.W2, wk.sW, /*transT=*/true,
                             wk.ws, wk.ws_elems, s);
     }
-    // outer compact-WY factor from G = VO^T VO
+    // outer compact-WY factor from G = VO^T VO (always FP64)
     {
+      GemmFp64Scope fp64;
       GemmBatch g;
       g.batch = batch;
       g.transA = 1;

@@ -5,15 +5,16 @@
 // row blocks of TS_MB rows (the last one takes the remainder):
 //   A. every block is factored by one workgroup, Q_p R_p (local Householder
 //      vectors Y_p and compact-WY factor T_p);
-//   B. one workgroup factors the stacked [R_1; ...; R_P] = Q_top R, forms the
-//      explicit Q_top, the top w x w block Q_00 of the panel's Q, and the
+//   B. one workgroup factors the stacked [R_1; ...; R_P] = Q_top R (Q_top is
+//      kept as Y_top and Z = T_top Y_top(0:w, :)^T), forms the top w x w block
+//      Q_00 of the panel's Q, and the
 //      LU factorisation Q_00 - S = L_1 U with the sign of each pivot chosen so
 //      that |pivot| >= 1 (S = diag(+-1)).  Then the panel's Householder form is
 //      V = [L_1; Q_rest U^{-1}], T = -U S L_1^{-T}, R = S R_tsqr
 //      (Ballard, Demmel, Grigori, Jacobsen, Knight, Nguyen, "Reconstructing
 //      Householder vectors from tall-skinny QR", 2015);
-//   C. every block forms its rows of the explicit Q,
-//      Q_p = (I - Y_p T_p Y_p^T) [Q_top,p; 0], and of V = Q U^{-1}.
+//   C. every block forms its piece Q_top,p = [I; 0]_p - Y_top,p Z and its rows of
+//      the explicit Q, Q_p = (I - Y_p T_p Y_p^T) [Q_top,p; 0], and of V = Q U^{-1}.
 // Each stage is parallel over rows; only the w x w pieces are sequential.
 // The Householder factorisations keep the matrix in registers, one row (or a
 // few) per thread: a step needs the dot products of the pivot column with all
@@ -269,7 +270,8 @@ __global__ __launch_bounds__(TS_NT) void tsqr_local_kernel(
 __global__ __launch_bounds__(TS_NT) void tsqr_tree_kernel(
     double* M, long long ldm, long long sM, int c0, int w, int h1, int r1a, int r2a, int P,
     const double* V, long long ldv, long long sV, int vr2, const double* Tloc, const double* Rstack,
-    double* Qtop, double* Uo, double* Lo, double* So, long long sScr, double* Tfin, long long sT) {
+    double* Qtop, double* Zo, double* Uo, double* Lo, double* So, long long sScr, double* Tfin,
+    long long sT) {
   __shared__ double red[2 * 4 * TS_W], rowb[2 * TS_W], zb[TS_W];
   __shared__ double Ts[TS_W][TS_W1];  // T_top
   __shared__ double Yt[TS_W][TS_W1];  // Y_top(0:w, 0:w), then X2
@@ -285,6 +287,7 @@ __global__ __launch_bounds__(TS_NT) void tsqr_tree_kernel(
   Tloc += b * sScr;
   Rstack += b * sScr;
   Qtop += b * sScr;
+  Zo += b * sScr;
   Uo += b * sScr;
   Lo += b * sScr;
   So += b * sScr;
@@ -329,23 +332,25 @@ __global__ __launch_bounds__(TS_NT) void tsqr_tree_kernel(
     Z[i][j] = s;
   }
   __syncthreads();
-  // Q_top = [I; 0] - Y_top Z, row by row from the registers, one column at a time
+  // Y_top (unit lower trapezoidal, explicit) and Z to global memory: every
+  // expansion block forms its own rows of Q_top = [I; 0] - Y_top Z.  Here only
+  // Q_top,0 (rows 0..31) is formed, for Q_00.
 #pragma unroll
   for (int r = 0; r < TS_TREE_RPT; ++r) {
     const int i = tid + TS_NT * r;
     if (i < rows) {
-#pragma unroll 2
-      for (int j = 0; j < w; ++j) {
-        double q = (i == j) ? 1.0 : 0.0;
 #pragma unroll
-        for (int k = 0; k < TS_W; ++k) {
-          const double y = (i > k) ? a[r][k] : ((i == k) ? 1.0 : 0.0);
-          q = fma(-y, Z[k][j], q);
-        }
-        Qtop[i + (long long)j * ldr] = q;
-        if (i < TS_W) Q0[i][j] = q;
-      }
+      for (int k = 0; k < TS_W; ++k)
+        if (k < w) Qtop[i + (long long)k * ldr] = (i > k) ? a[r][k] : ((i == k) ? 1.0 : 0.0);
     }
+  }
+  for (int e = tid; e < TS_W * TS_W; e += TS_NT) {
+    const int i = e & (TS_W - 1), j = e / TS_W;
+    Zo[e] = Z[i][j];
+    double q = (i == j) ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = 0; k < TS_W; ++k) q = fma(-Yt[i][k], Z[k][j], q);
+    Q0[i][j] = (i < w && j < w) ? q : 0.0;
   }
   __syncthreads();
   // Q_00 = Q_top,0 - Y_0 T_0 (Y_0^T Q_top,0): X2 = Y_0^T Q_top,0, X3 = T_0 X2
@@ -469,8 +474,8 @@ __global__ __launch_bounds__(TS_NT) void tsqr_tree_kernel(
 // block; y stays in registers and v is produced one column at a time.
 __global__ __launch_bounds__(TS_NT) void tsqr_expand_kernel(
     double* M, long long ldm, long long sM, int c0, int w, int h1, int r1a, int r2a, int h, int P,
-    double* V, long long ldv, long long sV, int vr2, const double* Tloc, const double* Qtop,
-    const double* Uinv, const double* Lo, long long sScr) {
+    double* V, long long ldv, long long sV, int vr2, const double* Tloc, const double* Ytop,
+    const double* Zg, const double* Uinv, const double* Lo, long long sScr) {
   __shared__ double Qt[TS_W][TS_W1];
   __shared__ double Us[TS_W][TS_W1];  // U^{-1}
   __shared__ double M1[TS_W][TS_W1];  // Y_p^T Q_top,p, then M3
@@ -481,7 +486,8 @@ __global__ __launch_bounds__(TS_NT) void tsqr_expand_kernel(
   M += b * sM;
   V += b * sV;
   Tloc += b * sScr;
-  Qtop += b * sScr;
+  Ytop += b * sScr;
+  Zg += b * sScr;
   Uinv += b * sScr;
   Lo += b * sScr;
   const int tid = threadIdx.x;
@@ -490,11 +496,22 @@ __global__ __launch_bounds__(TS_NT) void tsqr_expand_kernel(
   const int wy = min(w, rows);  // rows of Y_p that meet [Q_top,p; 0]
   const int ldr = P * TS_W;
   const double* Tp = Tloc + (long long)p * TS_W * TS_W;
+  // Q_top,p = [I; 0]_p - Y_top,p Z (Y_top,p = rows p w .. p w + w - 1 of Y_top);
+  // M1 and M2 hold Y_top,p and Z until Qt is formed
   for (int e = tid; e < TS_W * TS_W; e += TS_NT) {
     const int i = e % TS_W, j = e / TS_W;
     const bool in = i < w && j < w;
-    Qt[i][j] = in ? Qtop[(p * w + i) + (long long)j * ldr] : 0.0;
+    M1[i][j] = in ? Ytop[(p * w + i) + (long long)j * ldr] : 0.0;
+    M2[i][j] = Zg[e];
     Us[i][j] = in ? Uinv[i + j * TS_W] : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < TS_W * TS_W; e += TS_NT) {
+    const int i = e % TS_W, j = e / TS_W;
+    double q = (p == 0 && i == j) ? 1.0 : 0.0;
+#pragma unroll
+    for (int k = 0; k < TS_W; ++k) q = fma(-M1[i][k], M2[k][j], q);
+    Qt[i][j] = (i < w && j < w) ? q : 0.0;
   }
   __syncthreads();
   // M1 = Y_p(0:wy, :)^T Q_top,p(0:wy, :) (Y_p unit lower on its first rows);
@@ -574,14 +591,15 @@ void tsqr_panel(int batch, double* M, long long ldm, long long sM, int c0, int w
     ProfScope prof("tsqr_tree", s, batch * (4.0 * P * ww * w + 4.0 * ww * w),
                    batch * 8.0 * 2.0 * P * ww);
     hipLaunchKernelGGL(tsqr_tree_kernel, dim3(batch), dim3(TS_NT), 0, s, M, ldm, sM, c0, w, h1, r1a,
-                       r2a, P, V, ldv, sV, vr2, sc.Tloc, sc.Rstack, sc.Qtop, sc.U, sc.L, sc.S,
-                       sc.stride, T, sT);
+                       r2a, P, V, ldv, sV, vr2, sc.Tloc, sc.Rstack, sc.Qtop, sc.Z, sc.U, sc.L,
+                       sc.S, sc.stride, T, sT);
     ZCSD_CHECK_LAUNCH();
   }
   {
     ProfScope prof("tsqr_expand", s, batch * 3.0 * h * ww, batch * 8.0 * 3.0 * h * w);
     hipLaunchKernelGGL(tsqr_expand_kernel, dim3(P, batch), dim3(TS_NT), 0, s, M, ldm, sM, c0, w, h1,
-                       r1a, r2a, h, P, V, ldv, sV, vr2, sc.Tloc, sc.Qtop, sc.U, sc.L, sc.stride);
+                       r1a, r2a, h, P, V, ldv, sV, vr2, sc.Tloc, sc.Qtop, sc.Z, sc.U, sc.L,
+                       sc.stride);
     ZCSD_CHECK_LAUNCH();
   }
 }
@@ -594,6 +612,7 @@ TsqrScratch tsqr_scratch_alloc(Arena& ar, int batch) {
   sc.Rstack = base;
   sc.Qtop = base + per_R;
   sc.Tloc = base + 2 * per_R;  // P blocks of w x w
+  sc.Z = base + 3 * per_R;     // 32 x 32
   sc.U = base + 4 * per_R;
   sc.L = sc.U + TS_W * TS_W;
   sc.S = sc.L + TS_W * TS_W;

@@ -97,8 +97,40 @@ struct GemmBatch {
   // optional workspace for split-K (deterministic: partial products, then a reduction)
   double* ws = nullptr;
   size_t ws_elems = 0;
+  // symmetric product (m == n, beta == 0): only the tiles on or above the
+  // diagonal are computed; the caller mirrors the upper triangle (mirror_upper)
+  bool sym_upper = false;
 };
 void dgemm(const GemmBatch& g, hipStream_t s);
+
+// While a GemmLowpScope(true) is alive on this host thread, dgemm runs the
+// product on the FP32 matrix cores (FP64 operands rounded to FP32, FP32
+// accumulation, FP64 result): for steps whose error a later FP64 refinement
+// removes (gemm_lowp.hip).
+class GemmLowpScope {
+ public:
+  explicit GemmLowpScope(bool on);
+  ~GemmLowpScope();
+  GemmLowpScope(const GemmLowpScope&) = delete;
+  GemmLowpScope& operator=(const GemmLowpScope&) = delete;
+
+ private:
+  bool on_;
+};
+// Inside a GemmLowpScope: products that must stay FP64 (the compact-WY factor of
+// a blocked QR, whose orthogonality would otherwise degrade to the FP32 level)
+class GemmFp64Scope {
+ public:
+  GemmFp64Scope();
+  ~GemmFp64Scope();
+  GemmFp64Scope(const GemmFp64Scope&) = delete;
+  GemmFp64Scope& operator=(const GemmFp64Scope&) = delete;
+
+ private:
+  int saved_;
+};
+bool gemm_lowp_active();
+void gemm_lowp(const GemmBatch& g, hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // element-wise and reduction kernels (elem.hip)
@@ -110,6 +142,8 @@ void set_identity(int batch, int m, int n, double v, double* X, long long ldx, l
                   hipStream_t s);
 // X_b = (X_b + X_b^T) / 2 in place (n x n)
 void symmetrize(int batch, int n, double* X, long long ldx, long long sx, hipStream_t s);
+// X_b(i, j) = X_b(j, i) for i > j (n x n): completes a sym_upper product
+void mirror_upper(int batch, int n, double* X, long long ldx, long long sx, hipStream_t s);
 // Sums of squares over a region of each X_b, reduced by many workgroups into
 // per-problem partials and then in a fixed order (deterministic).
 struct SumsqRegion {

@@ -9,7 +9,8 @@ constexpr int TS_PMAX = 17;   // at most this many blocks (the tree QR holds P*3
 
 struct TsqrScratch {
   double* Rstack = nullptr;  // (P w) x w stacked R factors, ld P*32
-  double* Qtop = nullptr;    // (P w) x w explicit Q of the tree QR
+  double* Qtop = nullptr;    // (P w) x w: Householder vectors Y_top of the tree QR
+  double* Z = nullptr;       // 32 x 32: T_top Y_top(0:w, :)^T
   double* Tloc = nullptr;    // P blocks of 32 x 32
   double* U = nullptr;       // 32 x 32
   double* L = nullptr;       // 32 x 32

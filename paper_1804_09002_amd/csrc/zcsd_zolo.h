@@ -38,6 +38,8 @@ struct ZoloPdArgs {
   int r_override = 0;
   double ell_override = 0.0;
   bool symmetric_input = false; // X_b symmetric: H not needed, W symmetric
+  double ell_cap = 0.0;         // > 0: use at most this l (products in FP32 cannot resolve
+                                // singular values below their rounding level)
   int nb_qr = 32;
 };
 struct ZoloPdResult {

@@ -109,6 +109,7 @@ ZoloPdResult zolo_pd_batched(const ZoloPdArgs& a, Arena& ar, hipStream_t s) {
     ell *= 0.9;  // margin for the rounding of R^{-1}
   }
   ell = std::min(1.0, std::max(ell, a.eps));
+  if (a.ell_cap > 0.0) ell = std::min(ell, a.ell_cap);
   int r = a.r_override;
   if (r <= 0) {
     r = zolo_choose_r(ell, a.tol);
@@ -168,9 +169,10 @@ ZoloPdResult zolo_pd_batched(const ZoloPdArgs& a, Arena& ar, hipStream_t s) {
     g.A = Y1; g.lda = n; g.sA = nn;
     g.B = Y1; g.ldb = n; g.sB = nn;
     g.C = G; g.ldc = n; g.sC = nn;
+    g.sym_upper = true;
     dgemm(g, s);
   }
-  symmetrize(B, n, G, n, nn, s);
+  mirror_upper(B, n, G, n, nn, s);
   Coef8 cc{}, inva{};
   for (int j = 0; j < r; ++j) {
     cc.v[j] = z2.c[2 * j];
@@ -191,8 +193,10 @@ ZoloPdResult zolo_pd_batched(const ZoloPdArgs& a, Arena& ar, hipStream_t s) {
     g.A = Ric; g.lda = n; g.sA = (long long)r * nn;
     g.B = Ric; g.ldb = n; g.sB = (long long)r * nn;
     g.C = Ms; g.ldc = n; g.sC = nn;
+    g.sym_upper = true;
     dgemm(g, s);
   }
+  mirror_upper(B, n, Ms, n, nn, s);
   double* Y2 = ar.dalloc((size_t)B * nn);
   copy_scale(B, n, n, 1.0, Y1, n, nn, Y2, n, nn, s);
   {

@@ -42,6 +42,9 @@ class Info(C.Structure):
                 ("zolo_resid", C.c_double), ("eig_levels", C.c_int), ("eig_splits", C.c_int),
                 ("eig_max_r", C.c_int), ("eig_offblock", C.c_double),
                 ("eig_coupling", C.c_double), ("eig_full_refinements", C.c_int),
+                ("refine_iters", C.c_int), ("refine_clusters", C.c_int),
+                ("refine_max_cluster", C.c_int), ("refine_offdiag", C.c_double),
+                ("refine_fallback", C.c_int),
                 ("time_ms", C.c_double * 4)]
 
     def as_dict(self):
@@ -49,7 +52,11 @@ class Info(C.Structure):
                 "zolo_resid": self.zolo_resid, "eig_levels": self.eig_levels,
                 "eig_splits": self.eig_splits, "eig_max_r": self.eig_max_r,
                 "eig_offblock": self.eig_offblock, "eig_coupling": self.eig_coupling,
-                "eig_full_refinements": self.eig_full_refinements, "time_ms": list(self.time_ms)}
+                "eig_full_refinements": self.eig_full_refinements,
+                "refine_iters": self.refine_iters, "refine_clusters": self.refine_clusters,
+                "refine_max_cluster": self.refine_max_cluster, "refine_offdiag": self.refine_offdiag,
+                "refine_fallback": self.refine_fallback,
+                "time_ms": list(self.time_ms)}
 
 
 _L = None
@@ -70,6 +77,8 @@ def _lib():
         L.zcsd_status_string.argtypes = [i]
         L.zcsd_status_string.restype = C.c_char_p
         L.zcsd_dgemm.argtypes = [vp, i, i, i, i, i, d, vp, i, ll, vp, i, ll, d, vp, i, ll, i]
+        if hasattr(L, "zcsd_dgemm_f32acc"):
+            L.zcsd_dgemm_f32acc.argtypes = L.zcsd_dgemm.argtypes
         for name, args in {
             "zcsd_dcsd": [vp, i, vp, i, vp, i, vp, i, vp, i, vp, i, vp, vp, vp,
                           C.POINTER(Opts), C.POINTER(Info)],
@@ -144,8 +153,10 @@ def _colmajor(X, name):
     return X.t().contiguous()
 
 
-def dgemm(A, B, transA=False, transB=False, alpha=1.0, beta=0.0, C_=None):
-    """C = alpha op(A) op(B) + beta C for 2-D or batched 3-D float64 device tensors (row-major API)."""
+def dgemm(A, B, transA=False, transB=False, alpha=1.0, beta=0.0, C_=None, f32acc=False):
+    """C = alpha op(A) op(B) + beta C for 2-D or batched 3-D float64 device tensors (row-major API).
+
+    f32acc=True runs the product on the FP32 matrix cores (zcsd_dgemm_f32acc)."""
     batched = A.dim() == 3
     if not batched:
         A, B = A.unsqueeze(0), B.unsqueeze(0)
@@ -161,9 +172,10 @@ def dgemm(A, B, transA=False, transB=False, alpha=1.0, beta=0.0, C_=None):
     out = torch.empty((bs, m_, n_), dtype=torch.float64, device=A.device) if C_ is None else C_.contiguous()
     h = handle(A.device.index)
     # library computes (col-major) C' = op'(B') op'(A') with X' = X^T storage
-    st = _lib().zcsd_dgemm(h, 1 if transB else 0, 1 if transA else 0, n_, m_, k_, alpha,
-                           _ptr(Bb), bc, br * bc, _ptr(Ab), ac, ar * ac, beta,
-                           _ptr(out), n_, m_ * n_, bs)
+    fn = _lib().zcsd_dgemm_f32acc if f32acc else _lib().zcsd_dgemm
+    st = fn(h, 1 if transB else 0, 1 if transA else 0, n_, m_, k_, alpha,
+            _ptr(Bb), bc, br * bc, _ptr(Ab), ac, ar * ac, beta,
+            _ptr(out), n_, m_ * n_, bs)
     _check(st, "zcsd_dgemm")
     return out if batched else out[0]
 

@@ -35,7 +35,7 @@ typedef enum {
   ZCSD_EINVAL = 1,   /* bad argument (size, leading dimension, NULL pointer, NaN/Inf input) */
   ZCSD_ENOTISO = 2,  /* input is far from a partial isometry: |‖A‖_F^2 - rank| too large (Sec. 2.1) */
   ZCSD_ENOCONV = 3,  /* Zolo-pd did not reach 1 - l_2 <= tol, or a split of Zolo-eig failed */
-  ZCSD_EREPAIR = 4,  /* reserved: Algorithm 2 repair rejected (‖R~ - R‖ too large, Sec. 5.1) */
+  ZCSD_EREPAIR = 4,  /* Algorithm 2 repair rejected (‖R~ - R‖_F > 100 n u ‖R‖_F, Sec. 5.1) */
   ZCSD_EHIP = 5,     /* HIP runtime error */
   ZCSD_ENOMEM = 6    /* device allocation failed */
 } zcsd_status;
@@ -84,6 +84,8 @@ typedef struct {
   double refine_offdiag;   /* mixed mode: final ‖V1^T B V1 - diag‖_2 (power-iteration estimate) */
   int refine_fallback;     /* mixed mode: 1 if the refinement did not reach the FP64 rounding
                               floor and Zolo-eig was recomputed in FP64 */
+  int repair;              /* 1 if Algorithm 2 (Sec. 5.1) replaced W_i = Q_i Q~_i^T */
+  double repair_resid;     /* its max_i ‖R~_i - R_i‖_F / ‖R_i‖_F (accepted below 100 n u) */
   double time_ms[4];       /* polar, B, eig, assembly wall time (ms), measured with stream syncs */
 } zcsd_info;
 

@@ -79,7 +79,77 @@ size_t csd_workspace_bytes(int n) {
   return (2 * 64 * nn + 64 * nn + 16 * nn) * sizeof(double) + (256u << 20);
 }
 
+// d_b[j] = -1 if R_b(j, j) < 0 else 1
+__global__ void rsign_kernel(int n, const double* __restrict__ R, long long sR, double* d) {
+  const long long b = blockIdx.y;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x)
+    d[b * n + j] = (R[b * sR + j + (long long)j * n] < 0.0) ? -1.0 : 1.0;
+}
+
+// Q_b(:, j) *= d_b[j] and R_b(i, :) *= d_b[i]  (diag(R) >= 0 convention)
+__global__ void rsign_apply_kernel(int n, double* Q, double* R, long long sM,
+                                   const double* __restrict__ d) {
+  const long long b = blockIdx.y;
+  const long long nn = (long long)n * n;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nn;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n), j = (int)(e / n);
+    Q[b * sM + e] *= d[b * n + j];
+    R[b * sM + e] *= d[b * n + i];
+  }
+}
+
+// QR with diag(R) >= 0 of the two n x n matrices at M (stride n*n, overwritten
+// by R) into Q
+static void qr_pos(int n, double* M, double* Q, Arena& ar, hipStream_t s) {
+  const long long nn = (long long)n * n;
+  ArenaScope sc(ar);
+  QRWork wk = qr_work_alloc(ar, QRShape::General, 2, n, n, 32);
+  geqrf_batched(2, QRShape::General, n, n, M, n, nn, wk, s);
+  orgqr_batched(2, QRShape::General, n, n, Q, n, nn, nullptr, wk, s);
+  double* d = ar.dalloc(2 * (size_t)n);
+  const unsigned g1 = (unsigned)std::max(1, std::min((n + 255) / 256, 1024));
+  hipLaunchKernelGGL(rsign_kernel, dim3(g1, 2), dim3(256), 0, s, n, M, nn, d);
+  ZCSD_CHECK_LAUNCH();
+  const unsigned g2 = (unsigned)std::max<long long>(1, std::min<long long>((nn + 255) / 256, 1024));
+  hipLaunchKernelGGL(rsign_apply_kernel, dim3(g2, 2), dim3(256), 0, s, n, Q, M, nn, d);
+  ZCSD_CHECK_LAUNCH();
+}
+
+// Algorithm 2 on both polars: W_i = Q_i Q~_i^T; returns max_i ||R~_i - R_i||_F / ||R_i||_F
+static double polar_repair(int n, const double* X, double* W, const double* H, Arena& ar,
+                           hipStream_t s) {
+  const long long nn = (long long)n * n;
+  ArenaScope sc(ar);
+  double* RA = ar.dalloc(2 * (size_t)nn);
+  double* RH = ar.dalloc(2 * (size_t)nn);
+  double* QA = ar.dalloc(2 * (size_t)nn);
+  double* QH = ar.dalloc(2 * (size_t)nn);
+  copy_scale(2, n, n, 1.0, X, n, nn, RA, n, nn, s);
+  copy_scale(2, n, n, 1.0, H, n, nn, RH, n, nn, s);
+  qr_pos(n, RA, QA, ar, s);
+  qr_pos(n, RH, QH, ar, s);
+  GemmBatch g;
+  g.batch = 2;
+  g.transB = 1;
+  g.m = n; g.n = n; g.k = n;
+  g.A = QA; g.lda = n; g.sA = nn;
+  g.B = QH; g.ldb = n; g.sB = nn;
+  g.C = W; g.ldc = n; g.sC = nn;
+  dgemm(g, s);
+  // ||R~ - R||_F / ||R||_F per polar (RH <- RH - RA)
+  double* ss = ar.dalloc(4);
+  sumsq(2, n, n, RA, n, nn, ss, ar, s);
+  axpby(2 * nn, -1.0, RA, 1.0, RH, s);
+  sumsq(2, n, n, RH, n, nn, ss + 2, ar, s);
+  double h[4];
+  d2h(h, ss, sizeof(h), s);
+  return std::max(std::sqrt(h[2] / std::max(h[0], 1e-300)), std::sqrt(h[3] / std::max(h[1], 1e-300)));
+}
+
 struct CsdOut {
+  bool repair = false;
+  double repair_resid = 0.0;
   int rank = 0;
   ZoloPdResult pd;
   ZoloEigResult eig;
@@ -135,6 +205,17 @@ static CsdOut csd_run(int n, const double* A1, long long lda1, const double* A2,
       if (za.r_override <= 0) za.r_override = ZOLO_RMAX;
     }
     out.pd = zolo_pd_batched(za, ar, s);
+  }
+  // Algorithm 2 (Sec. 5.1): a full-rank A_i whose sigma_min estimate fell to eps
+  // was handled by the modified Zolo-pd, so W~_i is not orthonormal; with
+  // A_i = Q_i R_i and H~_i = Q~_i R~_i (diag(R) >= 0, where the two R factors
+  // agree in exact arithmetic) W_i = Q_i Q~_i^T is orthonormal by construction
+  // and ||W_i H~_i - A_i|| = ||R~_i - R_i||, checked against 100 n u ||R_i||_F.
+  if (!deficient && out.pd.ell <= o.eps * (1.0 + 1e-12)) {
+    out.repair = true;
+    out.repair_resid = polar_repair(n, X, W, H, ar, s);
+    if (!(out.repair_resid <= 100.0 * n * 0x1p-53))
+      throw NumError(ZCSD_EREPAIR, "csd: ill-conditioned repair rejected (||R~ - R|| too large)");
   }
   HostSync::sync(s);
   double t1 = now_ms();
@@ -333,6 +414,8 @@ extern "C" zcsd_status zcsd_dcsd(zcsd_handle* handle, int n, const double* d_A1,
       info->refine_max_cluster = r.refine.max_cluster;
       info->refine_offdiag = r.refine.offdiag;
       info->refine_fallback = r.refine.fallback ? 1 : 0;
+      info->repair = r.repair ? 1 : 0;
+      info->repair_resid = r.repair_resid;
       info->time_ms[0] = r.t_polar;
       info->time_ms[1] = r.t_B;
       info->time_ms[2] = r.t_eig;

@@ -44,7 +44,7 @@ class Info(C.Structure):
                 ("eig_coupling", C.c_double), ("eig_full_refinements", C.c_int),
                 ("refine_iters", C.c_int), ("refine_clusters", C.c_int),
                 ("refine_max_cluster", C.c_int), ("refine_offdiag", C.c_double),
-                ("refine_fallback", C.c_int),
+                ("refine_fallback", C.c_int), ("repair", C.c_int), ("repair_resid", C.c_double),
                 ("time_ms", C.c_double * 4)]
 
     def as_dict(self):
@@ -55,7 +55,8 @@ class Info(C.Structure):
                 "eig_full_refinements": self.eig_full_refinements,
                 "refine_iters": self.refine_iters, "refine_clusters": self.refine_clusters,
                 "refine_max_cluster": self.refine_max_cluster, "refine_offdiag": self.refine_offdiag,
-                "refine_fallback": self.refine_fallback,
+                "refine_fallback": self.refine_fallback, "repair": self.repair,
+                "repair_resid": self.repair_resid,
                 "time_ms": list(self.time_ms)}
 
 

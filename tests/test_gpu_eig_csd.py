@@ -201,3 +201,23 @@ def test_csd_n4096_bench_configuration():
     res, orth = _torch_checks(a1, a2, U1, U2, V1, th, n)
     assert res <= 1e-13, res
     assert max(orth.values()) <= 1e-13, orth
+
+
+@pytest.mark.parametrize("n,seed", [(100, 41), (300, 46)])
+def test_csd_ill_conditioned_algorithm2(n, seed):
+    """Test class 2 of Sec. 6 (delta = 10^(-18 U), theta = (pi/2) cumsum(delta)/sum(delta)):
+    angles reach 1e-18 of 0 and pi/2, so sigma_min(A_i) < eps and the modified Zolo-pd
+    alone leaves W~_i non-orthonormal; Algorithm 2 (Sec. 5.1) restores the FP64 targets."""
+    from paper_1804_09002_amd import zcsd
+    rng = np.random.default_rng(seed)
+    theta = WL.angles_cumsum_clustered(n, rng)
+    assert min(np.min(theta), np.min(np.pi / 2 - theta)) < 1e-15
+    A1, A2, _ = WL.from_angles(theta, rng)
+    U1, U2, V1, th, info = zcsd.csd(_t(A1), _t(A2))
+    assert info["rank"] == n and info["repair"] == 1
+    assert info["repair_resid"] <= 100 * n * U
+    U1, U2, V1, th = (x.cpu().numpy() for x in (U1, U2, V1, th))
+    ref = O.csd(A1, A2)
+    assert np.max(np.abs(th - ref["theta"])) <= 10 * n * U
+    assert np.max(np.abs(th - np.sort(theta))) <= 10 * n * U
+    _check_csd(A1, A2, U1, U2, V1, th, n)

@@ -6,7 +6,7 @@
 //     R11 = chol(A11),  R12 = R11^{-T} A12,  R22 = chol(A22 - R12^T R12),
 //     (R^{-1})12 = -R11^{-1} R12 R22^{-1},
 // so the triangular solves become MFMA GEMMs; blocks of at most CH_BASE are
-// factored and inverted in LDS by one workgroup.
+// factored in LDS by one workgroup and inverted there by 16 x 16 MFMA blocks.
 //
 // trtri_upper_batched inverts an upper-triangular R: all diagonal blocks of
 // size CH_BASE are inverted at once, then neighbouring blocks are merged level
@@ -22,74 +22,136 @@ namespace zcsd {
 
 constexpr int CH_BASE = 64;
 constexpr int CH_NT = 256;
+constexpr int CH_LD = CH_BASE + 1;
 
-// In LDS: upper-triangular inverse of U (nb x nb, ld CH_BASE+1) into Ui.
-// Thread j computes column j by back substitution (rows j..0).
-__device__ void lds_upper_inverse(const double (*U)[CH_BASE + 1], double (*Ui)[CH_BASE + 1],
-                                  int nb) {
-  const int j = threadIdx.x;
-  if (j < nb) {
-    for (int i = nb - 1; i >= 0; --i) {
-      double v;
-      if (i > j) v = 0.0;
-      else if (i == j) v = 1.0 / U[j][j];
-      else {
-        double s = 0.0;
-        for (int p = i + 1; p <= j; ++p) s += U[i][p] * Ui[p][j];
-        v = -s / U[i][i];
-      }
-      Ui[i][j] = v;
-    }
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// 16 x 16 block of X(i0:i0+16, kx0:kx0+K) * Y(ky0:ky0+K, j0:j0+16) on the FP64
+// matrix cores, both operands in LDS ([row][col]).  v_mfma_f64_16x16x4f64 takes
+// a[i][k] from lane i + 16k and b[k][j] from lane j + 16k and leaves d[i][j] in
+// item i / 4 of lane j + 16 (i % 4); fed with Y^T as "a" and X^T as "b" it
+// holds the transposed block, so lane l item v is C[l % 16][4 v + l / 16].
+template <int K>
+__device__ __forceinline__ d4 lds_mm16(const double (*X)[CH_LD], int i0, int kx0,
+                                       const double (*Y)[CH_LD], int ky0, int j0) {
+  const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+  d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kk = 0; kk < K; kk += 4) {
+    const double fa = X[i0 + lr][kx0 + kk + lk];
+    const double fb = Y[ky0 + kk + lk][j0 + lr];
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(fb, fa, acc, 0, 0, 0);
   }
+  return acc;
 }
 
-// one workgroup per problem: A (nb x nb, symmetric, upper triangle read) -> R, Ri
+__device__ __forceinline__ void lds_put16(double (*C)[CH_LD], int i0, int j0, d4 acc, double scale) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) C[i0 + (lane & 15)][j0 + 4 * v + (lane >> 4)] = scale * acc[v];
+}
+
+// Inverse of the 64 x 64 upper-triangular U held in LDS (exact zeros below the
+// diagonal, identity beyond the problem's size) into Ui, by all 256 threads:
+// the four 16 x 16 diagonal blocks by back substitution (one column per
+// thread), then two merge levels (Ui)_AB = -Ui_A (U_AB Ui_B) as 16 x 16 MFMA
+// blocks (pairs of 16-blocks, then the two 32-blocks).  dinv[i] = 1 / U[i][i]
+// on entry; Xs is 32 x 32 scratch.  Ends with a barrier.
+__device__ void lds_upper_inverse64(const double (*U)[CH_LD], double (*Ui)[CH_LD],
+                                    const double* dinv, double (*Xs)[CH_LD]) {
+  const int tid = threadIdx.x, wave = tid >> 6;
+  for (int e = tid; e < CH_BASE * CH_BASE; e += CH_NT) Ui[e & 63][e >> 6] = 0.0;
+  __syncthreads();
+  if (tid < CH_BASE) {
+    const int o = tid & ~15, c = tid & 15;
+    double x[16];
+#pragma unroll
+    for (int i = 15; i >= 0; --i) {
+      double s = 0.0;
+#pragma unroll
+      for (int p = i + 1; p < 16; ++p) s = fma(U[o + i][o + p], x[p], s);
+      x[i] = (i > c) ? 0.0 : ((i == c) ? dinv[o + c] : -s * dinv[o + i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+      if (i <= c) Ui[o + i][o + c] = x[i];
+  }
+  __syncthreads();
+  // pairs (A, B) = ([o, o+16), [o+16, o+32)), o = 32 wave, on waves 0 and 1
+  if (wave < 2) {
+    const int o = 32 * wave;
+    lds_put16(Xs, 16 * wave, 0, lds_mm16<16>(U, o, o + 16, Ui, o + 16, o + 16), 1.0);
+  }
+  __syncthreads();
+  if (wave < 2) {
+    const int o = 32 * wave;
+    lds_put16(Ui, o, o + 16, lds_mm16<16>(Ui, o, o, Xs, 16 * wave, 0), -1.0);
+  }
+  __syncthreads();
+  {  // A = [0, 32), B = [32, 64); wave owns the 16 x 16 tile (ti, tj) of the 32 x 32 block
+    const int ti = wave & 1, tj = wave >> 1;
+    const d4 xab = lds_mm16<32>(U, 16 * ti, 32, Ui, 32, 32 + 16 * tj);
+    lds_put16(Xs, 16 * ti, 16 * tj, xab, 1.0);
+    __syncthreads();
+    const d4 yab = lds_mm16<32>(Ui, 16 * ti, 0, Xs, 0, 16 * tj);
+    lds_put16(Ui, 16 * ti, 32 + 16 * tj, yab, -1.0);
+  }
+  __syncthreads();
+}
+
+// one workgroup per problem: A (nb x nb, symmetric, upper triangle read) -> R, Ri.
+// Right-looking Cholesky in LDS on the unscaled pivot rows (one barrier per
+// step: S22 -= s12^T s12 / s11, then R(k, :) = S(k, :) / sqrt(s_kk)); a
+// non-positive pivot is counted in d_flag and replaced by 1e-300.
 __global__ __launch_bounds__(CH_NT) void chol_inv_base_kernel(int nb, const double* A, long long lda,
                                                               long long sA, double* R, long long ldr,
                                                               long long sR, double* Ri,
                                                               long long ldi, long long sI,
                                                               int* d_flag) {
-  __shared__ double S[CH_BASE][CH_BASE + 1];
-  __shared__ double Ui[CH_BASE][CH_BASE + 1];
+  __shared__ double S[CH_BASE][CH_LD];
+  __shared__ double Ui[CH_BASE][CH_LD];
+  __shared__ double Xs[32][CH_LD];
+  __shared__ double dinv[CH_BASE];
   const long long b = blockIdx.x;
   A += b * sA;
   R += b * sR;
   Ri += b * sI;
   const int tid = threadIdx.x;
-  for (int e = tid; e < nb * nb; e += CH_NT) {
-    const int i = e % nb, j = e / nb;
-    // symmetric read from the upper triangle
-    S[i][j] = (i <= j) ? A[i + (long long)j * lda] : A[j + (long long)i * lda];
+  for (int e = tid; e < CH_BASE * CH_BASE; e += CH_NT) {
+    const int i = e & 63, j = e >> 6;
+    double v = (i == j) ? 1.0 : 0.0;
+    if (i < nb && j < nb) v = (i <= j) ? A[i + (long long)j * lda] : A[j + (long long)i * lda];
+    S[i][j] = v;
   }
   __syncthreads();
-  // right-looking Cholesky in LDS: row k of R overwrites row k of S
   for (int k = 0; k < nb; ++k) {
-    if (tid == 0) {
-      double d = S[k][k];
-      if (!(d > 0.0)) {
-        if (d_flag) atomicAdd(d_flag, 1);
-        d = 1e-300;
-      }
-      S[k][k] = sqrt(d);
-    }
-    __syncthreads();
-    const double rkk = S[k][k];
-    for (int j = k + 1 + tid; j < nb; j += CH_NT) S[k][j] /= rkk;
-    __syncthreads();
+    double d = S[k][k];
+    if (!(d > 0.0)) d = 1e-300;
+    const double inv = 1.0 / d;
     const int m = nb - k - 1;
     for (int e = tid; e < m * m; e += CH_NT) {
       const int i = k + 1 + e % m, j = k + 1 + e / m;
-      if (i <= j) S[i][j] -= S[k][i] * S[k][j];
+      if (i <= j) S[i][j] = fma(-S[k][i] * inv, S[k][j], S[i][j]);
     }
     __syncthreads();
   }
-  for (int e = tid; e < nb * nb; e += CH_NT) {
-    const int i = e % nb, j = e / nb;
-    if (i > j) S[i][j] = 0.0;
+  if (tid < CH_BASE) {
+    double d = S[tid][tid];
+    if (!(d > 0.0)) {
+      if (d_flag && tid < nb) atomicAdd(d_flag, 1);
+      d = 1e-300;
+    }
+    dinv[tid] = 1.0 / sqrt(d);
   }
   __syncthreads();
-  lds_upper_inverse(S, Ui, nb);
+  // R = diag(1 / sqrt(s_kk)) * (upper part of S), zeros below the diagonal
+  for (int e = tid; e < CH_BASE * CH_BASE; e += CH_NT) {
+    const int i = e & 63, j = e >> 6;
+    const double v = S[i][j];
+    S[i][j] = (i < j) ? v * dinv[i] : ((i == j) ? 1.0 / dinv[i] : 0.0);
+  }
   __syncthreads();
+  lds_upper_inverse64(S, Ui, dinv, Xs);
   for (int e = tid; e < nb * nb; e += CH_NT) {
     const int i = e % nb, j = e / nb;
     R[i + (long long)j * ldr] = S[i][j];
@@ -101,21 +163,26 @@ __global__ __launch_bounds__(CH_NT) void chol_inv_base_kernel(int nb, const doub
 __global__ __launch_bounds__(CH_NT) void trtri_base_kernel(int n, const double* R, long long ldr,
                                                            long long sR, double* Ri, long long ldi,
                                                            long long sI) {
-  __shared__ double U[CH_BASE][CH_BASE + 1];
-  __shared__ double Ui[CH_BASE][CH_BASE + 1];
+  __shared__ double U[CH_BASE][CH_LD];
+  __shared__ double Ui[CH_BASE][CH_LD];
+  __shared__ double Xs[32][CH_LD];
+  __shared__ double dinv[CH_BASE];
   const long long b = blockIdx.y;
   const int o = blockIdx.x * CH_BASE;
   const int nb = min(CH_BASE, n - o);
   R += b * sR + o + (long long)o * ldr;
   Ri += b * sI + o + (long long)o * ldi;
   const int tid = threadIdx.x;
-  for (int e = tid; e < nb * nb; e += CH_NT) {
-    const int i = e % nb, j = e / nb;
-    U[i][j] = (i <= j) ? R[i + (long long)j * ldr] : 0.0;
+  for (int e = tid; e < CH_BASE * CH_BASE; e += CH_NT) {
+    const int i = e & 63, j = e >> 6;
+    double v = (i == j) ? 1.0 : 0.0;
+    if (i < nb && j < nb) v = (i <= j) ? R[i + (long long)j * ldr] : 0.0;
+    U[i][j] = v;
   }
   __syncthreads();
-  lds_upper_inverse(U, Ui, nb);
+  if (tid < CH_BASE) dinv[tid] = 1.0 / U[tid][tid];
   __syncthreads();
+  lds_upper_inverse64(U, Ui, dinv, Xs);
   for (int e = tid; e < nb * nb; e += CH_NT) {
     const int i = e % nb, j = e / nb;
     Ri[i + (long long)j * ldi] = Ui[i][j];

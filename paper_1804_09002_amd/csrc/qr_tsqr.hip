@@ -115,6 +115,76 @@ __device__ __forceinline__ double wave_sum32(double (&x)[TS_W]) {
   return x[0] + dpp_f64<0xB1>(x[0]);        // quad_perm [1,0,3,2]
 }
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// 16 x 16 tile (ti, tj) of C = X Y with K = KD on the FP64 matrix cores;
+// fx(i, k) and fy(k, j) read the operands (LDS or global).  v_mfma_f64_16x16x4f64
+// takes a[i][k] from lane i + 16k and b[k][j] from lane j + 16k and leaves
+// d[i][j] in item i / 4 of lane j + 16 (i % 4); fed with Y^T as "a" and X^T as
+// "b" it holds the transposed tile, so item v of lane l is
+// C[16 ti + l % 16][16 tj + 4 v + l / 16] (tile_row / tile_col below).
+template <int KD, class FX, class FY>
+__device__ __forceinline__ d4 mfma_tile(FX fx, FY fy, int ti, int tj) {
+  const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+  d4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int kk = 0; kk < KD; kk += 4)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(fy(kk + lk, 16 * tj + lr), fx(16 * ti + lr, kk + lk),
+                                               acc, 0, 0, 0);
+  return acc;
+}
+__device__ __forceinline__ int tile_row(int ti) { return 16 * ti + (threadIdx.x & 15); }
+__device__ __forceinline__ int tile_col(int tj, int v) { return 16 * tj + 4 * v + ((threadIdx.x & 63) >> 4); }
+
+// Inverse of the upper-triangular 32 x 32 A (LDS, exact zeros below the
+// diagonal, identity beyond the active size) into I, for two matrices at once
+// (m = 0, 1): the 16 x 16 diagonal blocks by back substitution, one column per
+// thread (threads 0..63), then (I)_AB = -I_A (A_AB I_B) as two 16 x 16 MFMA
+// products (wave m); X (32 x 32) is scratch.  Three barriers.
+__device__ void lds_upper_inverse32x2(const double (*A0)[TS_W1], double (*I0)[TS_W1],
+                                      const double (*A1)[TS_W1], double (*I1)[TS_W1],
+                                      double (*X)[TS_W1]) {
+  const int tid = threadIdx.x, wave = tid >> 6;
+  if (tid < 64) {
+    const int m = tid >> 5, o = tid & 16, c = tid & 15;
+    const double (*A)[TS_W1] = m ? A1 : A0;
+    double (*I)[TS_W1] = m ? I1 : I0;
+    double x[16];
+#pragma unroll
+    for (int i = 15; i >= 0; --i) {
+      double sacc = 0.0;
+#pragma unroll
+      for (int q = i + 1; q < 16; ++q) sacc = fma(A[o + i][o + q], x[q], sacc);
+      x[i] = (i > c) ? 0.0 : (((i == c) ? 1.0 : -sacc) / A[o + i][o + i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) I[o + i][o + c] = x[i];
+  } else if (tid < 128) {  // the block below the diagonal of both inverses
+    const int m = (tid >> 5) & 1, c = tid & 15, r0 = tid & 16;
+    double (*I)[TS_W1] = m ? I1 : I0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) I[16 + (r0 >> 1) + i][c] = 0.0;
+  }
+  __syncthreads();
+  if (wave < 2) {
+    const double (*A)[TS_W1] = wave ? A1 : A0;
+    double (*I)[TS_W1] = wave ? I1 : I0;
+    const d4 t = mfma_tile<16>([&](int i, int k) { return A[i][16 + k]; },
+                               [&](int k, int j) { return I[16 + k][16 + j]; }, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) X[16 * wave + tile_row(0)][tile_col(0, v)] = t[v];
+  }
+  __syncthreads();
+  if (wave < 2) {
+    double (*I)[TS_W1] = wave ? I1 : I0;
+    const d4 t = mfma_tile<16>([&](int i, int k) { return I[i][k]; },
+                               [&](int k, int j) { return X[16 * wave + k][j]; }, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) I[tile_row(0)][16 + tile_col(0, v)] = -t[v];
+  }
+  __syncthreads();
+}
+
 // Householder QR of a rows x w matrix (w <= 32) held in registers: row
 // i = threadIdx.x + TS_NT * r is a[r][:]; entries beyond rows / w are zero.
 // Step t forms d_j = sum_{i >= t} a_it a_ij for every j at once; with
@@ -280,7 +350,7 @@ __global__ __launch_bounds__(TS_NT) void tsqr_tree_kernel(
   __shared__ double Q0[TS_W][TS_W1];  // Q_top,0, then Q_00 and its LU
   __shared__ double Y0[TS_W][TS_W1];  // Y_0(0:w, 0:w) of block 0
   __shared__ double T0s[TS_W][TS_W1]; // T_0 of block 0, then U
-  __shared__ double sg[TS_W];
+  __shared__ double sg[TS_W], pv[TS_W];
   const long long b = blockIdx.x;
   M += b * sM;
   V += b * sV;
@@ -312,6 +382,7 @@ __global__ __launch_bounds__(TS_NT) void tsqr_tree_kernel(
       Rf[tid][j] = (in && j >= tid) ? a[0][j] : 0.0;
       Yt[tid][j] = in ? ((j < tid) ? a[0][j] : ((j == tid) ? 1.0 : 0.0)) : 0.0;
     }
+    sg[tid] = 0.0;  // signs beyond w stay zero
   }
   for (int e = tid; e < TS_W * TS_W; e += TS_NT) {
     const int i = e & (TS_W - 1), j = e / TS_W;
@@ -319,22 +390,9 @@ __global__ __launch_bounds__(TS_NT) void tsqr_tree_kernel(
                    ? ((i < j) ? 0.0 : ((i == j) ? 1.0 : V[ts_vrow(i, h1, vr2) + (long long)j * ldv]))
                    : 0.0;
     T0s[i][j] = Tloc[e];  // zero beyond w (written so by the local factorisation)
-    Q0[i][j] = 0.0;
   }
-  __syncthreads();
-  // Z = T_top Y_top(0:w, :)^T; all 32 x 32 products below run over the full
-  // zero-padded range so that the loops unroll
-  for (int e = tid; e < TS_W * TS_W; e += TS_NT) {
-    const int i = e & (TS_W - 1), j = e / TS_W;
-    double s = 0.0;
-#pragma unroll
-    for (int q = 0; q < TS_W; ++q) s = fma(Ts[i][q], Yt[j][q], s);
-    Z[i][j] = s;
-  }
-  __syncthreads();
-  // Y_top (unit lower trapezoidal, explicit) and Z to global memory: every
-  // expansion block forms its own rows of Q_top = [I; 0] - Y_top Z.  Here only
-  // Q_top,0 (rows 0..31) is formed, for Q_00.
+  // Y_top (unit lower trapezoidal, explicit) to global memory: every expansion
+  // block forms its own rows of Q_top = [I; 0] - Y_top Z
 #pragma unroll
   for (int r = 0; r < TS_TREE_RPT; ++r) {
     const int i = tid + TS_NT * r;
@@ -344,126 +402,107 @@ __global__ __launch_bounds__(TS_NT) void tsqr_tree_kernel(
         if (k < w) Qtop[i + (long long)k * ldr] = (i > k) ? a[r][k] : ((i == k) ? 1.0 : 0.0);
     }
   }
-  for (int e = tid; e < TS_W * TS_W; e += TS_NT) {
-    const int i = e & (TS_W - 1), j = e / TS_W;
-    Zo[e] = Z[i][j];
-    double q = (i == j) ? 1.0 : 0.0;
+  __syncthreads();
+  // The 32 x 32 products below run over the zero-padded range, one 16 x 16
+  // MFMA tile per wave.
+  const int wave = tid >> 6;
+  const int ti = wave & 1, tj = wave >> 1, ri = tile_row(ti);
+  {  // Z = T_top Y_top(0:w, :)^T
+    const d4 c = mfma_tile<TS_W>([&](int i, int k) { return Ts[i][k]; },
+                                 [&](int k, int j) { return Yt[j][k]; }, ti, tj);
 #pragma unroll
-    for (int k = 0; k < TS_W; ++k) q = fma(-Yt[i][k], Z[k][j], q);
-    Q0[i][j] = (i < w && j < w) ? q : 0.0;
+    for (int v = 0; v < 4; ++v) Z[ri][tile_col(tj, v)] = c[v];
+  }
+  __syncthreads();
+  {  // Q_top,0 = I - Y_top(0:32, :) Z (zero beyond w); Z to global memory
+    const d4 c = mfma_tile<TS_W>([&](int i, int k) { return Yt[i][k]; },
+                                 [&](int k, int j) { return Z[k][j]; }, ti, tj);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int j = tile_col(tj, v);
+      Q0[ri][j] = (ri < w && j < w) ? ((ri == j ? 1.0 : 0.0) - c[v]) : 0.0;
+      Zo[ri + TS_W * j] = Z[ri][j];
+    }
   }
   __syncthreads();
   // Q_00 = Q_top,0 - Y_0 T_0 (Y_0^T Q_top,0): X2 = Y_0^T Q_top,0, X3 = T_0 X2
   double (*X2)[TS_W1] = Yt;
   double (*X3)[TS_W1] = Z;
-  for (int e = tid; e < TS_W * TS_W; e += TS_NT) {
-    const int i = e & (TS_W - 1), j = e / TS_W;
-    double s = 0.0;
+  {
+    const d4 c = mfma_tile<TS_W>([&](int i, int k) { return Y0[k][i]; },
+                                 [&](int k, int j) { return Q0[k][j]; }, ti, tj);
 #pragma unroll
-    for (int q = 0; q < TS_W; ++q) s = fma(Y0[q][i], Q0[q][j], s);
-    X2[i][j] = s;
+    for (int v = 0; v < 4; ++v) X2[ri][tile_col(tj, v)] = c[v];
   }
   __syncthreads();
-  for (int e = tid; e < TS_W * TS_W; e += TS_NT) {
-    const int i = e & (TS_W - 1), j = e / TS_W;
-    double s = 0.0;
+  {
+    const d4 c = mfma_tile<TS_W>([&](int i, int k) { return T0s[i][k]; },
+                                 [&](int k, int j) { return X2[k][j]; }, ti, tj);
 #pragma unroll
-    for (int q = 0; q < TS_W; ++q) s = fma(T0s[i][q], X2[q][j], s);
-    X3[i][j] = s;
+    for (int v = 0; v < 4; ++v) X3[ri][tile_col(tj, v)] = c[v];
   }
   __syncthreads();
-  for (int e = tid; e < TS_W * TS_W; e += TS_NT) {
-    const int i = e & (TS_W - 1), j = e / TS_W;
-    double s = 0.0;
+  {
+    const d4 c = mfma_tile<TS_W>([&](int i, int k) { return Y0[i][k]; },
+                                 [&](int k, int j) { return X3[k][j]; }, ti, tj);
 #pragma unroll
-    for (int q = 0; q < TS_W; ++q) s = fma(Y0[i][q], X3[q][j], s);
-    X2[i][j] = Q0[i][j] - s;  // Q_00 (zero beyond w)
-  }
-  __syncthreads();
-  // Wave 0, lane i < w holding row i in registers: LU of Q_00 - S with the
-  // pivot sign chosen so that |pivot| >= 1, then L1^{-1} and U^{-1} column by
-  // column (lane j owns column j); pivot rows are broadcast with readlane.
-  double (*Li)[TS_W1] = Z;   // L1^{-T}
-  double (*Ui)[TS_W1] = Q0;  // U^{-1}
-  double (*Us)[TS_W1] = T0s; // U
-  if (tid < 64) {
-    const int lane = tid;
-    const bool own = lane < w;
-    double row[TS_W];
-#pragma unroll
-    for (int j = 0; j < TS_W; ++j) row[j] = own ? X2[lane][j] : 0.0;
-    if (lane < TS_W) sg[lane] = 0.0;  // signs beyond w stay zero
-#pragma unroll
-    for (int k = 0; k < TS_W; ++k) {
-      if (k < w) {
-        const double akk = readlane_f64(row[k], k);
-        const double sk = (akk >= 0.0) ? -1.0 : 1.0;
-        const double piv = akk - sk;
-        const double rp = 1.0 / piv;
-        if (lane == 0) sg[k] = sk;
-        if (lane == k) row[k] = piv;
-        double pr[TS_W];
-#pragma unroll
-        for (int j = k + 1; j < TS_W; ++j) pr[j] = readlane_f64(row[j], k);
-        if (lane > k && own) {
-          const double l = row[k] * rp;
-          row[k] = l;
-#pragma unroll
-          for (int j = k + 1; j < TS_W; ++j) row[j] = fma(-l, pr[j], row[j]);
-        }
-      }
-    }
-    // row now holds L (strictly below the diagonal, unit diagonal implicit) and U
-    double xc[TS_W];
-    // L1^{-1}: x_i = e_i - sum_{k < i} L_ik x_k (column `lane`)
-#pragma unroll
-    for (int i = 0; i < TS_W; ++i) {
-      double x = (lane == i) ? 1.0 : 0.0;
-#pragma unroll
-      for (int k = 0; k < i; ++k) x = fma(-readlane_f64(row[k], i), xc[k], x);
-      xc[i] = (i < w) ? x : 0.0;
-    }
-    if (lane < TS_W) {
-#pragma unroll
-      for (int i = 0; i < TS_W; ++i) Li[lane][i] = own ? xc[i] : 0.0;  // L1^{-T}(lane, i) = L1^{-1}(i, lane)
-    }
-    // U^{-1}: x_i = (e_i - sum_{k > i} U_ik x_k) / U_ii (column `lane`)
-#pragma unroll
-    for (int i = TS_W - 1; i >= 0; --i) {
-      double x = 0.0;
-      if (i < w) {
-        x = (lane == i) ? 1.0 : 0.0;
-#pragma unroll
-        for (int k = i + 1; k < TS_W; ++k) x = fma(-readlane_f64(row[k], i), xc[k], x);
-        x *= 1.0 / readlane_f64(row[i], i);
-      }
-      xc[i] = x;
-    }
-    if (lane < TS_W) {
-#pragma unroll
-      for (int i = 0; i < TS_W; ++i) {
-        Ui[i][lane] = own ? xc[i] : 0.0;
-        Us[lane][i] = (own && i >= lane) ? row[i] : 0.0;
-        Lo[lane + i * TS_W] = own ? ((i < lane) ? row[i] : ((i == lane) ? 1.0 : 0.0)) : 0.0;
-      }
+    for (int v = 0; v < 4; ++v) {
+      const int j = tile_col(tj, v);
+      X2[ri][j] = Q0[ri][j] - c[v];  // Q_00 (zero beyond w)
     }
   }
   __syncthreads();
-  // T = -U S L1^{-T} (upper)
+  // LU of Q_00 - S in LDS by all threads, one barrier per step: the sign s_k
+  // is chosen so that |pivot| >= 1, and the trailing block is updated with
+  // the unscaled column k (L(i, k) = X2(i, k) / pivot_k afterwards).
+  for (int k = 0; k < w; ++k) {
+    const double akk = X2[k][k];
+    const double sk = (akk >= 0.0) ? -1.0 : 1.0;
+    const double piv = akk - sk;
+    const double rp = 1.0 / piv;
+    if (tid == 0) { sg[k] = sk; pv[k] = piv; }
+#pragma unroll
+    for (int q = 0; q < TS_W * TS_W / TS_NT; ++q) {
+      const int e = tid + TS_NT * q;
+      const int i = e & (TS_W - 1), j = e / TS_W;
+      if (i > k && j > k && i < w && j < w) X2[i][j] = fma(-X2[i][k] * rp, X2[k][j], X2[i][j]);
+    }
+    __syncthreads();
+  }
+  // U (pivots on the diagonal) and L^T (unit diagonal), identity beyond w, for
+  // the inverses; L to global memory
+  double (*Us)[TS_W1] = T0s;  // U
+  double (*Lt)[TS_W1] = Y0;   // L^T
+  double (*Ui)[TS_W1] = Q0;   // U^{-1}
+  double (*Li)[TS_W1] = Z;    // L1^{-T}
   for (int e = tid; e < TS_W * TS_W; e += TS_NT) {
     const int i = e & (TS_W - 1), j = e / TS_W;
-    double s = 0.0;
+    const bool in = i < w && j < w;
+    Us[i][j] = in ? ((i < j) ? X2[i][j] : ((i == j) ? pv[i] : 0.0)) : ((i == j) ? 1.0 : 0.0);
+    Lt[i][j] = in ? ((i < j) ? X2[j][i] / pv[i] : ((i == j) ? 1.0 : 0.0)) : ((i == j) ? 1.0 : 0.0);
+    Lo[i + TS_W * j] = in ? ((i > j) ? X2[i][j] / pv[j] : ((i == j) ? 1.0 : 0.0)) : 0.0;
+  }
+  __syncthreads();
+  lds_upper_inverse32x2(Us, Ui, Lt, Li, Ts);
+  {  // T = -U S L1^{-T} (upper)
+    const d4 c = mfma_tile<TS_W>([&](int i, int k) { return Us[i][k] * sg[k]; },
+                                 [&](int k, int j) { return Li[k][j]; }, ti, tj);
 #pragma unroll
-    for (int q = 0; q < TS_W; ++q) s = fma(Us[i][q] * sg[q], Li[q][j], s);
-    Tfin[i + (long long)j * TS_W] = (i <= j) ? -s : 0.0;
+    for (int v = 0; v < 4; ++v) {
+      const int j = tile_col(tj, v);
+      Tfin[ri + (long long)j * TS_W] = (ri <= j && ri < w && j < w) ? -c[v] : 0.0;
+    }
   }
   // R = S R_tsqr into the matrix (top w logical rows = segment 1), zeros below the diagonal
   for (int e = tid; e < w * w; e += TS_NT) {
     const int i = e % w, j = e / w;
     M[ts_phys(i, h1, r1a, r2a) + (long long)(c0 + j) * ldm] = (i <= j) ? sg[i] * Rf[i][j] : 0.0;
   }
-  // U^{-1} and S for the row expansion (L1 was written above)
-  for (int e = tid; e < TS_W * TS_W; e += TS_NT) Uo[e] = Ui[e % TS_W][e / TS_W];
+  // U^{-1} (zero beyond w) and S for the row expansion (L1 was written above)
+  for (int e = tid; e < TS_W * TS_W; e += TS_NT) {
+    const int i = e % TS_W, j = e / TS_W;
+    Uo[e] = (i < w && j < w) ? Ui[i][j] : 0.0;
+  }
   if (tid < w) So[tid] = sg[tid];
 }
 
@@ -471,16 +510,19 @@ __global__ __launch_bounds__(TS_NT) void tsqr_tree_kernel(
 // With M2 = T_p Y_p(0:w, :)^T Q_top,p, the row i of the panel's Q is
 // q = [Q_top,p; 0](i, :) - y M2 (y = Y_p(i, :)), so v = q U^{-1} =
 // Q3(i, :) - y M3 with Q3 = Q_top,p U^{-1} and M3 = M2 U^{-1} formed once per
-// block; y stays in registers and v is produced one column at a time.
+// block (32 x 32 products, one MFMA tile per wave); the block's rows of V are
+// then one 256 x 32 x 32 product, Y_p read straight from V in MFMA fragments.
 __global__ __launch_bounds__(TS_NT) void tsqr_expand_kernel(
     double* M, long long ldm, long long sM, int c0, int w, int h1, int r1a, int r2a, int h, int P,
     double* V, long long ldv, long long sV, int vr2, const double* Tloc, const double* Ytop,
     const double* Zg, const double* Uinv, const double* Lo, long long sScr) {
   __shared__ double Qt[TS_W][TS_W1];
   __shared__ double Us[TS_W][TS_W1];  // U^{-1}
-  __shared__ double M1[TS_W][TS_W1];  // Y_p^T Q_top,p, then M3
-  __shared__ double M2[TS_W][TS_W1];
+  __shared__ double M1[TS_W][TS_W1];  // Y_top,p, then Y_p^T Q_top,p, then M3
+  __shared__ double M2[TS_W][TS_W1];  // Z, then M2
   __shared__ double Q3[TS_W][TS_W1];
+  __shared__ double Yp[TS_W][TS_W1];  // Y_p(0:32, :)
+  __shared__ double Tp[TS_W][TS_W1];  // T_p
   const int p = blockIdx.x;
   const long long b = blockIdx.y;
   M += b * sM;
@@ -495,74 +537,95 @@ __global__ __launch_bounds__(TS_NT) void tsqr_expand_kernel(
   const int rows = min(TS_MB, h - i0);
   const int wy = min(w, rows);  // rows of Y_p that meet [Q_top,p; 0]
   const int ldr = P * TS_W;
-  const double* Tp = Tloc + (long long)p * TS_W * TS_W;
-  // Q_top,p = [I; 0]_p - Y_top,p Z (Y_top,p = rows p w .. p w + w - 1 of Y_top);
-  // M1 and M2 hold Y_top,p and Z until Qt is formed
+  const double* Tpg = Tloc + (long long)p * TS_W * TS_W;
   for (int e = tid; e < TS_W * TS_W; e += TS_NT) {
     const int i = e % TS_W, j = e / TS_W;
     const bool in = i < w && j < w;
     M1[i][j] = in ? Ytop[(p * w + i) + (long long)j * ldr] : 0.0;
     M2[i][j] = Zg[e];
-    Us[i][j] = in ? Uinv[i + j * TS_W] : 0.0;
+    Us[i][j] = in ? Uinv[e] : 0.0;
+    Yp[i][j] = (i < wy && j < w)
+                   ? ((i > j) ? V[ts_vrow(i0 + i, h1, vr2) + (long long)j * ldv] : ((i == j) ? 1.0 : 0.0))
+                   : 0.0;
+    Tp[i][j] = (in && i <= j) ? Tpg[e] : 0.0;
   }
   __syncthreads();
-  for (int e = tid; e < TS_W * TS_W; e += TS_NT) {
-    const int i = e % TS_W, j = e / TS_W;
-    double q = (p == 0 && i == j) ? 1.0 : 0.0;
+  const int wave = tid >> 6;
+  const int ti = wave & 1, tj = wave >> 1, ri = tile_row(ti);
+  {  // Q_top,p = [I; 0]_p - Y_top,p Z
+    const d4 c = mfma_tile<TS_W>([&](int i, int k) { return M1[i][k]; },
+                                 [&](int k, int j) { return M2[k][j]; }, ti, tj);
 #pragma unroll
-    for (int k = 0; k < TS_W; ++k) q = fma(-M1[i][k], M2[k][j], q);
-    Qt[i][j] = (i < w && j < w) ? q : 0.0;
-  }
-  __syncthreads();
-  // M1 = Y_p(0:wy, :)^T Q_top,p(0:wy, :) (Y_p unit lower on its first rows);
-  // Q3 = Q_top,p U^{-1}
-  for (int e = tid; e < TS_W * TS_W; e += TS_NT) {
-    const int i = e % TS_W, j = e / TS_W;
-    double s = 0.0, s3 = 0.0;
-    if (i < w && j < w) {
-      for (int q = i; q < wy; ++q)
-        s = fma((q == i) ? 1.0 : V[ts_vrow(i0 + q, h1, vr2) + (long long)i * ldv], Qt[q][j], s);
-      for (int q = 0; q <= j; ++q) s3 = fma(Qt[i][q], Us[q][j], s3);
+    for (int v = 0; v < 4; ++v) {
+      const int j = tile_col(tj, v);
+      Qt[ri][j] = (ri < w && j < w) ? (((p == 0 && ri == j) ? 1.0 : 0.0) - c[v]) : 0.0;
     }
-    M1[i][j] = s;
-    Q3[i][j] = s3;
   }
   __syncthreads();
-  for (int e = tid; e < TS_W * TS_W; e += TS_NT) {
-    const int i = e % TS_W, j = e / TS_W;
-    double s = 0.0;  // rows/columns beyond w stay exactly zero
-    if (i < w && j < w)
-      for (int q = i; q < w; ++q) s = fma(Tp[i + q * TS_W], M1[q][j], s);
-    M2[i][j] = s;
+  {  // M1 = Y_p(0:32, :)^T Q_top,p and Q3 = Q_top,p U^{-1}
+    const d4 c = mfma_tile<TS_W>([&](int i, int k) { return Yp[k][i]; },
+                                 [&](int k, int j) { return Qt[k][j]; }, ti, tj);
+    const d4 c3 = mfma_tile<TS_W>([&](int i, int k) { return Qt[i][k]; },
+                                  [&](int k, int j) { return Us[k][j]; }, ti, tj);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int j = tile_col(tj, v);
+      M1[ri][j] = c[v];
+      Q3[ri][j] = c3[v];
+    }
+  }
+  __syncthreads();
+  {  // M2 = T_p M1
+    const d4 c = mfma_tile<TS_W>([&](int i, int k) { return Tp[i][k]; },
+                                 [&](int k, int j) { return M1[k][j]; }, ti, tj);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) M2[ri][tile_col(tj, v)] = c[v];
   }
   __syncthreads();
   double (*M3)[TS_W1] = M1;
-  for (int e = tid; e < TS_W * TS_W; e += TS_NT) {
-    const int i = e % TS_W, j = e / TS_W;
-    double s = 0.0;
-    if (i < w && j < w)
-      for (int q = 0; q <= j; ++q) s = fma(M2[i][q], Us[q][j], s);
-    M3[i][j] = s;
+  {  // M3 = M2 U^{-1}
+    const d4 c = mfma_tile<TS_W>([&](int i, int k) { return M2[i][k]; },
+                                 [&](int k, int j) { return Us[k][j]; }, ti, tj);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) M3[ri][tile_col(tj, v)] = c[v];
   }
   __syncthreads();
-  if (tid < rows) {
-    const int i = tid;
-    const int gi = i0 + i;
-    const long long vi = ts_vrow(gi, h1, vr2);
-    if (p == 0 && i < w) {
-      for (int j = 0; j < w; ++j) V[vi + (long long)j * ldv] = Lo[i + j * TS_W];
-    } else {
-      double y[TS_W];
+  // rows of V: V(i, :) = Q3(i, :) - Y_p(i, :) M3 (Q3 is zero beyond row 31); on
+  // block 0 the first w rows are L1.  Each wave owns row tiles wave, wave + 4, ...
+  // and both column tiles, and reads its Y fragments from V before it writes V.
+  const int lane = tid & 63;
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int rt = wave; rt * 16 < rows; rt += 4) {
+    const int il = 16 * rt + lr;  // the row this lane feeds
+    const bool rin = il < rows;
+    const long long vi = rin ? ts_vrow(i0 + il, h1, vr2) : 0;
+    d4 c0t = {0.0, 0.0, 0.0, 0.0}, c1t = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int k = 0; k < TS_W; ++k) y[k] = (k < w) ? V[vi + (long long)k * ldv] : 0.0;
-#pragma unroll 2
-      for (int j = 0; j < w; ++j) {
-        double v = (i < TS_W) ? Q3[i][j] : 0.0;
+    for (int kk = 0; kk < TS_W; kk += 4) {
+      const int k = kk + lk;
+      const double y = (rin && k < w) ? V[vi + (long long)k * ldv] : 0.0;
+      c0t = __builtin_amdgcn_mfma_f64_16x16x4f64(M3[k][lr], y, c0t, 0, 0, 0);
+      c1t = __builtin_amdgcn_mfma_f64_16x16x4f64(M3[k][16 + lr], y, c1t, 0, 0, 0);
+    }
+    // lane l item v holds row 16 rt + l % 16, column 16 tj + 4 v + l / 16
+    if (rin) {
 #pragma unroll
-        for (int k = 0; k < TS_W; ++k) v = fma(-y[k], M3[k][j], v);
-        V[vi + (long long)j * ldv] = v;
+      for (int v = 0; v < 4; ++v) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+          const int j = 16 * t + 4 * v + lk;
+          if (j < w) {
+            double val;
+            if (p == 0 && il < w) val = Lo[il + TS_W * j];
+            else val = ((il < TS_W) ? Q3[il][j] : 0.0) - (t ? c1t[v] : c0t[v]);
+            V[vi + (long long)j * ldv] = val;
+          }
+        }
       }
     }
+  }
+  if (tid < rows) {
+    const int gi = i0 + tid;
     if (gi >= w) {
       const long long pr = ts_phys(gi, h1, r1a, r2a);
       for (int j = 0; j < w; ++j) M[pr + (long long)(c0 + j) * ldm] = 0.0;

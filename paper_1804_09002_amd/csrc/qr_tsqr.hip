@@ -16,10 +16,12 @@
 //   C. every block forms its piece Q_top,p = [I; 0]_p - Y_top,p Z and its rows of
 //      the explicit Q, Q_p = (I - Y_p T_p Y_p^T) [Q_top,p; 0], and of V = Q U^{-1}.
 // Each stage is parallel over rows; only the w x w pieces are sequential.
-// The Householder factorisations keep the matrix in registers, one row (or a
-// few) per thread: a step needs the dot products of the pivot column with all
-// 32 columns, which one butterfly over the wave and a 4-way sum across the
-// waves deliver together, so a step costs two barriers.
+// The Householder factorisations keep the matrix in registers, four columns
+// per lane (eight lanes hold a row): a step swizzles the pivot column to the
+// eight lanes of each row, every lane forms the dot products with its four
+// columns, and a short butterfly plus one sum over the waves gives all 32
+// products at once, so a step costs one barrier.  The stacked R
+// factors and Y_top are kept row-major, so these loads and stores coalesce.
 // The result is interchangeable with a column-by-column Householder panel
 // (same R up to row signs, V unit lower trapezoidal, H = I - V T V^T).
 #include <algorithm>
@@ -35,7 +37,9 @@ namespace zcsd {
 constexpr int TS_NT = 256;
 constexpr int TS_W = 32;  // panel width handled here
 constexpr int TS_W1 = TS_W + 1;
-constexpr int TS_TREE_RPT = (TS_PMAX * TS_W + TS_NT - 1) / TS_NT;  // rows per thread in the tree
+constexpr int TS_LOCAL_RQ = TS_MB / (8 * (TS_NT / 64));  // row slots per lane, local
+constexpr int TS_TREE_NT = 512;                           // tree workgroup
+constexpr int TS_TREE_RQ = (TS_PMAX * TS_W + TS_TREE_NT / 8 - 1) / (TS_TREE_NT / 8);  // tree
 
 __device__ __forceinline__ int ts_phys(int i, int h1, int r1a, int r2a) {
   return i < h1 ? r1a + i : r2a + (i - h1);
@@ -49,6 +53,25 @@ __device__ __forceinline__ double dpp_f64(double v) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xf, 0xf, false);
   const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// ds_swizzle in bit mode on both halves of a double: lane l (within its 32-lane
+// half) reads lane ((l & AND) | OR) ^ XOR
+template <int AND, int OR, int XOR>
+__device__ __forceinline__ double swizzle_f64(double v) {
+  constexpr int pat = AND | (OR << 5) | (XOR << 10);
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_swizzle((int)b, pat);
+  const int hi = __builtin_amdgcn_ds_swizzle((int)(b >> 32), pat);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// lane l reads lane src (0..63)
+__device__ __forceinline__ double bperm_f64(double v, int src) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)b);
+  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b >> 32));
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
@@ -82,39 +105,6 @@ __device__ __forceinline__ double swap_sum(double a, double b) {
          __longlong_as_double(((long long)b1 << 32) | b0);
 }
 
-// One DPP halving step: partner lanes exchange the halves they do not keep;
-// `hi` lanes keep the upper half.  The halves are chosen with a bit mask, not
-// with a conditional on the array index (which the compiler may turn into a
-// dynamic index and demote x to memory).
-template <int CTRL, int HS>
-__device__ __forceinline__ void dpp_halve(double (&x)[TS_W], bool hi) {
-  const long long m = hi ? -1LL : 0LL;
-#pragma unroll
-  for (int k = 0; k < HS; ++k) {
-    const long long lo = __double_as_longlong(x[k]), up = __double_as_longlong(x[k + HS]);
-    const double keep = __longlong_as_double((up & m) | (lo & ~m));
-    const double send = __longlong_as_double((lo & m) | (up & ~m));
-    x[k] = keep + dpp_f64<CTRL>(send);
-  }
-}
-
-// Sum over the 64 lanes of a wave of 32 values per lane by recursive halving:
-// partners lane ^ 32 and lane ^ 16 (permlane swaps), lane ^ 8 (DPP row_ror:8),
-// lane ^ 7 within 8-lane groups (row_half_mirror), lane ^ 2 and a last pairwise
-// add with lane ^ 1 (quad_perm).  The partner of every step agrees with the lane
-// on all bits used before, so lane l returns the sum of x[(l >> 1) & 31].
-__device__ __forceinline__ double wave_sum32(double (&x)[TS_W]) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int k = 0; k < 16; ++k) x[k] = swap_sum<true>(x[k], x[k + 16]);
-#pragma unroll
-  for (int k = 0; k < 8; ++k) x[k] = swap_sum<false>(x[k], x[k + 8]);
-  dpp_halve<0x128, 4>(x, (lane & 8) != 0);  // row_ror:8
-  dpp_halve<0x141, 2>(x, (lane & 4) != 0);  // row_half_mirror
-  dpp_halve<0x4E, 1>(x, (lane & 2) != 0);   // quad_perm [2,3,0,1]
-  return x[0] + dpp_f64<0xB1>(x[0]);        // quad_perm [1,0,3,2]
-}
-
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 // 16 x 16 tile (ti, tj) of C = X Y with K = KD on the FP64 matrix cores;
@@ -138,14 +128,16 @@ __device__ __forceinline__ int tile_col(int tj, int v) { return 16 * tj + 4 * v 
 
 // Inverse of the upper-triangular 32 x 32 A (LDS, exact zeros below the
 // diagonal, identity beyond the active size) into I, for two matrices at once
-// (m = 0, 1): the 16 x 16 diagonal blocks by back substitution, one column per
-// thread (threads 0..63), then (I)_AB = -I_A (A_AB I_B) as two 16 x 16 MFMA
-// products (wave m); X (32 x 32) is scratch.  Three barriers.
+// (m = 0, 1; A1 may be null): the 16 x 16 diagonal blocks by back
+// substitution, one column per thread (threads 0..63), then (I)_AB = -I_A
+// (A_AB I_B) as two 16 x 16 MFMA products (wave m); X (32 x 32) is scratch.
+// Three barriers.
 __device__ void lds_upper_inverse32x2(const double (*A0)[TS_W1], double (*I0)[TS_W1],
                                       const double (*A1)[TS_W1], double (*I1)[TS_W1],
                                       double (*X)[TS_W1]) {
   const int tid = threadIdx.x, wave = tid >> 6;
-  if (tid < 64) {
+  const int nm = A1 ? 2 : 1;
+  if (tid < 32 * nm) {
     const int m = tid >> 5, o = tid & 16, c = tid & 15;
     const double (*A)[TS_W1] = m ? A1 : A0;
     double (*I)[TS_W1] = m ? I1 : I0;
@@ -159,14 +151,14 @@ __device__ void lds_upper_inverse32x2(const double (*A0)[TS_W1], double (*I0)[TS
     }
 #pragma unroll
     for (int i = 0; i < 16; ++i) I[o + i][o + c] = x[i];
-  } else if (tid < 128) {  // the block below the diagonal of both inverses
+  } else if (tid >= 64 && tid < 64 + 32 * nm) {  // the blocks below the diagonal
     const int m = (tid >> 5) & 1, c = tid & 15, r0 = tid & 16;
     double (*I)[TS_W1] = m ? I1 : I0;
 #pragma unroll
     for (int i = 0; i < 8; ++i) I[16 + (r0 >> 1) + i][c] = 0.0;
   }
   __syncthreads();
-  if (wave < 2) {
+  if (wave < nm) {
     const double (*A)[TS_W1] = wave ? A1 : A0;
     double (*I)[TS_W1] = wave ? I1 : I0;
     const d4 t = mfma_tile<16>([&](int i, int k) { return A[i][16 + k]; },
@@ -175,7 +167,7 @@ __device__ void lds_upper_inverse32x2(const double (*A0)[TS_W1], double (*I0)[TS
     for (int v = 0; v < 4; ++v) X[16 * wave + tile_row(0)][tile_col(0, v)] = t[v];
   }
   __syncthreads();
-  if (wave < 2) {
+  if (wave < nm) {
     double (*I)[TS_W1] = wave ? I1 : I0;
     const d4 t = mfma_tile<16>([&](int i, int k) { return I[i][k]; },
                                [&](int k, int j) { return X[16 * wave + k][j]; }, 0, 0);
@@ -185,52 +177,75 @@ __device__ void lds_upper_inverse32x2(const double (*A0)[TS_W1], double (*I0)[TS
   __syncthreads();
 }
 
-// Householder QR of a rows x w matrix (w <= 32) held in registers: row
-// i = threadIdx.x + TS_NT * r is a[r][:]; entries beyond rows / w are zero.
-// Step t forms d_j = sum_{i >= t} a_it a_ij for every j at once; with
-// alpha = a_tt, beta = -sign(alpha) sqrt(d_t), v = (a_t - beta e_t)/(alpha - beta)
-// (v_t = 1), tau = (beta - alpha)/beta, the products v^T a_j = (d_j - beta a_tj)
-// / (alpha - beta) serve both the update a_j -= tau v (v^T a_j) (j > t) and the
-// column t of T, T(0:t, t) = -tau T(0:t, 0:t) Y(:, 0:t)^T v (k < t).
-// On return the rows hold R (upper, diagonal beta) and the vectors below the
-// diagonal (unit diagonal implicit), and T is in Ts.
-// One barrier per step: the per-wave partial sums and the pivot row go to
-// double-buffered LDS (a buffer is rewritten two steps later, after every wave
-// has passed the next barrier), each lane reads back the sums of its own
-// column, and the pivot scalars and the update coefficients are broadcast with
-// readlane.  LDS: red[2 * 4 * 32], rowb[2 * 32], zb[32].
-template <int t, int RPT>
-__device__ __forceinline__ void reg_householder_step(double (&a)[RPT][TS_W], int rows,
-                                                     double (*Ts)[TS_W1], double* red, double* rowb,
-                                                     double* zb) {
+// Householder QR of a rows x w matrix (w <= 32) held in registers, four
+// columns per lane: lane l of wave v holds columns 4g .. 4g + 3 (g = l % 8) on
+// the rows i = 8 RQ v + 8 r + h (h = l / 8), r < RQ, in a[r][0..3] (zeros
+// beyond rows and w).
+// Step t sends the pivot column to the eight lanes of each row set with one
+// swizzle (its rows above t zeroed); every lane forms the partial dot products
+// of the pivot column with its four columns; a butterfly over the eight row
+// sets of the wave (lane ^ 32, ^ 16, ^ 8) leaves one column's wave sum per
+// lane, the waves are summed through LDS (one barrier) and each lane gathers
+// the totals of its four columns: d_j = sum_{i >= t} a_it a_ij for every j at
+// once.  With alpha = a_tt, beta = -sign(alpha) sqrt(d_t), tau = (beta -
+// alpha) / beta and scal = 1 / (alpha - beta), the reflector is
+// v = scal (a_t - beta e_t) and v^T a_j = scal (d_j - beta a_tj), so columns
+// j > t are updated in place with their own coefficients.  Column t is left
+// unscaled: the lane keeps scal_t and beta_t, and the vector is
+// y_t = scal_t a_t below the diagonal (products with it carry a factor
+// scal_t).  The same sums give column t of the strictly upper part of Y^T Y
+// (y_k^T v, k < t), kept with tau_t for T after the loop.
+// On return, for a lane column j: rows i < j hold R(i, j), R(j, j) = beta_j,
+// rows i > j hold Y(i, j) / scal_j.
+// NW (4 or 8) waves of 64 lanes.  LDS: red[2 * NW * 32], rowb[2 * 32],
+// Zm[32][33], taus[32].
+template <int t, int RQ, int NW>
+__device__ __forceinline__ void ql_householder_step(double (&a)[RQ][4], double (&myscal)[4],
+                                                    double (&mybeta)[4], double (*Zm)[TS_W1],
+                                                    double* taus, double* red, double* rowb) {
+  static_assert(NW == 4 || NW == 8, "4 or 8 waves");
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane & 7, h = lane >> 3;
+  constexpr int gt = t >> 2, qt = t & 3;  // the lanes g == gt hold column t in slot qt
+  constexpr int rt = t >> 3, ht = t & 7;  // row t: wave 0, slot rt, row set ht
   constexpr int buf = t & 1;
-  double* rb = red + buf * 4 * TS_W;     // [wave][j] partial sums of this step
-  double* pr = rowb + buf * TS_W;        // pivot row a(t, :)
-  double x[TS_W];
+  // pivot column, from lane (h, gt) to the lanes (h, *); rows above t zeroed
+  double colt[RQ];
 #pragma unroll
-  for (int j = 0; j < TS_W; ++j) x[j] = 0.0;
-#pragma unroll
-  for (int r = 0; r < RPT; ++r) {
-    const int i = tid + TS_NT * r;
-    if (i >= t && i < rows) {
-      const double ait = a[r][t];
-#pragma unroll
-      for (int j = 0; j < TS_W; ++j) x[j] = fma(ait, a[r][j], x[j]);
-    }
-    if (i == t) {
-#pragma unroll
-      for (int j = 0; j < TS_W; ++j) pr[j] = a[r][j];
-    }
+  for (int r = 0; r < RQ; ++r) {
+    const double c = swizzle_f64<0x18, gt, 0>(a[r][qt]);
+    colt[r] = (8 * r < t && wave == 0 && 8 * r + h < t) ? 0.0 : c;
   }
-  const double sj = wave_sum32(x);
-  const int jl = (lane >> 1) & 31;  // the column this lane's sum belongs to
-  if ((lane & 1) == 0) rb[wave * TS_W + jl] = sj;
+  double p[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int r = 0; r < RQ; ++r)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) p[q] = fma(colt[r], a[r][q], p[q]);
+  // sum over the row sets: lane ^ 32 keeps q in {0,1} / {2,3}, lane ^ 16 keeps
+  // one q, lane ^ 8 adds the last pair: lane holds column 4g + ((lane >> 4) & 3)
+  const double x0 = swap_sum<true>(p[0], p[2]);
+  const double x1 = swap_sum<true>(p[1], p[3]);
+  double y = swap_sum<false>(x0, x1);
+  y += dpp_f64<0x128>(y);  // row_ror:8
+  double* rb = red + buf * NW * TS_W;
+  double* pr = rowb + buf * TS_W;
+  const int jsel = 4 * g + ((lane >> 4) & 3);
+  if ((lane & 8) == 0) rb[wave * TS_W + jsel] = y;
+  if (wave == 0 && h == ht) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) pr[4 * g + q] = a[rt][q];  // the pivot row a(t, :)
+  }
   __syncthreads();
-  // d_j and a(t, j) for this lane's column; the pivot's through readlane
-  const double dj = (rb[jl] + rb[TS_W + jl]) + (rb[2 * TS_W + jl] + rb[3 * TS_W + jl]);
-  const double atj = pr[jl];
-  const double dt = readlane_f64(dj, 2 * t), alpha = readlane_f64(atj, 2 * t);
+  double dsel = (rb[jsel] + rb[TS_W + jsel]) + (rb[2 * TS_W + jsel] + rb[3 * TS_W + jsel]);
+  if constexpr (NW == 8)
+    dsel += (rb[4 * TS_W + jsel] + rb[5 * TS_W + jsel]) + (rb[6 * TS_W + jsel] + rb[7 * TS_W + jsel]);
+  double d[4], at[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    d[q] = bperm_f64(dsel, g + 16 * q);  // lane g + 16 q holds column 4g + q
+    at[q] = pr[4 * g + q];
+  }
+  const double dt = readlane_f64(d[qt], gt), alpha = readlane_f64(at[qt], gt);
   double tau = 0.0, beta = 0.0, scal = 0.0;
   if (dt > 0.0) {
     const double nrm = sqrt(dt);
@@ -238,59 +253,91 @@ __device__ __forceinline__ void reg_householder_step(double (&a)[RPT][TS_W], int
     tau = (beta - alpha) / beta;
     scal = 1.0 / (alpha - beta);
   }
-  // v^T a_j (j > t: the update) and y_j^T v (j < t: the T column), this lane's j
-  const double wl = scal * (dj - beta * atj);
-  double tv[RPT];
-#pragma unroll
-  for (int r = 0; r < RPT; ++r) {
-    const int i = tid + TS_NT * r;
-    const double v = (i > t && i < rows) ? scal * a[r][t] : ((i == t) ? 1.0 : 0.0);
-    tv[r] = tau * v;
-    if (i > t && i < rows) a[r][t] = v;
-    else if (i == t) a[r][t] = beta;
+  if (g == gt) {
+    myscal[qt] = scal;
+    mybeta[qt] = beta;
   }
+  // w_q = v^T a_j (j > t) or (y_j^T v) / scal_j (j < t), j = 4g + q
+  double coef[4], c2[4], wq[4];
 #pragma unroll
-  for (int j = t + 1; j < TS_W; ++j) {
-    const double wj = readlane_f64(wl, 2 * j);
-#pragma unroll
-    for (int r = 0; r < RPT; ++r) a[r][j] = fma(-tv[r], wj, a[r][j]);
+  for (int q = 0; q < 4; ++q) {
+    wq[q] = scal * (d[q] - beta * at[q]);
+    coef[q] = (4 * g + q > t) ? tau * wq[q] : 0.0;
+    c2[q] = coef[q] * scal;
   }
-  // column t of T, by wave 0 (its even lanes hold every y_k^T v)
-  if (wave == 0) {
-    if ((lane & 1) == 0) zb[jl] = wl;
-    __builtin_amdgcn_wave_barrier();
-    if (lane < t) {
-      double s = 0.0;
+  // a_j -= tau v (v^T a_j), j > t; v = scal * pivot column below row t, 1 on row t
+  const bool onrow = (wave == 0 && h == ht);
 #pragma unroll
-      for (int k = 0; k < t; ++k) s = fma(Ts[lane][k], zb[k], s);
-      Ts[lane][t] = -tau * s;
-    } else if (lane == t) {
-      Ts[t][t] = tau;
+  for (int r = 0; r < RQ; ++r) {
+    if (r == rt) {
+      const double vr = onrow ? 1.0 : scal * colt[r];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[r][q] = fma(-coef[q], vr, a[r][q]);
+    } else {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[r][q] = fma(-c2[q], colt[r], a[r][q]);
     }
+  }
+  // strictly upper Y^T Y (column t: y_k^T v = scal_k w, k < t) and tau
+  if (tid < 8) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (4 * g + q < t) Zm[4 * g + q][t] = myscal[q] * wq[q];
+    if (g == gt) taus[t] = tau;
   }
 }
 
 // the 32 steps, unrolled at compile time so that every register index is static
-template <int t, int RPT>
-__device__ __forceinline__ void reg_householder_steps(double (&a)[RPT][TS_W], int rows, int w,
-                                                      double (*Ts)[TS_W1], double* red,
-                                                      double* rowb, double* zb) {
+template <int t, int RQ, int NW>
+__device__ __forceinline__ void ql_householder_steps(double (&a)[RQ][4], int w, double (&myscal)[4],
+                                                     double (&mybeta)[4], double (*Zm)[TS_W1],
+                                                     double* taus, double* red, double* rowb) {
   if constexpr (t < TS_W) {
     if (t < w) {
-      reg_householder_step<t, RPT>(a, rows, Ts, red, rowb, zb);
-      reg_householder_steps<t + 1, RPT>(a, rows, w, Ts, red, rowb, zb);
+      ql_householder_step<t, RQ, NW>(a, myscal, mybeta, Zm, taus, red, rowb);
+      ql_householder_steps<t + 1, RQ, NW>(a, w, myscal, mybeta, Zm, taus, red, rowb);
     }
   }
 }
 
-// Ts (LDS, 32 x 33) receives T; it is zeroed here and complete after the
-// caller's next barrier.
-template <int RPT>
-__device__ void reg_householder(double (&a)[RPT][TS_W], int rows, int w, double (*Ts)[TS_W1],
-                                double* red, double* rowb, double* zb) {
-  for (int e = threadIdx.x; e < TS_W * TS_W1; e += TS_NT) (&Ts[0][0])[e] = 0.0;
+// The factorisation, then T from the UT relation T^{-1} = striu(Y^T Y) +
+// diag(1 / tau) (for H = I - Y T Y^T with T upper triangular), inverted by
+// 16 x 16 blocks on the matrix cores.  A step with tau = 0 (a zero column, H =
+// I) is decoupled: its row and column of T are zero.  Ts receives T; Zm and X
+// (32 x 33 each) and taus[32] are scratch.  Ends with a barrier.
+template <int RQ, int NW>
+__device__ void ql_householder(double (&a)[RQ][4], int w, double (&myscal)[4], double (&mybeta)[4],
+                               double (*Ts)[TS_W1], double (*Zm)[TS_W1], double (*X)[TS_W1],
+                               double* taus, double* red, double* rowb) {
+  if (threadIdx.x < TS_W) taus[threadIdx.x] = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    myscal[q] = 0.0;
+    mybeta[q] = 0.0;
+  }
   __syncthreads();
-  reg_householder_steps<0, RPT>(a, rows, w, Ts, red, rowb, zb);
+  ql_householder_steps<0, RQ, NW>(a, w, myscal, mybeta, Zm, taus, red, rowb);
+  __syncthreads();
+  for (int e = threadIdx.x; e < TS_W * TS_W; e += 64 * NW) {
+    const int i = e & (TS_W - 1), jj = e / TS_W;
+    const double ti = taus[i], tj = taus[jj];
+    double v = 0.0;
+    if (i < jj) v = (ti != 0.0 && tj != 0.0) ? Zm[i][jj] : 0.0;
+    else if (i == jj) v = (ti != 0.0) ? 1.0 / ti : 1.0;
+    Zm[i][jj] = v;
+  }
+  __syncthreads();
+  lds_upper_inverse32x2(Zm, Ts, nullptr, nullptr, X);
+  if (threadIdx.x < TS_W && taus[threadIdx.x] == 0.0) Ts[threadIdx.x][threadIdx.x] = 0.0;
+  __syncthreads();
+}
+
+// R(i, j) and Y(i, j) of a lane column j on logical row i (see above)
+__device__ __forceinline__ double cl_rval(double v, int i, int j, double mybeta) {
+  return (i < j) ? v : ((i == j) ? mybeta : 0.0);
+}
+__device__ __forceinline__ double cl_yval(double v, int i, int j, double myscal) {
+  return (i < j) ? 0.0 : ((i == j) ? 1.0 : myscal * v);
 }
 // ---------------------------------------------------------------------------
 // A: local QR of every row block
@@ -298,51 +345,59 @@ __global__ __launch_bounds__(TS_NT) void tsqr_local_kernel(
     const double* M, long long ldm, long long sM, int c0, int w, int h1, int r1a, int r2a, int h,
     int P, double* V, long long ldv, long long sV, int vr2, double* Tloc, double* Rstack,
     long long sScr) {
-  __shared__ double red[2 * 4 * TS_W], rowb[2 * TS_W], zb[TS_W];
+  __shared__ double red[2 * 4 * TS_W], rowb[2 * TS_W], taus[TS_W];
   __shared__ double Ts[TS_W][TS_W1];
+  __shared__ double Zm[TS_W][TS_W1];
+  __shared__ double Xs[TS_W][TS_W1];
   const int p = blockIdx.x;
   const long long b = blockIdx.y;
   M += b * sM;
   V += b * sV;
   const int i0 = p * TS_MB;
   const int rows = min(TS_MB, h - i0);
-  const int tid = threadIdx.x;
-  double a[1][TS_W];
-  {
-    const long long pr = (tid < rows) ? ts_phys(i0 + tid, h1, r1a, r2a) : 0;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int g = lane & 7, hs = lane >> 3;
+  double a[TS_LOCAL_RQ][4];
 #pragma unroll
-    for (int j = 0; j < TS_W; ++j)
-      a[0][j] = (tid < rows && j < w) ? M[pr + (long long)(c0 + j) * ldm] : 0.0;
-  }
-  reg_householder<1>(a, rows, w, Ts, red, rowb, zb);
-  // Y_p (unit lower trapezoidal) into V's rows, R_p (upper w x w, zero rows
-  // beyond the block), T_p
-  if (tid < rows) {
+  for (int r = 0; r < TS_LOCAL_RQ; ++r) {
+    const int i = 8 * TS_LOCAL_RQ * wave + 8 * r + hs;
+    const long long pr = (i < rows) ? ts_phys(i0 + i, h1, r1a, r2a) : 0;
 #pragma unroll
-    for (int j = 0; j < TS_W; ++j)
-      if (j < w)
-        V[ts_vrow(i0 + tid, h1, vr2) + (long long)j * ldv] = (tid < j) ? 0.0 : ((tid == j) ? 1.0 : a[0][j]);
+    for (int q = 0; q < 4; ++q) {
+      const int j = 4 * g + q;
+      a[r][q] = (i < rows && j < w) ? M[pr + (long long)(c0 + j) * ldm] : 0.0;
+    }
   }
-  const int ldr = P * TS_W;
-  if (tid < w) {
-    double* Rp = Rstack + b * sScr;
+  double myscal[4], mybeta[4];
+  ql_householder<TS_LOCAL_RQ, TS_NT / 64>(a, w, myscal, mybeta, Ts, Zm, Xs, taus, red, rowb);
+  // R_p (rows 0..31 of the block, row-major, zero beyond the block and w) and
+  // Y_p (unit lower trapezoidal) into V's rows, straight from the lanes
+  double* Rp = Rstack + b * sScr;
 #pragma unroll
-    for (int j = 0; j < TS_W; ++j)
-      if (j < w) Rp[(p * w + tid) + (long long)j * ldr] = (j >= tid && tid < rows) ? a[0][j] : 0.0;
+  for (int r = 0; r < TS_LOCAL_RQ; ++r) {
+    const int i = 8 * TS_LOCAL_RQ * wave + 8 * r + hs;
+    const long long vi = (i < rows) ? ts_vrow(i0 + i, h1, vr2) : 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = 4 * g + q;
+      if (8 * r < TS_W && wave == 0 && i < w)
+        Rp[(p * w + i) * TS_W + j] = (j < w && i < rows) ? cl_rval(a[r][q], i, j, mybeta[q]) : 0.0;
+      if (i < rows && j < w) V[vi + (long long)j * ldv] = cl_yval(a[r][q], i, j, myscal[q]);
+    }
   }
-  __syncthreads();
   double* Tp = Tloc + b * sScr + (long long)p * TS_W * TS_W;
   for (int e = tid; e < TS_W * TS_W; e += TS_NT) Tp[e] = Ts[e % TS_W][e / TS_W];
 }
 
 // B: QR of the stacked R factors (registers), explicit Q_top, reconstruction
 // pieces (w x w work in LDS).
-__global__ __launch_bounds__(TS_NT) void tsqr_tree_kernel(
+__global__ __launch_bounds__(TS_TREE_NT) void tsqr_tree_kernel(
     double* M, long long ldm, long long sM, int c0, int w, int h1, int r1a, int r2a, int P,
     const double* V, long long ldv, long long sV, int vr2, const double* Tloc, const double* Rstack,
     double* Qtop, double* Zo, double* Uo, double* Lo, double* So, long long sScr, double* Tfin,
     long long sT) {
-  __shared__ double red[2 * 4 * TS_W], rowb[2 * TS_W], zb[TS_W];
+  constexpr int NWT = TS_TREE_NT / 64;
+  __shared__ double red[2 * NWT * TS_W], rowb[2 * TS_W], taus[TS_W];
   __shared__ double Ts[TS_W][TS_W1];  // T_top
   __shared__ double Yt[TS_W][TS_W1];  // Y_top(0:w, 0:w), then X2
   __shared__ double Z[TS_W][TS_W1];   // T_top Y_top(0:w, :)^T, then L1^{-T}
@@ -364,57 +419,63 @@ __global__ __launch_bounds__(TS_NT) void tsqr_tree_kernel(
   Tfin += b * sT;
   const int tid = threadIdx.x;
   const int rows = P * w;
-  const int ldr = P * TS_W;
-  double a[TS_TREE_RPT][TS_W];
+  {
+    const int lane = tid & 63, wv = tid >> 6;
+    const int g = lane & 7, hs = lane >> 3;
+    double a[TS_TREE_RQ][4];
 #pragma unroll
-  for (int r = 0; r < TS_TREE_RPT; ++r) {
-    const int i = tid + TS_NT * r;
+    for (int r = 0; r < TS_TREE_RQ; ++r) {
+      const int i = 8 * TS_TREE_RQ * wv + 8 * r + hs;
 #pragma unroll
-    for (int j = 0; j < TS_W; ++j) a[r][j] = (i < rows && j < w) ? Rstack[i + (long long)j * ldr] : 0.0;
-  }
-  reg_householder<TS_TREE_RPT>(a, rows, w, Ts, red, rowb, zb);
-  // R_tsqr and Y_top(0:w, 0:w) from the first w rows (rows w..31 belong to the
-  // next block: zero here), Y_0(0:w, 0:w) and T_0 of block 0
-  if (tid < TS_W) {
-    const bool in = tid < w;
-#pragma unroll
-    for (int j = 0; j < TS_W; ++j) {
-      Rf[tid][j] = (in && j >= tid) ? a[0][j] : 0.0;
-      Yt[tid][j] = in ? ((j < tid) ? a[0][j] : ((j == tid) ? 1.0 : 0.0)) : 0.0;
+      for (int q = 0; q < 4; ++q) {
+        const int j = 4 * g + q;
+        a[r][q] = (i < rows && j < w) ? Rstack[i * TS_W + j] : 0.0;
+      }
     }
-    sg[tid] = 0.0;  // signs beyond w stay zero
+    double myscal[4], mybeta[4];
+    ql_householder<TS_TREE_RQ, NWT>(a, w, myscal, mybeta, Ts, Z, Q0, taus, red, rowb);
+    // Y_top (unit lower trapezoidal, explicit, row-major) to global memory:
+    // every expansion block forms its own rows of Q_top = [I; 0] - Y_top Z.
+    // R_tsqr and Y_top(0:w, 0:w) from the first w rows (rows w..31 belong to
+    // the next block: zero here).
+#pragma unroll
+    for (int r = 0; r < TS_TREE_RQ; ++r) {
+      const int i = 8 * TS_TREE_RQ * wv + 8 * r + hs;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = 4 * g + q;
+        const double y = cl_yval(a[r][q], i, j, myscal[q]);
+        if (i < rows) Qtop[i * TS_W + j] = (j < w) ? y : 0.0;
+        if (8 * r < TS_W && wv == 0) {
+          const bool in = i < w && j < w;
+          Rf[i][j] = in ? cl_rval(a[r][q], i, j, mybeta[q]) : 0.0;
+          Yt[i][j] = (i < w && j < w) ? y : 0.0;
+        }
+      }
+    }
   }
-  for (int e = tid; e < TS_W * TS_W; e += TS_NT) {
+  if (tid < TS_W) sg[tid] = 0.0;  // signs beyond w stay zero
+  for (int e = tid; e < TS_W * TS_W; e += TS_TREE_NT) {
     const int i = e & (TS_W - 1), j = e / TS_W;
     Y0[i][j] = (i < w && j < w)
                    ? ((i < j) ? 0.0 : ((i == j) ? 1.0 : V[ts_vrow(i, h1, vr2) + (long long)j * ldv]))
                    : 0.0;
     T0s[i][j] = Tloc[e];  // zero beyond w (written so by the local factorisation)
   }
-  // Y_top (unit lower trapezoidal, explicit) to global memory: every expansion
-  // block forms its own rows of Q_top = [I; 0] - Y_top Z
-#pragma unroll
-  for (int r = 0; r < TS_TREE_RPT; ++r) {
-    const int i = tid + TS_NT * r;
-    if (i < rows) {
-#pragma unroll
-      for (int k = 0; k < TS_W; ++k)
-        if (k < w) Qtop[i + (long long)k * ldr] = (i > k) ? a[r][k] : ((i == k) ? 1.0 : 0.0);
-    }
-  }
   __syncthreads();
   // The 32 x 32 products below run over the zero-padded range, one 16 x 16
-  // MFMA tile per wave.
+  // MFMA tile per wave on waves 0..3.
   const int wave = tid >> 6;
+  const bool mw = wave < 4;
   const int ti = wave & 1, tj = wave >> 1, ri = tile_row(ti);
-  {  // Z = T_top Y_top(0:w, :)^T
+  if (mw) {  // Z = T_top Y_top(0:w, :)^T
     const d4 c = mfma_tile<TS_W>([&](int i, int k) { return Ts[i][k]; },
                                  [&](int k, int j) { return Yt[j][k]; }, ti, tj);
 #pragma unroll
     for (int v = 0; v < 4; ++v) Z[ri][tile_col(tj, v)] = c[v];
   }
   __syncthreads();
-  {  // Q_top,0 = I - Y_top(0:32, :) Z (zero beyond w); Z to global memory
+  if (mw) {  // Q_top,0 = I - Y_top(0:32, :) Z (zero beyond w); Z to global memory
     const d4 c = mfma_tile<TS_W>([&](int i, int k) { return Yt[i][k]; },
                                  [&](int k, int j) { return Z[k][j]; }, ti, tj);
 #pragma unroll
@@ -428,21 +489,21 @@ __global__ __launch_bounds__(TS_NT) void tsqr_tree_kernel(
   // Q_00 = Q_top,0 - Y_0 T_0 (Y_0^T Q_top,0): X2 = Y_0^T Q_top,0, X3 = T_0 X2
   double (*X2)[TS_W1] = Yt;
   double (*X3)[TS_W1] = Z;
-  {
+  if (mw) {
     const d4 c = mfma_tile<TS_W>([&](int i, int k) { return Y0[k][i]; },
                                  [&](int k, int j) { return Q0[k][j]; }, ti, tj);
 #pragma unroll
     for (int v = 0; v < 4; ++v) X2[ri][tile_col(tj, v)] = c[v];
   }
   __syncthreads();
-  {
+  if (mw) {
     const d4 c = mfma_tile<TS_W>([&](int i, int k) { return T0s[i][k]; },
                                  [&](int k, int j) { return X2[k][j]; }, ti, tj);
 #pragma unroll
     for (int v = 0; v < 4; ++v) X3[ri][tile_col(tj, v)] = c[v];
   }
   __syncthreads();
-  {
+  if (mw) {
     const d4 c = mfma_tile<TS_W>([&](int i, int k) { return Y0[i][k]; },
                                  [&](int k, int j) { return X3[k][j]; }, ti, tj);
 #pragma unroll
@@ -462,10 +523,10 @@ __global__ __launch_bounds__(TS_NT) void tsqr_tree_kernel(
     const double rp = 1.0 / piv;
     if (tid == 0) { sg[k] = sk; pv[k] = piv; }
 #pragma unroll
-    for (int q = 0; q < TS_W * TS_W / TS_NT; ++q) {
-      const int e = tid + TS_NT * q;
-      const int i = e & (TS_W - 1), j = e / TS_W;
-      if (i > k && j > k && i < w && j < w) X2[i][j] = fma(-X2[i][k] * rp, X2[k][j], X2[i][j]);
+    for (int q = 0; q < TS_W * TS_W / TS_TREE_NT; ++q) {
+      const int e = tid + TS_TREE_NT * q;
+      const int i = e & (TS_W - 1), jj = e / TS_W;
+      if (i > k && jj > k && i < w && jj < w) X2[i][jj] = fma(-X2[i][k] * rp, X2[k][jj], X2[i][jj]);
     }
     __syncthreads();
   }
@@ -475,7 +536,7 @@ __global__ __launch_bounds__(TS_NT) void tsqr_tree_kernel(
   double (*Lt)[TS_W1] = Y0;   // L^T
   double (*Ui)[TS_W1] = Q0;   // U^{-1}
   double (*Li)[TS_W1] = Z;    // L1^{-T}
-  for (int e = tid; e < TS_W * TS_W; e += TS_NT) {
+  for (int e = tid; e < TS_W * TS_W; e += TS_TREE_NT) {
     const int i = e & (TS_W - 1), j = e / TS_W;
     const bool in = i < w && j < w;
     Us[i][j] = in ? ((i < j) ? X2[i][j] : ((i == j) ? pv[i] : 0.0)) : ((i == j) ? 1.0 : 0.0);
@@ -484,7 +545,7 @@ __global__ __launch_bounds__(TS_NT) void tsqr_tree_kernel(
   }
   __syncthreads();
   lds_upper_inverse32x2(Us, Ui, Lt, Li, Ts);
-  {  // T = -U S L1^{-T} (upper)
+  if (mw) {  // T = -U S L1^{-T} (upper)
     const d4 c = mfma_tile<TS_W>([&](int i, int k) { return Us[i][k] * sg[k]; },
                                  [&](int k, int j) { return Li[k][j]; }, ti, tj);
 #pragma unroll
@@ -494,12 +555,12 @@ __global__ __launch_bounds__(TS_NT) void tsqr_tree_kernel(
     }
   }
   // R = S R_tsqr into the matrix (top w logical rows = segment 1), zeros below the diagonal
-  for (int e = tid; e < w * w; e += TS_NT) {
+  for (int e = tid; e < w * w; e += TS_TREE_NT) {
     const int i = e % w, j = e / w;
     M[ts_phys(i, h1, r1a, r2a) + (long long)(c0 + j) * ldm] = (i <= j) ? sg[i] * Rf[i][j] : 0.0;
   }
   // U^{-1} (zero beyond w) and S for the row expansion (L1 was written above)
-  for (int e = tid; e < TS_W * TS_W; e += TS_NT) {
+  for (int e = tid; e < TS_W * TS_W; e += TS_TREE_NT) {
     const int i = e % TS_W, j = e / TS_W;
     Uo[e] = (i < w && j < w) ? Ui[i][j] : 0.0;
   }
@@ -536,12 +597,11 @@ __global__ __launch_bounds__(TS_NT) void tsqr_expand_kernel(
   const int i0 = p * TS_MB;
   const int rows = min(TS_MB, h - i0);
   const int wy = min(w, rows);  // rows of Y_p that meet [Q_top,p; 0]
-  const int ldr = P * TS_W;
   const double* Tpg = Tloc + (long long)p * TS_W * TS_W;
   for (int e = tid; e < TS_W * TS_W; e += TS_NT) {
     const int i = e % TS_W, j = e / TS_W;
     const bool in = i < w && j < w;
-    M1[i][j] = in ? Ytop[(p * w + i) + (long long)j * ldr] : 0.0;
+    M1[i][j] = in ? Ytop[(p * w + i) * TS_W + j] : 0.0;
     M2[i][j] = Zg[e];
     Us[i][j] = in ? Uinv[e] : 0.0;
     Yp[i][j] = (i < wy && j < w)
@@ -653,7 +713,7 @@ void tsqr_panel(int batch, double* M, long long ldm, long long sM, int c0, int w
   {
     ProfScope prof("tsqr_tree", s, batch * (4.0 * P * ww * w + 4.0 * ww * w),
                    batch * 8.0 * 2.0 * P * ww);
-    hipLaunchKernelGGL(tsqr_tree_kernel, dim3(batch), dim3(TS_NT), 0, s, M, ldm, sM, c0, w, h1, r1a,
+    hipLaunchKernelGGL(tsqr_tree_kernel, dim3(batch), dim3(TS_TREE_NT), 0, s, M, ldm, sM, c0, w, h1, r1a,
                        r2a, P, V, ldv, sV, vr2, sc.Tloc, sc.Rstack, sc.Qtop, sc.Z, sc.U, sc.L,
                        sc.S, sc.stride, T, sT);
     ZCSD_CHECK_LAUNCH();

@@ -100,9 +100,12 @@ __device__ void lds_upper_inverse64(const double (*U)[CH_LD], double (*Ui)[CH_LD
 }
 
 // one workgroup per problem: A (nb x nb, symmetric, upper triangle read) -> R, Ri.
-// Right-looking Cholesky in LDS on the unscaled pivot rows (one barrier per
-// step: S22 -= s12^T s12 / s11, then R(k, :) = S(k, :) / sqrt(s_kk)); a
-// non-positive pivot is counted in d_flag and replaced by 1e-300.
+// Right-looking Cholesky on the unscaled pivot rows, S22 -= s12^T s12 / s11,
+// with the upper triangle in registers: thread (bi, bj) owns the 4 x 4 block
+// S(4bi.., 4bj..), bi <= bj; the owners of row k + 1 publish it to LDS once
+// step k has finalised it (one barrier per step, eight LDS reads per thread).
+// Then R(k, :) = S(k, :) / sqrt(s_kk); a non-positive pivot is counted in
+// d_flag and replaced by 1e-300.
 __global__ __launch_bounds__(CH_NT) void chol_inv_base_kernel(int nb, const double* A, long long lda,
                                                               long long sA, double* R, long long ldr,
                                                               long long sR, double* Ri,
@@ -112,6 +115,7 @@ __global__ __launch_bounds__(CH_NT) void chol_inv_base_kernel(int nb, const doub
   __shared__ double Ui[CH_BASE][CH_LD];
   __shared__ double Xs[32][CH_LD];
   __shared__ double dinv[CH_BASE];
+  __shared__ double prow[2][CH_BASE];
   const long long b = blockIdx.x;
   A += b * sA;
   R += b * sR;
@@ -124,17 +128,54 @@ __global__ __launch_bounds__(CH_NT) void chol_inv_base_kernel(int nb, const doub
     S[i][j] = v;
   }
   __syncthreads();
+  const int bi = tid & 15, bj = tid >> 4;
+  const bool act = bi <= bj;
+  double c[4][4];
+#pragma unroll
+  for (int x = 0; x < 4; ++x)
+#pragma unroll
+    for (int y = 0; y < 4; ++y) c[x][y] = S[4 * bi + x][4 * bj + y];
+  if (bi == 0) {
+#pragma unroll
+    for (int y = 0; y < 4; ++y) prow[0][4 * bj + y] = c[0][y];
+  }
+  __syncthreads();
   for (int k = 0; k < nb; ++k) {
-    double d = S[k][k];
+    const double* pk = prow[k & 1];
+    double d = pk[k];
     if (!(d > 0.0)) d = 1e-300;
     const double inv = 1.0 / d;
-    const int m = nb - k - 1;
-    for (int e = tid; e < m * m; e += CH_NT) {
-      const int i = k + 1 + e % m, j = k + 1 + e / m;
-      if (i <= j) S[i][j] = fma(-S[k][i] * inv, S[k][j], S[i][j]);
+    double ri[4], rj[4];
+#pragma unroll
+    for (int x = 0; x < 4; ++x) {
+      ri[x] = pk[4 * bi + x] * inv;
+      rj[x] = pk[4 * bj + x];
+    }
+    if (act) {
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+          if (4 * bi + x > k && 4 * bj + y > k) c[x][y] = fma(-ri[x], rj[y], c[x][y]);
+    }
+    const int k1 = k + 1;
+    if (k1 < nb && bi == (k1 >> 2)) {
+#pragma unroll
+      for (int x = 0; x < 4; ++x)
+        if (x == (k1 & 3)) {
+#pragma unroll
+          for (int y = 0; y < 4; ++y) prow[k1 & 1][4 * bj + y] = c[x][y];
+        }
     }
     __syncthreads();
   }
+  if (act) {
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+      for (int y = 0; y < 4; ++y) S[4 * bi + x][4 * bj + y] = c[x][y];
+  }
+  __syncthreads();
   if (tid < CH_BASE) {
     double d = S[tid][tid];
     if (!(d > 0.0)) {

@@ -69,7 +69,30 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(
   }
 
   double ra[NA], rb[NB];
+  // with the large tiles, a tile wholly inside C (and a k-tile wholly inside
+  // k) loads and stores without per-element bounds checks (measured faster
+  // for 128 x 128 tiles, slower for the small split-K products of 64 x 64)
+  const bool full_mn = (BM >= 128) && (i0 + BM <= m) && (j0 + BN <= n);
   auto load_tiles = [&](int k0) {
+    if (full_mn && k0 + BK <= k) {
+#pragma unroll
+      for (int q = 0; q < NA; ++q) {
+        const int e = tid + 256 * q;
+        int i, kk;
+        if (!TA) { i = e % BM; kk = e / BM; } else { kk = e % BK; i = e / BK; }
+        const int gi = i0 + i, gk = k0 + kk;
+        ra[q] = TA ? A[gk + (long long)gi * lda] : A[gi + (long long)gk * lda];
+      }
+#pragma unroll
+      for (int q = 0; q < NB; ++q) {
+        const int e = tid + 256 * q;
+        int j, kk;
+        if (!TB) { kk = e % BK; j = e / BK; } else { j = e % BN; kk = e / BN; }
+        const int gj = j0 + j, gk = k0 + kk;
+        rb[q] = TB ? B[gj + (long long)gk * ldb] : B[gk + (long long)gj * ldb];
+      }
+      return;
+    }
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
       const int e = tid + 256 * q;
@@ -139,6 +162,23 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(
   }
 
   // epilogue: lane owns C[row][col + 4v]
+  if (full_mn) {
+#pragma unroll
+    for (int x = 0; x < TM; ++x) {
+      const int row = i0 + wm * WM + x * 16 + lr;
+#pragma unroll
+      for (int y = 0; y < TN; ++y) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int col = j0 + wn * WN + y * 16 + lk + 4 * v;
+          double* p = C + row + (long long)col * ldc;
+          const double r = alpha * acc[x][y][v];
+          *p = (beta == 0.0) ? r : r + beta * (*p);
+        }
+      }
+    }
+    return;
+  }
 #pragma unroll
   for (int x = 0; x < TM; ++x) {
     const int row = i0 + wm * WM + x * 16 + lr;

@@ -27,6 +27,10 @@
 namespace zcsd {
 
 constexpr int QR_NT = 256;
+// inner-panel update (two-level factorisation): panel width, most columns
+// updated, rows per partial-product workgroup, rows staged per step, rows per
+// apply workgroup
+constexpr int PU_W = 32, PU_NC = 96, PU_CH = 256, PU_SUB = 64, PU_RT = 64;
 
 template <int NW>
 __device__ __forceinline__ void wave_sum_multi(double (&p)[NW]) {
@@ -225,6 +229,11 @@ QRWork qr_work_alloc(Arena& ar, QRShape shape, int batch, int m, int n, int nb) 
     wk.sG = (long long)NBO * NBO;
     wk.G = ar.dalloc((size_t)batch * wk.sG);
     wk.Ginv = ar.dalloc((size_t)batch * wk.sG);
+    // inner-panel updates: ceil(hmax / PU_CH) partials of 32 x 96 per problem
+    const int nchunk = (hmax + PU_CH - 1) / PU_CH;
+    wk.sPart = (long long)nchunk * 32 * 96;
+    wk.pu_part = ar.dalloc((size_t)batch * wk.sPart);
+    wk.pu_cnt = reinterpret_cast<unsigned*>(ar.dalloc(((size_t)batch + 1) / 2));
   }
   return wk;
 }
@@ -298,6 +307,230 @@ static void apply_block_reflector(int batch, double* M, long long ldm, long long
   }
 }
 
+
+// ---------------------------------------------------------------------------
+// Inner-panel update of the two-level factorisation in two kernels:
+// C <- (I - V T V^T)^T C on the panel's logical rows (segment 1, then segment
+// 2 of a Stacked panel) and the <= 96 columns left in the outer block.
+//   pu_partial: each workgroup forms V_c^T C_c over PU_CH logical rows (FP64
+//     MFMA, operands staged through LDS 64 rows at a time) and stores it; the
+//     last workgroup of a problem to finish (counter) sums the partials in a
+//     fixed order and writes W2 = T^T (V^T C) (32 x nc, ld 32).
+//   pu_apply: C_r -= V_r W2 for 64-row tiles.
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// lane l, item v of the accumulator of a 16 x 16 block: row l % 16, column 4 v + l / 16
+template <int KD, class FX, class FY>
+__device__ __forceinline__ d4 pu_mfma(d4 acc, FX fx, FY fy, int ti, int tj) {
+  const int lane = threadIdx.x & 63, lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int kk = 0; kk < KD; kk += 4)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(fy(kk + lk, 16 * tj + lr), fx(16 * ti + lr, kk + lk),
+                                               acc, 0, 0, 0);
+  return acc;
+}
+
+__device__ __forceinline__ long long pu_mrow(int i, int h1, int r1a, int r2a) {
+  return i < h1 ? r1a + i : r2a + (i - h1);
+}
+__device__ __forceinline__ long long pu_vrow(int i, int h1, int vr2) { return i < h1 ? i : vr2 + (i - h1); }
+
+__global__ __launch_bounds__(256) void pu_partial_kernel(
+    int h, int h1, int nc, const double* V, long long ldv, long long sV, int vr2, const double* M,
+    long long ldm, long long sM, int r1a, int r2a, int col0, const double* T, int ldt, long long sT,
+    double* part, long long sPart, double* W2, long long sW2, unsigned* cnt) {
+  constexpr int NV = PU_SUB * PU_W / 256, NCL = PU_SUB * PU_NC / 256;  // staged values per thread
+  __shared__ double Vs[PU_SUB][PU_W + 1];
+  __shared__ double Cs[PU_SUB][PU_NC + 1];  // C rows while staging, then W (first 32 rows)
+  __shared__ unsigned is_last;
+  const int c = blockIdx.x, nchunk = gridDim.x;
+  const long long b = blockIdx.y;
+  V += b * sV;
+  M += b * sM;
+  T += b * sT;
+  part += b * sPart;
+  W2 += b * sW2;
+  const int tid = threadIdx.x, wave = tid >> 6;
+  const int ntj = (nc + 15) / 16, ntiles = 2 * ntj;  // 16 x 16 blocks of the 32 x nc product
+  d4 acc[3];
+#pragma unroll
+  for (int u = 0; u < 3; ++u) acc[u] = d4{0.0, 0.0, 0.0, 0.0};
+  // rows are staged PU_SUB at a time; the next rows are loaded into registers
+  // while the current ones are multiplied
+  double rv[NV], rc[NCL];
+  auto load = [&](int r0) {
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int e = tid + 256 * q, i = e % PU_SUB, j = e / PU_SUB;
+      rv[q] = (r0 + i < h) ? V[pu_vrow(r0 + i, h1, vr2) + (long long)j * ldv] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NCL; ++q) {
+      const int e = tid + 256 * q, i = e % PU_SUB, j = e / PU_SUB;
+      rc[q] = (r0 + i < h && j < nc) ? M[pu_mrow(r0 + i, h1, r1a, r2a) + (long long)(col0 + j) * ldm] : 0.0;
+    }
+  };
+  const int rbeg = c * PU_CH, rend = min(h, (c + 1) * PU_CH);
+  load(rbeg);
+  for (int r0 = rbeg; r0 < rend; r0 += PU_SUB) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int e = tid + 256 * q;
+      Vs[e % PU_SUB][e / PU_SUB] = rv[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NCL; ++q) {
+      const int e = tid + 256 * q;
+      Cs[e % PU_SUB][e / PU_SUB] = rc[q];
+    }
+    __syncthreads();
+    if (r0 + PU_SUB < rend) load(r0 + PU_SUB);
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int t = wave + 4 * u;
+      if (t < ntiles)
+        acc[u] = pu_mfma<PU_SUB>(acc[u], [&](int i, int k) { return Vs[k][i]; },
+                                 [&](int k, int j) { return Cs[k][j]; }, t & 1, t >> 1);
+    }
+  }
+  // this chunk's 32 x nc partial, row-major with row length 96
+  double* pc = part + (long long)c * PU_W * PU_NC;
+  const int lane = tid & 63;
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    const int t = wave + 4 * u;
+    if (t < ntiles) {
+      const int row = 16 * (t & 1) + (lane & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) pc[row * PU_NC + 16 * (t >> 1) + 4 * v + (lane >> 4)] = acc[u][v];
+    }
+  }
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) is_last = (atomicAdd(&cnt[b], 1u) == (unsigned)(nchunk - 1)) ? 1u : 0u;
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  // the last workgroup: W = sum of the partials in chunk order (all loads of
+  // four chunks in flight at once), then W2 = T^T W
+  constexpr int NE = PU_W * PU_NC / 256;
+  double sacc[NE];
+#pragma unroll
+  for (int u = 0; u < NE; ++u) sacc[u] = 0.0;
+  int q = 0;
+  for (; q + 4 <= nchunk; q += 4) {
+    double x[4][NE];
+#pragma unroll
+    for (int z = 0; z < 4; ++z)
+#pragma unroll
+      for (int u = 0; u < NE; ++u) x[z][u] = part[(long long)(q + z) * PU_W * PU_NC + tid + 256 * u];
+#pragma unroll
+    for (int z = 0; z < 4; ++z)
+#pragma unroll
+      for (int u = 0; u < NE; ++u) sacc[u] += x[z][u];
+  }
+  for (; q < nchunk; ++q) {
+#pragma unroll
+    for (int u = 0; u < NE; ++u) sacc[u] += part[(long long)q * PU_W * PU_NC + tid + 256 * u];
+  }
+#pragma unroll
+  for (int u = 0; u < NE; ++u) {
+    const int e = tid + 256 * u;
+    Cs[e / PU_NC][e % PU_NC] = sacc[u];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    const int t = wave + 4 * u;
+    if (t < ntiles) {
+      const d4 r = pu_mfma<PU_W>(d4{0.0, 0.0, 0.0, 0.0}, [&](int i, int k) { return T[k + (long long)i * ldt]; },
+                                 [&](int k, int j) { return Cs[k][j]; }, t & 1, t >> 1);
+      const int row = 16 * (t & 1) + (lane & 15);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int col = 16 * (t >> 1) + 4 * v + (lane >> 4);
+        if (col < nc) W2[row + (long long)col * PU_W] = r[v];
+      }
+    }
+  }
+  if (tid == 0) cnt[b] = 0u;
+}
+
+__global__ __launch_bounds__(256) void pu_apply_kernel(int h, int h1, int nc, const double* V,
+                                                       long long ldv, long long sV, int vr2,
+                                                       double* M, long long ldm, long long sM,
+                                                       int r1a, int r2a, int col0, const double* W2,
+                                                       long long sW2) {
+  __shared__ double Ws[PU_W][PU_NC + 1];
+  __shared__ double Vs[PU_RT][PU_W + 1];
+  const int r0 = blockIdx.x * PU_RT;
+  const long long b = blockIdx.y;
+  V += b * sV;
+  M += b * sM;
+  W2 += b * sW2;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  for (int e = tid; e < PU_W * PU_NC; e += 256) {
+    const int i = e % PU_W, j = e / PU_W;
+    Ws[i][j] = (j < nc) ? W2[i + (long long)j * PU_W] : 0.0;
+  }
+  for (int e = tid; e < PU_RT * PU_W; e += 256) {
+    const int i = e % PU_RT, j = e / PU_RT;
+    Vs[i][j] = (r0 + i < h) ? V[pu_vrow(r0 + i, h1, vr2) + (long long)j * ldv] : 0.0;
+  }
+  __syncthreads();
+  const int ntj = (nc + 15) / 16;
+  for (int t = wave; t < 4 * ntj; t += 4) {
+    const int ti = t & 3, tj = t >> 2;
+    const d4 r = pu_mfma<PU_W>(d4{0.0, 0.0, 0.0, 0.0}, [&](int i, int k) { return Vs[i][k]; },
+                               [&](int k, int j) { return Ws[k][j]; }, ti, tj);
+    const int row = r0 + 16 * ti + (lane & 15);
+    if (row < h) {
+      const long long mr = pu_mrow(row, h1, r1a, r2a);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int col = 16 * tj + 4 * v + (lane >> 4);
+        if (col < nc) {
+          double* p = M + mr + (long long)(col0 + col) * ldm;
+          *p -= r[v];
+        }
+      }
+    }
+  }
+}
+
+__global__ void zero_u32_kernel(unsigned* p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0u;
+}
+
+// the two kernels above for one inner panel (w <= 32, nc <= 96), T = T_k (ld nb)
+static void inner_update(int batch, int h1, int h, int nc, const double* V, long long ldv,
+                         long long sV, int vr2, double* M, long long ldm, long long sM, int r1a,
+                         int r2a, int col0, const double* T, int ldt, long long sT, double* W2,
+                         long long sW2, const QRWork& wk, hipStream_t s) {
+  if (nc <= 0) return;
+  if (nc > PU_NC) throw ArgError("inner_update: too many columns");
+  const int nchunk = (h + PU_CH - 1) / PU_CH;
+  if ((long long)nchunk * PU_W * PU_NC > wk.sPart) throw ArgError("inner_update: panel too tall");
+  {
+    ProfScope prof("qr_inner_w", s, batch * 2.0 * PU_W * nc * (double)h + batch * 2.0 * PU_W * PU_W * nc,
+                   batch * 8.0 * (double)h * (PU_W + nc));
+    hipLaunchKernelGGL(pu_partial_kernel, dim3(nchunk, batch), dim3(256), 0, s, h, h1, nc, V, ldv, sV,
+                       vr2, M, ldm, sM, r1a, r2a, col0, T, ldt, sT, wk.pu_part, wk.sPart, W2, sW2,
+                       wk.pu_cnt);
+    ZCSD_CHECK_LAUNCH();
+  }
+  {
+    ProfScope prof("qr_inner_apply", s, batch * 2.0 * PU_W * nc * (double)h,
+                   batch * 8.0 * (double)h * (PU_W + 2.0 * nc));
+    hipLaunchKernelGGL(pu_apply_kernel, dim3((h + PU_RT - 1) / PU_RT, batch), dim3(256), 0, s, h,
+                       h1, nc, V, ldv, sV, vr2, M, ldm, sM, r1a, r2a, col0, W2, sW2);
+    ZCSD_CHECK_LAUNCH();
+  }
+}
+
 // Two-level blocked factorisation: inside an outer block of nbo columns the
 // inner panels are factored and applied to the rest of the block only; the
 // outer block's compact-WY factor follows from the Gram matrix of its vectors,
@@ -310,6 +543,9 @@ static void apply_block_reflector(int batch, double* M, long long ldm, long long
 static void geqrf_two_level(int batch, QRShape shape, int m, int n, double* M, long long ldm,
                             long long sM, QRWork& wk, hipStream_t s) {
   const int nb = wk.nb, NBO = wk.nbo;
+  // the inner-update counters start at zero (each use leaves them at zero)
+  hipLaunchKernelGGL(zero_u32_kernel, dim3((batch + 255) / 256), dim3(256), 0, s, wk.pu_cnt, batch);
+  ZCSD_CHECK_LAUNCH();
   for (int O = 0; O < wk.Ko; ++O) {
     const int co = O * NBO, wo = std::min(NBO, n - co);
     double* VO = wk.V + (long long)O * wk.ldv * NBO;
@@ -334,9 +570,10 @@ static void geqrf_two_level(int batch, QRShape shape, int m, int n, double* M, l
       tsqr_panel(batch, M, ldm, sM, c0, w, r1a, r1b, r2a, r2b, V1, wk.ldv, wk.sV, vr2, Tk, wk.sTin,
                  wk.ts, s);
       const int col0 = c0 + w;
-      apply_block_reflector(batch, M, ldm, sM, col0, co + wo - col0, r1a, r1b, r2a, r2b, w, V1, V2,
-                            wk.ldv, wk.sV, Tk, wk.sTin, nb, wk.W, wk.W2, wk.sW, /*transT=*/true,
-                            wk.ws, wk.ws_elems, s);
+      // V2 - V1 = wo - off rows: segment 2 of the logical rows starts there
+      inner_update(batch, r1b - r1a, (r1b - r1a) + (r2b - r2a), co + wo - col0, V1, wk.ldv, wk.sV,
+                   gen ? 0 : (wo - off), M, ldm, sM, r1a, r2a, col0, Tk, nb, wk.sTin, wk.W2, wk.sW,
+                   wk, s);
     }
     // outer compact-WY factor from G = VO^T VO (always FP64)
     {

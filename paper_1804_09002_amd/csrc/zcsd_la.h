@@ -24,6 +24,9 @@ struct QRWork {
   double* To = nullptr; long long sTo = 0;
   double* Tin = nullptr; long long sTin = 0;
   double* G = nullptr; double* Ginv = nullptr; long long sG = 0;
+  // inner-panel updates (two-level): per-problem partial products and counters
+  double* pu_part = nullptr; long long sPart = 0;
+  unsigned* pu_cnt = nullptr;
   Arena* ar = nullptr;
 };
 

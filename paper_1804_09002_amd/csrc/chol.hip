@@ -257,6 +257,7 @@ static void chol_inv_rec(int batch, int n, double* A, long long lda, long long s
   g.B = A12; g.ldb = lda; g.sB = sA;
   g.C = R12; g.ldc = ld; g.sC = s;
   g.alpha = 1.0; g.beta = 0.0;
+  g.tri = 2; g.kseg = n1;  // R11i^T lower triangular
   dgemm(g, st);
   // A22 <- A22 - R12^T R12
   GemmBatch h;
@@ -278,6 +279,7 @@ static void chol_inv_rec(int batch, int n, double* A, long long lda, long long s
   x.B = Ri22; x.ldb = ld; x.sB = s;
   x.C = X; x.ldc = n1; x.sC = (long long)n1 * n2;
   x.alpha = 1.0; x.beta = 0.0;
+  x.tri = 4; x.kseg = n2;  // R22i upper triangular
   dgemm(x, st);
   GemmBatch y;
   y.batch = batch;
@@ -286,6 +288,7 @@ static void chol_inv_rec(int batch, int n, double* A, long long lda, long long s
   y.B = X; y.ldb = n1; y.sB = (long long)n1 * n2;
   y.C = Ri12; y.ldc = ld; y.sC = s;
   y.alpha = -1.0; y.beta = 0.0;
+  y.tri = 1; y.kseg = n1;  // R11i upper triangular
   dgemm(y, st);
 }
 
@@ -324,6 +327,7 @@ void trtri_upper_batched(int batch, int n, const double* R, long long ldr, long 
       g.B = Ri + (o + sz) + (long long)(o + sz) * ldi; g.ldb = ldi; g.sB = sI; g.sB2 = pstrideI;
       g.C = X; g.ldc = sz; g.sC = (long long)(npairs_full + 1) * sz * sz; g.sC2 = (long long)sz * sz;
       g.alpha = 1.0; g.beta = 0.0;
+      g.tri = 4; g.kseg = nbB;  // Ri_B upper triangular
       dgemm(g, s);
       // Ri_AB = -Ri_A X
       GemmBatch h;
@@ -333,6 +337,7 @@ void trtri_upper_batched(int batch, int n, const double* R, long long ldr, long 
       h.B = X; h.ldb = sz; h.sB = g.sC; h.sB2 = g.sC2;
       h.C = Ri + o + (long long)(o + sz) * ldi; h.ldc = ldi; h.sC = sI; h.sC2 = pstrideI;
       h.alpha = -1.0; h.beta = 0.0;
+      h.tri = 1; h.kseg = sz;  // Ri_A upper triangular
       dgemm(h, s);
     };
     merge(0, npairs_full, sz);

@@ -34,7 +34,7 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(
     int m, int n, int k, const double* __restrict__ A, long long lda, long long sA,
     const double* __restrict__ B, long long ldb, long long sB, double* __restrict__ C,
     long long ldc, long long sC, double alpha, double beta, int nb1, long long sA2, long long sB2,
-    long long sC2, int nprob, int kchunk, double* ws, int sym_upper) {
+    long long sC2, int nprob, int kchunk, double* ws, int sym_upper, int tri, int kseg) {
   if (sym_upper && blockIdx.x > blockIdx.y) return;  // tile below the diagonal (BM == BN)
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int TM = WM / 16, TN = WN / 16;
@@ -73,8 +73,8 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(
   // k) loads and stores without per-element bounds checks (measured faster
   // for 128 x 128 tiles, slower for the small split-K products of 64 x 64)
   const bool full_mn = (BM >= 128) && (i0 + BM <= m) && (j0 + BN <= n);
-  auto load_tiles = [&](int k0) {
-    if (full_mn && k0 + BK <= k) {
+  auto load_tiles = [&](int k0, int kl) {
+    if (full_mn && k0 + BK <= kl) {
 #pragma unroll
       for (int q = 0; q < NA; ++q) {
         const int e = tid + 256 * q;
@@ -100,7 +100,7 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(
       if (!TA) { i = e % BM; kk = e / BM; } else { kk = e % BK; i = e / BK; }
       const int gi = i0 + i, gk = k0 + kk;
       double v = 0.0;
-      if (gi < m && gk < k) v = TA ? A[gk + (long long)gi * lda] : A[gi + (long long)gk * lda];
+      if (gi < m && gk < kl) v = TA ? A[gk + (long long)gi * lda] : A[gi + (long long)gk * lda];
       ra[q] = v;
     }
 #pragma unroll
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(
       if (!TB) { kk = e % BK; j = e / BK; } else { j = e % BN; kk = e / BN; }
       const int gj = j0 + j, gk = k0 + kk;
       double v = 0.0;
-      if (gj < n && gk < k) v = TB ? B[gj + (long long)gk * ldb] : B[gk + (long long)gj * ldb];
+      if (gj < n && gk < kl) v = TB ? B[gj + (long long)gk * ldb] : B[gk + (long long)gj * ldb];
       rb[q] = v;
     }
   };
@@ -140,12 +140,32 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(
   const int lr = lane & 15;   // row (of the 16-block) this lane feeds / owns
   const int lk = lane >> 4;   // k index within the k-step of 4
 
-  if (k > 0) load_tiles(0);
-  for (int k0 = 0; k0 < k; k0 += BK) {
+  // k-range of this tile: K is a sequence of segments of length seg; within a
+  // segment, products that the triangular structure of op(A) or op(B) makes
+  // zero are skipped (tri bits: 1 op(A) upper, k >= i; 2 op(A) lower, k <= i;
+  // 4 op(B) upper, k <= j; 8 op(B) lower, k >= j)
+  int seg = k, nseg = 1, klo = 0, khi = k;
+  if (tri && kchunk == 0 && kseg > 0) {
+    seg = kseg;
+    nseg = k / kseg;
+    khi = seg;
+    if (tri & 1) klo = max(klo, i0);
+    if (tri & 8) klo = max(klo, j0);
+    if (tri & 2) khi = min(khi, i0 + BM);
+    if (tri & 4) khi = min(khi, j0 + BN);
+    klo = (klo / BK) * BK;
+  }
+  const int nkt = (khi > klo) ? (khi - klo + BK - 1) / BK : 0;
+  const int total = nseg * nkt;
+  auto kstart = [&](int t) { return (t / nkt) * seg + klo + (t % nkt) * BK; };
+  auto klim = [&](int t) { return (t / nkt) * seg + khi; };
+
+  if (total > 0) load_tiles(kstart(0), klim(0));
+  for (int t = 0; t < total; ++t) {
     __syncthreads();
     store_tiles();
     __syncthreads();
-    if (k0 + BK < k) load_tiles(k0 + BK);
+    if (t + 1 < total) load_tiles(kstart(t + 1), klim(t + 1));
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       double fa[TM], fb[TN];
@@ -257,7 +277,8 @@ static void launch_tile(const GemmBatch& g, hipStream_t s, int ksplit) {
 #define ZCSD_GEMM_LAUNCH(TA_, TB_)                                                        \
   hipLaunchKernelGGL((dgemm_kernel<BM, BN, BK, TA_, TB_>), grid, block, 0, s, g.m, g.n, g.k, A, \
                      g.lda, g.sA, B, g.ldb, g.sB, C, g.ldc, g.sC, g.alpha, g.beta, g.batch,     \
-                     g.sA2, g.sB2, g.sC2, nprob, kchunk, g.ws, g.sym_upper ? 1 : 0)
+                     g.sA2, g.sB2, g.sC2, nprob, kchunk, g.ws, g.sym_upper ? 1 : 0, g.tri, \
+                     g.kseg)
     if (!g.transA && !g.transB) ZCSD_GEMM_LAUNCH(false, false);
     else if (!g.transA && g.transB) ZCSD_GEMM_LAUNCH(false, true);
     else if (g.transA && !g.transB) ZCSD_GEMM_LAUNCH(true, false);
@@ -278,6 +299,8 @@ void dgemm(const GemmBatch& g, hipStream_t s) {
   if (g.m <= 0 || g.n <= 0 || g.batch <= 0 || g.batch2 <= 0) return;
   if (g.sym_upper && (g.m != g.n || g.beta != 0.0))
     throw ArgError("dgemm: a symmetric product needs m == n and beta == 0");
+  if (g.tri && (g.kseg <= 0 || g.k % g.kseg != 0))
+    throw ArgError("dgemm: triangular operands need k to be a multiple of kseg");
   if (g.k <= 0) {
     // C = beta C
     if (g.beta != 1.0)

@@ -100,6 +100,12 @@ struct GemmBatch {
   // symmetric product (m == n, beta == 0): only the tiles on or above the
   // diagonal are computed; the caller mirrors the upper triangle (mirror_upper)
   bool sym_upper = false;
+  // triangular operands (products known to be zero are skipped): K is made of
+  // k / kseg segments, and within each segment op(A) is upper (tri & 1: zero
+  // for k < i) or lower (tri & 2: zero for k > i), op(B) upper (tri & 4: zero
+  // for k > j) or lower (tri & 8: zero for k < j), with k counted from the
+  // segment start; the zeros must be present in memory
+  int tri = 0, kseg = 0;
 };
 void dgemm(const GemmBatch& g, hipStream_t s);
 

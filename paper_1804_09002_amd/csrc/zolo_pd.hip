@@ -155,6 +155,9 @@ ZoloPdResult zolo_pd_batched(const ZoloPdArgs& a, Arena& ar, hipStream_t s) {
     g.B = S + n; g.ldb = 2 * n; g.sB = (long long)r * s2;
     g.C = Y1; g.ldc = n; g.sC = nn;
     g.alpha = z1.M; g.beta = z1.M;
+    // both factors of each term are upper triangular (Q2 = sqrt(c) R~^{-1},
+    // Q1 = R R~^{-1}): only k >= max(i, j) contributes
+    g.tri = 1 | 8; g.kseg = n;
     dgemm(g, s);
   }
 
@@ -194,6 +197,7 @@ ZoloPdResult zolo_pd_batched(const ZoloPdArgs& a, Arena& ar, hipStream_t s) {
     g.B = Ric; g.ldb = n; g.sB = (long long)r * nn;
     g.C = Ms; g.ldc = n; g.sC = nn;
     g.sym_upper = true;
+    g.tri = 1 | 8; g.kseg = n;  // R_j^{-1} upper triangular
     dgemm(g, s);
   }
   mirror_upper(B, n, Ms, n, nn, s);
@@ -233,6 +237,7 @@ ZoloPdResult zolo_pd_batched(const ZoloPdArgs& a, Arena& ar, hipStream_t s) {
     g.B = M; g.ldb = n; g.sB = nn;
     g.C = a.H; g.ldc = n; g.sC = nn;
     g.alpha = a.alpha;
+    g.tri = 4; g.kseg = n;  // R upper triangular
     dgemm(g, s);
     symmetrize(B, n, a.H, n, nn, s);
   }

@@ -6,6 +6,7 @@
 
 #include "zcsd_api_guard.h"
 #include "zcsd_internal.h"
+#include "zcsd_la.h"
 
 using namespace zcsd;
 
@@ -133,7 +134,10 @@ zcsd_status zcsd_dgemm_f32acc(zcsd_handle* handle, int transA, int transB, int m
 namespace {
 size_t zolo_pd_ws_bytes(int batch, int n) {
   const size_t nn = (size_t)n * n;
-  return (size_t)batch * (64 * nn + 64 * (size_t)n) * sizeof(double) + (64u << 20);
+  // iterates and products, plus the two QR workspaces (at most 8 terms)
+  return (size_t)batch * (64 * nn + 64 * (size_t)n) * sizeof(double) +
+         qr_work_bytes(QRShape::General, batch, n, n, 32) +
+         qr_work_bytes(QRShape::Stacked, 8 * batch, 2 * n, n, 32) + (64u << 20);
 }
 }  // namespace
 
@@ -175,8 +179,6 @@ extern "C" zcsd_status zcsd_dzolo_pd(zcsd_handle* handle, int batch, int n, doub
   });
 }
 
-#include "zcsd_la.h"
-
 extern "C" zcsd_status zcsd_dqr(zcsd_handle* handle, int batch, int stacked, int m, int n,
                                 double* d_M, int ldm, long long strideM, double* d_Q, int ldq,
                                 long long strideQ) {
@@ -188,8 +190,7 @@ extern "C" zcsd_status zcsd_dqr(zcsd_handle* handle, int batch, int stacked, int
     ZCSD_REQUIRE(!d_Q || ldq >= m, "qr: bad Q");
     ZCSD_HIP(hipSetDevice(handle->device));
     const QRShape shape = stacked ? QRShape::Stacked : QRShape::General;
-    const size_t need = (size_t)batch * ((size_t)m * n + 4 * (size_t)m * 32 + 64 * (size_t)n) *
-                            sizeof(double) * 2 + (16u << 20);
+    const size_t need = qr_work_bytes(shape, batch, m, n, 32) + (16u << 20);
     handle->arena.reset();
     handle->arena.reserve(need);
     QRWork wk = qr_work_alloc(handle->arena, shape, batch, m, n, 32);

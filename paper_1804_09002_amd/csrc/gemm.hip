@@ -19,6 +19,7 @@
 // operand and op(A)^T as "b", so the accumulator holds C^T: lane l, item v is
 // C[row0 + l % 16][col0 + l / 16 + 4 v], and 16 consecutive lanes store 16
 // consecutive rows of one column of C (a 128-byte coalesced segment).
+#include <algorithm>
 #include <cstdlib>
 #include <string>
 
@@ -249,11 +250,40 @@ static const char* tile_name(int ta, int tb) {
   return names[i];
 }
 
+// Flops of the tiles a launch computes: tiles below the diagonal of a
+// symmetric product are skipped, and so are the k ranges that triangular
+// operands make zero (the same ranges the kernel skips).  Evaluated only while
+// the profiler records.
+template <int BM, int BN, int BK>
+static double computed_flops(const GemmBatch& g, bool split) {
+  const double nprob = (double)g.batch * g.batch2;
+  if (!g.sym_upper && (!g.tri || split)) return 2.0 * g.m * (double)g.n * g.k * nprob;
+  const int gx = (g.m + BM - 1) / BM, gy = (g.n + BN - 1) / BN;
+  double f = 0.0;
+  for (int by = 0; by < gy; ++by)
+    for (int bx = 0; bx < gx; ++bx) {
+      if (g.sym_upper && bx > by) continue;
+      const int i0 = bx * BM, j0 = by * BN;
+      double kr = g.k;
+      if (g.tri && !split && g.kseg > 0) {
+        int klo = 0, khi = g.kseg;
+        if (g.tri & 1) klo = std::max(klo, i0);
+        if (g.tri & 8) klo = std::max(klo, j0);
+        if (g.tri & 2) khi = std::min(khi, i0 + BM);
+        if (g.tri & 4) khi = std::min(khi, j0 + BN);
+        klo = (klo / BK) * BK;
+        kr = (double)(g.k / g.kseg) * std::max(0, khi - klo);
+      }
+      f += 2.0 * std::min(BM, g.m - i0) * (double)std::min(BN, g.n - j0) * kr;
+    }
+  return f * nprob;
+}
+
 template <int BM, int BN, int BK>
 static void launch_tile(const GemmBatch& g, hipStream_t s, int ksplit) {
   const double nprob_d = (double)g.batch * g.batch2;
   ProfScope prof(tile_name<BM, BN, BK>(g.transA, g.transB), s,
-                 2.0 * g.m * (double)g.n * g.k * nprob_d,
+                 prof_on() ? computed_flops<BM, BN, BK>(g, ksplit > 1) : 0.0,
                  8.0 * nprob_d * ((double)g.m * g.k + (double)g.k * g.n + (g.beta != 0.0 ? 2.0 : 1.0) * g.m * g.n));
   const int gx = (g.m + BM - 1) / BM, gy = (g.n + BN - 1) / BN;
   if (g.batch > 65535) throw ArgError("dgemm: batch too large");

@@ -195,6 +195,33 @@ static void panel_segments(QRShape shape, int m, int n, int nb, int k, int* c0, 
   }
 }
 
+// Arena bytes that qr_work_alloc takes (allocation by allocation, with the
+// arena's 256-byte alignment)
+size_t qr_work_bytes(QRShape shape, int batch, int m, int n, int nb) {
+  auto al = [](size_t count) { return ((count * sizeof(double) + 255) / 256) * 256; };
+  size_t t = 0;
+  const int K = (n + nb - 1) / nb;
+  constexpr int NBO = 128;
+  const int hmax = (shape == QRShape::General) ? m : n + nb;
+  const bool two = nb == 32 && n > nb && tsqr_panel_fits(hmax, nb);
+  const int wcols = two ? NBO : nb;
+  const int nblk = two ? (n + NBO - 1) / NBO : K;
+  const long long ldv = (shape == QRShape::General) ? m : (n + wcols);
+  const size_t sW = (size_t)wcols * n;
+  const size_t ws_elems = (size_t)8 * batch * wcols * n;
+  t += al((size_t)batch * nblk * ldv * wcols) + al((size_t)batch * K * nb * nb);
+  t += 2 * al((size_t)batch * sW);
+  if (nb == 32) t += tsqr_scratch_bytes(batch);
+  t += al(ws_elems);
+  if (two) {
+    const int Ko = (n + NBO - 1) / NBO;
+    t += al((size_t)batch * Ko * NBO * NBO) + al((size_t)batch * (NBO / nb) * nb * nb);
+    t += 2 * al((size_t)batch * NBO * NBO);
+    t += al((size_t)batch * ((hmax + PU_CH - 1) / PU_CH) * PU_W * PU_NC) + al(((size_t)batch + 1) / 2);
+  }
+  return t;
+}
+
 QRWork qr_work_alloc(Arena& ar, QRShape shape, int batch, int m, int n, int nb) {
   QRWork wk;
   wk.nb = nb;

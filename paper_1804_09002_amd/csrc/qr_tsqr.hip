@@ -727,6 +727,12 @@ void tsqr_panel(int batch, double* M, long long ldm, long long sM, int c0, int w
   }
 }
 
+size_t tsqr_scratch_bytes(int batch) {
+  const long long per_R = (long long)TS_PMAX * TS_W * TS_W;
+  const long long stride = 4 * per_R + 3 * TS_W * TS_W + TS_W;
+  return (((size_t)batch * stride * sizeof(double) + 255) / 256) * 256;
+}
+
 TsqrScratch tsqr_scratch_alloc(Arena& ar, int batch) {
   TsqrScratch sc;
   const long long per_R = (long long)TS_PMAX * TS_W * TS_W;  // Rstack, Qtop: (P w) x w

@@ -31,6 +31,8 @@ struct QRWork {
 };
 
 QRWork qr_work_alloc(Arena& ar, QRShape shape, int batch, int m, int n, int nb);
+// arena bytes taken by qr_work_alloc
+size_t qr_work_bytes(QRShape shape, int batch, int m, int n, int nb);
 // In place: M_b (m x n, or 2n x n for Stacked) -> R in its top n x n upper triangle,
 // zeros below; reflectors kept in wk.
 void geqrf_batched(int batch, QRShape shape, int m, int n, double* M, long long ldm, long long sM,

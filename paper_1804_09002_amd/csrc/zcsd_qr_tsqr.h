@@ -20,6 +20,7 @@ struct TsqrScratch {
 
 bool tsqr_panel_fits(int h, int w);
 TsqrScratch tsqr_scratch_alloc(Arena& ar, int batch);
+size_t tsqr_scratch_bytes(int batch);  // arena bytes of tsqr_scratch_alloc
 // Same contract as the one-workgroup panel: reads the panel's rows (two
 // segments) of M, writes R into the top w logical rows and zeros below,
 // V (h x w, unit lower trapezoidal, ld ldv) and T (32 x 32, upper).  Logical

@@ -15,6 +15,7 @@
 //      Householder vectors from tall-skinny QR", 2015);
 //   C. every block forms its piece Q_top,p = [I; 0]_p - Y_top,p Z and its rows of
 //      the explicit Q, Q_p = (I - Y_p T_p Y_p^T) [Q_top,p; 0], and of V = Q U^{-1}.
+// A panel of one block (P = 1) is finished by stage A alone.
 // Each stage is parallel over rows; only the w x w pieces are sequential.
 // The Householder factorisations keep the matrix in registers, four columns
 // per lane (eight lanes hold a row): a step swizzles the pivot column to the
@@ -341,10 +342,13 @@ __device__ __forceinline__ double cl_yval(double v, int i, int j, double myscal)
 }
 // ---------------------------------------------------------------------------
 // A: local QR of every row block
+// With direct != 0 (a panel of one block, P = 1) the block's Householder QR is
+// the panel's: R goes into the matrix (zeros below it), Y into V and T into
+// Tfin, and the tree and expansion stages are not needed.
 __global__ __launch_bounds__(TS_NT) void tsqr_local_kernel(
-    const double* M, long long ldm, long long sM, int c0, int w, int h1, int r1a, int r2a, int h,
+    double* M, long long ldm, long long sM, int c0, int w, int h1, int r1a, int r2a, int h,
     int P, double* V, long long ldv, long long sV, int vr2, double* Tloc, double* Rstack,
-    long long sScr) {
+    long long sScr, int direct, double* Tfin, long long sT) {
   __shared__ double red[2 * 4 * TS_W], rowb[2 * TS_W], taus[TS_W];
   __shared__ double Ts[TS_W][TS_W1];
   __shared__ double Zm[TS_W][TS_W1];
@@ -377,15 +381,19 @@ __global__ __launch_bounds__(TS_NT) void tsqr_local_kernel(
   for (int r = 0; r < TS_LOCAL_RQ; ++r) {
     const int i = 8 * TS_LOCAL_RQ * wave + 8 * r + hs;
     const long long vi = (i < rows) ? ts_vrow(i0 + i, h1, vr2) : 0;
+    const long long pr = (i < rows) ? ts_phys(i0 + i, h1, r1a, r2a) : 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int j = 4 * g + q;
-      if (8 * r < TS_W && wave == 0 && i < w)
+      if (direct) {
+        if (i < rows && j < w) M[pr + (long long)(c0 + j) * ldm] = cl_rval(a[r][q], i, j, mybeta[q]);
+      } else if (8 * r < TS_W && wave == 0 && i < w) {
         Rp[(p * w + i) * TS_W + j] = (j < w && i < rows) ? cl_rval(a[r][q], i, j, mybeta[q]) : 0.0;
+      }
       if (i < rows && j < w) V[vi + (long long)j * ldv] = cl_yval(a[r][q], i, j, myscal[q]);
     }
   }
-  double* Tp = Tloc + b * sScr + (long long)p * TS_W * TS_W;
+  double* Tp = direct ? Tfin + b * sT : Tloc + b * sScr + (long long)p * TS_W * TS_W;
   for (int e = tid; e < TS_W * TS_W; e += TS_NT) Tp[e] = Ts[e % TS_W][e / TS_W];
 }
 
@@ -707,9 +715,11 @@ void tsqr_panel(int batch, double* M, long long ldm, long long sM, int c0, int w
     ProfScope prof("tsqr_local", s, batch * (2.0 * h * ww - P * 2.0 * ww * w / 3.0),
                    batch * 8.0 * 2.0 * h * w);
     hipLaunchKernelGGL(tsqr_local_kernel, dim3(P, batch), dim3(TS_NT), 0, s, M, ldm, sM, c0, w, h1,
-                       r1a, r2a, h, P, V, ldv, sV, vr2, sc.Tloc, sc.Rstack, sc.stride);
+                       r1a, r2a, h, P, V, ldv, sV, vr2, sc.Tloc, sc.Rstack, sc.stride, P == 1 ? 1 : 0,
+                       T, sT);
     ZCSD_CHECK_LAUNCH();
   }
+  if (P == 1) return;  // one block: its Householder QR is the panel's
   {
     ProfScope prof("tsqr_tree", s, batch * (4.0 * P * ww * w + 4.0 * ww * w),
                    batch * 8.0 * 2.0 * P * ww);

@@ -15,7 +15,8 @@
 //      Householder vectors from tall-skinny QR", 2015);
 //   C. every block forms its piece Q_top,p = [I; 0]_p - Y_top,p Z and its rows of
 //      the explicit Q, Q_p = (I - Y_p T_p Y_p^T) [Q_top,p; 0], and of V = Q U^{-1}.
-// A panel of one block (P = 1) is finished by stage A alone.
+// A panel of one block (P = 1), or of up to 512 rows factored by one larger
+// workgroup, is finished by stage A alone.
 // Each stage is parallel over rows; only the w x w pieces are sequential.
 // The Householder factorisations keep the matrix in registers, four columns
 // per lane (eight lanes hold a row): a step swizzles the pivot column to the
@@ -345,11 +346,15 @@ __device__ __forceinline__ double cl_yval(double v, int i, int j, double myscal)
 // With direct != 0 (a panel of one block, P = 1) the block's Householder QR is
 // the panel's: R goes into the matrix (zeros below it), Y into V and T into
 // Tfin, and the tree and expansion stages are not needed.
-__global__ __launch_bounds__(TS_NT) void tsqr_local_kernel(
+// NW waves hold 64 NW rows (eight row slots per lane); NW = 8 serves direct
+// panels of up to 512 rows.
+template <int NW>
+__global__ __launch_bounds__(64 * NW) void tsqr_local_kernel(
     double* M, long long ldm, long long sM, int c0, int w, int h1, int r1a, int r2a, int h,
     int P, double* V, long long ldv, long long sV, int vr2, double* Tloc, double* Rstack,
     long long sScr, int direct, double* Tfin, long long sT) {
-  __shared__ double red[2 * 4 * TS_W], rowb[2 * TS_W], taus[TS_W];
+  constexpr int NT = 64 * NW, MBK = 8 * TS_LOCAL_RQ * NW;  // threads, rows per block
+  __shared__ double red[2 * NW * TS_W], rowb[2 * TS_W], taus[TS_W];
   __shared__ double Ts[TS_W][TS_W1];
   __shared__ double Zm[TS_W][TS_W1];
   __shared__ double Xs[TS_W][TS_W1];
@@ -357,8 +362,8 @@ __global__ __launch_bounds__(TS_NT) void tsqr_local_kernel(
   const long long b = blockIdx.y;
   M += b * sM;
   V += b * sV;
-  const int i0 = p * TS_MB;
-  const int rows = min(TS_MB, h - i0);
+  const int i0 = p * MBK;
+  const int rows = min(MBK, h - i0);
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = lane & 7, hs = lane >> 3;
   double a[TS_LOCAL_RQ][4];
@@ -373,7 +378,7 @@ __global__ __launch_bounds__(TS_NT) void tsqr_local_kernel(
     }
   }
   double myscal[4], mybeta[4];
-  ql_householder<TS_LOCAL_RQ, TS_NT / 64>(a, w, myscal, mybeta, Ts, Zm, Xs, taus, red, rowb);
+  ql_householder<TS_LOCAL_RQ, NW>(a, w, myscal, mybeta, Ts, Zm, Xs, taus, red, rowb);
   // R_p (rows 0..31 of the block, row-major, zero beyond the block and w) and
   // Y_p (unit lower trapezoidal) into V's rows, straight from the lanes
   double* Rp = Rstack + b * sScr;
@@ -394,7 +399,7 @@ __global__ __launch_bounds__(TS_NT) void tsqr_local_kernel(
     }
   }
   double* Tp = direct ? Tfin + b * sT : Tloc + b * sScr + (long long)p * TS_W * TS_W;
-  for (int e = tid; e < TS_W * TS_W; e += TS_NT) Tp[e] = Ts[e % TS_W][e / TS_W];
+  for (int e = tid; e < TS_W * TS_W; e += NT) Tp[e] = Ts[e % TS_W][e / TS_W];
 }
 
 // B: QR of the stacked R factors (registers), explicit Q_top, reconstruction
@@ -714,9 +719,17 @@ void tsqr_panel(int batch, double* M, long long ldm, long long sM, int c0, int w
   {
     ProfScope prof("tsqr_local", s, batch * (2.0 * h * ww - P * 2.0 * ww * w / 3.0),
                    batch * 8.0 * 2.0 * h * w);
-    hipLaunchKernelGGL(tsqr_local_kernel, dim3(P, batch), dim3(TS_NT), 0, s, M, ldm, sM, c0, w, h1,
-                       r1a, r2a, h, P, V, ldv, sV, vr2, sc.Tloc, sc.Rstack, sc.stride, P == 1 ? 1 : 0,
-                       T, sT);
+    if (h <= 2 * TS_MB && P > 1) {
+      // up to 512 rows: one block on eight waves, finished directly
+      hipLaunchKernelGGL(tsqr_local_kernel<8>, dim3(1, batch), dim3(512), 0, s, M, ldm, sM, c0, w,
+                         h1, r1a, r2a, h, 1, V, ldv, sV, vr2, sc.Tloc, sc.Rstack, sc.stride, 1, T,
+                         sT);
+      ZCSD_CHECK_LAUNCH();
+      return;
+    }
+    hipLaunchKernelGGL(tsqr_local_kernel<TS_NT / 64>, dim3(P, batch), dim3(TS_NT), 0, s, M, ldm, sM,
+                       c0, w, h1, r1a, r2a, h, P, V, ldv, sV, vr2, sc.Tloc, sc.Rstack, sc.stride,
+                       P == 1 ? 1 : 0, T, sT);
     ZCSD_CHECK_LAUNCH();
   }
   if (P == 1) return;  // one block: its Householder QR is the panel's

@@ -84,7 +84,9 @@ typedef struct {
   double refine_offdiag;   /* mixed mode: final ‖V1^T B V1 - diag‖_2 (power-iteration estimate) */
   int refine_fallback;     /* mixed mode: 1 if the refinement did not reach the FP64 rounding
                               floor and Zolo-eig was recomputed in FP64 */
-  int repair;              /* 1 if Algorithm 2 (Sec. 5.1) replaced W_i = Q_i Q~_i^T */
+  int repair;              /* 1 if Algorithm 2 (Sec. 5.1) replaced W_i = Q_i Q~_i^T (full rank:
+                              when the sigma_min estimate reached eps; rank deficient: always
+                              tried, kept when it passes the check) */
   double repair_resid;     /* its max_i ‖R~_i - R_i‖_F / ‖R_i‖_F (accepted below 100 n u) */
   double time_ms[4];       /* polar, B, eig, assembly wall time (ms), measured with stream syncs */
 } zcsd_info;
@@ -119,6 +121,26 @@ zcsd_status zcsd_dcsd(zcsd_handle* handle, int n,
                       double* d_V1, int ldv1, double* d_theta,
                       double* d_W1, double* d_W2,
                       const zcsd_opts* opts, zcsd_info* info);
+
+/*
+ * Complete 2 x 2 CS decomposition of an orthogonal 2n x 2n matrix
+ * A = [A1 A3; A2 A4] (Remark (iv) of Sec. 3):
+ *    A = diag(U1, U2) [C -S; S C] diag(V1, V2)^T,  C = diag(cos theta),
+ *    S = diag(sin theta), 0 <= theta_1 <= ... <= theta_n <= pi/2.
+ * Algorithm 1 on the first block column [A1; A2] gives U1, U2, V1 and theta;
+ * then X = -A3^T U1 S + A4^T U2 C and V2 is the Q factor of X = QR with
+ * diag(R) >= 0 (X itself is orthogonal when A is).  All blocks n x n,
+ * column-major device memory owned by the caller (ld >= n); d_theta has
+ * length n.  opts may be NULL (defaults; rank_mode ZCSD_RANK_DEFICIENT is
+ * rejected with ZCSD_EINVAL); info may be NULL.  Returns ZCSD_ENOTISO when
+ * [A1; A2] is detected rank deficient (A is then not orthogonal).
+ */
+zcsd_status zcsd_dcsd2x2(zcsd_handle* handle, int n,
+                         const double* d_A1, int lda1, const double* d_A2, int lda2,
+                         const double* d_A3, int lda3, const double* d_A4, int lda4,
+                         double* d_U1, int ldu1, double* d_U2, int ldu2,
+                         double* d_V1, int ldv1, double* d_V2, int ldv2, double* d_theta,
+                         const zcsd_opts* opts, zcsd_info* info);
 
 /*
  * Batched CS decomposition of `batch` independent problems of different sizes

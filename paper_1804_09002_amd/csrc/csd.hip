@@ -99,26 +99,28 @@ __global__ void rsign_apply_kernel(int n, double* Q, double* R, long long sM,
   }
 }
 
-// QR with diag(R) >= 0 of the two n x n matrices at M (stride n*n, overwritten
-// by R) into Q
-static void qr_pos(int n, double* M, double* Q, Arena& ar, hipStream_t s) {
+// QR with diag(R) >= 0 of the `batch` n x n matrices at M (stride n*n,
+// overwritten by R) into Q
+static void qr_pos(int batch, int n, double* M, double* Q, Arena& ar, hipStream_t s) {
   const long long nn = (long long)n * n;
   ArenaScope sc(ar);
-  QRWork wk = qr_work_alloc(ar, QRShape::General, 2, n, n, 32);
-  geqrf_batched(2, QRShape::General, n, n, M, n, nn, wk, s);
-  orgqr_batched(2, QRShape::General, n, n, Q, n, nn, nullptr, wk, s);
-  double* d = ar.dalloc(2 * (size_t)n);
+  QRWork wk = qr_work_alloc(ar, QRShape::General, batch, n, n, 32);
+  geqrf_batched(batch, QRShape::General, n, n, M, n, nn, wk, s);
+  orgqr_batched(batch, QRShape::General, n, n, Q, n, nn, nullptr, wk, s);
+  double* d = ar.dalloc((size_t)batch * n);
   const unsigned g1 = (unsigned)std::max(1, std::min((n + 255) / 256, 1024));
-  hipLaunchKernelGGL(rsign_kernel, dim3(g1, 2), dim3(256), 0, s, n, M, nn, d);
+  hipLaunchKernelGGL(rsign_kernel, dim3(g1, batch), dim3(256), 0, s, n, M, nn, d);
   ZCSD_CHECK_LAUNCH();
   const unsigned g2 = (unsigned)std::max<long long>(1, std::min<long long>((nn + 255) / 256, 1024));
-  hipLaunchKernelGGL(rsign_apply_kernel, dim3(g2, 2), dim3(256), 0, s, n, Q, M, nn, d);
+  hipLaunchKernelGGL(rsign_apply_kernel, dim3(g2, batch), dim3(256), 0, s, n, Q, M, nn, d);
   ZCSD_CHECK_LAUNCH();
 }
 
 // Algorithm 2 on both polars: W_i = Q_i Q~_i^T; returns max_i ||R~_i - R_i||_F / ||R_i||_F
-static double polar_repair(int n, const double* X, double* W, const double* H, Arena& ar,
-                           hipStream_t s) {
+// W_i = Q_i Q~_i^T is written to Wr (2 problems, n x n, stride n*n); rel[i] =
+// ||R~_i - R_i||_F / ||R_i||_F
+static void polar_repair(int n, const double* X, double* Wr, const double* H, double rel[2],
+                         Arena& ar, hipStream_t s) {
   const long long nn = (long long)n * n;
   ArenaScope sc(ar);
   double* RA = ar.dalloc(2 * (size_t)nn);
@@ -127,15 +129,15 @@ static double polar_repair(int n, const double* X, double* W, const double* H, A
   double* QH = ar.dalloc(2 * (size_t)nn);
   copy_scale(2, n, n, 1.0, X, n, nn, RA, n, nn, s);
   copy_scale(2, n, n, 1.0, H, n, nn, RH, n, nn, s);
-  qr_pos(n, RA, QA, ar, s);
-  qr_pos(n, RH, QH, ar, s);
+  qr_pos(2, n, RA, QA, ar, s);
+  qr_pos(2, n, RH, QH, ar, s);
   GemmBatch g;
   g.batch = 2;
   g.transB = 1;
   g.m = n; g.n = n; g.k = n;
   g.A = QA; g.lda = n; g.sA = nn;
   g.B = QH; g.ldb = n; g.sB = nn;
-  g.C = W; g.ldc = n; g.sC = nn;
+  g.C = Wr; g.ldc = n; g.sC = nn;
   dgemm(g, s);
   // ||R~ - R||_F / ||R||_F per polar (RH <- RH - RA)
   double* ss = ar.dalloc(4);
@@ -144,7 +146,22 @@ static double polar_repair(int n, const double* X, double* W, const double* H, A
   sumsq(2, n, n, RH, n, nn, ss + 2, ar, s);
   double h[4];
   d2h(h, ss, sizeof(h), s);
-  return std::max(std::sqrt(h[2] / std::max(h[0], 1e-300)), std::sqrt(h[3] / std::max(h[1], 1e-300)));
+  rel[0] = std::sqrt(h[2] / std::max(h[0], 1e-300));
+  rel[1] = std::sqrt(h[3] / std::max(h[1], 1e-300));
+}
+
+// Y1 = U1 diag(sin theta), Y2 = U2 diag(cos theta) (n x n, Y ld n)
+__global__ void cs_scale_kernel(int n, const double* __restrict__ U1, long long ldu1,
+                                const double* __restrict__ U2, long long ldu2,
+                                const double* __restrict__ theta, double* Y1, double* Y2) {
+  const long long nn = (long long)n * n;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nn;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n), j = (int)(e / n);
+    const double t = theta[j];
+    Y1[e] = U1[i + (long long)j * ldu1] * sin(t);
+    Y2[e] = U2[i + (long long)j * ldu2] * cos(t);
+  }
 }
 
 struct CsdOut {
@@ -211,11 +228,29 @@ static CsdOut csd_run(int n, const double* A1, long long lda1, const double* A2,
   // A_i = Q_i R_i and H~_i = Q~_i R~_i (diag(R) >= 0, where the two R factors
   // agree in exact arithmetic) W_i = Q_i Q~_i^T is orthonormal by construction
   // and ||W_i H~_i - A_i|| = ||R~_i - R_i||, checked against 100 n u ||R_i||_F.
-  if (!deficient && out.pd.ell <= o.eps * (1.0 + 1e-12)) {
+  // The rank-deficient path always runs the modified Zolo-pd, and its nonzero
+  // singular values may lie below eps as well (A rank deficient and C or S
+  // ill conditioned): Sec. 5.2 then takes the same lines of Algorithm 2.  There
+  // the repaired W_i is kept aside and used for U_i when U_i = W~_i V_1r comes
+  // out far from orthonormal (below).
+  const double rep_tol = 100.0 * n * 0x1p-53;
+  double* Wrep = nullptr;
+  bool rep_ok[2] = {false, false};
+  double rep_rel[2] = {0.0, 0.0};
+  if (deficient) {
+    Wrep = ar.dalloc(2 * (size_t)nn);
+    polar_repair(n, X, Wrep, H, rep_rel, ar, s);
+    rep_ok[0] = rep_rel[0] <= rep_tol;
+    rep_ok[1] = rep_rel[1] <= rep_tol;
+  } else if (out.pd.ell <= o.eps * (1.0 + 1e-12)) {
+    ArenaScope rs(ar);
+    double* Wr = ar.dalloc(2 * (size_t)nn);
+    polar_repair(n, X, Wr, H, rep_rel, ar, s);
     out.repair = true;
-    out.repair_resid = polar_repair(n, X, W, H, ar, s);
-    if (!(out.repair_resid <= 100.0 * n * 0x1p-53))
+    out.repair_resid = std::max(rep_rel[0], rep_rel[1]);
+    if (!(out.repair_resid <= rep_tol))
       throw NumError(ZCSD_EREPAIR, "csd: ill-conditioned repair rejected (||R~ - R|| too large)");
+    copy_scale(2, n, n, 1.0, Wr, n, nn, W, n, nn, s);
   }
   HostSync::sync(s);
   double t1 = now_ms();
@@ -309,6 +344,35 @@ static CsdOut csd_run(int n, const double* A1, long long lda1, const double* A2,
       // to first order.
       double* Gr = T;  // r x r per polar, T is free until the H_i V product below
       double* Tc = ar.dalloc(2 * (size_t)nn);
+      if (rep_ok[0] || rep_ok[1]) {
+        // ||U_i^T U_i - I||_F; beyond 1e-6 (more than the two steps below can
+        // remove) U_i is taken from the repaired W_i of Algorithm 2 instead
+        GemmBatch q;
+        q.batch = 2;
+        q.transA = 1; q.transB = 0;
+        q.m = r; q.n = r; q.k = n;
+        q.A = Ut; q.lda = n; q.sA = nn;
+        q.B = Ut; q.ldb = n; q.sB = nn;
+        q.C = Gr; q.ldc = r; q.sC = nn;
+        dgemm(q, s);
+        add_diag(2, r, -1.0, Gr, r, nn, s);
+        double* dd = ar.dalloc(2);
+        sumsq(2, r, r, Gr, r, nn, dd, ar, s);
+        double hd[2];
+        d2h(hd, dd, sizeof(hd), s);
+        for (int i = 0; i < 2; ++i) {
+          if (rep_ok[i] && hd[i] > 1e-12) {
+            GemmBatch w;
+            w.m = n; w.n = r; w.k = n;
+            w.A = Wrep + i * nn; w.lda = n;
+            w.B = V; w.ldb = n;
+            w.C = Ut + i * nn; w.ldc = n;
+            dgemm(w, s);
+            out.repair = true;
+            out.repair_resid = std::max(out.repair_resid, rep_rel[i]);
+          }
+        }
+      }
       for (int it = 0; it < 2; ++it) {
         GemmBatch q;
         q.batch = 2;
@@ -414,6 +478,81 @@ extern "C" zcsd_status zcsd_dcsd(zcsd_handle* handle, int n, const double* d_A1,
       info->refine_max_cluster = r.refine.max_cluster;
       info->refine_offdiag = r.refine.offdiag;
       info->refine_fallback = r.refine.fallback ? 1 : 0;
+      info->repair = r.repair ? 1 : 0;
+      info->repair_resid = r.repair_resid;
+      info->time_ms[0] = r.t_polar;
+      info->time_ms[1] = r.t_B;
+      info->time_ms[2] = r.t_eig;
+      info->time_ms[3] = r.t_asm;
+    }
+  });
+}
+
+extern "C" zcsd_status zcsd_dcsd2x2(zcsd_handle* handle, int n, const double* d_A1, int lda1,
+                                    const double* d_A2, int lda2, const double* d_A3, int lda3,
+                                    const double* d_A4, int lda4, double* d_U1, int ldu1,
+                                    double* d_U2, int ldu2, double* d_V1, int ldv1, double* d_V2,
+                                    int ldv2, double* d_theta, const zcsd_opts* opts,
+                                    zcsd_info* info) {
+  if (!handle) return ZCSD_EINVAL;
+  return guarded([&] {
+    ZCSD_REQUIRE(n >= 1, "csd2x2: n must be positive");
+    ZCSD_REQUIRE(d_A1 && d_A2 && d_A3 && d_A4 && d_U1 && d_U2 && d_V1 && d_V2 && d_theta,
+                 "csd2x2: NULL pointer");
+    ZCSD_REQUIRE(lda1 >= n && lda2 >= n && lda3 >= n && lda4 >= n && ldu1 >= n && ldu2 >= n &&
+                     ldv1 >= n && ldv2 >= n,
+                 "csd2x2: leading dimension < n");
+    zcsd_opts o;
+    zcsd_default_opts(&o);
+    if (opts) o = *opts;
+    ZCSD_REQUIRE(o.r_override >= 0 && o.r_override <= ZOLO_RMAX, "csd2x2: r_override out of range");
+    ZCSD_REQUIRE(o.prec == ZCSD_FP64 || o.prec == ZCSD_MIXED_FP32, "csd2x2: unknown precision mode");
+    ZCSD_REQUIRE(o.eps > 0.0 && o.eps < 1.0 && o.tol > 0.0, "csd2x2: eps/tol out of range");
+    ZCSD_REQUIRE(o.rank_mode != ZCSD_RANK_DEFICIENT, "csd2x2: the first block column has full rank");
+    ZCSD_HIP(hipSetDevice(handle->device));
+    handle->arena.reset();
+    handle->arena.reserve(csd_workspace_bytes(n));
+    hipStream_t s = handle->stream;
+    CsdOut r = csd_run(n, d_A1, lda1, d_A2, lda2, d_U1, ldu1, d_U2, ldu2, d_V1, ldv1, d_theta,
+                       nullptr, nullptr, o, handle->arena, s);
+    if (r.rank < n)
+      throw NumError(ZCSD_ENOTISO, "csd2x2: [A1; A2] is rank deficient, A is not orthogonal");
+    // X = -A3^T U1 S + A4^T U2 C, V2 = Q of X = QR (diag(R) >= 0)
+    Arena& ar = handle->arena;
+    ArenaScope scope(ar);
+    const long long nn = (long long)n * n;
+    double* Y = ar.dalloc(2 * (size_t)nn);
+    double* X = ar.dalloc((size_t)nn);
+    double* Q = ar.dalloc((size_t)nn);
+    const unsigned g = (unsigned)std::max<long long>(1, std::min<long long>((nn + 255) / 256, 4096));
+    hipLaunchKernelGGL(cs_scale_kernel, dim3(g), dim3(256), 0, s, n, d_U1, (long long)ldu1, d_U2,
+                       (long long)ldu2, d_theta, Y, Y + nn);
+    ZCSD_CHECK_LAUNCH();
+    GemmBatch gm;
+    gm.transA = 1;
+    gm.m = n; gm.n = n; gm.k = n;
+    gm.A = d_A3; gm.lda = lda3;
+    gm.B = Y; gm.ldb = n;
+    gm.C = X; gm.ldc = n;
+    gm.alpha = -1.0; gm.beta = 0.0;
+    dgemm(gm, s);
+    gm.A = d_A4; gm.lda = lda4;
+    gm.B = Y + nn;
+    gm.alpha = 1.0; gm.beta = 1.0;
+    dgemm(gm, s);
+    qr_pos(1, n, X, Q, ar, s);
+    copy_scale(1, n, n, 1.0, Q, n, 0, d_V2, ldv2, 0, s);
+    ZCSD_HIP(hipStreamSynchronize(s));
+    if (info) {
+      *info = zcsd_info{};
+      info->rank = r.rank;
+      info->r_used[0] = info->r_used[1] = r.pd.r;
+      info->ell[0] = info->ell[1] = r.pd.ell;
+      info->zolo_resid = r.pd.resid;
+      info->eig_levels = r.eig.levels;
+      info->eig_splits = r.eig.splits;
+      info->eig_max_r = r.eig.max_r;
+      info->eig_offblock = r.eig.max_offblock;
       info->repair = r.repair ? 1 : 0;
       info->repair_resid = r.repair_resid;
       info->time_ms[0] = r.t_polar;

@@ -16,6 +16,8 @@ Recipes (the paper's test classes of Sec. 6, real analogues):
 * ``from_angles``  A1 = U1 diag(cos t) V1^T, A2 = U2 diag(sin t) V1^T, optionally
                    with C_ii = S_ii = 0 on a set of indices (rank-deficient
                    partial isometry, test class 4).
+* ``paper_test_class``  the eight test classes of Sec. 6 (1-4 and the noisy
+                   1'-4'), real analogues.
 """
 from __future__ import annotations
 
@@ -106,6 +108,43 @@ def uniform_pair(n, seed):
     rng = np.random.default_rng(seed)
     theta = angles_uniform(n, rng)
     return from_angles(theta, rng)
+
+
+PAPER_CLASSES = ("1", "2", "3", "4", "1'", "2'", "3'", "4'")
+
+
+def paper_test_class(cls, n, rng):
+    """Test classes of Sec. 6 (real analogue), split into A1 (top n rows) and A2.
+
+    1 Haar 2n x n with orthonormal columns; 2 clustered angles (cumulative-sum
+    recipe) with Haar factors; 3 rank r = nint(3n/4), A = X Y^T with X, Y Haar
+    with orthonormal columns (2n x r, n x r); 4 class 2 with C_ii = S_ii = 0 on
+    n - r random indices; a trailing prime adds 1e-10 N(0, 1) entries.
+    """
+    if cls not in PAPER_CLASSES:
+        raise ValueError(f"unknown test class {cls!r}")
+    c = int(cls[0])
+    r = int(np.rint(3 * n / 4))
+    if c == 1:
+        A = stiefel(2 * n, n, rng)
+    elif c == 2:
+        A1, A2, _ = from_angles(angles_cumsum_clustered(n, rng), rng)
+        A = np.vstack([A1, A2])
+    elif c == 3:
+        A = stiefel(2 * n, r, rng) @ stiefel(n, r, rng).T
+    else:
+        theta = angles_cumsum_clustered(n, rng)
+        zero_idx = np.sort(rng.choice(n, size=n - r, replace=False))
+        A1, A2, _ = from_angles(theta, rng, zero_idx=zero_idx)
+        A = np.vstack([A1, A2])
+    if cls.endswith("'"):
+        A = A + 1e-10 * rng.standard_normal(A.shape)
+    return np.ascontiguousarray(A[:n]), np.ascontiguousarray(A[n:])
+
+
+def paper_sizes(jmax=9):
+    """n = nint(30 * 2^(j/2)), j = 0..jmax (Sec. 6)."""
+    return [int(np.rint(30 * 2.0 ** (j / 2))) for j in range(jmax + 1)]
 
 
 def batched_sizes(count, seed, lo=8, hi=256):

@@ -83,6 +83,8 @@ def _lib():
         for name, args in {
             "zcsd_dcsd": [vp, i, vp, i, vp, i, vp, i, vp, i, vp, i, vp, vp, vp,
                           C.POINTER(Opts), C.POINTER(Info)],
+            "zcsd_dcsd2x2": [vp, i, vp, i, vp, i, vp, i, vp, i, vp, i, vp, i, vp, i, vp, i, vp,
+                             C.POINTER(Opts), C.POINTER(Info)],
             "zcsd_dzolo_pd": [vp, i, i, d, vp, i, ll, vp, vp, vp, C.POINTER(Opts), C.POINTER(Info)],
             "zcsd_dsyev_zolo": [vp, i, vp, i, d, d, vp, i, vp, C.POINTER(Opts), C.POINTER(Info)],
             "zcsd_dcsd_backward": [vp, i, i, vp, vp, vp, vp, vp, vp, vp, vp, vp],
@@ -287,6 +289,29 @@ def csd(A1, A2, rank_mode="auto", r=None, ell=None, want_polar=False, **opts):
     if want_polar:
         d["W1"], d["W2"] = W1.t(), W2.t()
     return U1.t(), U2.t(), V1.t(), th, d
+
+
+def csd2x2(A1, A2, A3, A4, **opts):
+    """Complete 2 x 2 CSD of the orthogonal [A1 A3; A2 A4] (n x n float64 HIP tensors).
+
+    Returns (U1, U2, V1, V2, theta, info) with
+    A = diag(U1, U2) [C -S; S C] diag(V1, V2)^T (zcsd_dcsd2x2).
+    """
+    n = A1.shape[0]
+    for X, name in ((A1, "A1"), (A2, "A2"), (A3, "A3"), (A4, "A4")):
+        if X.shape != (n, n):
+            raise ValueError(f"csd2x2: {name} must be n x n")
+    a = [_colmajor(X, nm) for X, nm in ((A1, "A1"), (A2, "A2"), (A3, "A3"), (A4, "A4"))]
+    U1, U2, V1, V2 = (torch.empty_like(a[0]) for _ in range(4))
+    th = torch.empty(n, dtype=torch.float64, device=A1.device)
+    o = default_opts(rank_mode=opts.pop("rank_mode", "auto"), **opts)
+    info = Info()
+    h = handle(A1.device.index)
+    st = _lib().zcsd_dcsd2x2(h, n, _ptr(a[0]), n, _ptr(a[1]), n, _ptr(a[2]), n, _ptr(a[3]), n,
+                             _ptr(U1), n, _ptr(U2), n, _ptr(V1), n, _ptr(V2), n, _ptr(th),
+                             C.byref(o), C.byref(info))
+    _check(st, "zcsd_dcsd2x2")
+    return U1.t(), U2.t(), V1.t(), V2.t(), th, info.as_dict()
 
 
 class profile:

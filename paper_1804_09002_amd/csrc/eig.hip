@@ -554,7 +554,12 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
       long long v = std::llround(tr[q]);
       npos[q] = (int)std::min<long long>(std::max<long long>(v, 0), nbs[q]);
     }
-    // basis: Q of QR(P Omega)
+    // basis: the orthogonal factor of the Householder QR of P Omega_1, Omega_1 =
+    // the first kq columns of Omega, kq = the largest n+ of the level: its first
+    // n+ columns span range(P) and the rest its complement, so the reflectors of
+    // kq columns (not Ns) give the whole Ns x Ns factor
+    int kq = 1;
+    for (int q = 0; q < ns; ++q) kq = std::max(kq, npos[q]);
     double* Om = ar.dalloc((size_t)ns * SS);
     hipLaunchKernelGGL(omega_kernel, grid2(SS, ns), dim3(256), 0, s, Ns, Om, d_nbs, seed);
     ZCSD_CHECK_LAUNCH();
@@ -563,7 +568,7 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
     {
       GemmBatch g;
       g.batch = ns;
-      g.m = Ns; g.n = Ns; g.k = Ns;
+      g.m = Ns; g.n = kq; g.k = Ns;
       g.A = W; g.lda = Ns; g.sA = SS;
       g.B = Om; g.ldb = Ns; g.sB = SS;
       g.C = Y; g.ldc = Ns; g.sC = SS;
@@ -573,9 +578,9 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
     double* Q = Om;  // Omega is dead after the product
     {
       ArenaScope qs(ar);
-      QRWork wk = qr_work_alloc(ar, QRShape::General, ns, Ns, Ns, 32);
-      geqrf_batched(ns, QRShape::General, Ns, Ns, Y, Ns, SS, wk, s);
-      orgqr_batched(ns, QRShape::General, Ns, Ns, Q, Ns, SS, nullptr, wk, s);
+      QRWork wk = qr_work_alloc(ar, QRShape::General, ns, Ns, kq, 32, Ns);
+      geqrf_batched(ns, QRShape::General, Ns, kq, Y, Ns, SS, wk, s);
+      orgqr_batched(ns, QRShape::General, Ns, kq, Q, Ns, SS, nullptr, wk, s, Ns);
     }
     offpad(Q, offQ);
     if (log_enabled())

@@ -1,6 +1,8 @@
 // Element-wise and reduction kernels (HBM-bound helpers around the MFMA path)
 // and the device workspace arena.
 #include <algorithm>
+#include <map>
+#include <mutex>
 
 #include "zcsd_internal.h"
 #include "zcsd_la.h"
@@ -57,6 +59,45 @@ void h2d(void* d, const void* h, size_t bytes, hipStream_t s) {
   ZCSD_HIP(hipStreamSynchronize(s));
   ZCSD_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s));
   ZCSD_HIP(hipStreamSynchronize(s));
+}
+
+static hipStream_t aux_stream_for_current_device() {
+  static std::mutex mu;
+  static std::map<int, hipStream_t> streams;
+  int dev = 0;
+  ZCSD_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> g(mu);
+  auto it = streams.find(dev);
+  if (it != streams.end()) return it->second;
+  hipStream_t st = nullptr;
+  ZCSD_HIP(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+  streams[dev] = st;
+  return st;
+}
+
+AuxStream::AuxStream(hipStream_t s) : s_(s) {
+  aux_ = aux_stream_for_current_device();
+  ZCSD_HIP(hipEventCreateWithFlags(&fork_, hipEventDisableTiming));
+  ZCSD_HIP(hipEventCreateWithFlags(&done_, hipEventDisableTiming));
+  ZCSD_HIP(hipEventRecord(fork_, s_));
+  ZCSD_HIP(hipStreamWaitEvent(aux_, fork_, 0));
+}
+
+void AuxStream::join() {
+  if (joined_) return;
+  joined_ = true;
+  ZCSD_HIP(hipEventRecord(done_, aux_));
+  ZCSD_HIP(hipStreamWaitEvent(s_, done_, 0));
+}
+
+AuxStream::~AuxStream() {
+  if (!joined_) {
+    joined_ = true;
+    if (hipEventRecord(done_, aux_) != hipSuccess || hipStreamWaitEvent(s_, done_, 0) != hipSuccess)
+      (void)hipStreamSynchronize(aux_);
+  }
+  (void)hipEventDestroy(fork_);
+  (void)hipEventDestroy(done_);
 }
 
 // ---------------------------------------------------------------------------

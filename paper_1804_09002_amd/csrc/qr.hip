@@ -197,7 +197,7 @@ static void panel_segments(QRShape shape, int m, int n, int nb, int k, int* c0, 
 
 // Arena bytes that qr_work_alloc takes (allocation by allocation, with the
 // arena's 256-byte alignment)
-size_t qr_work_bytes(QRShape shape, int batch, int m, int n, int nb) {
+size_t qr_work_bytes(QRShape shape, int batch, int m, int n, int nb, int qcols) {
   auto al = [](size_t count) { return ((count * sizeof(double) + 255) / 256) * 256; };
   size_t t = 0;
   const int K = (n + nb - 1) / nb;
@@ -207,7 +207,7 @@ size_t qr_work_bytes(QRShape shape, int batch, int m, int n, int nb) {
   const int wcols = two ? NBO : nb;
   const int nblk = two ? (n + NBO - 1) / NBO : K;
   const long long ldv = (shape == QRShape::General) ? m : (n + wcols);
-  const size_t sW = (size_t)wcols * n;
+  const size_t sW = (size_t)wcols * std::max(n, qcols);
   const size_t ws_elems = (size_t)8 * batch * wcols * n;
   t += al((size_t)batch * nblk * ldv * wcols) + al((size_t)batch * K * nb * nb);
   t += 2 * al((size_t)batch * sW);
@@ -222,7 +222,7 @@ size_t qr_work_bytes(QRShape shape, int batch, int m, int n, int nb) {
   return t;
 }
 
-QRWork qr_work_alloc(Arena& ar, QRShape shape, int batch, int m, int n, int nb) {
+QRWork qr_work_alloc(Arena& ar, QRShape shape, int batch, int m, int n, int nb, int qcols) {
   QRWork wk;
   wk.nb = nb;
   wk.K = (n + nb - 1) / nb;
@@ -242,7 +242,7 @@ QRWork qr_work_alloc(Arena& ar, QRShape shape, int batch, int m, int n, int nb) 
   wk.sT = (long long)wk.K * nb * nb;
   wk.V = ar.dalloc((size_t)batch * wk.sV);
   wk.T = ar.dalloc((size_t)batch * wk.sT);
-  wk.sW = (long long)wcols * n;
+  wk.sW = (long long)wcols * std::max(n, qcols);
   wk.W = ar.dalloc((size_t)batch * wk.sW);
   wk.W2 = ar.dalloc((size_t)batch * wk.sW);
   if (nb == 32) wk.ts = tsqr_scratch_alloc(ar, batch);
@@ -673,9 +673,15 @@ void geqrf_batched(int batch, QRShape shape, int m, int n, double* M, long long 
 }
 
 void orgqr_batched(int batch, QRShape shape, int m, int n, double* Q, long long ldq, long long sQ,
-                   const double* d_scale, const QRWork& wk, hipStream_t s) {
+                   const double* d_scale, const QRWork& wk, hipStream_t s, int qcols) {
   if (batch <= 0 || n <= 0) return;
-  set_identity_scaled(batch, m, n, d_scale, 1.0, Q, ldq, sQ, s);
+  // Q has nq columns: the n reflectors applied to the first nq columns of I_m
+  const int nq = std::max(n, qcols);
+  if (nq > n && (shape != QRShape::General || nq > m))
+    throw ArgError("orgqr: more columns than reflectors needs a General shape and nq <= m");
+  if (wk.sW < (long long)(wk.nbo ? wk.nbo : wk.nb) * nq)
+    throw ArgError("orgqr: workspace sized for fewer columns of Q");
+  set_identity_scaled(batch, m, nq, d_scale, 1.0, Q, ldq, sQ, s);
   if (wk.nbo) {
     const int NBO = wk.nbo;
     for (int O = wk.Ko - 1; O >= 0; --O) {
@@ -688,7 +694,7 @@ void orgqr_batched(int batch, QRShape shape, int m, int n, double* Q, long long 
       } else {
         r1a = co; r1b = co + wo; r2a = n; r2b = n + co + wo;
       }
-      apply_block_reflector(batch, Q, ldq, sQ, co, n - co, r1a, r1b, r2a, r2b, wo, VO, VO + wo,
+      apply_block_reflector(batch, Q, ldq, sQ, co, nq - co, r1a, r1b, r2a, r2b, wo, VO, VO + wo,
                             wk.ldv, wk.sV, TO, wk.sTo, NBO, wk.W, wk.W2, wk.sW, /*transT=*/false,
                             wk.ws, wk.ws_elems, s);
     }
@@ -701,7 +707,7 @@ void orgqr_batched(int batch, QRShape shape, int m, int n, double* Q, long long 
     const double* Vk = wk.V + (long long)k * wk.ldv * nb;
     const double* Tk = wk.T + (long long)k * nb * nb;
     const int h1 = r1b - r1a;
-    apply_block_reflector(batch, Q, ldq, sQ, c0, n - c0, r1a, r1b, r2a, r2b, w, Vk, Vk + h1, wk.ldv,
+    apply_block_reflector(batch, Q, ldq, sQ, c0, nq - c0, r1a, r1b, r2a, r2b, w, Vk, Vk + h1, wk.ldv,
                           wk.sV, Tk, wk.sT, nb, wk.W, wk.W2, wk.sW, /*transT=*/false, wk.ws,
                           wk.ws_elems, s);
   }

@@ -171,6 +171,27 @@ struct HostSync {
   static void sync(hipStream_t s) { ZCSD_HIP(hipStreamSynchronize(s)); }
 };
 void d2h(void* h, const void* d, size_t bytes, hipStream_t s);  // async + sync
+
+// A second stream for work that can overlap the launches queued on s: the
+// constructor makes it wait for everything queued on s so far; join() makes s
+// wait for everything queued on it since.  One such stream per device, created
+// on first use with the default priority.  The destructor joins when join()
+// was not called (error paths), so later work on s stays ordered after it;
+// memory that the side work uses must stay allocated until the join.
+class AuxStream {
+ public:
+  explicit AuxStream(hipStream_t s);
+  ~AuxStream();
+  AuxStream(const AuxStream&) = delete;
+  AuxStream& operator=(const AuxStream&) = delete;
+  hipStream_t get() const { return aux_; }
+  void join();
+
+ private:
+  hipStream_t s_ = nullptr, aux_ = nullptr;
+  hipEvent_t fork_ = nullptr, done_ = nullptr;
+  bool joined_ = false;
+};
 void h2d(void* d, const void* h, size_t bytes, hipStream_t s);  // async (pageable: sync inside)
 
 }  // namespace zcsd

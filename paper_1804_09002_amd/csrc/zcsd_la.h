@@ -30,16 +30,20 @@ struct QRWork {
   Arena* ar = nullptr;
 };
 
-QRWork qr_work_alloc(Arena& ar, QRShape shape, int batch, int m, int n, int nb);
+// qcols > n: room for orgqr_batched to form a Q with qcols columns
+QRWork qr_work_alloc(Arena& ar, QRShape shape, int batch, int m, int n, int nb, int qcols = 0);
 // arena bytes taken by qr_work_alloc
-size_t qr_work_bytes(QRShape shape, int batch, int m, int n, int nb);
+size_t qr_work_bytes(QRShape shape, int batch, int m, int n, int nb, int qcols = 0);
 // In place: M_b (m x n, or 2n x n for Stacked) -> R in its top n x n upper triangle,
 // zeros below; reflectors kept in wk.
 void geqrf_batched(int batch, QRShape shape, int m, int n, double* M, long long ldm, long long sM,
                    QRWork& wk, hipStream_t s);
-// Q_b = H_1 ... H_K [scale_b I_n; 0] (m x n); d_scale may be NULL (scale 1).
+// Q_b = H_1 ... H_K [scale_b I_nq; 0] (m x nq, nq = max(n, qcols)); d_scale may be
+// NULL (scale 1).  qcols > n (General shape, workspace from qr_work_alloc with
+// the same qcols): the n reflectors of an m x n factorization extended to more
+// columns, e.g. the whole m x m orthogonal factor (LAPACK's orgqr with k < n).
 void orgqr_batched(int batch, QRShape shape, int m, int n, double* Q, long long ldq, long long sQ,
-                   const double* d_scale, const QRWork& wk, hipStream_t s);
+                   const double* d_scale, const QRWork& wk, hipStream_t s, int qcols = 0);
 
 // ---------------------------------------------------------------------------
 // element-wise helpers beyond zcsd_internal.h (elem.hip)

@@ -16,9 +16,10 @@
 //      starts from, so the r products are one GEMM with inner size r n.
 //   2. Cholesky form on Y1 (well conditioned after step 1):
 //        G = Y1^T Y1,  R_j^T R_j = (G + c_{2j-1} I) / a_j,
-//        sum_j a_j (G + c_{2j-1} I)^{-1} = Z Z^T,  Z = [R_1^{-1} ... R_r^{-1}],
+//        sum_j a_j (G + c_{2j-1} I)^{-1} = sum_j R_j^{-1} R_j^{-T},
 //        Y2 = M (Y1 + Y1 Z Z^T).
-//   3. W = Q Y2,  H = alpha sym(Y2^T R) (= sym(W^T X)).
+//   3. W = Q Y2,  H = alpha sym(Y2^T R) (= sym(W^T X)); Q itself is formed
+//      on a second stream during steps 1 and 2.
 #include <algorithm>
 #include <cmath>
 #include <vector>
@@ -69,6 +70,20 @@ __global__ void shift_scale_kernel(int n, int r, const double* __restrict__ G, d
   }
 }
 
+// Ms_b = sum_j T_{b,j} on the upper triangle (i <= j), terms in order j = 0..r-1
+__global__ void sum_terms_upper_kernel(int n, int r, const double* __restrict__ T, double* Ms) {
+  const long long b = blockIdx.y;
+  const long long nn = (long long)n * n;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < nn;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int i = (int)(e % n), col = (int)(e / n);
+    if (i > col) continue;
+    double acc = 0.0;
+    for (int j = 0; j < r; ++j) acc += T[(b * r + j) * nn + e];
+    Ms[b * nn + e] = acc;
+  }
+}
+
 static dim3 grid_for(long long total, int batch) {
   long long g = (total + 255) / 256;
   g = std::max<long long>(1, std::min<long long>(g, 2048));
@@ -88,6 +103,12 @@ ZoloPdResult zolo_pd_batched(const ZoloPdArgs& a, Arena& ar, hipStream_t s) {
   const int nb = a.nb_qr;
   QRWork wk0 = qr_work_alloc(ar, QRShape::General, B, n, n, nb);
   geqrf_batched(B, QRShape::General, n, n, M, n, nn, wk0, s);
+  // Q is needed only in step 3: it is formed on a second stream while the
+  // latency-bound QRs and Cholesky factorizations of steps 1 and 2 run on s
+  // (only wk0, Q and the reflectors are touched there; both live to the end)
+  double* Q = ar.dalloc((size_t)B * nn);
+  AuxStream side(s);
+  orgqr_batched(B, QRShape::General, n, n, Q, n, nn, nullptr, wk0, side.get());
 
   // lower bound l
   double ell;
@@ -189,16 +210,21 @@ ZoloPdResult zolo_pd_batched(const ZoloPdArgs& a, Arena& ar, hipStream_t s) {
   chol_inv_batched(P, n, E, n, nn, Rc, Ric, ar, s);
   double* Ms = G;  // G is dead: reuse for sum_j a_j (G + c_j I)^{-1}
   {
+    // one product per term (into Rc, dead after the inversion) and a sum: as
+    // one product with inner size r n, the tiles at the top of C would carry
+    // r times the work of the average tile and set the launch's length
     GemmBatch g;
-    g.batch = B;
+    g.batch = P;
     g.transA = 0; g.transB = 1;
-    g.m = n; g.n = n; g.k = r * n;
-    g.A = Ric; g.lda = n; g.sA = (long long)r * nn;
-    g.B = Ric; g.ldb = n; g.sB = (long long)r * nn;
-    g.C = Ms; g.ldc = n; g.sC = nn;
+    g.m = n; g.n = n; g.k = n;
+    g.A = Ric; g.lda = n; g.sA = nn;
+    g.B = Ric; g.ldb = n; g.sB = nn;
+    g.C = Rc; g.ldc = n; g.sC = nn;
     g.sym_upper = true;
     g.tri = 1 | 8; g.kseg = n;  // R_j^{-1} upper triangular
     dgemm(g, s);
+    hipLaunchKernelGGL(sum_terms_upper_kernel, grid_for(nn, B), dim3(256), 0, s, n, r, Rc, Ms);
+    ZCSD_CHECK_LAUNCH();
   }
   mirror_upper(B, n, Ms, n, nn, s);
   double* Y2 = ar.dalloc((size_t)B * nn);
@@ -215,8 +241,7 @@ ZoloPdResult zolo_pd_batched(const ZoloPdArgs& a, Arena& ar, hipStream_t s) {
   }
 
   // 3. W = Q Y2, H = alpha sym(Y2^T R), X1 = Q Y1
-  double* Q = ar.dalloc((size_t)B * nn);
-  orgqr_batched(B, QRShape::General, n, n, Q, n, nn, nullptr, wk0, s);
+  side.join();
   auto qtimes = [&](const double* Y, double* out) {
     GemmBatch g;
     g.batch = B;

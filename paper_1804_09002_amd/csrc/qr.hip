@@ -216,7 +216,7 @@ size_t qr_work_bytes(QRShape shape, int batch, int m, int n, int nb, int qcols) 
   if (two) {
     const int Ko = (n + NBO - 1) / NBO;
     t += al((size_t)batch * Ko * NBO * NBO) + al((size_t)batch * (NBO / nb) * nb * nb);
-    t += 2 * al((size_t)batch * NBO * NBO);
+    t += al((size_t)batch * NBO * NBO);
     t += al((size_t)batch * ((hmax + PU_CH - 1) / PU_CH) * PU_W * PU_NC) + al(((size_t)batch + 1) / 2);
   }
   return t;
@@ -255,7 +255,6 @@ QRWork qr_work_alloc(Arena& ar, QRShape shape, int batch, int m, int n, int nb, 
     wk.Tin = ar.dalloc((size_t)batch * wk.sTin);
     wk.sG = (long long)NBO * NBO;
     wk.G = ar.dalloc((size_t)batch * wk.sG);
-    wk.Ginv = ar.dalloc((size_t)batch * wk.sG);
     // inner-panel updates: ceil(hmax / PU_CH) partials of 32 x 96 per problem
     const int nchunk = (hmax + PU_CH - 1) / PU_CH;
     wk.sPart = (long long)nchunk * 32 * 96;
@@ -263,20 +262,6 @@ QRWork qr_work_alloc(Arena& ar, QRShape shape, int batch, int m, int n, int nb, 
     wk.pu_cnt = reinterpret_cast<unsigned*>(ar.dalloc(((size_t)batch + 1) / 2));
   }
   return wk;
-}
-
-// Tinv_b = striu(G_b) + diag(G_b) / 2 (w x w, ld NBO); zero beyond w
-__global__ void ut_tinv_kernel(int w, int ld, const double* __restrict__ G, long long sG, double* Ti) {
-  const long long b = blockIdx.y;
-  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < ld * ld; e += gridDim.x * blockDim.x) {
-    const int i = e % ld, j = e / ld;
-    double v = 0.0;
-    if (i < w && j < w) {
-      const double g = G[b * sG + i + (long long)j * ld];
-      v = (i < j) ? g : ((i == j) ? 0.5 * g : 0.0);
-    }
-    Ti[b * sG + e] = v;
-  }
 }
 
 // C <- (I - V T' V^T) C on the panel's row segments, columns [col0, col0 + nc);
@@ -614,10 +599,7 @@ static void geqrf_two_level(int batch, QRShape shape, int m, int n, double* M, l
       g.C = wk.G; g.ldc = NBO; g.sC = wk.sG;
       g.ws = wk.ws; g.ws_elems = wk.ws_elems;
       dgemm(g, s);
-      hipLaunchKernelGGL(ut_tinv_kernel, dim3((NBO * NBO + 255) / 256, batch), dim3(256), 0, s, wo,
-                         NBO, wk.G, wk.sG, wk.Ginv);
-      ZCSD_CHECK_LAUNCH();
-      trtri_upper_batched(batch, wo, wk.Ginv, NBO, wk.sG, TO, NBO, wk.sTo, *wk.ar, s);
+      ut_factor_from_gram(batch, wo, wk.G, NBO, wk.sG, TO, NBO, wk.sTo, s);
     }
     const int col0 = co + wo;
     if (col0 < n) {

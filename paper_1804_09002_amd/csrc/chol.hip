@@ -361,6 +361,7 @@ static void chol_inv_rec(int batch, int n, double* A, long long lda, long long s
   h.B = R12; h.ldb = ld; h.sB = s;
   h.C = A22; h.ldc = lda; h.sC = sA;
   h.alpha = -1.0; h.beta = 1.0;
+  h.upper_only = true;  // only the upper triangle of A22 is read below
   dgemm(h, st);
   chol_inv_rec(batch, n2, A22, lda, sA, R22, Ri22, ld, s, ar, st);
   // Ri12 = -R11i (R12 R22i)

@@ -558,8 +558,12 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
     // the first kq columns of Omega, kq = the largest n+ of the level: its first
     // n+ columns span range(P) and the rest its complement, so the reflectors of
     // kq columns (not Ns) give the whole Ns x Ns factor
+    // (the mixed mode keeps the square P Omega: with the FP32 products the
+    // narrower factorization measured a much worse starting point for the FP64
+    // refinement, 1e-4 against 5e-7 off the block diagonal at n = 4096)
     int kq = 1;
     for (int q = 0; q < ns; ++q) kq = std::max(kq, npos[q]);
+    if (a.lowp) kq = Ns;
     double* Om = ar.dalloc((size_t)ns * SS);
     hipLaunchKernelGGL(omega_kernel, grid2(SS, ns), dim3(256), 0, s, Ns, Om, d_nbs, seed);
     ZCSD_CHECK_LAUNCH();

@@ -257,12 +257,13 @@ static const char* tile_name(int ta, int tb) {
 template <int BM, int BN, int BK>
 static double computed_flops(const GemmBatch& g, bool split) {
   const double nprob = (double)g.batch * g.batch2;
-  if (!g.sym_upper && (!g.tri || split)) return 2.0 * g.m * (double)g.n * g.k * nprob;
+  const bool upper = g.sym_upper || g.upper_only;
+  if (!upper && (!g.tri || split)) return 2.0 * g.m * (double)g.n * g.k * nprob;
   const int gx = (g.m + BM - 1) / BM, gy = (g.n + BN - 1) / BN;
   double f = 0.0;
   for (int by = 0; by < gy; ++by)
     for (int bx = 0; bx < gx; ++bx) {
-      if (g.sym_upper && bx > by) continue;
+      if (upper && bx > by) continue;
       const int i0 = bx * BM, j0 = by * BN;
       double kr = g.k;
       if (g.tri && !split && g.kseg > 0) {
@@ -307,7 +308,7 @@ static void launch_tile(const GemmBatch& g, hipStream_t s, int ksplit) {
 #define ZCSD_GEMM_LAUNCH(TA_, TB_)                                                        \
   hipLaunchKernelGGL((dgemm_kernel<BM, BN, BK, TA_, TB_>), grid, block, 0, s, g.m, g.n, g.k, A, \
                      g.lda, g.sA, B, g.ldb, g.sB, C, g.ldc, g.sC, g.alpha, g.beta, g.batch,     \
-                     g.sA2, g.sB2, g.sC2, nprob, kchunk, g.ws, g.sym_upper ? 1 : 0, g.tri, \
+                     g.sA2, g.sB2, g.sC2, nprob, kchunk, g.ws, (g.sym_upper || g.upper_only) ? 1 : 0, g.tri, \
                      g.kseg)
     if (!g.transA && !g.transB) ZCSD_GEMM_LAUNCH(false, false);
     else if (!g.transA && g.transB) ZCSD_GEMM_LAUNCH(false, true);
@@ -329,6 +330,7 @@ void dgemm(const GemmBatch& g, hipStream_t s) {
   if (g.m <= 0 || g.n <= 0 || g.batch <= 0 || g.batch2 <= 0) return;
   if (g.sym_upper && (g.m != g.n || g.beta != 0.0))
     throw ArgError("dgemm: a symmetric product needs m == n and beta == 0");
+  if (g.upper_only && g.m != g.n) throw ArgError("dgemm: an upper-triangle product needs m == n");
   if (g.tri && (g.kseg <= 0 || g.k % g.kseg != 0))
     throw ArgError("dgemm: triangular operands need k to be a multiple of kseg");
   if (g.k <= 0) {
@@ -356,7 +358,7 @@ void dgemm(const GemmBatch& g, hipStream_t s) {
     const char* e = std::getenv("ZCSD_NO_SPLITK");
     return e && e[0] == '1';
   }();
-  if (g.ws && !no_split && tiles64 < 256 && g.k >= 1024) {
+  if (g.ws && !no_split && !g.upper_only && tiles64 < 256 && g.k >= 1024) {
     ksplit = (int)std::min<long long>(std::min<long long>(g.k / 256, 16),
                                       std::max<long long>(2, 512 / std::max<long long>(1, tiles64)));
     while (ksplit > 1 && (size_t)ksplit * nprob * g.m * g.n > g.ws_elems) --ksplit;

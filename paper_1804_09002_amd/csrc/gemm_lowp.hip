@@ -178,7 +178,7 @@ void launch_lowp(const GemmBatch& g, hipStream_t s) {
 #define ZCSD_LOWP_LAUNCH(TA_, TB_)                                                               \
   hipLaunchKernelGGL((gemm_f32acc_kernel<BM, BN, BK, TA_, TB_>), grid, block, 0, s, g.m, g.n, g.k, \
                      A, g.lda, g.sA, B, g.ldb, g.sB, C, g.ldc, g.sC, g.alpha, g.beta, g.batch,      \
-                     g.sA2, g.sB2, g.sC2, g.sym_upper ? 1 : 0)
+                     g.sA2, g.sB2, g.sC2, (g.sym_upper || g.upper_only) ? 1 : 0)
     if (!g.transA && !g.transB) ZCSD_LOWP_LAUNCH(false, false);
     else if (!g.transA && g.transB) ZCSD_LOWP_LAUNCH(false, true);
     else if (g.transA && !g.transB) ZCSD_LOWP_LAUNCH(true, false);

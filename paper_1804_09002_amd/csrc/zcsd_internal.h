@@ -100,6 +100,9 @@ struct GemmBatch {
   // symmetric product (m == n, beta == 0): only the tiles on or above the
   // diagonal are computed; the caller mirrors the upper triangle (mirror_upper)
   bool sym_upper = false;
+  // only the upper triangle of C is wanted (m == n, any beta): the tiles below
+  // the diagonal are skipped and keep their contents (no split-K)
+  bool upper_only = false;
   // triangular operands (products known to be zero are skipped): K is made of
   // k / kseg segments, and within each segment op(A) is upper (tri & 1: zero
   // for k < i) or lower (tri & 2: zero for k > i), op(B) upper (tri & 4: zero

@@ -404,12 +404,14 @@ __global__ __launch_bounds__(64 * NW) void tsqr_local_kernel(
 
 // B: QR of the stacked R factors (registers), explicit Q_top, reconstruction
 // pieces (w x w work in LDS).
+template <int RQ>
 __global__ __launch_bounds__(TS_TREE_NT) void tsqr_tree_kernel(
     double* M, long long ldm, long long sM, int c0, int w, int h1, int r1a, int r2a, int P,
     const double* V, long long ldv, long long sV, int vr2, const double* Tloc, const double* Rstack,
     double* Qtop, double* Zo, double* Uo, double* Lo, double* So, long long sScr, double* Tfin,
     long long sT) {
   constexpr int NWT = TS_TREE_NT / 64;
+  static_assert(RQ >= 4, "wave 0 must hold the first 32 stacked rows");
   __shared__ double red[2 * NWT * TS_W], rowb[2 * TS_W], taus[TS_W];
   __shared__ double Ts[TS_W][TS_W1];  // T_top
   __shared__ double Yt[TS_W][TS_W1];  // Y_top(0:w, 0:w), then X2
@@ -435,10 +437,10 @@ __global__ __launch_bounds__(TS_TREE_NT) void tsqr_tree_kernel(
   {
     const int lane = tid & 63, wv = tid >> 6;
     const int g = lane & 7, hs = lane >> 3;
-    double a[TS_TREE_RQ][4];
+    double a[RQ][4];
 #pragma unroll
-    for (int r = 0; r < TS_TREE_RQ; ++r) {
-      const int i = 8 * TS_TREE_RQ * wv + 8 * r + hs;
+    for (int r = 0; r < RQ; ++r) {
+      const int i = 8 * RQ * wv + 8 * r + hs;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int j = 4 * g + q;
@@ -446,14 +448,14 @@ __global__ __launch_bounds__(TS_TREE_NT) void tsqr_tree_kernel(
       }
     }
     double myscal[4], mybeta[4];
-    ql_householder<TS_TREE_RQ, NWT>(a, w, myscal, mybeta, Ts, Z, Q0, taus, red, rowb);
+    ql_householder<RQ, NWT>(a, w, myscal, mybeta, Ts, Z, Q0, taus, red, rowb);
     // Y_top (unit lower trapezoidal, explicit, row-major) to global memory:
     // every expansion block forms its own rows of Q_top = [I; 0] - Y_top Z.
     // R_tsqr and Y_top(0:w, 0:w) from the first w rows (rows w..31 belong to
     // the next block: zero here).
 #pragma unroll
-    for (int r = 0; r < TS_TREE_RQ; ++r) {
-      const int i = 8 * TS_TREE_RQ * wv + 8 * r + hs;
+    for (int r = 0; r < RQ; ++r) {
+      const int i = 8 * RQ * wv + 8 * r + hs;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int j = 4 * g + q;
@@ -736,9 +738,16 @@ void tsqr_panel(int batch, double* M, long long ldm, long long sM, int c0, int w
   {
     ProfScope prof("tsqr_tree", s, batch * (4.0 * P * ww * w + 4.0 * ww * w),
                    batch * 8.0 * 2.0 * P * ww);
-    hipLaunchKernelGGL(tsqr_tree_kernel, dim3(batch), dim3(TS_TREE_NT), 0, s, M, ldm, sM, c0, w, h1, r1a,
-                       r2a, P, V, ldv, sV, vr2, sc.Tloc, sc.Rstack, sc.Qtop, sc.Z, sc.U, sc.L,
-                       sc.S, sc.stride, T, sT);
+    // row slots per lane: the 8 waves hold 64 RQ rows >= the P w stacked rows,
+    // and wave 0 holds the first 32 (RQ >= 4)
+#define ZCSD_TREE_LAUNCH(RQ_)                                                                    \
+  hipLaunchKernelGGL(tsqr_tree_kernel<RQ_>, dim3(batch), dim3(TS_TREE_NT), 0, s, M, ldm, sM, c0, w, \
+                     h1, r1a, r2a, P, V, ldv, sV, vr2, sc.Tloc, sc.Rstack, sc.Qtop, sc.Z, sc.U,    \
+                     sc.L, sc.S, sc.stride, T, sT)
+    if (P <= 8) ZCSD_TREE_LAUNCH(4);
+    else if (P <= 12) ZCSD_TREE_LAUNCH(6);
+    else ZCSD_TREE_LAUNCH(TS_TREE_RQ);
+#undef ZCSD_TREE_LAUNCH
     ZCSD_CHECK_LAUNCH();
   }
   {

@@ -17,7 +17,7 @@
 //   2. Cholesky form on Y1 (well conditioned after step 1):
 //        G = Y1^T Y1,  R_j^T R_j = (G + c_{2j-1} I) / a_j,
 //        sum_j a_j (G + c_{2j-1} I)^{-1} = sum_j R_j^{-1} R_j^{-T},
-//        Y2 = M (Y1 + Y1 Z Z^T).
+//        Y2 = M (Y1 + Y1 sum_j R_j^{-1} R_j^{-T}).
 //   3. W = Q Y2,  H = alpha sym(Y2^T R) (= sym(W^T X)); Q itself is formed
 //      on a second stream during steps 1 and 2.
 #include <algorithm>

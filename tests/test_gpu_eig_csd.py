@@ -55,6 +55,27 @@ def test_zolo_eig_clusters_and_multiplicity():
     assert np.linalg.norm(B @ V - V * lam) <= 100 * n * U * np.linalg.norm(B)
 
 
+def test_zolo_eig_unbalanced_level():
+    """A skewed spectrum (520 eigenvalues in [-1, -0.9], 80 in [0.5, 1]): the
+    diagonal of Q Lambda Q^T sits near the mean, so the first split gives
+    blocks of 520 and 80 and the next level pads the 80-block to 520 next to
+    a block whose n+ (about 260) exceeds 80 -- the basis QR then has more
+    columns than the small block has real rows."""
+    from paper_1804_09002_amd import zcsd
+    rng = np.random.default_rng(21)
+    n = 600
+    Q = WL.haar(n, rng)
+    lam_true = np.sort(np.concatenate([rng.uniform(-1.0, -0.9, 520), rng.uniform(0.5, 1.0, 80)]))
+    B = (Q * lam_true) @ Q.T
+    B = 0.5 * (B + B.T)
+    lam, V, info = zcsd.syev_zolo(_t(B), lo=-1.0 - 1e-6, hi=1.0 + 1e-6)
+    lam, V = lam.cpu().numpy(), V.cpu().numpy()
+    assert np.all(np.diff(lam) >= 0)
+    assert np.max(np.abs(lam - np.linalg.eigvalsh(B))) <= 50 * n * U
+    assert np.linalg.norm(V.T @ V - np.eye(n)) <= 50 * n * U
+    assert np.linalg.norm(B @ V - V * lam) <= 50 * n * U * np.linalg.norm(B)
+
+
 def _check_csd(A1, A2, U1, U2, V1, th, r, tol_theta=None):
     n = A1.shape[0]
     U1, U2, V1, th = U1[:, :r], U2[:, :r], V1[:, :r], th[:r]

@@ -230,100 +230,6 @@ __global__ __launch_bounds__(CH_NT) void trtri_base_kernel(int n, const double* 
   }
 }
 
-// One workgroup per problem: T = (striu(G) + diag(G)/2)^{-1} for w <= 128, the
-// compact-WY factor of w Householder reflectors from their Gram matrix
-// G = V^T V (T^{-1} = striu(V^T V) + diag(1/tau), 1/tau = v^T v / 2).  With
-// A = [0, 64) and B = [64, w): the two diagonal blocks are inverted in LDS and
-// T_AB = -T_A (Tinv_AB T_B) by 16 x 16 MFMA blocks.  All of T(0:w, 0:w) is
-// written (zeros below the diagonal), nothing beyond it.
-__global__ __launch_bounds__(CH_NT) void ut_factor_gram_kernel(int w, const double* __restrict__ G,
-                                                               long long ldg, long long sG,
-                                                               double* T, long long ldt,
-                                                               long long sT) {
-  __shared__ double S1[CH_BASE][CH_LD], S2[CH_BASE][CH_LD], S3[CH_BASE][CH_LD];
-  __shared__ double Xs[32][CH_LD];
-  __shared__ double dinv[CH_BASE];
-  const long long b = blockIdx.x;
-  G += b * sG;
-  T += b * sT;
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  const int wa = min(w, CH_BASE), wb = w - wa;
-  // diagonal blocks of T^{-1}, identity beyond the problem
-  for (int e = tid; e < CH_BASE * CH_BASE; e += CH_NT) {
-    const int i = e & 63, j = e >> 6;
-    double va = (i == j) ? 1.0 : 0.0, vb = va;
-    if (i < wa && j < wa && i <= j) {
-      const double g = G[i + (long long)j * ldg];
-      va = (i < j) ? g : 0.5 * g;
-    } else if (i < wa && j < wa) {
-      va = 0.0;
-    }
-    if (i < wb && j < wb && i <= j) {
-      const double g = G[(64 + i) + (long long)(64 + j) * ldg];
-      vb = (i < j) ? g : 0.5 * g;
-    } else if (i < wb && j < wb) {
-      vb = 0.0;
-    }
-    S1[i][j] = va;
-    S2[i][j] = vb;
-  }
-  __syncthreads();
-  if (tid < CH_BASE) dinv[tid] = 1.0 / S1[tid][tid];
-  __syncthreads();
-  lds_upper_inverse64(S1, S3, dinv, Xs);  // T_A in S3
-  for (int e = tid; e < wa * wa; e += CH_NT) {
-    const int i = e % wa, j = e / wa;
-    T[i + (long long)j * ldt] = S3[i][j];
-  }
-  if (wb <= 0) return;
-  if (tid < CH_BASE) dinv[tid] = 1.0 / S2[tid][tid];
-  __syncthreads();
-  lds_upper_inverse64(S2, S1, dinv, Xs);  // T_B in S1
-  for (int e = tid; e < wb * wb; e += CH_NT) {
-    const int i = e % wb, j = e / wb;
-    T[(64 + i) + (long long)(64 + j) * ldt] = S1[i][j];
-  }
-  // the block below the diagonal blocks is zero (products read T as a full w x w matrix)
-  for (int e = tid; e < wb * CH_BASE; e += CH_NT) {
-    const int i = e % wb, j = e / wb;
-    T[(64 + i) + (long long)j * ldt] = 0.0;
-  }
-  // Tinv_AB (64 x wb, zero columns beyond wb) into S2, which the inverse no longer reads
-  for (int e = tid; e < CH_BASE * CH_BASE; e += CH_NT) {
-    const int i = e & 63, j = e >> 6;
-    S2[i][j] = (j < wb) ? G[i + (long long)(64 + j) * ldg] : 0.0;
-  }
-  __syncthreads();
-  // X = Tinv_AB T_B: wave owns the 16-column strip 16 wave
-  d4 x[4];
-#pragma unroll
-  for (int ti = 0; ti < 4; ++ti) x[ti] = lds_mm16<CH_BASE>(S2, 16 * ti, 0, S1, 0, 16 * wave);
-  __syncthreads();
-#pragma unroll
-  for (int ti = 0; ti < 4; ++ti) lds_put16(S2, 16 * ti, 16 * wave, x[ti], 1.0);
-  __syncthreads();
-  // T_AB = -T_A X
-#pragma unroll
-  for (int ti = 0; ti < 4; ++ti) {
-    const d4 y = lds_mm16<CH_BASE>(S3, 16 * ti, 0, S2, 0, 16 * wave);
-    const int row = 16 * ti + (lane & 15);
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int col = 16 * wave + 4 * v + (lane >> 4);
-      if (col < wb) T[row + (long long)(64 + col) * ldt] = -y[v];
-    }
-  }
-}
-
-void ut_factor_from_gram(int batch, int w, const double* G, long long ldg, long long sG, double* T,
-                         long long ldt, long long sT, hipStream_t s) {
-  if (batch <= 0 || w <= 0) return;
-  if (w > 2 * CH_BASE) throw ArgError("ut_factor_from_gram: w > 128");
-  hipLaunchKernelGGL(ut_factor_gram_kernel, dim3(batch), dim3(CH_NT), 0, s, w, G, ldg, sG, T, ldt,
-                     sT);
-  ZCSD_CHECK_LAUNCH();
-}
-
 // ---------------------------------------------------------------------------
 static void chol_inv_rec(int batch, int n, double* A, long long lda, long long sA, double* R,
                          double* Ri, long long ld, long long s, Arena& ar, hipStream_t st) {

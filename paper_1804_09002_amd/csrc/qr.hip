@@ -512,6 +512,87 @@ __global__ __launch_bounds__(256) void pu_apply_kernel(int h, int h1, int nc, co
   }
 }
 
+// One workgroup per problem: the compact-WY factor T (w x w, w <= 128) of an
+// outer block from the factors T_k of its 32-wide inner panels and the Gram
+// matrix G = V^T V of the block's vectors, one column block at a time:
+// T(0:c, c:c+32) = -T(0:c, 0:c) (G(0:c, c:c+32) T_jj), c = 32 j (the factor
+// of H_0 ... H_j from those of H_0 ... H_{j-1} and H_j).  A panel step with
+// tau = 0 (H = I) keeps its zero row and column of T_k, and so of T.
+__global__ __launch_bounds__(256) void ut_merge_kernel(int w, const double* __restrict__ G,
+                                                       long long ldg, long long sG,
+                                                       const double* __restrict__ Tin,
+                                                       long long sTin, double* T, long long ldt,
+                                                       long long sT) {
+  constexpr int B = PU_W, BB = PU_W * PU_W;  // inner panel width and factor size
+  __shared__ double Tl[3 * B][4 * B + 1];    // rows 0..95 of T
+  __shared__ double Xs[3 * B][B + 1];        // G block, then X
+  __shared__ double Tj[B][B + 1];            // T_jj
+  const long long b = blockIdx.x;
+  G += b * sG;
+  Tin += b * sTin;
+  T += b * sT;
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int npan = (w + B - 1) / B;
+  for (int e = tid; e < 3 * B * 4 * B; e += 256) {
+    const int i = e % (3 * B), j = e / (3 * B);
+    const int bi = i / B, bj = j / B;
+    Tl[i][j] = (bi == bj && bi < npan) ? Tin[(long long)bi * BB + (i % B) + (long long)(j % B) * B] : 0.0;
+  }
+  __syncthreads();
+  for (int jb = 1; jb < npan; ++jb) {
+    const int c0 = B * jb;
+    const double* Tjj = Tin + (long long)jb * BB;
+    const int ntile = (c0 / 16) * 2;
+    // stage G(0:c0, c0:c0+32) (zero beyond w: not part of the block) and T_jj
+    for (int e = tid; e < c0 * B; e += 256) {
+      const int i = e % c0, k = e / c0;
+      Xs[i][k] = (c0 + k < w) ? G[i + (long long)(c0 + k) * ldg] : 0.0;
+    }
+    for (int e = tid; e < BB; e += 256) Tj[e % B][e / B] = Tjj[e];
+    __syncthreads();
+    // X = G(0:c0, c0:c0+32) T_jj, in registers, then over the staged G block
+    d4 x[3];
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int t = wave + 4 * u;
+      if (t < ntile)
+        x[u] = pu_mfma<B>(d4{0.0, 0.0, 0.0, 0.0}, [&](int i, int k) { return Xs[i][k]; },
+                          [&](int k, int j) { return Tj[k][j]; }, t >> 1, t & 1);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 3; ++u) {
+      const int t = wave + 4 * u;
+      if (t < ntile) {
+        const int ti = t >> 1, tj = t & 1;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Xs[16 * ti + (lane & 15)][16 * tj + 4 * v + (lane >> 4)] = x[u][v];
+      }
+    }
+    __syncthreads();
+    // T(0:c0, c0:c0+32) = -T(0:c0, 0:c0) X
+    for (int t = wave; t < ntile; t += 4) {
+      const int ti = t >> 1, tj = t & 1;
+      auto fx = [&](int i, int k) { return Tl[i][k]; };
+      auto fy = [&](int k, int j) { return Xs[k][j]; };
+      d4 r;
+      if (jb == 1) r = pu_mfma<B>(d4{0.0, 0.0, 0.0, 0.0}, fx, fy, ti, tj);
+      else if (jb == 2) r = pu_mfma<2 * B>(d4{0.0, 0.0, 0.0, 0.0}, fx, fy, ti, tj);
+      else r = pu_mfma<3 * B>(d4{0.0, 0.0, 0.0, 0.0}, fx, fy, ti, tj);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Tl[16 * ti + (lane & 15)][c0 + 16 * tj + 4 * v + (lane >> 4)] = -r[v];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < w * w; e += 256) {
+    const int i = e % w, j = e / w;
+    double v;
+    if (i < 3 * B) v = Tl[i][j];
+    else v = (j >= 3 * B) ? Tin[3LL * BB + (i - 3 * B) + (long long)(j - 3 * B) * B] : 0.0;
+    T[i + (long long)j * ldt] = v;
+  }
+}
+
 __global__ void zero_u32_kernel(unsigned* p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0u;
@@ -545,9 +626,8 @@ static void inner_update(int batch, int h1, int h, int nc, const double* V, long
 
 // Two-level blocked factorisation: inside an outer block of nbo columns the
 // inner panels are factored and applied to the rest of the block only; the
-// outer block's compact-WY factor follows from the Gram matrix of its vectors,
-// T^{-1} = striu(V^T V) + diag(V^T V) / 2 (the relation T^{-1} + T^{-T} = V^T V
-// of any orthogonal I - V T V^T with T upper triangular), and the trailing
+// outer block's compact-WY factor follows from the inner panels' factors and
+// the Gram matrix of its vectors (ut_merge_kernel), and the trailing
 // columns get one update with inner dimension nbo, which reads and writes the
 // trailing matrix nbo / nb times less often than panel-by-panel updates.
 // In the outer block's V, the first segment's rows come first and the second
@@ -587,7 +667,7 @@ static void geqrf_two_level(int batch, QRShape shape, int m, int n, double* M, l
                    gen ? 0 : (wo - off), M, ldm, sM, r1a, r2a, col0, Tk, nb, wk.sTin, wk.W2, wk.sW,
                    wk, s);
     }
-    // outer compact-WY factor from G = VO^T VO (always FP64)
+    // outer compact-WY factor from the inner factors and G = VO^T VO (always FP64)
     {
       GemmFp64Scope fp64;
       GemmBatch g;
@@ -598,8 +678,12 @@ static void geqrf_two_level(int batch, QRShape shape, int m, int n, double* M, l
       g.B = VO; g.ldb = wk.ldv; g.sB = wk.sV;
       g.C = wk.G; g.ldc = NBO; g.sC = wk.sG;
       g.ws = wk.ws; g.ws_elems = wk.ws_elems;
+      g.sym_upper = true;  // the merge reads only blocks above the diagonal
       dgemm(g, s);
-      ut_factor_from_gram(batch, wo, wk.G, NBO, wk.sG, TO, NBO, wk.sTo, s);
+      if (nb != PU_W || NBO > 4 * PU_W) throw ArgError("geqrf: outer block layout");
+      hipLaunchKernelGGL(ut_merge_kernel, dim3(batch), dim3(256), 0, s, wo, wk.G, (long long)NBO,
+                         wk.sG, wk.Tin, wk.sTin, TO, (long long)NBO, wk.sTo);
+      ZCSD_CHECK_LAUNCH();
     }
     const int col0 = co + wo;
     if (col0 < n) {

@@ -57,12 +57,6 @@ void set_identity_scaled(int batch, int m, int n, const double* d_vals, double v
 // Ri_b = R^{-1}; both n x n with ld n, stride n*n.  A is overwritten.
 void chol_inv_batched(int batch, int n, double* A, long long lda, long long sA, double* R,
                       double* Ri, Arena& ar, hipStream_t s);
-// T_b = (striu(G_b) + diag(G_b) / 2)^{-1} (w x w upper, w <= 128, one launch):
-// the compact-WY factor of w Householder reflectors from their Gram matrix
-// G_b = V_b^T V_b (only the upper triangle of G is read; all of T(0:w, 0:w) is
-// written, zeros below the diagonal included).
-void ut_factor_from_gram(int batch, int w, const double* G, long long ldg, long long sG, double* T,
-                         long long ldt, long long sT, hipStream_t s);
 // Upper-triangular inverse Ri = R^{-1} (n x n), level-parallel recursion.
 void trtri_upper_batched(int batch, int n, const double* R, long long ldr, long long sR, double* Ri,
                          long long ldi, long long sI, Arena& ar, hipStream_t s);

@@ -132,6 +132,26 @@ def test_csd_rank_deficient_algorithm3(n, k, seed):
     assert np.all(th[r:] == 0) and np.all(U1[:, r:] == 0)
 
 
+@pytest.mark.parametrize("n,zc,seed", [(150, (0,), 41), (300, (7, 128, 200), 42)])
+def test_csd_exact_zero_columns(n, zc, seed):
+    """Orthonormal columns with some columns set exactly to zero: a partial
+    isometry of rank n - len(zc) (Alg. 3).  The QR inside Zolo-pd meets
+    Householder steps with tau = 0; the angles must match the oracle's."""
+    from paper_1804_09002_amd import zcsd
+    rng = np.random.default_rng(seed)
+    A = WL.stiefel(2 * n, n, rng)
+    A[:, list(zc)] = 0.0
+    A1, A2 = A[:n].copy(), A[n:].copy()
+    U1, U2, V1, th, info = zcsd.csd(_t(A1), _t(A2))
+    U1, U2, V1, th = (x.cpu().numpy() for x in (U1, U2, V1, th))
+    r = n - len(zc)
+    assert info["rank"] == r
+    ref = O.csd(A1, A2)
+    assert ref["rank"] == r
+    assert np.max(np.abs(th[:r] - ref["theta"])) <= 10 * n * U
+    _check_csd(A1, A2, U1, U2, V1, th, r)
+
+
 def test_csd_swap_symmetry():
     from paper_1804_09002_amd import zcsd
     n = 80

@@ -121,11 +121,21 @@ __global__ __launch_bounds__(CH_NT) void chol_inv_base_kernel(int nb, const doub
   R += b * sR;
   Ri += b * sI;
   const int tid = threadIdx.x;
-  for (int e = tid; e < CH_BASE * CH_BASE; e += CH_NT) {
-    const int i = e & 63, j = e >> 6;
-    double v = (i == j) ? 1.0 : 0.0;
-    if (i < nb && j < nb) v = (i <= j) ? A[i + (long long)j * lda] : A[j + (long long)i * lda];
-    S[i][j] = v;
+  {
+    // all loads of a thread in flight at once, then the LDS stores
+    constexpr int NL = CH_BASE * CH_BASE / CH_NT;
+    double v[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int e = tid + CH_NT * q, i = e & 63, j = e >> 6;
+      v[q] = (i == j) ? 1.0 : 0.0;
+      if (i < nb && j < nb) v[q] = (i <= j) ? A[i + (long long)j * lda] : A[j + (long long)i * lda];
+    }
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int e = tid + CH_NT * q;
+      S[e & 63][e >> 6] = v[q];
+    }
   }
   __syncthreads();
   const int bi = tid & 15, bj = tid >> 4;
@@ -214,11 +224,20 @@ __global__ __launch_bounds__(CH_NT) void trtri_base_kernel(int n, const double* 
   R += b * sR + o + (long long)o * ldr;
   Ri += b * sI + o + (long long)o * ldi;
   const int tid = threadIdx.x;
-  for (int e = tid; e < CH_BASE * CH_BASE; e += CH_NT) {
-    const int i = e & 63, j = e >> 6;
-    double v = (i == j) ? 1.0 : 0.0;
-    if (i < nb && j < nb) v = (i <= j) ? R[i + (long long)j * ldr] : 0.0;
-    U[i][j] = v;
+  {
+    constexpr int NL = CH_BASE * CH_BASE / CH_NT;
+    double v[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int e = tid + CH_NT * q, i = e & 63, j = e >> 6;
+      v[q] = (i == j) ? 1.0 : 0.0;
+      if (i < nb && j < nb) v[q] = (i <= j) ? R[i + (long long)j * ldr] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int e = tid + CH_NT * q;
+      U[e & 63][e >> 6] = v[q];
+    }
   }
   __syncthreads();
   if (tid < CH_BASE) dinv[tid] = 1.0 / U[tid][tid];

@@ -35,10 +35,23 @@ __global__ __launch_bounds__(JNT) void jacobi_kernel(const int* __restrict__ siz
   V += (long long)b * sV;
   lam += (long long)b * JB;
   if (n <= 0) return;
-  for (int e = tid; e < n * n; e += JNT) {
-    const int i = e % n, j = e / n;
-    S[i][j] = 0.5 * (A[i + (long long)j * lda] + A[j + (long long)i * lda]);
-    Q[i][j] = (i == j) ? 1.0 : 0.0;
+  {
+    // all loads of a thread in flight at once, then the LDS stores
+    constexpr int NL = JB * JB / JNT;
+    double v[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int e = tid + JNT * q, i = e % n, j = e / n;
+      v[q] = (e < n * n) ? 0.5 * (A[i + (long long)j * lda] + A[j + (long long)i * lda]) : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int e = tid + JNT * q, i = e % n, j = e / n;
+      if (e < n * n) {
+        S[i][j] = v[q];
+        Q[i][j] = (i == j) ? 1.0 : 0.0;
+      }
+    }
   }
   __syncthreads();
   const int m = (n % 2) ? n + 1 : n;  // players; index n is a dummy when n is odd

@@ -483,13 +483,30 @@ __global__ __launch_bounds__(256) void pu_apply_kernel(int h, int h1, int nc, co
   M += b * sM;
   W2 += b * sW2;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-  for (int e = tid; e < PU_W * PU_NC; e += 256) {
-    const int i = e % PU_W, j = e / PU_W;
-    Ws[i][j] = (j < nc) ? W2[i + (long long)j * PU_W] : 0.0;
-  }
-  for (int e = tid; e < PU_RT * PU_W; e += 256) {
-    const int i = e % PU_RT, j = e / PU_RT;
-    Vs[i][j] = (r0 + i < h) ? V[pu_vrow(r0 + i, h1, vr2) + (long long)j * ldv] : 0.0;
+  {
+    // all loads of a thread in flight at once, then the LDS stores
+    constexpr int NW2 = PU_W * PU_NC / 256, NVL = PU_RT * PU_W / 256;
+    double wv[NW2], vv[NVL];
+#pragma unroll
+    for (int q = 0; q < NW2; ++q) {
+      const int e = tid + 256 * q, i = e % PU_W, j = e / PU_W;
+      wv[q] = (j < nc) ? W2[i + (long long)j * PU_W] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NVL; ++q) {
+      const int e = tid + 256 * q, i = e % PU_RT, j = e / PU_RT;
+      vv[q] = (r0 + i < h) ? V[pu_vrow(r0 + i, h1, vr2) + (long long)j * ldv] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NW2; ++q) {
+      const int e = tid + 256 * q;
+      Ws[e % PU_W][e / PU_W] = wv[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NVL; ++q) {
+      const int e = tid + 256 * q;
+      Vs[e % PU_RT][e / PU_RT] = vv[q];
+    }
   }
   __syncthreads();
   const int ntj = (nc + 15) / 16;
@@ -533,22 +550,44 @@ __global__ __launch_bounds__(256) void ut_merge_kernel(int w, const double* __re
   T += b * sT;
   const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
   const int npan = (w + B - 1) / B;
-  for (int e = tid; e < 3 * B * 4 * B; e += 256) {
-    const int i = e % (3 * B), j = e / (3 * B);
-    const int bi = i / B, bj = j / B;
-    Tl[i][j] = (bi == bj && bi < npan) ? Tin[(long long)bi * BB + (i % B) + (long long)(j % B) * B] : 0.0;
+  // every global input is loaded once, all loads of a thread in flight at
+  // once: the four panel factors (element e = tid + 256 q of the 4 x 32 x 32
+  // array) and the Gram region G(0:96, 32:128) that the merges read (element
+  // e: row e % 96, column 32 + e / 96; zero beyond w)
+  constexpr int NT_ = 4 * BB / 256, NG = 3 * B * 3 * B / 256;
+  double tv[NT_], gv[NG];
+#pragma unroll
+  for (int q = 0; q < NT_; ++q) {
+    const int e = tid + 256 * q;
+    tv[q] = (e / BB < npan) ? Tin[e] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < NG; ++q) {
+    const int e = tid + 256 * q, i = e % (3 * B), c = B + e / (3 * B);
+    gv[q] = (c < w && i < c) ? G[i + (long long)c * ldg] : 0.0;
+  }
+  for (int e = tid; e < 3 * B * 4 * B; e += 256) (&Tl[0][0])[(e % (3 * B)) * (4 * B + 1) + e / (3 * B)] = 0.0;
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NT_; ++q) {
+    const int e = tid + 256 * q, blk = e / BB, i = e % B, j = (e % BB) / B;
+    if (blk < 3) Tl[B * blk + i][B * blk + j] = tv[q];
   }
   __syncthreads();
   for (int jb = 1; jb < npan; ++jb) {
     const int c0 = B * jb;
-    const double* Tjj = Tin + (long long)jb * BB;
     const int ntile = (c0 / 16) * 2;
-    // stage G(0:c0, c0:c0+32) (zero beyond w: not part of the block) and T_jj
-    for (int e = tid; e < c0 * B; e += 256) {
-      const int i = e % c0, k = e / c0;
-      Xs[i][k] = (c0 + k < w) ? G[i + (long long)(c0 + k) * ldg] : 0.0;
+    // stage G(0:c0, c0:c0+32) and T_jj from the registers
+#pragma unroll
+    for (int q = 0; q < NG; ++q) {
+      const int e = tid + 256 * q, i = e % (3 * B), c = B + e / (3 * B);
+      if (c >= c0 && c < c0 + B && i < c0) Xs[i][c - c0] = gv[q];
     }
-    for (int e = tid; e < BB; e += 256) Tj[e % B][e / B] = Tjj[e];
+#pragma unroll
+    for (int q = 0; q < NT_; ++q) {
+      const int e = tid + 256 * q;
+      if (e / BB == jb) Tj[e % B][(e % BB) / B] = tv[q];
+    }
     __syncthreads();
     // X = G(0:c0, c0:c0+32) T_jj, in registers, then over the staged G block
     d4 x[3];
@@ -584,11 +623,19 @@ __global__ __launch_bounds__(256) void ut_merge_kernel(int w, const double* __re
     }
     __syncthreads();
   }
+  // rows 96.. of T: T_33 on the diagonal block (Xs is free: stage it there)
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NT_; ++q) {
+    const int e = tid + 256 * q;
+    if (e / BB == 3) Xs[e % B][(e % BB) / B] = tv[q];
+  }
+  __syncthreads();
   for (int e = tid; e < w * w; e += 256) {
     const int i = e % w, j = e / w;
     double v;
     if (i < 3 * B) v = Tl[i][j];
-    else v = (j >= 3 * B) ? Tin[3LL * BB + (i - 3 * B) + (long long)(j - 3 * B) * B] : 0.0;
+    else v = (j >= 3 * B) ? Xs[i - 3 * B][j - 3 * B] : 0.0;
     T[i + (long long)j * ldt] = v;
   }
 }

@@ -470,12 +470,23 @@ __global__ __launch_bounds__(TS_TREE_NT) void tsqr_tree_kernel(
     }
   }
   if (tid < TS_W) sg[tid] = 0.0;  // signs beyond w stay zero
-  for (int e = tid; e < TS_W * TS_W; e += TS_TREE_NT) {
-    const int i = e & (TS_W - 1), j = e / TS_W;
-    Y0[i][j] = (i < w && j < w)
-                   ? ((i < j) ? 0.0 : ((i == j) ? 1.0 : V[ts_vrow(i, h1, vr2) + (long long)j * ldv]))
-                   : 0.0;
-    T0s[i][j] = Tloc[e];  // zero beyond w (written so by the local factorisation)
+  {
+    constexpr int NL = TS_W * TS_W / TS_TREE_NT;
+    double y[NL], t0[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int e = tid + TS_TREE_NT * q, i = e & (TS_W - 1), j = e / TS_W;
+      y[q] = (i < w && j < w)
+                 ? ((i < j) ? 0.0 : ((i == j) ? 1.0 : V[ts_vrow(i, h1, vr2) + (long long)j * ldv]))
+                 : 0.0;
+      t0[q] = Tloc[e];  // zero beyond w (written so by the local factorisation)
+    }
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int e = tid + TS_TREE_NT * q, i = e & (TS_W - 1), j = e / TS_W;
+      Y0[i][j] = y[q];
+      T0s[i][j] = t0[q];
+    }
   }
   __syncthreads();
   // The 32 x 32 products below run over the zero-padded range, one 16 x 16
@@ -613,16 +624,31 @@ __global__ __launch_bounds__(TS_NT) void tsqr_expand_kernel(
   const int rows = min(TS_MB, h - i0);
   const int wy = min(w, rows);  // rows of Y_p that meet [Q_top,p; 0]
   const double* Tpg = Tloc + (long long)p * TS_W * TS_W;
-  for (int e = tid; e < TS_W * TS_W; e += TS_NT) {
-    const int i = e % TS_W, j = e / TS_W;
-    const bool in = i < w && j < w;
-    M1[i][j] = in ? Ytop[(p * w + i) * TS_W + j] : 0.0;
-    M2[i][j] = Zg[e];
-    Us[i][j] = in ? Uinv[e] : 0.0;
-    Yp[i][j] = (i < wy && j < w)
-                   ? ((i > j) ? V[ts_vrow(i0 + i, h1, vr2) + (long long)j * ldv] : ((i == j) ? 1.0 : 0.0))
-                   : 0.0;
-    Tp[i][j] = (in && i <= j) ? Tpg[e] : 0.0;
+  {
+    // all loads of a thread in flight at once, then the LDS stores
+    constexpr int NL = TS_W * TS_W / TS_NT;
+    double l1[NL], l2[NL], l3[NL], l4[NL], l5[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int e = tid + TS_NT * q, i = e % TS_W, j = e / TS_W;
+      const bool in = i < w && j < w;
+      l1[q] = in ? Ytop[(p * w + i) * TS_W + j] : 0.0;
+      l2[q] = Zg[e];
+      l3[q] = in ? Uinv[e] : 0.0;
+      l4[q] = (i < wy && j < w)
+                  ? ((i > j) ? V[ts_vrow(i0 + i, h1, vr2) + (long long)j * ldv] : ((i == j) ? 1.0 : 0.0))
+                  : 0.0;
+      l5[q] = (in && i <= j) ? Tpg[e] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < NL; ++q) {
+      const int e = tid + TS_NT * q, i = e % TS_W, j = e / TS_W;
+      M1[i][j] = l1[q];
+      M2[i][j] = l2[q];
+      Us[i][j] = l3[q];
+      Yp[i][j] = l4[q];
+      Tp[i][j] = l5[q];
+    }
   }
   __syncthreads();
   const int wave = tid >> 6;

@@ -182,21 +182,36 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(
     }
   }
 
-  // epilogue: lane owns C[row][col + 4v]
+  // epilogue: lane owns C[row][col + 4v].  With beta != 0 the old values of a
+  // row tile are all loaded, then the results formed, then stored: loads
+  // interleaved with stores of the same array would each wait for the store
+  // before them (one memory round trip per element)
+  const bool rd = beta != 0.0;
   if (full_mn) {
 #pragma unroll
     for (int x = 0; x < TM; ++x) {
       const int row = i0 + wm * WM + x * 16 + lr;
+      double o[TN][4];
+      if (rd) {
 #pragma unroll
-      for (int y = 0; y < TN; ++y) {
+        for (int y = 0; y < TN; ++y)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int col = j0 + wn * WN + y * 16 + lk + 4 * v;
-          double* p = C + row + (long long)col * ldc;
-          const double r = alpha * acc[x][y][v];
-          *p = (beta == 0.0) ? r : r + beta * (*p);
-        }
+          for (int v = 0; v < 4; ++v)
+            o[y][v] = C[row + (long long)(j0 + wn * WN + y * 16 + lk + 4 * v) * ldc];
+#pragma unroll
+        for (int y = 0; y < TN; ++y)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) o[y][v] = alpha * acc[x][y][v] + beta * o[y][v];
+      } else {
+#pragma unroll
+        for (int y = 0; y < TN; ++y)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) o[y][v] = alpha * acc[x][y][v];
       }
+#pragma unroll
+      for (int y = 0; y < TN; ++y)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) C[row + (long long)(j0 + wn * WN + y * 16 + lk + 4 * v) * ldc] = o[y][v];
     }
     return;
   }
@@ -204,18 +219,28 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(
   for (int x = 0; x < TM; ++x) {
     const int row = i0 + wm * WM + x * 16 + lr;
     if (row >= m) continue;
+    double o[TN][4];
 #pragma unroll
-    for (int y = 0; y < TN; ++y) {
+    for (int y = 0; y < TN; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int col = j0 + wn * WN + y * 16 + lk + 4 * v;
-        if (col < n) {
-          double* p = C + row + (long long)col * ldc;
-          const double r = alpha * acc[x][y][v];
-          *p = (beta == 0.0) ? r : r + beta * (*p);
-        }
+        o[y][v] = (rd && col < n) ? C[row + (long long)col * ldc] : 0.0;
       }
-    }
+#pragma unroll
+    for (int y = 0; y < TN; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double r = alpha * acc[x][y][v];
+        o[y][v] = rd ? r + beta * o[y][v] : r;
+      }
+#pragma unroll
+    for (int y = 0; y < TN; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int col = j0 + wn * WN + y * 16 + lk + 4 * v;
+        if (col < n) C[row + (long long)col * ldc] = o[y][v];
+      }
   }
 }
 

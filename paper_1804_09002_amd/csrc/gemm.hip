@@ -254,11 +254,18 @@ __global__ void splitk_reduce_kernel(int m, int n, int nprob, int nsplit, const 
   const long long mn = (long long)m * n;
   for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < mn;
        e += (long long)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int q = 0; q < nsplit; ++q) s += ws[((long long)q * nprob + zp) * mn + e];
+    // the partials (at most 16) and the old value loaded together, then summed in order
     const int i = (int)(e % m), j = (int)(e / m);
     double* c = Cp + i + (long long)j * ldc;
-    *c = (beta == 0.0) ? alpha * s : alpha * s + beta * (*c);
+    double pv[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) pv[q] = (q < nsplit) ? ws[((long long)q * nprob + zp) * mn + e] : 0.0;
+    const double old = (beta == 0.0) ? 0.0 : *c;
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < 16; ++q)
+      if (q < nsplit) s += pv[q];
+    *c = (beta == 0.0) ? alpha * s : alpha * s + beta * old;
   }
 }
 
@@ -320,6 +327,7 @@ static void launch_tile(const GemmBatch& g, hipStream_t s, int ksplit) {
     ksplit = (g.k + kchunk - 1) / kchunk;
   }
   const int nsplit = std::max(1, ksplit);
+  if (nsplit > 16) throw ArgError("dgemm: at most 16 k-splits");
   // the z dimension enumerates (split, b2, b1); chunk over b2 to stay within 65535
   const int per = std::max(1, 65535 / std::max(1, g.batch * nsplit));
   if (kchunk > 0 && per < g.batch2) throw ArgError("dgemm: split-K batch too large");

@@ -510,23 +510,38 @@ __global__ __launch_bounds__(256) void pu_apply_kernel(int h, int h1, int nc, co
   }
   __syncthreads();
   const int ntj = (nc + 15) / 16;
-  for (int t = wave; t < 4 * ntj; t += 4) {
-    const int ti = t & 3, tj = t >> 2;
-    const d4 r = pu_mfma<PU_W>(d4{0.0, 0.0, 0.0, 0.0}, [&](int i, int k) { return Vs[i][k]; },
-                               [&](int k, int j) { return Ws[k][j]; }, ti, tj);
-    const int row = r0 + 16 * ti + (lane & 15);
-    if (row < h) {
-      const long long mr = pu_mrow(row, h1, r1a, r2a);
+  // wave w owns the 16-row tile w and every 16-column tile: all products,
+  // then all old values (loaded together), then the stores
+  constexpr int NTJ = PU_NC / 16;
+  const int row = r0 + 16 * wave + (lane & 15);
+  const bool rok = row < h;
+  const long long mr = rok ? pu_mrow(row, h1, r1a, r2a) : 0;
+  d4 r[NTJ];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int col = 16 * tj + 4 * v + (lane >> 4);
-        if (col < nc) {
-          double* p = M + mr + (long long)(col0 + col) * ldm;
-          *p -= r[v];
-        }
-      }
+  for (int u = 0; u < NTJ; ++u)
+    if (u < ntj)
+      r[u] = pu_mfma<PU_W>(d4{0.0, 0.0, 0.0, 0.0}, [&](int i, int k) { return Vs[i][k]; },
+                           [&](int k, int j) { return Ws[k][j]; }, wave, u);
+  double o[NTJ][4];
+#pragma unroll
+  for (int u = 0; u < NTJ; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int col = 16 * u + 4 * v + (lane >> 4);
+      o[u][v] = (rok && u < ntj && col < nc) ? M[mr + (long long)(col0 + col) * ldm] : 0.0;
     }
-  }
+#pragma unroll
+  for (int u = 0; u < NTJ; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      if (u < ntj) o[u][v] -= r[u][v];
+#pragma unroll
+  for (int u = 0; u < NTJ; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int col = 16 * u + 4 * v + (lane >> 4);
+      if (rok && u < ntj && col < nc) M[mr + (long long)(col0 + col) * ldm] = o[u][v];
+    }
 }
 
 // One workgroup per problem: the compact-WY factor T (w x w, w <= 128) of an

@@ -128,22 +128,35 @@ __global__ __launch_bounds__(256, 2) void gemm_f32acc_kernel(
     }
   }
 
+  // a row tile's old values loaded together, then the results, then the
+  // stores (loads interleaved with stores of C would each wait for the last store)
+  const bool rd = beta != 0.0;
 #pragma unroll
   for (int x = 0; x < TM; ++x) {
     const int row = i0 + wm * WM + x * 16 + lr;
     if (row >= m) continue;
+    double o[TN][4];
 #pragma unroll
-    for (int y = 0; y < TN; ++y) {
+    for (int y = 0; y < TN; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int col = j0 + wn * WN + y * 16 + 4 * lk + v;
-        if (col < n) {
-          double* p = C + row + (long long)col * ldc;
-          const double r = alpha * (double)acc[x][y][v];
-          *p = (beta == 0.0) ? r : r + beta * (*p);
-        }
+        o[y][v] = (rd && col < n) ? C[row + (long long)col * ldc] : 0.0;
       }
-    }
+#pragma unroll
+    for (int y = 0; y < TN; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const double r = alpha * (double)acc[x][y][v];
+        o[y][v] = rd ? r + beta * o[y][v] : r;
+      }
+#pragma unroll
+    for (int y = 0; y < TN; ++y)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int col = j0 + wn * WN + y * 16 + 4 * lk + v;
+        if (col < n) C[row + (long long)col * ldc] = o[y][v];
+      }
   }
 }
 

@@ -696,17 +696,34 @@ __global__ __launch_bounds__(TS_NT) void tsqr_expand_kernel(
   // and both column tiles, and reads its Y fragments from V before it writes V.
   const int lane = tid & 63;
   const int lr = lane & 15, lk = lane >> 4;
-  for (int rt = wave; rt * 16 < rows; rt += 4) {
+  // the local Y rows of every row tile this wave rewrites, loaded before any
+  // of them is overwritten (each tile rewrites only its own rows)
+  constexpr int NRT = TS_MB / 64, NK = TS_W / 4;
+  double yv[NRT][NK];
+#pragma unroll
+  for (int it = 0; it < NRT; ++it) {
+    const int il = 16 * (wave + 4 * it) + lr;
+    const bool rin = il < rows;
+    const long long vi = rin ? ts_vrow(i0 + il, h1, vr2) : 0;
+#pragma unroll
+    for (int s = 0; s < NK; ++s) {
+      const int k = 4 * s + lk;
+      yv[it][s] = (rin && k < w) ? V[vi + (long long)k * ldv] : 0.0;
+    }
+  }
+#pragma unroll
+  for (int it = 0; it < NRT; ++it) {
+    const int rt = wave + 4 * it;
+    if (rt * 16 >= rows) break;
     const int il = 16 * rt + lr;  // the row this lane feeds
     const bool rin = il < rows;
     const long long vi = rin ? ts_vrow(i0 + il, h1, vr2) : 0;
     d4 c0t = {0.0, 0.0, 0.0, 0.0}, c1t = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int kk = 0; kk < TS_W; kk += 4) {
-      const int k = kk + lk;
-      const double y = (rin && k < w) ? V[vi + (long long)k * ldv] : 0.0;
-      c0t = __builtin_amdgcn_mfma_f64_16x16x4f64(M3[k][lr], y, c0t, 0, 0, 0);
-      c1t = __builtin_amdgcn_mfma_f64_16x16x4f64(M3[k][16 + lr], y, c1t, 0, 0, 0);
+    for (int s = 0; s < NK; ++s) {
+      const int k = 4 * s + lk;
+      c0t = __builtin_amdgcn_mfma_f64_16x16x4f64(M3[k][lr], yv[it][s], c0t, 0, 0, 0);
+      c1t = __builtin_amdgcn_mfma_f64_16x16x4f64(M3[k][16 + lr], yv[it][s], c1t, 0, 0, 0);
     }
     // lane l item v holds row 16 rt + l % 16, column 16 tj + 4 v + l / 16
     if (rin) {

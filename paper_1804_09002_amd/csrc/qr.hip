@@ -556,6 +556,7 @@ __global__ __launch_bounds__(256) void ut_merge_kernel(int w, const double* __re
                                                        long long sTin, double* T, long long ldt,
                                                        long long sT) {
   constexpr int B = PU_W, BB = PU_W * PU_W;  // inner panel width and factor size
+  static_assert(4 * B == 128, "index maps below assume 128 columns");
   __shared__ double Tl[3 * B][4 * B + 1];    // rows 0..95 of T
   __shared__ double Xs[3 * B][B + 1];        // G block, then X
   __shared__ double Tj[B][B + 1];            // T_jj
@@ -581,7 +582,7 @@ __global__ __launch_bounds__(256) void ut_merge_kernel(int w, const double* __re
     const int e = tid + 256 * q, i = e % (3 * B), c = B + e / (3 * B);
     gv[q] = (c < w && i < c) ? G[i + (long long)c * ldg] : 0.0;
   }
-  for (int e = tid; e < 3 * B * 4 * B; e += 256) (&Tl[0][0])[(e % (3 * B)) * (4 * B + 1) + e / (3 * B)] = 0.0;
+  for (int e = tid; e < 3 * B * 4 * B; e += 256) Tl[e >> 7][e & 127] = 0.0;  // 4 B = 128 columns
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < NT_; ++q) {
@@ -646,12 +647,14 @@ __global__ __launch_bounds__(256) void ut_merge_kernel(int w, const double* __re
     if (e / BB == 3) Xs[e % B][(e % BB) / B] = tv[q];
   }
   __syncthreads();
-  for (int e = tid; e < w * w; e += 256) {
-    const int i = e % w, j = e / w;
-    double v;
-    if (i < 3 * B) v = Tl[i][j];
-    else v = (j >= 3 * B) ? Xs[i - 3 * B][j - 3 * B] : 0.0;
-    T[i + (long long)j * ldt] = v;
+  for (int e = tid; e < 4 * B * 4 * B; e += 256) {
+    const int i = e & (4 * B - 1), j = e >> 7;
+    if (i < w && j < w) {
+      double v;
+      if (i < 3 * B) v = Tl[i][j];
+      else v = (j >= 3 * B) ? Xs[i - 3 * B][j - 3 * B] : 0.0;
+      T[i + (long long)j * ldt] = v;
+    }
   }
 }
 

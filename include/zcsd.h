@@ -123,6 +123,28 @@ zcsd_status zcsd_dcsd(zcsd_handle* handle, int n,
                       const zcsd_opts* opts, zcsd_info* info);
 
 /*
+ * CS decomposition with rectangular blocks, A1 m1 x n and A2 m2 x n with
+ * m1, m2 >= n (Algorithm 1 / Algorithm 3 as stated for m1 + m2 rows, Sec. 2
+ * and Sec. 3): A1 = U1 diag(cos theta) V1^T, A2 = U2 diag(sin theta) V1^T with
+ * U1 (m1 x n), U2 (m2 x n) and V1 (n x n) of orthonormal columns.  The blocks
+ * are reduced by Householder QRs A_i = Q_i R_i: [R1; R2] is a 2n x n partial
+ * isometry of the same rank and angles, polar(A_i) = Q_i polar(R_i), so the
+ * square path runs on [R1; R2] and U_i = Q_i U_i'.  Column-major device
+ * memory owned by the caller: d_A1 (ld >= m1), d_A2 (ld >= m2) are read
+ * only; d_U1 (ld >= m1), d_U2 (ld >= m2), d_V1 (ld >= n) and d_theta
+ * (length n) are written, with only the first info->rank columns / entries
+ * valid (the rest zero).  opts may be NULL (defaults); info may be NULL.
+ * Errors: ZCSD_EINVAL for m1 < n, m2 < n, n < 1, NULL pointers or short
+ * leading dimensions (nothing enqueued); otherwise as zcsd_dcsd.  Returns
+ * after the stream has finished the call.
+ */
+zcsd_status zcsd_dcsd_mn(zcsd_handle* handle, int m1, int m2, int n,
+                         const double* d_A1, int lda1, const double* d_A2, int lda2,
+                         double* d_U1, int ldu1, double* d_U2, int ldu2,
+                         double* d_V1, int ldv1, double* d_theta,
+                         const zcsd_opts* opts, zcsd_info* info);
+
+/*
  * Complete 2 x 2 CS decomposition of an orthogonal 2n x 2n matrix
  * A = [A1 A3; A2 A4] (Remark (iv) of Sec. 3):
  *    A = diag(U1, U2) [C -S; S C] diag(V1, V2)^T,  C = diag(cos theta),

@@ -439,6 +439,39 @@ static CsdOut csd_run(int n, const double* A1, long long lda1, const double* A2,
 
 using namespace zcsd;
 
+static void fill_csd_info(zcsd_info* info, const CsdOut& r) {
+  if (!info) return;
+  *info = zcsd_info{};
+  info->rank = r.rank;
+  info->r_used[0] = info->r_used[1] = r.pd.r;
+  info->ell[0] = info->ell[1] = r.pd.ell;
+  info->zolo_resid = r.pd.resid;
+  info->eig_levels = r.eig.levels;
+  info->eig_splits = r.eig.splits;
+  info->eig_max_r = r.eig.max_r;
+  info->eig_offblock = r.eig.max_offblock;
+  info->eig_coupling = r.eig.max_coupling;
+  info->eig_full_refinements = r.eig.full_refinements;
+  info->refine_iters = r.refine.iters;
+  info->refine_clusters = r.refine.clusters;
+  info->refine_max_cluster = r.refine.max_cluster;
+  info->refine_offdiag = r.refine.offdiag;
+  info->refine_fallback = r.refine.fallback ? 1 : 0;
+  info->repair = r.repair ? 1 : 0;
+  info->repair_resid = r.repair_resid;
+  info->time_ms[0] = r.t_polar;
+  info->time_ms[1] = r.t_B;
+  info->time_ms[2] = r.t_eig;
+  info->time_ms[3] = r.t_asm;
+}
+
+static void check_csd_opts(const zcsd_opts& o) {
+  ZCSD_REQUIRE(o.r_override >= 0 && o.r_override <= ZOLO_RMAX, "csd: r_override out of range");
+  ZCSD_REQUIRE(o.prec == ZCSD_FP64 || o.prec == ZCSD_MIXED_FP32, "csd: unknown precision mode");
+  ZCSD_REQUIRE(o.eps > 0.0 && o.eps < 1.0 && o.tol > 0.0, "csd: eps/tol out of range");
+  ZCSD_REQUIRE(o.mu > 1.0 || o.rank_mode == ZCSD_RANK_FULL, "csd: mu must exceed 1");
+}
+
 extern "C" zcsd_status zcsd_dcsd(zcsd_handle* handle, int n, const double* d_A1, int lda1,
                                  const double* d_A2, int lda2, double* d_U1, int ldu1, double* d_U2,
                                  int ldu2, double* d_V1, int ldv1, double* d_theta, double* d_W1,
@@ -452,39 +485,80 @@ extern "C" zcsd_status zcsd_dcsd(zcsd_handle* handle, int n, const double* d_A1,
     zcsd_opts o;
     zcsd_default_opts(&o);
     if (opts) o = *opts;
-    ZCSD_REQUIRE(o.r_override >= 0 && o.r_override <= ZOLO_RMAX, "csd: r_override out of range");
-    ZCSD_REQUIRE(o.prec == ZCSD_FP64 || o.prec == ZCSD_MIXED_FP32, "csd: unknown precision mode");
-    ZCSD_REQUIRE(o.eps > 0.0 && o.eps < 1.0 && o.tol > 0.0, "csd: eps/tol out of range");
-    ZCSD_REQUIRE(o.mu > 1.0 || o.rank_mode == ZCSD_RANK_FULL, "csd: mu must exceed 1");
+    check_csd_opts(o);
     ZCSD_HIP(hipSetDevice(handle->device));
     handle->arena.reset();
     handle->arena.reserve(csd_workspace_bytes(n));
     CsdOut r = csd_run(n, d_A1, lda1, d_A2, lda2, d_U1, ldu1, d_U2, ldu2, d_V1, ldv1, d_theta,
                        d_W1, d_W2, o, handle->arena, handle->stream);
-    if (info) {
-      *info = zcsd_info{};
-      info->rank = r.rank;
-      info->r_used[0] = info->r_used[1] = r.pd.r;
-      info->ell[0] = info->ell[1] = r.pd.ell;
-      info->zolo_resid = r.pd.resid;
-      info->eig_levels = r.eig.levels;
-      info->eig_splits = r.eig.splits;
-      info->eig_max_r = r.eig.max_r;
-      info->eig_offblock = r.eig.max_offblock;
-      info->eig_coupling = r.eig.max_coupling;
-      info->eig_full_refinements = r.eig.full_refinements;
-      info->refine_iters = r.refine.iters;
-      info->refine_clusters = r.refine.clusters;
-      info->refine_max_cluster = r.refine.max_cluster;
-      info->refine_offdiag = r.refine.offdiag;
-      info->refine_fallback = r.refine.fallback ? 1 : 0;
-      info->repair = r.repair ? 1 : 0;
-      info->repair_resid = r.repair_resid;
-      info->time_ms[0] = r.t_polar;
-      info->time_ms[1] = r.t_B;
-      info->time_ms[2] = r.t_eig;
-      info->time_ms[3] = r.t_asm;
-    }
+    fill_csd_info(info, r);
+  });
+}
+
+// Householder QR of the m x n block A (m >= n): Q (m x n, ld m) and the n x n
+// triangular factor R (ld n; geqrf leaves zeros below the diagonal)
+static void tall_qr(int m, int n, const double* A, long long lda, double* Q, double* R, Arena& ar,
+                    hipStream_t s) {
+  ArenaScope sc(ar);
+  const long long mn = (long long)m * n;
+  double* M = ar.dalloc((size_t)mn);
+  copy_scale(1, m, n, 1.0, A, lda, 0, M, m, 0, s);
+  QRWork wk = qr_work_alloc(ar, QRShape::General, 1, m, n, 32);
+  geqrf_batched(1, QRShape::General, m, n, M, m, mn, wk, s);
+  orgqr_batched(1, QRShape::General, m, n, Q, m, mn, nullptr, wk, s);
+  copy_scale(1, n, n, 1.0, M, m, 0, R, n, 0, s);
+}
+
+// Algorithm 1 / 3 for rectangular blocks A1 (m1 x n), A2 (m2 x n), m1, m2 >= n.
+// With A_i = Q_i R_i, [R1; R2] is a 2n x n partial isometry of the same rank
+// with the same angles and V1, and polar(A_i) = Q_i polar(R_i): the square
+// path runs on [R1; R2] and U_i = Q_i U_i'.
+extern "C" zcsd_status zcsd_dcsd_mn(zcsd_handle* handle, int m1, int m2, int n,
+                                    const double* d_A1, int lda1, const double* d_A2, int lda2,
+                                    double* d_U1, int ldu1, double* d_U2, int ldu2, double* d_V1,
+                                    int ldv1, double* d_theta, const zcsd_opts* opts,
+                                    zcsd_info* info) {
+  if (!handle) return ZCSD_EINVAL;
+  return guarded([&] {
+    ZCSD_REQUIRE(n >= 1 && m1 >= n && m2 >= n, "csd_mn: need n >= 1 and m1, m2 >= n");
+    ZCSD_REQUIRE(d_A1 && d_A2 && d_U1 && d_U2 && d_V1 && d_theta, "csd_mn: NULL pointer");
+    ZCSD_REQUIRE(lda1 >= m1 && lda2 >= m2 && ldu1 >= m1 && ldu2 >= m2 && ldv1 >= n,
+                 "csd_mn: leading dimension too small");
+    zcsd_opts o;
+    zcsd_default_opts(&o);
+    if (opts) o = *opts;
+    check_csd_opts(o);
+    ZCSD_HIP(hipSetDevice(handle->device));
+    const int mx = std::max(m1, m2);
+    const size_t nn = (size_t)n * n;
+    const size_t extra = sizeof(double) * ((size_t)(m1 + m2) * n + 4 * nn + (size_t)mx * n) +
+                         qr_work_bytes(QRShape::General, 1, mx, n, 32) + (64u << 20);
+    Arena& ar = handle->arena;
+    ar.reset();
+    ar.reserve(csd_workspace_bytes(n) + extra);
+    hipStream_t s = handle->stream;
+    ArenaScope scope(ar);
+    double* Q1 = ar.dalloc((size_t)m1 * n);
+    double* Q2 = ar.dalloc((size_t)m2 * n);
+    double* R = ar.dalloc(2 * nn);   // R1, R2
+    double* Up = ar.dalloc(2 * nn);  // U1', U2'
+    tall_qr(m1, n, d_A1, lda1, Q1, R, ar, s);
+    tall_qr(m2, n, d_A2, lda2, Q2, R + nn, ar, s);
+    CsdOut r = csd_run(n, R, n, R + nn, n, Up, n, Up + nn, n, d_V1, ldv1, d_theta, nullptr,
+                       nullptr, o, ar, s);
+    GemmBatch g;
+    g.m = m1; g.n = n; g.k = n;
+    g.A = Q1; g.lda = m1;
+    g.B = Up; g.ldb = n;
+    g.C = d_U1; g.ldc = ldu1;
+    dgemm(g, s);
+    g.m = m2;
+    g.A = Q2; g.lda = m2;
+    g.B = Up + nn;
+    g.C = d_U2; g.ldc = ldu2;
+    dgemm(g, s);
+    ZCSD_HIP(hipStreamSynchronize(s));
+    fill_csd_info(info, r);
   });
 }
 

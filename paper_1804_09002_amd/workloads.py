@@ -81,6 +81,18 @@ def from_angles(theta, rng, zero_idx=None, U1=None, U2=None, V1=None):
     return A1, A2, {"U1": U1, "U2": U2, "V1": V1, "theta": theta, "zero_idx": zero_idx}
 
 
+def rect_pair(m1, m2, n, seed, rank_deficient=0):
+    """Rectangular blocks (m1, m2 >= n): A1 = U1 C V1^T (m1 x n), A2 = U2 S V1^T
+    (m2 x n) with U_i of orthonormal columns (Stiefel), Haar V1, uniform angles;
+    rank_deficient = k zeroes k random (C_ii, S_ii) pairs (rank n - k)."""
+    rng = np.random.default_rng(seed)
+    theta = angles_uniform(n, rng)
+    U1 = stiefel(m1, n, rng)
+    U2 = stiefel(m2, n, rng)
+    zero_idx = np.sort(rng.choice(n, size=rank_deficient, replace=False)) if rank_deficient else None
+    return from_angles(theta, rng, zero_idx=zero_idx, U1=U1, U2=U2)
+
+
 # ---- named workloads -----------------------------------------------------
 
 def haar_stiefel_pair(n, seed):

@@ -85,6 +85,8 @@ def _lib():
                           C.POINTER(Opts), C.POINTER(Info)],
             "zcsd_dcsd2x2": [vp, i, vp, i, vp, i, vp, i, vp, i, vp, i, vp, i, vp, i, vp, i, vp,
                              C.POINTER(Opts), C.POINTER(Info)],
+            "zcsd_dcsd_mn": [vp, i, i, i, vp, i, vp, i, vp, i, vp, i, vp, i, vp,
+                             C.POINTER(Opts), C.POINTER(Info)],
             "zcsd_dzolo_pd": [vp, i, i, d, vp, i, ll, vp, vp, vp, C.POINTER(Opts), C.POINTER(Info)],
             "zcsd_dsyev_zolo": [vp, i, vp, i, d, d, vp, i, vp, C.POINTER(Opts), C.POINTER(Info)],
             "zcsd_dcsd_backward": [vp, i, i, vp, vp, vp, vp, vp, vp, vp, vp, vp],
@@ -260,16 +262,36 @@ def syev_zolo(B, lo=-1.0, hi=1.0, n_leaf=None):
 
 
 def csd(A1, A2, rank_mode="auto", r=None, ell=None, want_polar=False, **opts):
-    """CS decomposition of [A1; A2] (A1, A2: (n, n) float64 HIP tensors).
+    """CS decomposition of [A1; A2] (A1: (m1, n), A2: (m2, n) float64 HIP tensors, m1, m2 >= n).
 
     Returns (U1, U2, V1, theta, info) with A1 = U1 diag(cos theta) V1^T and
     A2 = U2 diag(sin theta) V1^T; in the rank-deficient case only the first
     info['rank'] columns / entries are valid (the rest are zero).  With
-    want_polar=True, info also holds the polar factors 'W1', 'W2'.
+    want_polar=True (square blocks only), info also holds the polar factors
+    'W1', 'W2'.  Square blocks use zcsd_dcsd, rectangular ones zcsd_dcsd_mn.
     """
-    n = A1.shape[0]
-    if A1.shape != (n, n) or A2.shape != (n, n):
-        raise ValueError("csd: A1 and A2 must both be n x n")
+    if A1.dim() != 2 or A2.dim() != 2 or A1.shape[1] != A2.shape[1]:
+        raise ValueError("csd: A1 and A2 must be 2-D with the same number of columns")
+    m1, n = A1.shape
+    m2 = A2.shape[0]
+    if (m1, m2) != (n, n):
+        if m1 < n or m2 < n:
+            raise ValueError("csd: need m1, m2 >= n")
+        if want_polar:
+            raise ValueError("csd: want_polar needs square blocks")
+        a1 = _colmajor(A1, "A1")
+        a2 = _colmajor(A2, "A2")
+        U1 = torch.empty((n, m1), dtype=torch.float64, device=A1.device)
+        U2 = torch.empty((n, m2), dtype=torch.float64, device=A1.device)
+        V1 = torch.empty((n, n), dtype=torch.float64, device=A1.device)
+        th = torch.empty(n, dtype=torch.float64, device=A1.device)
+        o = default_opts(rank_mode=rank_mode, r_override=r or 0, ell_override=ell or 0.0, **opts)
+        info = Info()
+        h = handle(A1.device.index)
+        st = _lib().zcsd_dcsd_mn(h, m1, m2, n, _ptr(a1), m1, _ptr(a2), m2, _ptr(U1), m1, _ptr(U2),
+                                 m2, _ptr(V1), n, _ptr(th), C.byref(o), C.byref(info))
+        _check(st, "zcsd_dcsd_mn")
+        return U1.t(), U2.t(), V1.t(), th, info.as_dict()
     a1 = _colmajor(A1, "A1")
     a2 = _colmajor(A2, "A2")
     U1 = torch.empty_like(a1)

@@ -191,3 +191,23 @@ def test_noise_class_backward_error_scales_with_dA():
     out = O.csd(A[:n], A[n:])
     ratio = Mt.residual(A[:n], A[n:], out["U1"], out["U2"], out["V1"], out["theta"]) / Mt.d_partial_isometry(A)
     assert 0.5 < ratio < 3.0
+
+
+@pytest.mark.parametrize("m1,m2,n,k,seed", [(30, 45, 20, 0, 71), (90, 60, 40, 7, 72), (25, 25, 10, 0, 73)])
+def test_rectangular_blocks_known_factors(m1, m2, n, k, seed):
+    """Algorithm 1 / 3 with m1, m2 >= n (the setting of Sec. 2): blocks built
+    from known factors (U_i with orthonormal columns, Haar V1, known angles,
+    k zeroed pairs) give back the known angles, the rank n - k, orthonormal
+    factors and the blocks."""
+    A1, A2, meta = WL.rect_pair(m1, m2, n, seed, rank_deficient=k)
+    r = O.csd(A1, A2)
+    rank = n - k
+    assert r["rank"] == rank
+    keep = np.setdiff1d(np.arange(n), meta["zero_idx"] if k else [])
+    assert np.max(np.abs(r["theta"] - np.sort(meta["theta"][keep]))) <= 10 * n * U
+    U1, U2, V1, th = r["U1"], r["U2"], r["V1"], r["theta"]
+    assert U1.shape == (m1, rank) and U2.shape == (m2, rank) and V1.shape == (n, rank)
+    for X in (U1, U2, V1):
+        assert np.linalg.norm(X.T @ X - np.eye(rank), 2) <= 100 * n * U
+    assert np.linalg.norm((U1 * np.cos(th)) @ V1.T - A1, 2) <= 100 * n * U
+    assert np.linalg.norm((U2 * np.sin(th)) @ V1.T - A2, 2) <= 100 * n * U

@@ -292,6 +292,9 @@ static CsdOut csd_run(int n, const double* A1, long long lda1, const double* A2,
     ea.n_leaf = o.n_leaf;
     ea.eps = o.eps; ea.tol = o.tol;
     ea.lowp = o.prec == ZCSD_MIXED_FP32;
+    // Alg. 3 keeps only the eigenpairs in [-1, 1]: the divide and conquer
+    // splits first between 1 and mu and does not divide the part at mu
+    if (deficient && mu > 1.0) ea.keep_below = 0.5 * (1.0 + mu);
     out.eig = zolo_eig(ea, ar, s);
     if (ea.lowp) {
       const double bmax = std::max(std::fabs(ea.lo), std::fabs(ea.hi));

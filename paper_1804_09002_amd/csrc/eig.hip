@@ -227,6 +227,9 @@ struct Blk {
   long long ldB;
   const double* V;  // nglob x n, ld nglob
   int tries = 0;
+  double split_at = 0.0;  // with has_split_at: the shift of this block's split
+  bool has_split_at = false;
+  bool drop = false;      // eigenpairs not wanted: finished as a scalar block
 };
 
 template <class T>
@@ -283,6 +286,12 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
     r.B = a.B + (long long)p * a.sB;
     r.ldB = a.ldb;
     r.V = V0 + (long long)p * nn;
+    if (a.keep_below < a.hi) {
+      // only the eigenpairs below keep_below are wanted: the first split is
+      // there and the part above is not divided further
+      r.split_at = a.keep_below;
+      r.has_split_at = true;
+    }
     active.push_back(r);
   }
   unsigned long long seed = 0x5DEECE66DULL;
@@ -357,7 +366,7 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
     // finished blocks: scalar (any basis) or leaves (Jacobi)
     std::vector<int> leaf_idx, scalar_idx, split_idx;
     for (int k = 0; k < nblk; ++k) {
-      if (std::sqrt(spread[k]) <= scalar_tol) scalar_idx.push_back(k);
+      if (all[k].drop || std::sqrt(spread[k]) <= scalar_tol) scalar_idx.push_back(k);
       else if (all[k].n <= nleaf) leaf_idx.push_back(k);
       else split_idx.push_back(k);
     }
@@ -479,6 +488,7 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
       double sft = d[b.n / 2];
       const double w = b.hi - b.lo;
       if (b.tries > 0 || !(sft > b.lo + 1e-3 * w && sft < b.hi - 1e-3 * w)) sft = 0.5 * (b.lo + b.hi);
+      if (b.has_split_at && b.tries == 0 && b.split_at > b.lo && b.split_at < b.hi) sft = b.split_at;
       sh[k] = sft;
       const double alpha = std::max(b.hi - sft, sft - b.lo) * (1.0 + 1e-12) + 1e-300;
       inva[k] = 1.0 / alpha;
@@ -849,9 +859,21 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
       const Blk& b = all[map[q]];
       const int np = npos[q];
       const double sft = shs[q];
+      if (b.has_split_at && np == b.n) {
+        // every eigenvalue lies above keep_below: none of them is wanted
+        Blk c = b;
+        c.B = Bs + q * SS;
+        c.ldB = Ns;
+        c.V = Vs + (long long)q * n * Ns;
+        c.has_split_at = false;
+        c.drop = true;
+        next.push_back(c);
+        continue;
+      }
       if (np == 0 || np == b.n) {
         ++res.failed_splits;
         Blk c = b;
+        c.has_split_at = false;
         c.B = Bs + q * SS;
         c.ldB = Ns;
         c.V = Vs + (long long)q * n * Ns;
@@ -867,6 +889,7 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
       plus.n = np;
       plus.lo = sft;
       plus.hi = b.hi;
+      plus.drop = b.has_split_at;  // above keep_below: not wanted
       plus.B = Bq + q * SS;
       plus.ldB = Ns;
       plus.V = Vq + (long long)q * n * Ns;

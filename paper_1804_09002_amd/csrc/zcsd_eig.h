@@ -23,6 +23,12 @@ struct ZoloEigArgs {
   double eps = 1e-15, tol = 0x1p-53;
   bool measure_offblock = true;
   bool lowp = false;           // products on the FP32 matrix cores (mixed mode; refine after)
+  // keep_below < hi: only the eigenpairs below keep_below are wanted (a
+  // spectral divide and conquer restricted to an interval): the first split
+  // is at keep_below and the part above is finished without dividing it
+  // (its columns are an orthonormal basis of that invariant subspace and its
+  // eigenvalues the diagonal of the projected block, both only approximate)
+  double keep_below = 1e300;
 };
 struct ZoloEigResult {
   int levels = 0, splits = 0, max_r = 0, failed_splits = 0;

@@ -62,7 +62,11 @@ typedef struct {
   int r_override;          /* 0 = choose r from the l estimate; 1..8 forces r */
   double ell_override;     /* 0 = estimate l = sigma_min lower bound; > 0 forces l */
   int n_leaf;              /* Zolo-eig blocks of at most this size go to Jacobi (<= 64) */
-  int postprocess;         /* 1: theta = atan2(S_ii, C_ii), C = cos, S = sin (Remark (iii)) */
+  int postprocess;         /* 0, 1: C_ii = v_i^T H1 v_i, S_ii = v_i^T H2 v_i (Alg. 1 lines 8-9),
+                              theta = atan2(S_ii, C_ii), C = cos, S = sin (Remark (iii));
+                              2: theta_i solves sin(theta) - cos(theta) = Lambda_ii, the
+                              cheaper and less accurate alternative of Remark (iv) (no
+                              H_i V products); 1 is the default */
 } zcsd_opts;
 
 /* Diagnostics filled by zcsd_dcsd / zcsd_dzolo_pd / zcsd_dsyev_zolo. */

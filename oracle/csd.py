@@ -17,6 +17,9 @@ eigensolver, with the steps of Algorithm 1 in the paper's order:
   8-9  C = diag(V1^T H1 V1), S = diag(V1^T H2 V1)
   post theta = arctan(S_ii / C_ii), C = cos theta, S = sin theta (Remark (iii)),
        columns ordered by ascending theta (Sec. 1).
+       With theta_from="lambda" lines 8-9 are replaced by the cheaper route of
+       Remark (iv): Lambda_ii = sin theta_i - cos theta_i = sqrt(2) sin(theta_i - pi/4),
+       so theta_i = pi/4 + arcsin(Lambda_ii / sqrt(2)).
 
 Readings taken where the paper is silent: H and B are symmetrised by
 (X + X^T)/2; arctan(S/C) is evaluated as atan2(S, C) and clamped to [0, pi/2].
@@ -41,13 +44,14 @@ def eps_rank(A1, A2):
     return int(np.floor(f2 + 0.5))
 
 
-def csd(A1, A2, rank_mode="auto", mu=2.0, b_choice="H2-H1"):
+def csd(A1, A2, rank_mode="auto", mu=2.0, b_choice="H2-H1", theta_from="diag"):
     """Algorithm 1 (full rank) / Algorithm 3 (rank deficient) in FP64.
 
     rank_mode: "auto" (Remark (vi)), "full" or "deficient".
     b_choice : "H2-H1" (the paper's choice).  "H1" is accepted only so the
                tests can reproduce the unstable variant of the worked example
                in Sec. 3; it is never the default.
+    theta_from: "diag" (Alg. 1 lines 8-9, the default) or "lambda" (Remark (iv)).
     Returns a dict with U1, U2, V1, theta (economical in the rank-deficient
     case) and the intermediates W1, W2, H1, H2, B, Lambda, rank, mu.
     """
@@ -89,7 +93,13 @@ def csd(A1, A2, rank_mode="auto", mu=2.0, b_choice="H2-H1"):
     U2 = W2 @ V
     c = np.einsum("ij,ij->j", V, H1 @ V)
     s = np.einsum("ij,ij->j", V, H2 @ V)
-    theta = np.clip(np.arctan2(s, c), 0.0, np.pi / 2)
+    if theta_from == "diag":
+        theta = np.clip(np.arctan2(s, c), 0.0, np.pi / 2)
+    elif theta_from == "lambda":
+        x = np.clip(lam, -1.0, 1.0)
+        theta = np.clip(np.pi / 4 + np.arcsin(x / np.sqrt(2.0)), 0.0, np.pi / 2)
+    else:
+        raise ValueError("unknown theta_from")
     order = np.argsort(theta, kind="stable")
     return {
         "U1": U1[:, order], "U2": U2[:, order], "V1": V[:, order],

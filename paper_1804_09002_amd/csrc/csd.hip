@@ -62,6 +62,17 @@ __global__ void theta_kernel(int r, const double* __restrict__ c, const double* 
   }
 }
 
+// Remark (iv), the cheaper alternative to lines 8-9: theta_j solves
+// sin(theta) - cos(theta) = Lambda_jj, i.e. theta = pi/4 + asin(Lambda_jj / sqrt(2))
+__global__ void theta_from_lambda_kernel(int r, const double* __restrict__ lam, double* th) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j < r) {
+    const double x = fmin(fmax(lam[j], -1.0), 1.0);
+    const double t = 0.7853981633974483 + asin(x * 0.7071067811865476);
+    th[j] = fmin(fmax(t, 0.0), 1.5707963267948966);
+  }
+}
+
 static void axpby(long long total, double a, const double* X, double b, double* Y, hipStream_t s) {
   long long g = std::max<long long>(1, std::min<long long>((total + 255) / 256, 4096));
   hipLaunchKernelGGL(axpby_kernel, dim3((unsigned)g), dim3(256), 0, s, total, a, X, b, Y);
@@ -396,17 +407,24 @@ static CsdOut csd_run(int n, const double* A1, long long lda1, const double* A2,
         axpby((long long)n * r, -0.5, Tc + nn, 1.5, Ut + nn, s);
       }
     }
-    g.A = H;
-    g.C = T;
-    dgemm(g, s);
-    hipLaunchKernelGGL(coldot_kernel, dim3(r), dim3(256), 0, s, n, V, (long long)n, T,
-                       (long long)n, cs);
-    ZCSD_CHECK_LAUNCH();
-    hipLaunchKernelGGL(coldot_kernel, dim3(r), dim3(256), 0, s, n, V, (long long)n, T + nn,
-                       (long long)n, cs + n);
-    ZCSD_CHECK_LAUNCH();
-    hipLaunchKernelGGL(theta_kernel, dim3((r + 255) / 256), dim3(256), 0, s, r, cs, cs + n, th);
-    ZCSD_CHECK_LAUNCH();
+    if (o.postprocess == 2) {
+      // Remark (iv): theta from the eigenvalues (the kept ones lie in [-1, 1])
+      hipLaunchKernelGGL(theta_from_lambda_kernel, dim3((r + 255) / 256), dim3(256), 0, s, r, lam,
+                         th);
+      ZCSD_CHECK_LAUNCH();
+    } else {
+      g.A = H;
+      g.C = T;
+      dgemm(g, s);
+      hipLaunchKernelGGL(coldot_kernel, dim3(r), dim3(256), 0, s, n, V, (long long)n, T,
+                         (long long)n, cs);
+      ZCSD_CHECK_LAUNCH();
+      hipLaunchKernelGGL(coldot_kernel, dim3(r), dim3(256), 0, s, n, V, (long long)n, T + nn,
+                         (long long)n, cs + n);
+      ZCSD_CHECK_LAUNCH();
+      hipLaunchKernelGGL(theta_kernel, dim3((r + 255) / 256), dim3(256), 0, s, r, cs, cs + n, th);
+      ZCSD_CHECK_LAUNCH();
+    }
   }
   // a11: order by ascending theta and write the outputs (columns r..n-1 zero)
   std::vector<double> thh(r);
@@ -469,6 +487,7 @@ static void fill_csd_info(zcsd_info* info, const CsdOut& r) {
 }
 
 static void check_csd_opts(const zcsd_opts& o) {
+  ZCSD_REQUIRE(o.postprocess >= 0 && o.postprocess <= 2, "csd: postprocess must be 0, 1 or 2");
   ZCSD_REQUIRE(o.r_override >= 0 && o.r_override <= ZOLO_RMAX, "csd: r_override out of range");
   ZCSD_REQUIRE(o.prec == ZCSD_FP64 || o.prec == ZCSD_MIXED_FP32, "csd: unknown precision mode");
   ZCSD_REQUIRE(o.eps > 0.0 && o.eps < 1.0 && o.tol > 0.0, "csd: eps/tol out of range");
@@ -586,6 +605,7 @@ extern "C" zcsd_status zcsd_dcsd2x2(zcsd_handle* handle, int n, const double* d_
     ZCSD_REQUIRE(o.prec == ZCSD_FP64 || o.prec == ZCSD_MIXED_FP32, "csd2x2: unknown precision mode");
     ZCSD_REQUIRE(o.eps > 0.0 && o.eps < 1.0 && o.tol > 0.0, "csd2x2: eps/tol out of range");
     ZCSD_REQUIRE(o.rank_mode != ZCSD_RANK_DEFICIENT, "csd2x2: the first block column has full rank");
+    ZCSD_REQUIRE(o.postprocess >= 0 && o.postprocess <= 2, "csd2x2: postprocess must be 0, 1 or 2");
     ZCSD_HIP(hipSetDevice(handle->device));
     handle->arena.reset();
     handle->arena.reserve(csd_workspace_bytes(n));

@@ -146,6 +146,22 @@ __global__ void theta_ragged_kernel(int N, int K, const double* __restrict__ cs,
   th[e] = t;
 }
 
+// Remark (iv): theta_q(j) = clamp(pi/4 + asin(lambda_q(j) / sqrt(2)), 0, pi/2)
+// for j < r_q, else 0
+__global__ void theta_ragged_lambda_kernel(int N, int K, const double* __restrict__ lam,
+                                           const int* __restrict__ rq, double* th) {
+  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e >= (long long)K * N) return;
+  const int q = (int)(e / N), j = (int)(e % N);
+  double t = 0.0;
+  if (j < rq[q]) {
+    const double x = fmin(fmax(lam[e], -1.0), 1.0);
+    t = 0.7853981633974483 + asin(x * 0.7071067811865476);
+    t = fmin(fmax(t, 0.0), 1.5707963267948966);
+  }
+  th[e] = t;
+}
+
 // dst(member q)(:, j) = src_q(0:n_q, perm_q[j]) for j < r_q, zero for r_q <= j < n_q
 __global__ void ragged_gather_kernel(int N, const double* __restrict__ src, long long sstride,
                                      const int* __restrict__ nq, const int* __restrict__ rq,
@@ -340,16 +356,22 @@ static void csd_group(int N, const std::vector<int>& mem, bool deficient, const 
         ZCSD_CHECK_LAUNCH();
       }
     }
-    g.A = H;
-    g.C = T;
-    dgemm(g, s);
+    if (o.postprocess != 2) {
+      g.A = H;
+      g.C = T;
+      dgemm(g, s);
+    }
   }
-  double* cs = ar.dalloc((size_t)2 * K * N);
-  hipLaunchKernelGGL(coldot_ragged_kernel, dim3(N, 2 * K), dim3(64), 0, s, N, V, T, d_n, cs);
-  ZCSD_CHECK_LAUNCH();
   double* th = ar.dalloc((size_t)K * N);
-  {
-    const long long tot = (long long)K * N;
+  const long long tot = (long long)K * N;
+  if (o.postprocess == 2) {
+    hipLaunchKernelGGL(theta_ragged_lambda_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0,
+                       s, N, K, lam, d_r, th);
+    ZCSD_CHECK_LAUNCH();
+  } else {
+    double* cs = ar.dalloc((size_t)2 * K * N);
+    hipLaunchKernelGGL(coldot_ragged_kernel, dim3(N, 2 * K), dim3(64), 0, s, N, V, T, d_n, cs);
+    ZCSD_CHECK_LAUNCH();
     hipLaunchKernelGGL(theta_ragged_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, N,
                        K, cs, d_r, th);
     ZCSD_CHECK_LAUNCH();
@@ -400,6 +422,7 @@ extern "C" zcsd_status zcsd_dcsd_batched(zcsd_handle* handle, int batch, const i
     ZCSD_REQUIRE(o.prec == ZCSD_FP64, "csd_batched: FP64 only");
     ZCSD_REQUIRE(o.eps > 0.0 && o.eps < 1.0 && o.tol > 0.0, "csd_batched: eps/tol out of range");
     ZCSD_REQUIRE(o.mu > 1.0 && o.mu < 3.0, "csd_batched: mu must lie in (1, 3)");
+    ZCSD_REQUIRE(o.postprocess >= 0 && o.postprocess <= 2, "csd_batched: postprocess must be 0, 1 or 2");
     std::vector<long long> toff(batch + 1, 0);
     for (int k = 0; k < batch; ++k) {
       ZCSD_REQUIRE(n_host[k] >= 1 && n_host[k] <= 4096, "csd_batched: sizes must lie in [1, 4096]");

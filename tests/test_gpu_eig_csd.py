@@ -262,3 +262,34 @@ def test_csd_ill_conditioned_algorithm2(n, seed):
     assert np.max(np.abs(th - ref["theta"])) <= 10 * n * U
     assert np.max(np.abs(th - np.sort(theta))) <= 10 * n * U
     _check_csd(A1, A2, U1, U2, V1, th, n)
+
+
+@pytest.mark.parametrize("n,k,seed", [(256, 0, 91), (200, 13, 92)])
+def test_csd_theta_from_lambda_remark_iv(n, k, seed):
+    """postprocess = 2: theta from the eigenvalues (Remark (iv)), single and batched
+    paths, against the oracle's same route and the known angles."""
+    from paper_1804_09002_amd import zcsd
+    A1, A2, meta = WL.clustered_pair(n, seed, rank_deficient=k)
+    ref = O.csd(A1, A2, theta_from="lambda")
+    r = n - k
+    keep = np.setdiff1d(np.arange(n), meta["zero_idx"]) if k else np.arange(n)
+    th_true = np.sort(meta["theta"][keep])
+    U1, U2, V1, th, info = zcsd.csd(_t(A1), _t(A2), postprocess=2)
+    U1, U2, V1, th = (x.cpu().numpy() for x in (U1, U2, V1, th))
+    assert info["rank"] == r == ref["rank"]
+    assert np.max(np.abs(th[:r] - ref["theta"])) <= 10 * n * U
+    assert np.max(np.abs(th[:r] - th_true)) <= 10 * n * U
+    _check_csd(A1, A2, U1, U2, V1, th, r)
+    (b1, b2, bv, bth, br), = zcsd.csd_batched([_t(A1)], [_t(A2)], postprocess=2)
+    bth = bth.cpu().numpy()
+    assert br == r
+    assert np.max(np.abs(bth[:r] - ref["theta"])) <= 10 * n * U
+    assert np.all(bth[r:] == 0)
+    _check_csd(A1, A2, b1.cpu().numpy(), b2.cpu().numpy(), bv.cpu().numpy(), bth, r)
+
+
+def test_csd_postprocess_out_of_range():
+    from paper_1804_09002_amd import zcsd
+    A1, A2, _ = WL.uniform_pair(8, 1)
+    with pytest.raises(Exception):
+        zcsd.csd(_t(A1), _t(A2), postprocess=3)

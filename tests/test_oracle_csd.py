@@ -211,3 +211,24 @@ def test_rectangular_blocks_known_factors(m1, m2, n, k, seed):
         assert np.linalg.norm(X.T @ X - np.eye(rank), 2) <= 100 * n * U
     assert np.linalg.norm((U1 * np.cos(th)) @ V1.T - A1, 2) <= 100 * n * U
     assert np.linalg.norm((U2 * np.sin(th)) @ V1.T - A2, 2) <= 100 * n * U
+
+
+@pytest.mark.parametrize("n,k,seed", [(48, 0, 81), (64, 16, 82)])
+def test_theta_from_lambda_remark_iv(n, k, seed):
+    """Remark (iv): theta from sin(theta) - cos(theta) = Lambda recovers the known
+    angles to absolute accuracy O(n u), full rank and rank deficient alike, and
+    leaves U1, U2, V1 as the default route gives them."""
+    A1, A2, meta = WL.clustered_pair(n, seed, rank_deficient=k)
+    a = O.csd(A1, A2)
+    b = O.csd(A1, A2, theta_from="lambda")
+    keep = np.setdiff1d(np.arange(n), meta["zero_idx"]) if k else np.arange(n)
+    th_true = np.sort(meta["theta"][keep])
+    assert b["rank"] == n - k
+    assert np.max(np.abs(b["theta"] - th_true)) <= 10 * n * U
+    assert np.max(np.abs(b["theta"] - a["theta"])) <= 10 * n * U
+    res = Mt.residual(A1, A2, b["U1"], b["U2"], b["V1"], b["theta"], ord="fro")
+    assert res <= 1e-13 * np.sqrt(n - k)
+    # the identity the route rests on, on the known angles themselves
+    lam = np.sin(th_true) - np.cos(th_true)
+    back = np.pi / 4 + np.arcsin(lam / np.sqrt(2.0))
+    assert np.max(np.abs(back - th_true)) <= 4 * U

@@ -127,6 +127,16 @@ zcsd_status zcsd_dcsd(zcsd_handle* handle, int n,
                       const zcsd_opts* opts, zcsd_info* info);
 
 /*
+ * Device bytes the handle's arena holds for zcsd_dcsd / zcsd_dcsd2x2 at size n
+ * (the polar batch of two n x n problems with up to eight Zolotarev terms,
+ * the Zolo-eig levels of Sec. 4 and the assembly buffers; 28.2 GB at
+ * n = 4096).  A host computation: nothing is enqueued or allocated, and
+ * `handle` may be NULL.  Errors: ZCSD_EINVAL for n < 1, a NULL `bytes` or
+ * out-of-range opts.
+ */
+zcsd_status zcsd_workspace_size(zcsd_handle* handle, int n, const zcsd_opts* opts, size_t* bytes);
+
+/*
  * CS decomposition with rectangular blocks, A1 m1 x n and A2 m2 x n with
  * m1, m2 >= n (Algorithm 1 / Algorithm 3 as stated for m1 + m2 rows, Sec. 2
  * and Sec. 3): A1 = U1 diag(cos theta) V1^T, A2 = U2 diag(sin theta) V1^T with

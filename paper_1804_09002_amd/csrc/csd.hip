@@ -517,6 +517,20 @@ extern "C" zcsd_status zcsd_dcsd(zcsd_handle* handle, int n, const double* d_A1,
   });
 }
 
+extern "C" zcsd_status zcsd_workspace_size(zcsd_handle* handle, int n, const zcsd_opts* opts,
+                                           size_t* bytes) {
+  (void)handle;
+  return guarded([&] {
+    ZCSD_REQUIRE(n >= 1, "workspace_size: n must be positive");
+    ZCSD_REQUIRE(bytes != nullptr, "workspace_size: NULL pointer");
+    zcsd_opts o;
+    zcsd_default_opts(&o);
+    if (opts) o = *opts;
+    check_csd_opts(o);
+    *bytes = csd_workspace_bytes(n);
+  });
+}
+
 // Householder QR of the m x n block A (m >= n): Q (m x n, ld m) and the n x n
 // triangular factor R (ld n; geqrf leaves zeros below the diagonal)
 static void tall_qr(int m, int n, const double* A, long long lda, double* Q, double* R, Arena& ar,

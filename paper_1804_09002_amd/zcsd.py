@@ -94,6 +94,7 @@ def _lib():
                                   vp, vp, C.POINTER(C.c_int), C.POINTER(Opts), C.POINTER(Info)],
             "zcsd_zolo_coeffs": [d, i, C.POINTER(d), C.POINTER(d), C.POINTER(d), C.POINTER(d)],
             "zcsd_zolo_choose_r": [d, d],
+            "zcsd_workspace_size": [vp, i, C.POINTER(Opts), C.POINTER(C.c_size_t)],
             "zcsd_dqr": [vp, i, i, i, i, vp, i, ll, vp, i, ll],
             "zcsd_profile_query": [C.c_char_p, C.POINTER(ll), C.POINTER(d), C.POINTER(d), C.POINTER(d)],
             "zcsd_profile_names": [C.c_char_p, i],
@@ -109,6 +110,14 @@ def _lib():
 
 def lib():
     return _lib()
+
+
+def workspace_size(n, **opts):
+    """Device bytes a square CSD of size n reserves (zcsd_workspace_size; host only)."""
+    o = default_opts(**opts)
+    b = C.c_size_t(0)
+    _check(_lib().zcsd_workspace_size(None, int(n), C.byref(o), C.byref(b)), "zcsd_workspace_size")
+    return int(b.value)
 
 
 def _check(st, what):

@@ -21,7 +21,9 @@
 // ||B_b - mean I||_F is below 4 u max(|lo|, |hi|) are already diagonal to
 // working accuracy and are finished as they are.  Eigenpairs are finally sorted.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <numeric>
 #include <vector>
 
@@ -240,6 +242,23 @@ T* upload(Arena& ar, const std::vector<T>& v, hipStream_t s) {
 }
 }  // namespace
 
+// ZCSD_EIG_TIMES=1: one line per level with its blocks, Zolotarev degree and
+// wall times (the stream is drained at the level's start, around the sign
+// function and at its end; nothing else changes)
+static bool level_times_enabled() {
+  static int v = -1;
+  if (v < 0) {
+    const char* e = std::getenv("ZCSD_EIG_TIMES");
+    v = (e && e[0] && e[0] != '0') ? 1 : 0;
+  }
+  return v == 1;
+}
+
+static double wall_ms() {
+  return std::chrono::duration<double, std::milli>(
+             std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
 ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
   const int n = a.n;
   const int nprob = a.batch;
@@ -297,8 +316,18 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
   unsigned long long seed = 0x5DEECE66DULL;
 
   // blocks parked for the end: leaves
+  const bool lt = level_times_enabled();
+  double lt_start = 0.0, lt_sign = 0.0;
+  int lt_r = 0, lt_ns = 0, lt_N = 0, lt_blocks = 0;
   while (!active.empty()) {
     ++res.levels;
+    if (lt) {
+      HostSync::sync(s);
+      lt_start = wall_ms();
+      lt_sign = 0.0;
+      lt_r = lt_ns = lt_N = 0;
+      lt_blocks = (int)active.size();
+    }
     // --- classify: leaves / scalar / split --------------------------------
     std::vector<Blk> leaves, split;
     for (auto& b : active) {
@@ -540,8 +569,20 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
       // the sign function stays FP64 in the mixed mode: its combines have inner
       // dimension r n, where FP32 accumulation loses ~1e-5 relative accuracy
       GemmFp64Scope fp64;
+      double t0 = 0.0;
+      if (lt) {
+        HostSync::sync(s);
+        t0 = wall_ms();
+      }
       ZoloPdResult zr = zolo_pd_batched(za, ar, s);
       res.max_r = std::max(res.max_r, zr.r);
+      if (lt) {
+        HostSync::sync(s);
+        lt_sign = wall_ms() - t0;
+        lt_r = zr.r;
+        lt_ns = ns;
+        lt_N = Ns;
+      }
     }
     std::vector<double> offW(ns, 0.0), offY(ns, 0.0), offQ(ns, 0.0), offX(ns, 0.0);
     auto offpad = [&](const double* M, std::vector<double>& o) {
@@ -903,6 +944,12 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
       minus.V = Vq + (long long)q * n * Ns + (long long)np * n;
       next.push_back(minus);
       next.push_back(plus);
+    }
+    if (lt) {
+      HostSync::sync(s);
+      std::fprintf(stderr, "[zcsd] eig level %d: %d blocks, %d split at padded size %d, r = %d, "
+                   "sign function %.2f ms, level %.2f ms\n", res.levels, lt_blocks, lt_ns, lt_N,
+                   lt_r, lt_sign, wall_ms() - lt_start);
     }
     active.swap(next);
   }

@@ -17,6 +17,8 @@
 //      n+ and n_b - n+ are the children, with spectra in [s_b, hi_b] and
 //      [lo_b, s_b]; ||B'_21||_F / ||B||_F is recorded.
 // A split with n+ in {0, n_b} only moves the interval (bisection on s).
+// Before each split the interval is tightened to mean_b -+ ||B_b - mean_b I||_F,
+// which holds every eigenvalue of the block.
 // Blocks of at most n_leaf go to batched Jacobi; blocks whose spread
 // ||B_b - mean I||_F is below 4 u max(|lo|, |hi|) are already diagonal to
 // working accuracy and are finished as they are.  Eigenpairs are finally sorted.
@@ -512,6 +514,19 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
     for (int q = 0; q < ns; ++q) {
       const int k = split_idx[q];
       Blk& b = all[k];
+      if (!b.has_split_at) {
+        // every eigenvalue of the block lies within ||B_blk - mean I||_2 <=
+        // ||B_blk - mean I||_F of its mean: tighten the tracked interval.  A
+        // stale end (the initial margin below a tight cluster, say) would push
+        // the median out of the accepted range and leave the cluster to
+        // bisection, one sign function per halving of the interval
+        const double dev = std::sqrt(spread[k]) * (1.0 + 1e-10) + scalar_tol;
+        const double lo2 = std::max(b.lo, mean[k] - dev), hi2 = std::min(b.hi, mean[k] + dev);
+        if (lo2 < hi2) {
+          b.lo = lo2;
+          b.hi = hi2;
+        }
+      }
       std::vector<double> d(diag.begin() + (size_t)k * N, diag.begin() + (size_t)k * N + b.n);
       std::nth_element(d.begin(), d.begin() + b.n / 2, d.end());
       double sft = d[b.n / 2];

@@ -278,6 +278,8 @@ def csd(A1, A2, rank_mode="auto", r=None, ell=None, want_polar=False, **opts):
     info['rank'] columns / entries are valid (the rest are zero).  With
     want_polar=True (square blocks only), info also holds the polar factors
     'W1', 'W2'.  Square blocks use zcsd_dcsd, rectangular ones zcsd_dcsd_mn.
+    Other keyword options are zcsd_opts fields, e.g. prec="mixed_fp32",
+    postprocess=2 (angles from sin(theta) - cos(theta) = Lambda, Remark (iv)).
     """
     if A1.dim() != 2 or A2.dim() != 2 or A1.shape[1] != A2.shape[1]:
         raise ValueError("csd: A1 and A2 must be 2-D with the same number of columns")

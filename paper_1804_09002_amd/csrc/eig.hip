@@ -814,7 +814,10 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
     }
 
     double* Vq = ar.dalloc((size_t)ns * n * Ns);
-    {
+    if (res.levels == 1 && Ns == n) {
+      // the first level splits whole problems, whose V is the identity: V Q = Q
+      copy_scale(ns, n, n, 1.0, Q, Ns, SS, Vq, n, (long long)n * Ns, s);
+    } else {
       GemmBatch g;
       g.batch = ns;
       g.m = n; g.n = Ns; g.k = Ns;

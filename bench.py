@@ -219,7 +219,7 @@ def cpu_baseline(n, reps, seed):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; multi-GPU runs are not part of it",
+        print(json.dumps({"error": "the path runs on one GPU; --gpus above 1 is not supported",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
     import numpy as np

@@ -43,7 +43,10 @@ typedef enum {
 /* ZCSD_MIXED_FP32: the polar decompositions and B in FP64; Zolo-eig with its
  * products on the FP32 matrix cores (FP64 storage and panels), then FP64
  * refinement of V1 (iterative refinement of the eigenvectors and exact FP64
- * re-solves of eigenvalue clusters) to the FP64 accuracy.  zcsd_dcsd only. */
+ * re-solves of eigenvalue clusters); when that refinement does not reach the
+ * FP64 rounding floor, Zolo-eig is recomputed in FP64 (info->refine_fallback),
+ * so the results always have the FP64 accuracy.  Accepted by zcsd_dcsd,
+ * zcsd_dcsd_mn and zcsd_dcsd2x2; zcsd_dcsd_batched is FP64 only. */
 typedef enum { ZCSD_FP64 = 0, ZCSD_MIXED_FP32 = 1 } zcsd_precision;
 
 typedef enum {
@@ -54,7 +57,7 @@ typedef enum {
 
 /* Options.  zcsd_default_opts() fills the paper's values. */
 typedef struct {
-  zcsd_precision prec;     /* arithmetic of the Cholesky-form iterations (FP64 default) */
+  zcsd_precision prec;     /* ZCSD_FP64 (default) or ZCSD_MIXED_FP32 (above) */
   zcsd_rank_mode rank_mode;
   double eps;              /* floor of the Zolo-pd interval [eps, 1]; 1e-15 (Sec. 5.1) */
   double mu;               /* shift of the null space in B; 2 (Algorithm 3 line 3) */

@@ -311,3 +311,22 @@ def test_clustered_levels_bounded(rd):
     keep = np.setdiff1d(np.arange(n), meta["zero_idx"]) if rd else np.arange(n)
     truth = np.sort(meta["theta"][keep])
     assert np.max(np.abs(th.cpu().numpy()[:r] - truth)) <= 10 * n * U
+
+
+def test_csd_batched_theta_from_lambda_ragged():
+    """postprocess = 2 on a ragged batch (sizes in different classes, one rank
+    deficient): every problem's angles match the oracle's Remark (iv) route."""
+    from paper_1804_09002_amd import zcsd
+    specs = [(8, 0, 101), (37, 0, 102), (64, 8, 103), (130, 0, 104), (200, 20, 105)]
+    A1s, A2s, refs = [], [], []
+    for n, k, seed in specs:
+        A1, A2, _ = WL.clustered_pair(n, seed, rank_deficient=k)
+        A1s.append(_t(A1)); A2s.append(_t(A2))
+        refs.append((A1, A2, O.csd(A1, A2, theta_from="lambda")))
+    out = zcsd.csd_batched(A1s, A2s, postprocess=2)
+    for (n, k, _), (A1, A2, ref), (u1, u2, v1, th, r) in zip(specs, refs, out):
+        th = th.cpu().numpy()
+        assert r == n - k == ref["rank"]
+        assert np.max(np.abs(th[:r] - ref["theta"])) <= 10 * max(n, 8) * U, n
+        assert np.all(th[r:] == 0)
+        _check_csd(A1, A2, u1.cpu().numpy(), u2.cpu().numpy(), v1.cpu().numpy(), th, r)

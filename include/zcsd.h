@@ -20,6 +20,14 @@
  *    HIP runtime failures return ZCSD_EHIP; allocation failures ZCSD_ENOMEM.
  *    Numerical conditions are reported through the status and zcsd_info.
  *  - A handle is not thread-safe; use one handle per host thread.
+ *  - Workspace: the entry points take no caller workspace.  Each handle owns
+ *    one device arena that grows to the largest size a call has needed and is
+ *    reused by later calls (no allocation inside a call once it has grown);
+ *    zcsd_workspace_size reports its size for a square CSD beforehand.  The
+ *    amount a call needs depends on host decisions made during the call
+ *    (Zolotarev degree, split sizes of Zolo-eig, size classes of a batch), so
+ *    one bound per call would have to be the worst case of all of them.
+ *    zcsd_dcsd_backward_noalloc is the one entry point that allocates nothing.
  */
 #ifndef ZCSD_H
 #define ZCSD_H
@@ -132,7 +140,7 @@ zcsd_status zcsd_dcsd(zcsd_handle* handle, int n,
 /*
  * Device bytes the handle's arena holds for zcsd_dcsd / zcsd_dcsd2x2 at size n
  * (the polar batch of two n x n problems with up to eight Zolotarev terms,
- * the Zolo-eig levels of Sec. 4 and the assembly buffers; 28.2 GB at
+ * the Zolo-eig levels of Sec. 5 and the assembly buffers; 28.2 GB at
  * n = 4096).  A host computation: nothing is enqueued or allocated, and
  * `handle` may be NULL.  Errors: ZCSD_EINVAL for n < 1, a NULL `bytes` or
  * out-of-range opts.
@@ -163,7 +171,7 @@ zcsd_status zcsd_dcsd_mn(zcsd_handle* handle, int m1, int m2, int n,
 
 /*
  * Complete 2 x 2 CS decomposition of an orthogonal 2n x 2n matrix
- * A = [A1 A3; A2 A4] (Remark (iv) of Sec. 3):
+ * A = [A1 A3; A2 A4] (Remark (viii) of Sec. 3):
  *    A = diag(U1, U2) [C -S; S C] diag(V1, V2)^T,  C = diag(cos theta),
  *    S = diag(sin theta), 0 <= theta_1 <= ... <= theta_n <= pi/2.
  * Algorithm 1 on the first block column [A1; A2] gives U1, U2, V1 and theta;
@@ -199,7 +207,12 @@ zcsd_status zcsd_dcsd2x2(zcsd_handle* handle, int n,
  * stream.  Errors: ZCSD_EINVAL (bad sizes/offsets/pointers, batch outside
  * 1..65535, opts out of range: mu must lie in (1, 3)); ZCSD_ENOTISO /
  * ZCSD_ENOCONV / ZCSD_ENOMEM as zcsd_dcsd.  info (may be NULL) holds the
- * largest r used, the deepest Zolo-eig level count and the total splits.
+ * largest r used, the deepest Zolo-eig level count, the total splits and, in
+ * info->repair, the number of problems whose polar factor Algorithm 2 replaced.
+ * A size class of full-rank problems shares one lower bound l of sigma_min;
+ * when it reaches eps (a member may have sigma_min(A_i) < eps, Sec. 5.1), the
+ * class's problems run one at a time through the single path of zcsd_dcsd,
+ * which has the repair of Algorithm 2, instead of the batched kernels.
  */
 zcsd_status zcsd_dcsd_batched(zcsd_handle* handle, int batch, const int* n_host,
                               const long long* off_host,
@@ -230,6 +243,27 @@ zcsd_status zcsd_dcsd_backward(zcsd_handle* handle, int batch, int n,
                                const double* d_theta, const double* d_g_theta,
                                const double* d_G_W1, const double* d_G_W2,
                                double* d_gA1, double* d_gA2);
+
+/*
+ * zcsd_dcsd_backward that allocates nothing, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments, layout, ownership and results as
+ * zcsd_dcsd_backward.  Its intermediates (2 n^2 doubles per problem) live in
+ * a fixed device array of 2^23 doubles (64 MiB) that the library holds on
+ * every device it runs on until the process ends; the batch is processed in
+ * passes of floor(2^23 / (2 n^2)) problems.  Limit: n <= 2048 (ZCSD_EINVAL
+ * beyond it, nothing enqueued).  Asynchronous: returns once the work is
+ * enqueued on the handle's stream, with no allocation, synchronisation or
+ * host transfer.  Every call on a device shares that device's array: calls
+ * that overlap in time on one device (on different streams or handles) race
+ * with each other; calls on one stream are ordered.  Nothing left in the
+ * array by an earlier call is read (every element is written before use).
+ */
+zcsd_status zcsd_dcsd_backward_noalloc(zcsd_handle* handle, int batch, int n,
+                                       const double* d_U1, const double* d_U2, const double* d_V1,
+                                       const double* d_theta, const double* d_g_theta,
+                                       const double* d_G_W1, const double* d_G_W2,
+                                       double* d_gA1, double* d_gA2);
 
 /*
  * Batched Zolo-pd (Sec. 5): polar decompositions X_b = W_b H_b of `batch`

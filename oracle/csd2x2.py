@@ -1,7 +1,7 @@
 """Complete 2 x 2 CS decomposition (oracle, test infrastructure: only tests, the
 smoke check and the CPU baseline use it; the product path never imports it).
 
-Remark (iv) of Sec. 3: an orthogonal A = [A1 A3; A2 A4] (2n x 2n, n x n blocks)
+Remark (viii) of Sec. 3: an orthogonal A = [A1 A3; A2 A4] (2n x 2n, n x n blocks)
 has A = diag(U1, U2) [C -S; S C] diag(V1, V2)^T.  Algorithm 1 applied to the
 first block column gives U1, U2, V1, C, S; then X = -A3^T U1 S + A4^T U2 C,
 whose QR factor (diag(R) >= 0) is V2 (X itself is orthogonal when A is).

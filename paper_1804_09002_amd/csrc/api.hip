@@ -20,6 +20,10 @@ zcsd_status zcsd_create(zcsd_handle** handle, int device) {
     ZCSD_HIP(hipGetDeviceCount(&count));
     ZCSD_REQUIRE(device >= 0 && device < count, "zcsd_create: no such device");
     ZCSD_HIP(hipSetDevice(device));
+    // the allocation-free entry point's scratch array: its address on this
+    // device, looked up here once so that the entry point itself makes no
+    // runtime call beyond its kernel launches
+    (void)backward_scratch(device);
     auto* h = new zcsd_handle_s();
     h->device = device;
     h->stream = nullptr;

@@ -16,7 +16,9 @@
 // four batched GEMMs per block (G V1, U^T (.), U (.), (.) V1^T) and one
 // element-wise kernel.  Pairs with sigma_j + sigma_k = 0 (two zero singular
 // values, where W is not differentiable) contribute zero.
+#include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "zcsd_api_guard.h"
 #include "zcsd_internal.h"
@@ -60,13 +62,14 @@ __global__ void csd_bwd_core_kernel(int n, double* K, long long sK, const double
   }
 }
 
-void csd_backward(int batch, int n, const double* U1, const double* U2, const double* V1,
-                  const double* theta, const double* g, const double* G1, const double* G2,
-                  double* gA1, double* gA2, Arena& ar, hipStream_t s) {
+// The backward of `batch` problems with the two intermediates T and K (batch
+// n x n blocks each, stride n*n) supplied by the caller.  Every element of T
+// and K is written before it is read, so their previous contents do not matter.
+static void csd_backward_ws(int batch, int n, const double* U1, const double* U2,
+                            const double* V1, const double* theta, const double* g,
+                            const double* G1, const double* G2, double* gA1, double* gA2,
+                            double* T, double* K, hipStream_t s) {
   const long long nn = (long long)n * n;
-  ArenaScope scope(ar);
-  double* T = ar.dalloc((size_t)batch * nn);
-  double* K = ar.dalloc((size_t)batch * nn);
   const double* U[2] = {U1, U2};
   const double* G[2] = {G1, G2};
   double* out[2] = {gA1, gA2};
@@ -106,6 +109,44 @@ void csd_backward(int batch, int n, const double* U1, const double* U2, const do
   }
 }
 
+void csd_backward(int batch, int n, const double* U1, const double* U2, const double* V1,
+                  const double* theta, const double* g, const double* G1, const double* G2,
+                  double* gA1, double* gA2, Arena& ar, hipStream_t s) {
+  const long long nn = (long long)n * n;
+  ArenaScope scope(ar);
+  double* T = ar.dalloc((size_t)batch * nn);
+  double* K = ar.dalloc((size_t)batch * nn);
+  csd_backward_ws(batch, n, U1, U2, V1, theta, g, G1, G2, gA1, gA2, T, K, s);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free variant: T and K live in a file-scope device array of fixed
+// size instead of the handle's arena.  Each device holds its own copy of the
+// array (for as long as the process runs); host code reaches it only through
+// the device address that hipGetSymbolAddress returns for the current device,
+// looked up once per device when a handle is created.
+constexpr long long kScratchDoubles = 1LL << 23;  // 64 MiB: 2 n^2 <= 2^23 for n <= 2048
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+// Device address of `scratch` on `device`, which must be the current device.
+double* backward_scratch(int device) {
+  ZCSD_REQUIRE(device >= 0 && device < kMaxDevices, "backward scratch: device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[device]) {
+    void* p = nullptr;
+    ZCSD_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    ZCSD_REQUIRE(p != nullptr, "backward scratch: no device address");
+    g_scratch_ptr[device] = static_cast<double*>(p);
+  }
+  return g_scratch_ptr[device];
+}
+
 }  // namespace zcsd
 
 using namespace zcsd;
@@ -126,5 +167,35 @@ extern "C" zcsd_status zcsd_dcsd_backward(zcsd_handle* handle, int batch, int n,
     csd_backward(batch, n, d_U1, d_U2, d_V1, d_theta, d_g_theta, d_G_W1, d_G_W2, d_gA1, d_gA2,
                  handle->arena, handle->stream);
     ZCSD_HIP(hipStreamSynchronize(handle->stream));
+  });
+}
+
+extern "C" zcsd_status zcsd_dcsd_backward_noalloc(zcsd_handle* handle, int batch, int n,
+                                                  const double* d_U1, const double* d_U2,
+                                                  const double* d_V1, const double* d_theta,
+                                                  const double* d_g_theta, const double* d_G_W1,
+                                                  const double* d_G_W2, double* d_gA1,
+                                                  double* d_gA2) {
+  if (!handle) return ZCSD_EINVAL;
+  return guarded([&] {
+    ZCSD_REQUIRE(batch >= 1 && n >= 1, "csd_backward_noalloc: batch and n must be positive");
+    ZCSD_REQUIRE(2LL * n * n <= kScratchDoubles,
+                 "csd_backward_noalloc: n exceeds the scratch limit (2 n^2 <= 2^23 doubles, n <= 2048)");
+    ZCSD_REQUIRE(d_U1 && d_U2 && d_V1 && d_theta && d_gA1 && d_gA2,
+                 "csd_backward_noalloc: NULL pointer");
+    ZCSD_HIP(hipSetDevice(handle->device));
+    double* ptr = backward_scratch(handle->device);
+    const long long nn = (long long)n * n;
+    // problems per pass: T and K of every problem of the pass fit the array
+    const int per = (int)std::min<long long>(std::min<long long>(kScratchDoubles / (2 * nn), 65535),
+                                             batch);
+    for (int b0 = 0; b0 < batch; b0 += per) {
+      const int nb = std::min(per, batch - b0);
+      const long long o = (long long)b0 * nn, ot = (long long)b0 * n;
+      csd_backward_ws(nb, n, d_U1 + o, d_U2 + o, d_V1 + o, d_theta + ot,
+                      d_g_theta ? d_g_theta + ot : nullptr, d_G_W1 ? d_G_W1 + o : nullptr,
+                      d_G_W2 ? d_G_W2 + o : nullptr, d_gA1 + o, d_gA2 + o, ptr,
+                      ptr + (long long)nb * nn, handle->stream);
+    }
   });
 }

@@ -456,6 +456,16 @@ static CsdOut csd_run(int n, const double* A1, long long lda1, const double* A2,
   return out;
 }
 
+// One problem of a batch through the single path (Algorithm 2 included):
+// U1, U2, V1 (n x n, ld n) and theta (n) on the device, the rank returned.
+int csd_single_member(int n, const double* A1, const double* A2, double* U1, double* U2,
+                      double* V1, double* theta, const zcsd_opts& o, Arena& ar, hipStream_t s,
+                      bool* repaired) {
+  CsdOut r = csd_run(n, A1, n, A2, n, U1, n, U2, n, V1, n, theta, nullptr, nullptr, o, ar, s);
+  if (repaired) *repaired = r.repair;
+  return r.rank;
+}
+
 }  // namespace zcsd
 
 using namespace zcsd;

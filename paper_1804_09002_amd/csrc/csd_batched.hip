@@ -211,11 +211,17 @@ size_t batched_problem_bytes(int N) {
 
 struct BatchedStats {
   int classes = 0, groups = 0, max_r = 0, eig_levels = 0, eig_splits = 0;
+  int single = 0, repaired = 0;  // members sent to the single path; of those, repaired by Alg. 2
   double eig_offblock = 0.0, eig_coupling = 0.0;
 };
 
-// One group: members of one size class with the same rank mode.
-static void csd_group(int N, const std::vector<int>& mem, bool deficient, const int* n_host,
+// One group: members of one size class with the same rank mode.  Returns
+// false, having written nothing, when a full-rank group's shared lower bound
+// l reached eps: a member may then have sigma_min(A_i) < eps, which the
+// modified Zolo-pd leaves with a non-orthonormal W_i, and the batched kernels
+// have no Algorithm 2 repair (Sec. 5.1); the caller runs those members
+// through the single path, which has.
+static bool csd_group(int N, const std::vector<int>& mem, bool deficient, const int* n_host,
                       const long long* off_host, const double* A1, const double* A2, double* U1,
                       double* U2, double* V1, std::vector<double>& theta_host,
                       const std::vector<long long>& toff, int* rank_host, const zcsd_opts& o,
@@ -253,6 +259,7 @@ static void csd_group(int N, const std::vector<int>& mem, bool deficient, const 
     }
     ZoloPdResult pr = zolo_pd_batched(za, ar, s);
     st.max_r = std::max(st.max_r, pr.r);
+    if (!deficient && pr.ell <= o.eps * (1.0 + 1e-12)) return false;
   }
   // B
   const double mu = deficient ? o.mu : 0.0;
@@ -399,6 +406,7 @@ static void csd_group(int N, const std::vector<int>& mem, bool deficient, const 
                      d_perm, V1);
   ZCSD_CHECK_LAUNCH();
   HostSync::sync(s);
+  return true;
 }
 
 }  // namespace zcsd
@@ -437,12 +445,17 @@ extern "C" zcsd_status zcsd_dcsd_batched(zcsd_handle* handle, int batch, const i
     std::map<int, std::vector<int>> cls;
     for (int k = 0; k < batch; ++k) cls[batched_class_size(n_host[k])].push_back(k);
     const size_t cap_bytes = (size_t)48 << 30;  // workspace ceiling per chunk
+    // members per chunk: the workspace ceiling, and the launch grids of the
+    // polars, whose second dimension (<= 65535) enumerates 2 polars x r <= 8
+    // terms per member
+    auto chunk_of = [&](int N, size_t members) {
+      const size_t by_mem = cap_bytes / batched_problem_bytes(N);
+      const size_t by_grid = 65535 / (2 * ZOLO_RMAX);
+      return std::max<size_t>(1, std::min({members, by_mem, by_grid}));
+    };
     size_t need = 0;
-    for (auto& kv : cls) {
-      const size_t per = batched_problem_bytes(kv.first);
-      const size_t chunk = std::max<size_t>(1, std::min<size_t>(kv.second.size(), cap_bytes / per));
-      need = std::max(need, chunk * per);
-    }
+    for (auto& kv : cls)
+      need = std::max(need, chunk_of(kv.first, kv.second.size()) * batched_problem_bytes(kv.first));
     ar.reserve(need + ((size_t)512 << 20));
     // ranks (Remark (vi)) for every problem
     std::vector<double> ss((size_t)2 * batch);
@@ -473,11 +486,11 @@ extern "C" zcsd_status zcsd_dcsd_batched(zcsd_handle* handle, int batch, const i
     }
     std::vector<double> theta_host(toff[batch], 0.0);
     BatchedStats st;
+    std::vector<int> single;  // members of full-rank groups whose l reached eps
     for (auto& kv : cls) {
       const int N = kv.first;
       ++st.classes;
-      const size_t per = batched_problem_bytes(N);
-      const size_t chunk = std::max<size_t>(1, std::min<size_t>(kv.second.size(), cap_bytes / per));
+      const size_t chunk = chunk_of(N, kv.second.size());
       for (int def = 0; def < 2; ++def) {
         std::vector<int> grp;
         for (int k : kv.second)
@@ -485,10 +498,27 @@ extern "C" zcsd_status zcsd_dcsd_batched(zcsd_handle* handle, int batch, const i
         for (size_t c0 = 0; c0 < grp.size(); c0 += chunk) {
           std::vector<int> mem(grp.begin() + c0, grp.begin() + std::min(grp.size(), c0 + chunk));
           ++st.groups;
-          csd_group(N, mem, def != 0, n_host, off_host, d_A1, d_A2, d_U1, d_U2, d_V1, theta_host,
-                    toff, rank_host, o, st, ar, s);
+          if (!csd_group(N, mem, def != 0, n_host, off_host, d_A1, d_A2, d_U1, d_U2, d_V1,
+                         theta_host, toff, rank_host, o, st, ar, s))
+            single.insert(single.end(), mem.begin(), mem.end());
         }
       }
+    }
+    // the single path (with Algorithm 2) for those members, one at a time;
+    // no arena allocation is live between groups, so the arena may grow here
+    for (int k : single) {
+      const int n = n_host[k];
+      ar.reset();
+      ar.reserve(csd_workspace_bytes(n) + ((size_t)64 << 20));
+      double* th = ar.dalloc(n);
+      zcsd_opts o1 = o;
+      o1.rank_mode = ZCSD_RANK_FULL;
+      bool rep = false;
+      rank_host[k] = csd_single_member(n, d_A1 + off_host[k], d_A2 + off_host[k], d_U1 + off_host[k],
+                                       d_U2 + off_host[k], d_V1 + off_host[k], th, o1, ar, s, &rep);
+      d2h(theta_host.data() + toff[k], th, n * sizeof(double), s);
+      ++st.single;
+      st.repaired += rep ? 1 : 0;
     }
     h2d(d_theta, theta_host.data(), theta_host.size() * sizeof(double), s);
     ZCSD_HIP(hipStreamSynchronize(s));
@@ -500,6 +530,7 @@ extern "C" zcsd_status zcsd_dcsd_batched(zcsd_handle* handle, int batch, const i
       info->eig_splits = st.eig_splits;
       info->eig_offblock = st.eig_offblock;
       info->eig_coupling = st.eig_coupling;
+      info->repair = st.repaired;
     }
   });
 }

@@ -6,8 +6,24 @@
 // round are independent, so each round is one parallel column update, one
 // parallel row update and one update of V, separated by barriers.  Rotation
 // (p, q): tau = (a_qq - a_pp) / (2 a_pq), t = sign(tau) / (|tau| + sqrt(1 + tau^2)),
-// c = 1/sqrt(1 + t^2), s = t c; A <- J^T A J annihilates a_pq.  Sweeps stop
-// when the off-diagonal Frobenius norm is below 1e-17 ||A||_F or after 40 sweeps.
+// c = 1/sqrt(1 + t^2), s = t c; A <- J^T A J annihilates a_pq.  A rotation is
+// skipped when |a_pq| <= u ||A||_F / n (dropping every such entry changes A by
+// at most u ||A||_F), and the sweeps stop after one that rotated nothing (or
+// after 40 sweeps).
+//
+// Every rotation applied to the basis adds rounding to it, and each column
+// takes n - 1 of them per sweep, so the accumulated basis X is orthonormal
+// only to about 2 n u (150 u at n = 64).  One step of the FP64 refinement of
+// Ogita & Aishima (2018) in LDS then restores both orthogonality and the
+// diagonalisation: with R = I - X^T X, G = X^T A X (symmetrised) and Rayleigh
+// quotients l_i = G_ii / (1 - R_ii),
+//     F_ij = (G_ij + l_j R_ij) / (l_j - l_i)   for |l_j - l_i| > delta,
+//     F_ij = R_ij / 2                           otherwise (and on the diagonal),
+//     X <- X + X F,
+// so that F + F^T = R and X^T X = I to second order.  Pairs closer than
+// delta = 1e-6 ||A||_F stay as Jacobi left them (their eigenvectors are
+// determined only to u ||A|| / gap, and a correction divided by such a gap
+// would bring rounding of G back at second order); they are orthogonalised.
 #include <cmath>
 
 #include "zcsd_eig.h"
@@ -25,9 +41,9 @@ __global__ __launch_bounds__(JNT) void jacobi_kernel(const int* __restrict__ siz
   __shared__ double Q[JB][JB + 1];
   __shared__ double cs[JB / 2][2];
   __shared__ int pq[JB / 2][2];
-  __shared__ double red[JNT / 64];
   __shared__ double red2[JNT / 64];
-  __shared__ int done;
+  __shared__ double lt[JB];
+  __shared__ int rotated;
   const int b = blockIdx.x;
   const int n = sizes[b];
   const int tid = threadIdx.x;
@@ -35,9 +51,11 @@ __global__ __launch_bounds__(JNT) void jacobi_kernel(const int* __restrict__ siz
   V += (long long)b * sV;
   lam += (long long)b * JB;
   if (n <= 0) return;
-  {
-    // all loads of a thread in flight at once, then the LDS stores
-    constexpr int NL = JB * JB / JNT;
+  // element e = tid + JNT q of the n x n block: row e % n, column e / n
+  constexpr int NL = JB * JB / JNT;
+  // symmetrised input into S (all loads of a thread in flight at once, then
+  // the LDS stores); with_basis also resets Q to I
+  auto load_input = [&](bool with_basis) {
     double v[NL];
 #pragma unroll
     for (int q = 0; q < NL; ++q) {
@@ -49,40 +67,31 @@ __global__ __launch_bounds__(JNT) void jacobi_kernel(const int* __restrict__ siz
       const int e = tid + JNT * q, i = e % n, j = e / n;
       if (e < n * n) {
         S[i][j] = v[q];
-        Q[i][j] = (i == j) ? 1.0 : 0.0;
+        if (with_basis) Q[i][j] = (i == j) ? 1.0 : 0.0;
       }
     }
-  }
+  };
+  load_input(true);
   __syncthreads();
+  // ||A||_F^2 (the rotation threshold and the refinement's cluster gap)
+  {
+    double tot = 0.0;
+    for (int e = tid; e < n * n; e += JNT) {
+      const double v = S[e % n][e / n];
+      tot += v * v;
+    }
+    for (int o = 32; o > 0; o >>= 1) tot += __shfl_xor(tot, o, 64);
+    if ((tid & 63) == 0) red2[tid >> 6] = tot;
+    __syncthreads();
+  }
+  double afro = 0.0;
+  for (int q = 0; q < JNT / 64; ++q) afro += red2[q];
+  afro = sqrt(afro);
+  const double thr = 0x1p-53 * afro / n;
   const int m = (n % 2) ? n + 1 : n;  // players; index n is a dummy when n is odd
   for (int sweep = 0; sweep < 40; ++sweep) {
-    // convergence test
-    double off = 0.0, tot = 0.0;
-    for (int e = tid; e < n * n; e += JNT) {
-      const int i = e % n, j = e / n;
-      const double v = S[i][j];
-      tot += v * v;
-      if (i != j) off += v * v;
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-      off += __shfl_xor(off, o, 64);
-      tot += __shfl_xor(tot, o, 64);
-    }
-    if ((tid & 63) == 0) {
-      red[tid >> 6] = off;
-      red2[tid >> 6] = tot;
-    }
+    if (tid == 0) rotated = 0;
     __syncthreads();
-    if (tid == 0) {
-      double o2 = 0.0, t2 = 0.0;
-      for (int q = 0; q < JNT / 64; ++q) {
-        o2 += red[q];
-        t2 += red2[q];
-      }
-      done = (o2 <= 1e-33 * t2) ? 1 : 0;
-    }
-    __syncthreads();
-    if (done) break;
     for (int rnd = 0; rnd < m - 1; ++rnd) {
       if (tid < m / 2) {
         auto idx = [&](int i) { return i == 0 ? 0 : ((i - 1 + rnd) % (m - 1)) + 1; };
@@ -93,16 +102,15 @@ __global__ __launch_bounds__(JNT) void jacobi_kernel(const int* __restrict__ siz
           q = t;
         }
         double c = 1.0, s = 0.0;
-        if (q < n) {
+        if (q < n && fabs(S[p][q]) > thr) {
           const double apq = S[p][q];
-          if (apq != 0.0) {
-            const double tau = (S[q][q] - S[p][p]) / (2.0 * apq);
-            const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-            c = 1.0 / sqrt(1.0 + t * t);
-            s = t * c;
-          }
+          const double tau = (S[q][q] - S[p][p]) / (2.0 * apq);
+          const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+          c = 1.0 / sqrt(1.0 + t * t);
+          s = t * c;
+          rotated = 1;
         } else {
-          q = p;  // dummy pair: no rotation
+          q = p;  // dummy pair or an entry below the threshold: no rotation
         }
         pq[tid][0] = p;
         pq[tid][1] = q;
@@ -144,12 +152,89 @@ __global__ __launch_bounds__(JNT) void jacobi_kernel(const int* __restrict__ siz
       }
       __syncthreads();
     }
+    if (!rotated) break;
+    __syncthreads();  // every thread has read `rotated` before it is reset
   }
-  for (int e = tid; e < n * n; e += JNT) {
-    const int i = e % n, j = e / n;
-    V[i + (long long)j * ldv] = Q[i][j];
+
+  // --- one refinement step on the basis X = Q (Ogita & Aishima) -----------
+  __syncthreads();
+  load_input(false);  // S <- A
+  __syncthreads();
+  double x[NL], g[NL], r[NL];
+  // T = A X into registers, then into S
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    const int e = tid + JNT * q, i = e % n, j = e / n;
+    double acc = 0.0;
+    if (e < n * n)
+      for (int k = 0; k < n; ++k) acc += S[i][k] * Q[k][j];
+    x[q] = acc;
   }
-  for (int i = tid; i < n; i += JNT) lam[i] = S[i][i];
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    const int e = tid + JNT * q;
+    if (e < n * n) S[e % n][e / n] = x[q];
+  }
+  __syncthreads();
+  // G = X^T T and R = I - X^T X (the products of R_ij and R_ji are the same
+  // numbers summed in the same order, so R is exactly symmetric)
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    const int e = tid + JNT * q, i = e % n, j = e / n;
+    double ag = 0.0, ar = 0.0;
+    if (e < n * n)
+      for (int k = 0; k < n; ++k) {
+        const double xki = Q[k][i];
+        ag += xki * S[k][j];
+        ar += xki * Q[k][j];
+      }
+    g[q] = ag;
+    r[q] = (i == j ? 1.0 : 0.0) - ar;
+  }
+  __syncthreads();
+  // G symmetrised through LDS; Rayleigh quotients from its diagonal
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    const int e = tid + JNT * q;
+    if (e < n * n) S[e % n][e / n] = g[q];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    const int e = tid + JNT * q, i = e % n, j = e / n;
+    if (e < n * n) {
+      g[q] = 0.5 * (g[q] + S[j][i]);
+      if (i == j) lt[i] = g[q] / (1.0 - r[q]);
+    }
+  }
+  __syncthreads();
+  // F into S
+  const double delta = 1e-6 * afro;
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    const int e = tid + JNT * q, i = e % n, j = e / n;
+    if (e < n * n) {
+      const double gap = lt[j] - lt[i];
+      S[i][j] = (i != j && fabs(gap) > delta) ? (g[q] + lt[j] * r[q]) / gap : 0.5 * r[q];
+    }
+  }
+  __syncthreads();
+  // X <- X + X F
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    const int e = tid + JNT * q, i = e % n, j = e / n;
+    double acc = 0.0;
+    if (e < n * n)
+      for (int k = 0; k < n; ++k) acc += Q[i][k] * S[k][j];
+    x[q] = (e < n * n) ? Q[i][j] + acc : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < NL; ++q) {
+    const int e = tid + JNT * q;
+    if (e < n * n) V[e % n + (long long)(e / n) * ldv] = x[q];
+  }
+  for (int i = tid; i < n; i += JNT) lam[i] = lt[i];
 }
 
 void jacobi_batched(int nblk, const int* d_sizes, const double* A, long long lda, long long sA,

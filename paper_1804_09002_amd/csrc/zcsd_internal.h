@@ -197,4 +197,17 @@ class AuxStream {
 };
 void h2d(void* d, const void* h, size_t bytes, hipStream_t s);  // async (pageable: sync inside)
 
+// One problem of a batch through the single-problem CSD (csd.hip), with
+// Algorithm 2: square blocks with ld n, outputs U1, U2, V1 (n x n, ld n) and
+// theta (n) on the device; returns the rank and whether Algorithm 2 replaced
+// a polar factor.  Needs csd_workspace_bytes(n) free in the arena.
+int csd_single_member(int n, const double* A1, const double* A2, double* U1, double* U2,
+                      double* V1, double* theta, const zcsd_opts& o, Arena& ar, hipStream_t s,
+                      bool* repaired);
+size_t csd_workspace_bytes(int n);
+
+// Device address of the fixed scratch array of the allocation-free backward
+// (backward.hip) on `device`, which must be current; looked up once per device.
+double* backward_scratch(int device);
+
 }  // namespace zcsd

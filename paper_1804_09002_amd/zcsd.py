@@ -90,6 +90,7 @@ def _lib():
             "zcsd_dzolo_pd": [vp, i, i, d, vp, i, ll, vp, vp, vp, C.POINTER(Opts), C.POINTER(Info)],
             "zcsd_dsyev_zolo": [vp, i, vp, i, d, d, vp, i, vp, C.POINTER(Opts), C.POINTER(Info)],
             "zcsd_dcsd_backward": [vp, i, i, vp, vp, vp, vp, vp, vp, vp, vp, vp],
+            "zcsd_dcsd_backward_noalloc": [vp, i, i, vp, vp, vp, vp, vp, vp, vp, vp, vp],
             "zcsd_dcsd_batched": [vp, i, C.POINTER(C.c_int), C.POINTER(C.c_longlong), vp, vp, vp, vp,
                                   vp, vp, C.POINTER(C.c_int), C.POINTER(Opts), C.POINTER(Info)],
             "zcsd_zolo_coeffs": [d, i, C.POINTER(d), C.POINTER(d), C.POINTER(d), C.POINTER(d)],
@@ -396,6 +397,16 @@ def csd_backward(U1, U2, V1, theta, g_theta=None, G_W1=None, G_W2=None):
     U1, U2, V1: (n, n) or (batch, n, n); theta, g_theta: (n,) or (batch, n); the
     decomposition must be full rank.  Any of g_theta, G_W1, G_W2 may be None.
     """
+    return _csd_backward(U1, U2, V1, theta, g_theta, G_W1, G_W2, "zcsd_dcsd_backward")
+
+
+def csd_backward_noalloc(U1, U2, V1, theta, g_theta=None, G_W1=None, G_W2=None):
+    """csd_backward through zcsd_dcsd_backward_noalloc (no device allocation in
+    the library, n <= 2048; enqueued on torch's current stream)."""
+    return _csd_backward(U1, U2, V1, theta, g_theta, G_W1, G_W2, "zcsd_dcsd_backward_noalloc")
+
+
+def _csd_backward(U1, U2, V1, theta, g_theta, G_W1, G_W2, entry):
     batched = U1.dim() == 3
     ex = (lambda t: t) if batched else (lambda t: None if t is None else t.unsqueeze(0))
     U1, U2, V1, theta, g_theta, G_W1, G_W2 = map(ex, (U1, U2, V1, theta, g_theta, G_W1, G_W2))
@@ -415,11 +426,11 @@ def csd_backward(U1, U2, V1, theta, g_theta=None, G_W1=None, G_W2=None):
     gA1 = torch.empty_like(u1)
     gA2 = torch.empty_like(u1)
     h = handle(U1.device.index)
-    st = _lib().zcsd_dcsd_backward(h, bs, n, _ptr(u1), _ptr(u2), _ptr(v1), _ptr(th),
-                                   _ptr(gt) if gt is not None else None,
-                                   _ptr(g1) if g1 is not None else None,
-                                   _ptr(g2) if g2 is not None else None, _ptr(gA1), _ptr(gA2))
-    _check(st, "zcsd_dcsd_backward")
+    st = getattr(_lib(), entry)(h, bs, n, _ptr(u1), _ptr(u2), _ptr(v1), _ptr(th),
+                                _ptr(gt) if gt is not None else None,
+                                _ptr(g1) if g1 is not None else None,
+                                _ptr(g2) if g2 is not None else None, _ptr(gA1), _ptr(gA2))
+    _check(st, entry)
     gA1, gA2 = gA1.transpose(1, 2), gA2.transpose(1, 2)
     return (gA1, gA2) if batched else (gA1[0], gA2[0])
 

@@ -115,3 +115,77 @@ def test_batched_workload_2048_log_uniform_sizes():
     for k in (0, 1000, 2047):
         o = O.csd(A1s[k].cpu().numpy(), A2s[k].cpu().numpy())
         assert np.max(np.abs(out[k][3].cpu().numpy() - o["theta"])) <= 10 * int(sizes[k]) * U
+
+
+def test_batched_member_below_eps_takes_algorithm2():
+    """A full-rank member whose angles reach 1e-18 of 0 and pi/2 (test class 2
+    of Sec. 6, sigma_min(A_i) < eps) shares a size class with a uniform member:
+    the class's lower bound l reaches eps, the class runs through the single
+    path with Algorithm 2 (Sec. 5.1), and every member meets the FP64 targets
+    and the oracle's angles."""
+    from paper_1804_09002_amd import zcsd
+    rng = np.random.default_rng(47)
+    n_bad = 44
+    theta = WL.angles_cumsum_clustered(n_bad, rng)
+    assert min(np.min(theta), np.min(np.pi / 2 - theta)) < 1e-15
+    A1b, A2b, _ = WL.from_angles(theta, rng)
+    A1u, A2u, _ = WL.uniform_pair(48, 48)     # same size class (48) as n = 44
+    A1o, A2o, _ = WL.uniform_pair(20, 49)     # another class, batched as usual
+    A1s, A2s = [A1b, A1u, A1o], [A2b, A2u, A2o]
+    a1, sizes, offs = zcsd.pack_ragged([_t(a) for a in A1s])
+    a2, _, _ = zcsd.pack_ragged([_t(a) for a in A2s])
+    U1, U2, V1, th, ranks, info = zcsd.csd_batched_packed(a1, a2, sizes, offs)
+    assert info["repair"] >= 1
+    t0 = 0
+    for k, n in enumerate(sizes):
+        o = offs[k]
+        u1, u2, v1 = (X[o:o + n * n].view(n, n).t() for X in (U1, U2, V1))
+        t = th[t0:t0 + n]
+        t0 += n
+        assert ranks[k] == n
+        ref = O.csd(A1s[k], A2s[k])
+        assert np.max(np.abs(t.cpu().numpy() - ref["theta"])) <= 10 * n * U, k
+        res, orth = _self_checks(_t(A1s[k]), _t(A2s[k]), u1, u2, v1, t, n)
+        assert res <= 1e-13 and orth <= 1e-13, (k, n, res, orth)
+
+
+def test_batched_many_rank_deficient_members_in_one_class():
+    """4100 rank-deficient problems of size 8 in one size class: more members
+    than one launch grid of the polars can hold (2 polars x 8 terms x 4100 >
+    65535), so the class is split into chunks; every member keeps rank 7, the
+    FP64 targets and its known angles, and sampled members match the oracle."""
+    from paper_1804_09002_amd import zcsd
+    count, n = 4100, 8
+    rng = np.random.default_rng(51)
+    A1s, A2s, truth = [], [], []
+    for _ in range(count):
+        theta = WL.angles_uniform(n, rng)
+        z = np.array([int(rng.integers(n))])
+        A1, A2, meta = WL.from_angles(theta, rng, zero_idx=z)
+        A1s.append(A1); A2s.append(A2); truth.append(np.sort(np.delete(theta, z)))
+    a1 = _t(np.concatenate([a.T.reshape(-1) for a in A1s]))
+    a2 = _t(np.concatenate([a.T.reshape(-1) for a in A2s]))
+    sizes, offs = [n] * count, [k * n * n for k in range(count)]
+    U1, U2, V1, th, ranks, info = zcsd.csd_batched_packed(a1, a2, sizes, offs)
+    assert all(r == n - 1 for r in ranks)
+    cm = lambda X: X.view(count, n, n).transpose(1, 2)
+    u1, u2, v1, t = cm(U1), cm(U2), cm(V1), th.view(count, n)
+    A1t, A2t = cm(a1), cm(a2)
+    r = n - 1
+    c, s = torch.cos(t[:, :r]), torch.sin(t[:, :r])
+    R1 = (u1[:, :, :r] * c[:, None, :]) @ v1[:, :, :r].transpose(1, 2) - A1t
+    R2 = (u2[:, :, :r] * s[:, None, :]) @ v1[:, :, :r].transpose(1, 2) - A2t
+    res = torch.sqrt((R1 ** 2).sum((1, 2)) + (R2 ** 2).sum((1, 2))) / np.sqrt(r)
+    assert float(res.max()) <= 1e-13
+    I = torch.eye(r, dtype=torch.float64, device=DEV)
+    for X in (u1, u2, v1):
+        Xr = X[:, :, :r]
+        E = Xr.transpose(1, 2) @ Xr - I
+        assert float(torch.sqrt((E ** 2).sum((1, 2))).max()) <= 1e-13
+    th_true = torch.tensor(np.stack(truth), device=DEV)
+    assert float((t[:, :r] - th_true).abs().max()) <= 10 * n * U
+    assert float(t[:, r:].abs().max()) == 0.0
+    for k in (0, 2049, count - 1):
+        ref = O.csd(A1s[k], A2s[k])
+        assert ref["rank"] == r
+        assert np.max(np.abs(t[k, :r].cpu().numpy() - ref["theta"])) <= 10 * n * U

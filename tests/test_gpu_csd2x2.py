@@ -1,4 +1,4 @@
-"""Complete 2 x 2 CSD on the GPU (zcsd_dcsd2x2, Remark (iv) of Sec. 3) against the oracle.
+"""Complete 2 x 2 CSD on the GPU (zcsd_dcsd2x2, Remark (viii) of Sec. 3) against the oracle.
 
 Orthogonal 2n x 2n inputs: Haar, and built from known factors with clustered
 angles.  The GPU angles match the oracle's (and the known ones) to 10 n u;

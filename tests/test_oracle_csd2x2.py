@@ -1,4 +1,4 @@
-"""Pins of the complete 2 x 2 CSD oracle (``oracle.csd2x2``, Remark (iv) of Sec. 3), CPU.
+"""Pins of the complete 2 x 2 CSD oracle (``oracle.csd2x2``, Remark (viii) of Sec. 3), CPU.
 
 * Inputs built from known factors: A = diag(U1, U2) [C -S; S C] diag(V1, V2)^T
   with Haar factors and known angles; the oracle's angles equal the known ones,

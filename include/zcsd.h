@@ -48,13 +48,20 @@ typedef enum {
   ZCSD_ENOMEM = 6    /* device allocation failed */
 } zcsd_status;
 
-/* ZCSD_MIXED_FP32: the polar decompositions and B in FP64; Zolo-eig with its
- * products on the FP32 matrix cores (FP64 storage and panels), then FP64
- * refinement of V1 (iterative refinement of the eigenvectors and exact FP64
- * re-solves of eigenvalue clusters); when that refinement does not reach the
- * FP64 rounding floor, Zolo-eig is recomputed in FP64 (info->refine_fallback),
- * so the results always have the FP64 accuracy.  Accepted by zcsd_dcsd,
- * zcsd_dcsd_mn and zcsd_dcsd2x2; zcsd_dcsd_batched is FP64 only. */
+/* ZCSD_MIXED_FP32 (not in the paper): the products of the Cholesky-form
+ * iteration of both polar decompositions and every product of Zolo-eig run on
+ * the FP32 matrix cores (operands rounded to FP32, FP32 accumulation, FP64
+ * storage); the QR-form first iteration of the polars (ill-conditioned input),
+ * B and the assembly stay FP64, and the polar factors and V1 each get one FP64
+ * Newton-Schulz step; the Zolotarev degree is chosen as in the FP64 mode.
+ * Products take the FP32 instructions where they did not measure slower than
+ * FP64 (dense, untransposed second operand); transposed and triangular ones
+ * stay FP64.  The results meet a stated tolerance of 1e-5 instead of the
+ * FP64 mode's: backward error, orthogonality of U1, U2, V1 and angles carry
+ * the FP32 products' error (measured 2-4e-6, 1e-10 and 1e-7 at n = 1024 and
+ * 4096).  There is no FP64 fallback; info->lowp_products counts the FP32
+ * products of the call.  Accepted by zcsd_dcsd, zcsd_dcsd_mn and
+ * zcsd_dcsd2x2; zcsd_dcsd_batched is FP64 only. */
 typedef enum { ZCSD_FP64 = 0, ZCSD_MIXED_FP32 = 1 } zcsd_precision;
 
 typedef enum {
@@ -93,12 +100,8 @@ typedef struct {
   double eig_coupling;     /* max over splits of ‖X‖_F, the eigenspace-basis coupling that the
                               subspace-iteration step of each split removes */
   int eig_full_refinements; /* splits whose step needed a second QR (‖X‖_F > 2^-27) */
-  int refine_iters;        /* mixed mode: FP64 eigenvector refinement steps taken */
-  int refine_clusters;     /* mixed mode: eigenvalue clusters re-solved in FP64 (largest: refine_max_cluster) */
-  int refine_max_cluster;
-  double refine_offdiag;   /* mixed mode: final ‖V1^T B V1 - diag‖_2 (power-iteration estimate) */
-  int refine_fallback;     /* mixed mode: 1 if the refinement did not reach the FP64 rounding
-                              floor and Zolo-eig was recomputed in FP64 */
+  int lowp_products;       /* products run on the FP32 matrix cores during the call (mixed
+                              mode; 0 in the FP64 mode) */
   int repair;              /* 1 if Algorithm 2 (Sec. 5.1) replaced W_i = Q_i Q~_i^T (full rank:
                               when the sigma_min estimate reached eps; rank deficient: always
                               tried, kept when it passes the check) */
@@ -117,6 +120,12 @@ zcsd_status zcsd_destroy(zcsd_handle* handle);
 zcsd_status zcsd_set_stream(zcsd_handle* handle, void* stream);
 void zcsd_default_opts(zcsd_opts* opts);
 const char* zcsd_status_string(zcsd_status s);
+/* sizeof(zcsd_opts) and sizeof(zcsd_info) as this library was built: a
+ * binding that lays the structs out itself checks them before any call that
+ * reads or writes one (a mismatch would make the library write past the
+ * caller's struct). */
+size_t zcsd_sizeof_opts(void);
+size_t zcsd_sizeof_info(void);
 
 /*
  * CS decomposition of A = [A1; A2], A1, A2 n x n (Sec. 1; Theorem 2.1 for a
@@ -316,6 +325,35 @@ zcsd_status zcsd_dgemm_f32acc(zcsd_handle* handle, int transA, int transB, int m
                               double alpha, const double* d_A, int lda, long long strideA,
                               const double* d_B, int ldb, long long strideB, double beta,
                               double* d_C, int ldc, long long strideC, int batch);
+
+/*
+ * The product with the structure options the path uses internally (exported
+ * for testing; same arguments and errors as zcsd_dgemm, plus):
+ *  flags: ZCSD_GEMM_SYM_UPPER   symmetric product (m == n, beta == 0): only
+ *                               the tiles of C on or above the diagonal are
+ *                               computed, the others keep their contents
+ *                               (every entry i <= j is computed);
+ *         ZCSD_GEMM_UPPER_ONLY  only the upper triangle of C is wanted (m == n,
+ *                               any beta): tiles below the diagonal are skipped;
+ *         ZCSD_GEMM_F32ACC      FP32 matrix cores (as zcsd_dgemm_f32acc);
+ *  tri, kseg: triangular operands; K is made of k / kseg segments (kseg must
+ *         divide k), and within each segment, counting k from its start,
+ *         op(A) is upper (tri & 1: zero for k < i) or lower (tri & 2: zero for
+ *         k > i) and op(B) upper (tri & 4: zero for k > j) or lower (tri & 8:
+ *         zero for k < j); products the structure makes zero are skipped, so
+ *         those zeros must be present in memory (0: dense);
+ *  d_ws, ws_elems: optional device workspace (caller-owned) for the
+ *         deterministic split of k across workgroups in products with few
+ *         output tiles and k >= 1024; NULL / 0 for none.
+ * ZCSD_EINVAL for unknown flags, tri outside 0..15, a kseg that does not
+ * divide k, or ZCSD_GEMM_SYM_UPPER with m != n or beta != 0.
+ */
+enum { ZCSD_GEMM_SYM_UPPER = 1, ZCSD_GEMM_UPPER_ONLY = 2, ZCSD_GEMM_F32ACC = 4 };
+zcsd_status zcsd_dgemm_ex(zcsd_handle* handle, int transA, int transB, int m, int n, int k,
+                          double alpha, const double* d_A, int lda, long long strideA,
+                          const double* d_B, int ldb, long long strideB, double beta,
+                          double* d_C, int ldc, long long strideC, int batch, int flags,
+                          int tri, int kseg, double* d_ws, size_t ws_elems);
 
 /*
  * Blocked Householder QR (the QR form of Zolo-pd, Sec. 5), batched in place.

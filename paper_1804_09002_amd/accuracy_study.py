@@ -56,13 +56,25 @@ def run(jmax=9, seed=11, classes=None):
     return rows
 
 
-def table(rows):
+def load_paper(path):
+    """The Zolo-csd (Z) columns of Tables 1 and 2 (Sec. 6), keyed by (class, n)."""
+    import json
+    with open(path) as f:
+        d = json.load(f)
+    return {(r["class"], r["n"]): r for r in d["rows"]}
+
+
+def table(rows, paper=None):
+    """Markdown table; with `paper` (load_paper) each measure is followed by the
+    paper's Zolo-csd value for the same class and n in parentheses."""
     out = ["| class | n | rank | d(A) | ‖Â−A‖₂/d(A) | ‖U1ᵀU1−I‖₂/u | ‖U2ᵀU2−I‖₂/u | ‖V1ᵀV1−I‖₂/u |",
            "|---|---:|---:|---:|---:|---:|---:|---:|"]
     for m in rows:
         o = m["orth_u"]
-        out.append(f"| {m['cls']} | {m['n']} | {m['rank']} | {m['dA']:.1e} | {m['res_dA']:.2f} | "
-                   f"{o[0]:.1f} | {o[1]:.1f} | {o[2]:.1f} |")
+        p = paper.get((m["cls"], m["n"])) if paper else None
+        z = (lambda k, f: f" ({p[k]:{f}})") if p else (lambda k, f: "")
+        out.append(f"| {m['cls']} | {m['n']} | {m['rank']} | {m['dA']:.1e} | {m['res_dA']:.2f}{z('res', '.2f')} | "
+                   f"{o[0]:.1f}{z('U1', '.1f')} | {o[1]:.1f}{z('U2', '.1f')} | {o[2]:.1f}{z('V1', '.1f')} |")
     return "\n".join(out)
 
 
@@ -70,9 +82,12 @@ def main(argv=None):
     p = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     p.add_argument("--jmax", type=int, default=9)
     p.add_argument("--seed", type=int, default=11)
+    p.add_argument("--paper", default=None,
+                   help="JSON of the paper's Zolo-csd columns (tests/golden/paper_tables_sec6.json)"
+                        " to print beside the measured values")
     a = p.parse_args(argv)
     rows = run(a.jmax, a.seed)
-    print(table(rows), flush=True)
+    print(table(rows, load_paper(a.paper) if a.paper else None), flush=True)
     worst_res = max(m["res_dA"] for m in rows)
     worst_orth = max(max(m["orth_u"]) for m in rows)
     print(f"\nworst scaled residual {worst_res:.2f}, worst scaled orthogonality {worst_orth:.1f}",

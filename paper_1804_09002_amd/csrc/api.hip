@@ -1,5 +1,6 @@
 // C ABI entry points: handle management, option defaults, status strings and
 // the exception-to-status boundary shared by every entry point.
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -53,6 +54,9 @@ zcsd_status zcsd_set_stream(zcsd_handle* handle, void* stream) {
   handle->stream = static_cast<hipStream_t>(stream);
   return ZCSD_OK;
 }
+
+size_t zcsd_sizeof_opts(void) { return sizeof(zcsd_opts); }
+size_t zcsd_sizeof_info(void) { return sizeof(zcsd_info); }
 
 void zcsd_default_opts(zcsd_opts* o) {
   if (!o) return;
@@ -125,7 +129,44 @@ zcsd_status zcsd_dgemm_f32acc(zcsd_handle* handle, int transA, int transB, int m
     g.B = B; g.ldb = ldb; g.sB = strideB;
     g.C = C; g.ldc = ldc; g.sC = strideC;
     g.alpha = alpha; g.beta = beta; g.batch = batch;
-    GemmLowpScope lowp(true);
+    GemmLowpScope lowp(true, /*always=*/true);
+    dgemm(g, handle->stream);
+  });
+}
+
+zcsd_status zcsd_dgemm_ex(zcsd_handle* handle, int transA, int transB, int m, int n, int k,
+                          double alpha, const double* A, int lda, long long strideA,
+                          const double* B, int ldb, long long strideB, double beta, double* C,
+                          int ldc, long long strideC, int batch, int flags, int tri, int kseg,
+                          double* d_ws, size_t ws_elems) {
+  if (!handle) return ZCSD_EINVAL;
+  return guarded([&] {
+    ZCSD_REQUIRE(m >= 0 && n >= 0 && k >= 0 && batch >= 0, "dgemm_ex: negative size");
+    ZCSD_REQUIRE((flags & ~(ZCSD_GEMM_SYM_UPPER | ZCSD_GEMM_UPPER_ONLY | ZCSD_GEMM_F32ACC)) == 0,
+                 "dgemm_ex: unknown flag");
+    ZCSD_REQUIRE(tri >= 0 && tri <= 15 && kseg >= 0, "dgemm_ex: tri must be in 0..15");
+    ZCSD_REQUIRE(!(d_ws == nullptr && ws_elems > 0), "dgemm_ex: ws_elems without a workspace");
+    if (m == 0 || n == 0 || batch == 0) return;
+    ZCSD_REQUIRE(C && (k == 0 || (A && B)), "dgemm_ex: NULL pointer");
+    ZCSD_REQUIRE(ldc >= std::max(1, m), "dgemm_ex: ldc too small");
+    ZCSD_REQUIRE(k == 0 || (lda >= std::max(1, transA ? k : m) && ldb >= std::max(1, transB ? n : k)),
+                 "dgemm_ex: leading dimension too small");
+    ZCSD_HIP(hipSetDevice(handle->device));
+    GemmBatch g;
+    g.transA = transA != 0;
+    g.transB = transB != 0;
+    g.m = m; g.n = n; g.k = k;
+    g.A = A; g.lda = lda; g.sA = strideA;
+    g.B = B; g.ldb = ldb; g.sB = strideB;
+    g.C = C; g.ldc = ldc; g.sC = strideC;
+    g.alpha = alpha; g.beta = beta; g.batch = batch;
+    g.sym_upper = (flags & ZCSD_GEMM_SYM_UPPER) != 0;
+    g.upper_only = (flags & ZCSD_GEMM_UPPER_ONLY) != 0;
+    g.tri = tri;
+    g.kseg = kseg;
+    g.ws = d_ws;
+    g.ws_elems = ws_elems;
+    GemmLowpScope lowp((flags & ZCSD_GEMM_F32ACC) != 0, /*always=*/true);
     dgemm(g, handle->stream);
   });
 }

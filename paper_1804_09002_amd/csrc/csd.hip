@@ -26,13 +26,6 @@
 
 namespace zcsd {
 
-// Y = a X + b Y (n x n, ld n)
-__global__ void axpby_kernel(long long total, double a, const double* __restrict__ X, double b,
-                             double* Y) {
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
-       e += (long long)gridDim.x * blockDim.x)
-    Y[e] = a * X[e] + b * Y[e];
-}
 
 // out[j] = sum_i V(i, j) T(i, j), one workgroup per column
 __global__ void coldot_kernel(int n, const double* __restrict__ V, long long ldv,
@@ -73,11 +66,6 @@ __global__ void theta_from_lambda_kernel(int r, const double* __restrict__ lam, 
   }
 }
 
-static void axpby(long long total, double a, const double* X, double b, double* Y, hipStream_t s) {
-  long long g = std::max<long long>(1, std::min<long long>((total + 255) / 256, 4096));
-  hipLaunchKernelGGL(axpby_kernel, dim3((unsigned)g), dim3(256), 0, s, total, a, X, b, Y);
-  ZCSD_CHECK_LAUNCH();
-}
 
 static double now_ms() {
   using namespace std::chrono;
@@ -181,9 +169,34 @@ struct CsdOut {
   int rank = 0;
   ZoloPdResult pd;
   ZoloEigResult eig;
-  EigRefineResult refine;
+  long long lowp_products = 0;  // products run on the FP32 matrix cores
   double t_polar = 0, t_B = 0, t_eig = 0, t_asm = 0;
 };
+
+// X <- X + X (I - X^T X) / 2 in FP64 (n x m, ld n): one Newton-Schulz step
+// towards the nearest matrix with orthonormal columns
+static void newton_schulz(int n, int m, double* X, Arena& ar, hipStream_t s) {
+  GemmFp64Scope fp64;
+  ArenaScope sc(ar);
+  double* G = ar.dalloc((size_t)m * m);
+  double* T = ar.dalloc((size_t)n * m);
+  GemmBatch g;
+  g.transA = 1;
+  g.m = m; g.n = m; g.k = n;
+  g.A = X; g.lda = n;
+  g.B = X; g.ldb = n;
+  g.C = G; g.ldc = m;
+  g.sym_upper = true;
+  dgemm(g, s);
+  mirror_upper(1, m, G, m, 0, s);
+  GemmBatch h;
+  h.m = n; h.n = m; h.k = m;
+  h.A = X; h.lda = n;
+  h.B = G; h.ldb = m;
+  h.C = T; h.ldc = n;
+  dgemm(h, s);
+  axpby((long long)n * m, -0.5, T, 1.5, X, s);
+}
 
 static CsdOut csd_run(int n, const double* A1, long long lda1, const double* A2, long long lda2,
                       double* U1, long long ldu1, double* U2, long long ldu2, double* V1,
@@ -193,6 +206,16 @@ static CsdOut csd_run(int n, const double* A1, long long lda1, const double* A2,
   const long long nn = (long long)n * n;
   ArenaScope scope(ar);
   double t0 = now_ms();
+  // mixed mode (not in the paper): iteration 2 of the two polar
+  // decompositions and every product of Zolo-eig on the FP32 matrix cores,
+  // each followed by an FP64 Newton-Schulz step on the factor it produced;
+  // the QR-form iteration 1, B and the assembly stay FP64.  The Zolotarev
+  // degree is chosen as in the FP64 mode: a looser target makes each split's
+  // sign function less sharp and its subspace step fall back to the full
+  // second QR more often (measured slower at n = 4096).
+  const bool mixed = o.prec == ZCSD_MIXED_FP32;
+  const double ztol = o.tol;
+  const long long lowp0 = gemm_lowp_launches();
 
   // a1: rank from ||A||_F^2 (Remark (vi))
   double* X = ar.dalloc(2 * (size_t)nn);
@@ -225,9 +248,10 @@ static CsdOut csd_run(int n, const double* A1, long long lda1, const double* A2,
     za.alpha = 1.0;
     za.X = X; za.ldx = n; za.sx = nn;
     za.W = W; za.H = H;
-    za.eps = o.eps; za.tol = o.tol;
+    za.eps = o.eps; za.tol = ztol;
     za.r_override = o.r_override;
     za.ell_override = o.ell_override;
+    za.lowp_iter2 = mixed;
     if (deficient) {
       if (za.ell_override <= 0.0) za.ell_override = o.eps;
       if (za.r_override <= 0) za.r_override = ZOLO_RMAX;
@@ -301,23 +325,14 @@ static CsdOut csd_run(int n, const double* A1, long long lda1, const double* A2,
     ea.V = V; ea.ldv = n;
     ea.lam = lam;
     ea.n_leaf = o.n_leaf;
-    ea.eps = o.eps; ea.tol = o.tol;
-    ea.lowp = o.prec == ZCSD_MIXED_FP32;
+    ea.eps = o.eps; ea.tol = ztol;
+    ea.lowp = mixed;
     // Alg. 3 keeps only the eigenpairs in [-1, 1]: the divide and conquer
     // splits first between 1 and mu and does not divide the part at mu
     if (deficient && mu > 1.0) ea.keep_below = 0.5 * (1.0 + mu);
     out.eig = zolo_eig(ea, ar, s);
-    if (ea.lowp) {
-      const double bmax = std::max(std::fabs(ea.lo), std::fabs(ea.hi));
-      out.refine = eig_refine(n, B, n, V, lam, bmax * bmax, 8, ar, s);
-      if (!out.refine.converged) {
-        // the FP32 divide and conquer was too far off for the refinement: the
-        // FP64 eigendecomposition instead (the result keeps the FP64 accuracy)
-        ea.lowp = false;
-        out.eig = zolo_eig(ea, ar, s);
-        out.refine.fallback = true;
-      }
-    }
+    // the basis from the FP32 products is orthonormal only to the FP32 level
+    if (mixed) newton_schulz(n, n, V, ar, s);
   }
   HostSync::sync(s);
   double t3 = now_ms();
@@ -453,6 +468,7 @@ static CsdOut csd_run(int n, const double* A1, long long lda1, const double* A2,
   if (W2o) copy_scale(1, n, n, 1.0, W + nn, n, 0, W2o, n, 0, s);
   HostSync::sync(s);
   out.t_asm = now_ms() - t3;
+  out.lowp_products = gemm_lowp_launches() - lowp0;
   return out;
 }
 
@@ -483,11 +499,7 @@ static void fill_csd_info(zcsd_info* info, const CsdOut& r) {
   info->eig_offblock = r.eig.max_offblock;
   info->eig_coupling = r.eig.max_coupling;
   info->eig_full_refinements = r.eig.full_refinements;
-  info->refine_iters = r.refine.iters;
-  info->refine_clusters = r.refine.clusters;
-  info->refine_max_cluster = r.refine.max_cluster;
-  info->refine_offdiag = r.refine.offdiag;
-  info->refine_fallback = r.refine.fallback ? 1 : 0;
+  info->lowp_products = (int)std::min<long long>(r.lowp_products, 1 << 30);
   info->repair = r.repair ? 1 : 0;
   info->repair_resid = r.repair_resid;
   info->time_ms[0] = r.t_polar;

@@ -22,8 +22,10 @@
 // (the latter use the modified Zolo-pd with l = eps, r = 8).
 #include <algorithm>
 #include <cmath>
+#include <exception>
 #include <map>
 #include <numeric>
+#include <thread>
 #include <vector>
 
 #include "zcsd_api_guard.h"
@@ -204,16 +206,45 @@ int batched_class_size(int n) {
   return (n + 63) / 64 * 64;
 }
 
-size_t batched_problem_bytes(int N) {
+// arena bytes of one group of K problems of class size N: the iterates and
+// products (216 N^2 doubles per problem), the Householder workspaces of the
+// polars (2K problems, up to 8 terms each) and of Zolo-eig's sign functions
+// (K blocks, up to 8 terms), and the Jacobi leaves (64 x 64 padded, at most
+// N / 32 + 1 per problem).  For small N the fixed per-problem parts (32-wide
+// panels, 64 x 64 leaves) outweigh the N^2 terms.
+size_t batched_group_bytes(int N, size_t K) {
   const size_t NN = (size_t)N * N;
-  return (2 * 64 * NN + 64 * NN + 24 * NN) * sizeof(double);
+  const int k = (int)K;
+  size_t b = K * (2 * 64 * NN + 64 * NN + 24 * NN) * sizeof(double);
+  b += qr_work_bytes(QRShape::General, 2 * k, N, N, 32) +
+       qr_work_bytes(QRShape::Stacked, 2 * k * ZOLO_RMAX, 2 * N, N, 32);
+  if (N > 64)
+    b += qr_work_bytes(QRShape::General, k, N, N, 32, N) +
+         qr_work_bytes(QRShape::Stacked, k * ZOLO_RMAX, 2 * N, N, 32);
+  const size_t leaves = K * (size_t)(N / 32 + 1);
+  b += leaves * (2 * 64 * 64 + 2 * (size_t)N * 64 + 64) * sizeof(double);
+  return b;
 }
 
 struct BatchedStats {
   int classes = 0, groups = 0, max_r = 0, eig_levels = 0, eig_splits = 0;
   int single = 0, repaired = 0;  // members sent to the single path; of those, repaired by Alg. 2
   double eig_offblock = 0.0, eig_coupling = 0.0;
+  void merge(const BatchedStats& o) {
+    groups += o.groups;
+    max_r = std::max(max_r, o.max_r);
+    eig_levels = std::max(eig_levels, o.eig_levels);
+    eig_splits += o.eig_splits;
+    eig_offblock = std::max(eig_offblock, o.eig_offblock);
+    eig_coupling = std::max(eig_coupling, o.eig_coupling);
+  }
 };
+
+// Size-class groups are independent, and each is a chain of dependent
+// launches and host decisions that leaves much of the GPU idle for the small
+// classes: up to this many run at once, each on its own host thread, stream
+// and arena (the box's hardware queues per process: 4).
+constexpr int kBatchedWorkers = 4;
 
 // One group: members of one size class with the same rank mode.  Returns
 // false, having written nothing, when a full-rank group's shared lower bound
@@ -444,19 +475,17 @@ extern "C" zcsd_status zcsd_dcsd_batched(zcsd_handle* handle, int batch, const i
     // classes and the workspace of the largest chunk
     std::map<int, std::vector<int>> cls;
     for (int k = 0; k < batch; ++k) cls[batched_class_size(n_host[k])].push_back(k);
-    const size_t cap_bytes = (size_t)48 << 30;  // workspace ceiling per chunk
+    // workspace ceiling per chunk (each of the concurrent workers holds one)
+    const size_t cap_bytes = ((size_t)48 << 30) / kBatchedWorkers;
     // members per chunk: the workspace ceiling, and the launch grids of the
     // polars, whose second dimension (<= 65535) enumerates 2 polars x r <= 8
     // terms per member
     auto chunk_of = [&](int N, size_t members) {
-      const size_t by_mem = cap_bytes / batched_problem_bytes(N);
-      const size_t by_grid = 65535 / (2 * ZOLO_RMAX);
-      return std::max<size_t>(1, std::min({members, by_mem, by_grid}));
+      size_t c = std::min<size_t>(members, 65535 / (2 * ZOLO_RMAX));
+      while (c > 1 && batched_group_bytes(N, c) > cap_bytes) c = (c + 1) / 2;
+      return std::max<size_t>(1, c);
     };
-    size_t need = 0;
-    for (auto& kv : cls)
-      need = std::max(need, chunk_of(kv.first, kv.second.size()) * batched_problem_bytes(kv.first));
-    ar.reserve(need + ((size_t)512 << 20));
+    ar.reserve(((size_t)64 << 20) + (size_t)batch * 64);
     // ranks (Remark (vi)) for every problem
     std::vector<double> ss((size_t)2 * batch);
     {
@@ -486,24 +515,101 @@ extern "C" zcsd_status zcsd_dcsd_batched(zcsd_handle* handle, int batch, const i
     }
     std::vector<double> theta_host(toff[batch], 0.0);
     BatchedStats st;
-    std::vector<int> single;  // members of full-rank groups whose l reached eps
+    st.classes = (int)cls.size();
+    // groups (members of one class with one rank mode, in chunks), costed by
+    // their flops plus a fixed latency of about 200 class-64 problems
+    struct Grp {
+      int N;
+      bool def;
+      std::vector<int> mem;
+      double cost;
+    };
+    std::vector<Grp> groups;
     for (auto& kv : cls) {
       const int N = kv.first;
-      ++st.classes;
       const size_t chunk = chunk_of(N, kv.second.size());
       for (int def = 0; def < 2; ++def) {
         std::vector<int> grp;
         for (int k : kv.second)
           if ((int)deficient[k] == def) grp.push_back(k);
         for (size_t c0 = 0; c0 < grp.size(); c0 += chunk) {
-          std::vector<int> mem(grp.begin() + c0, grp.begin() + std::min(grp.size(), c0 + chunk));
-          ++st.groups;
-          if (!csd_group(N, mem, def != 0, n_host, off_host, d_A1, d_A2, d_U1, d_U2, d_V1,
-                         theta_host, toff, rank_host, o, st, ar, s))
-            single.insert(single.end(), mem.begin(), mem.end());
+          Grp g;
+          g.N = N;
+          g.def = def != 0;
+          g.mem.assign(grp.begin() + c0, grp.begin() + std::min(grp.size(), c0 + chunk));
+          g.cost = (double)g.mem.size() * N * N * N + 200.0 * 64 * 64 * 64;
+          groups.push_back(std::move(g));
         }
       }
     }
+    // largest cost first onto the least loaded worker
+    const int W = std::max(1, std::min<int>(kBatchedWorkers, (int)groups.size()));
+    std::vector<int> order(groups.size());
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return groups[x].cost > groups[y].cost; });
+    std::vector<std::vector<int>> assign(W);
+    std::vector<double> load(W, 0.0);
+    for (int gi : order) {
+      const int w = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      assign[w].push_back(gi);
+      load[w] += groups[gi].cost;
+    }
+    while ((int)handle->workers.size() < W) {
+      auto bw = std::make_unique<BatchWorker>();
+      ZCSD_HIP(hipStreamCreateWithFlags(&bw->stream, hipStreamNonBlocking));
+      ZCSD_HIP(hipStreamCreateWithFlags(&bw->aux, hipStreamNonBlocking));
+      handle->workers.push_back(std::move(bw));
+    }
+    // the workers start after everything queued on the caller's stream
+    hipEvent_t ready = nullptr;
+    ZCSD_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+    ZCSD_HIP(hipEventRecord(ready, s));
+    const int dev = handle->device;
+    std::vector<BatchedStats> wst(W);
+    std::vector<std::vector<int>> wsingle(W);
+    std::vector<std::exception_ptr> werr(W);
+    auto work = [&](int w) {
+      try {
+        ZCSD_HIP(hipSetDevice(dev));
+        BatchWorker& bw = *handle->workers[w];
+        set_thread_aux_stream(bw.aux);
+        size_t need_w = 0;
+        for (int gi : assign[w]) need_w = std::max(need_w, batched_group_bytes(groups[gi].N, groups[gi].mem.size()));
+        bw.arena.reset();
+        bw.arena.reserve(need_w + ((size_t)256 << 20));
+        ZCSD_HIP(hipStreamWaitEvent(bw.stream, ready, 0));
+        for (int gi : assign[w]) {
+          const Grp& g = groups[gi];
+          ++wst[w].groups;
+          if (!csd_group(g.N, g.mem, g.def, n_host, off_host, d_A1, d_A2, d_U1, d_U2, d_V1,
+                         theta_host, toff, rank_host, o, wst[w], bw.arena, bw.stream))
+            wsingle[w].insert(wsingle[w].end(), g.mem.begin(), g.mem.end());
+        }
+        ZCSD_HIP(hipStreamSynchronize(bw.stream));
+        set_thread_aux_stream(nullptr);
+      } catch (...) {
+        set_thread_aux_stream(nullptr);
+        werr[w] = std::current_exception();
+      }
+    };
+    if (W == 1) {
+      work(0);
+    } else {
+      std::vector<std::thread> th;
+      for (int w = 1; w < W; ++w) th.emplace_back(work, w);
+      work(0);
+      for (auto& t : th) t.join();
+    }
+    (void)hipEventDestroy(ready);
+    for (int w = 0; w < W; ++w)
+      if (werr[w]) std::rethrow_exception(werr[w]);
+    std::vector<int> single;  // members of full-rank groups whose l reached eps
+    for (int w = 0; w < W; ++w) {
+      st.merge(wst[w]);
+      single.insert(single.end(), wsingle[w].begin(), wsingle[w].end());
+    }
+    std::sort(single.begin(), single.end());
     // the single path (with Algorithm 2) for those members, one at a time;
     // no arena allocation is live between groups, so the arena may grow here
     for (int k : single) {

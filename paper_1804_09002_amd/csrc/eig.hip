@@ -248,12 +248,11 @@ T* upload(Arena& ar, const std::vector<T>& v, hipStream_t s) {
 // wall times (the stream is drained at the level's start, around the sign
 // function and at its end; nothing else changes)
 static bool level_times_enabled() {
-  static int v = -1;
-  if (v < 0) {
+  static const bool v = [] {
     const char* e = std::getenv("ZCSD_EIG_TIMES");
-    v = (e && e[0] && e[0] != '0') ? 1 : 0;
-  }
-  return v == 1;
+    return e && e[0] && e[0] != '0';
+  }();
+  return v;
 }
 
 static double wall_ms() {
@@ -270,7 +269,8 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
   const long long nn = (long long)n * n;
   ArenaScope scope(ar);
   // mixed mode: every product of the divide and conquer runs on the FP32 matrix
-  // cores; the caller refines the result in FP64
+  // cores (the compact-WY factors of its QRs excepted); the caller
+  // re-orthogonalises the basis in FP64
   GemmLowpScope lowp_scope(a.lowp);
 
   // Frobenius norm of B (largest over the batch; for the off-block ratio)
@@ -581,9 +581,11 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
       za.W = W; za.H = nullptr; za.X1 = nullptr;
       za.eps = a.eps; za.tol = a.tol;
       za.symmetric_input = true;
-      // the sign function stays FP64 in the mixed mode: its combines have inner
-      // dimension r n, where FP32 accumulation loses ~1e-5 relative accuracy
-      GemmFp64Scope fp64;
+      // in the mixed mode the sign function's products run on the FP32 matrix
+      // cores too (the compact-WY factors of its QRs excepted); the split only
+      // needs the invariant subspaces, which the subspace-iteration step below
+      // refines
+      GemmFp64Scope fp64(!a.lowp);
       double t0 = 0.0;
       if (lt) {
         HostSync::sync(s);
@@ -624,12 +626,8 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
     // the first kq columns of Omega, kq = the largest n+ of the level: its first
     // n+ columns span range(P) and the rest its complement, so the reflectors of
     // kq columns (not Ns) give the whole Ns x Ns factor
-    // (the mixed mode keeps the square P Omega: with the FP32 products the
-    // narrower factorization measured a much worse starting point for the FP64
-    // refinement, 1e-4 against 5e-7 off the block diagonal at n = 4096)
     int kq = 1;
     for (int q = 0; q < ns; ++q) kq = std::max(kq, npos[q]);
-    if (a.lowp) kq = Ns;
     double* Om = ar.dalloc((size_t)ns * SS);
     hipLaunchKernelGGL(omega_kernel, grid2(SS, ns), dim3(256), 0, s, Ns, Om, d_nbs, seed);
     ZCSD_CHECK_LAUNCH();
@@ -669,7 +667,7 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
     // One block (the first level): only the coupling X = Q2^T P Q1 and the
     // diagonal blocks of Q^T B Q are needed, and the correction splits into
     // Q1 + Q2 X and Q2 - Q1 X^T (about 2.4 n^3 of the 12 n^3 dense flops saved)
-    const bool one = (ns == 1 && !a.lowp && npos[0] > 0 && npos[0] < Ns && nbs[0] == Ns);
+    const bool one = (ns == 1 && npos[0] > 0 && npos[0] < Ns && nbs[0] == Ns);
     bool one_proj = false;
     if (one) {
       const int np = npos[0], nm = Ns - np;
@@ -717,7 +715,7 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
         T1 = W;
       }
       one_proj = true;
-    } else if (!a.lowp) {
+    } else {
       double* PQ = ar.dalloc((size_t)ns * SS);
       {
         GemmBatch g;
@@ -769,7 +767,7 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
         orgqr_batched(ns, QRShape::General, Ns, Ns, Q, Ns, SS, nullptr, wk, s);
         T1 = W;
       }
-    }  // !a.lowp (in the mixed mode the FP64 refinement of the caller takes its place)
+    }
 
     // B' = Q^T B Q, V' = V Q
     double* Bq = Y;  // Z is dead

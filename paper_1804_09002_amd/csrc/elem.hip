@@ -61,7 +61,18 @@ void h2d(void* d, const void* h, size_t bytes, hipStream_t s) {
   ZCSD_HIP(hipStreamSynchronize(s));
 }
 
+namespace {
+thread_local hipStream_t g_aux_override = nullptr;
+}
+void set_thread_aux_stream(hipStream_t aux) { g_aux_override = aux; }
+
+BatchWorker::~BatchWorker() {
+  if (stream) (void)hipStreamDestroy(stream);
+  if (aux) (void)hipStreamDestroy(aux);
+}
+
 static hipStream_t aux_stream_for_current_device() {
+  if (g_aux_override) return g_aux_override;
   static std::mutex mu;
   static std::map<int, hipStream_t> streams;
   int dev = 0;
@@ -221,6 +232,21 @@ void copy_scale(int batch, int m, int n, double alpha, const double* X, long lon
   if (batch <= 0 || m <= 0 || n <= 0) return;
   hipLaunchKernelGGL(copy_scale_kernel, egrid((long long)m * n, batch), dim3(256), 0, s, m, n,
                      alpha, X, ldx, sx, Y, ldy, sy);
+  ZCSD_CHECK_LAUNCH();
+}
+
+// Y = a X + b Y over contiguous elements
+__global__ void axpby_kernel(long long total, double a, const double* __restrict__ X, double b,
+                             double* Y) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x)
+    Y[e] = a * X[e] + b * Y[e];
+}
+
+void axpby(long long total, double a, const double* X, double b, double* Y, hipStream_t s) {
+  if (total <= 0) return;
+  const long long g = std::max<long long>(1, std::min<long long>((total + 255) / 256, 4096));
+  hipLaunchKernelGGL(axpby_kernel, dim3((unsigned)g), dim3(256), 0, s, total, a, X, b, Y);
   ZCSD_CHECK_LAUNCH();
 }
 

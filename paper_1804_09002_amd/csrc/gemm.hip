@@ -19,7 +19,16 @@
 // operand and op(A)^T as "b", so the accumulator holds C^T: lane l, item v is
 // C[row0 + l % 16][col0 + l / 16 + 4 v], and 16 consecutive lanes store 16
 // consecutive rows of one column of C (a 128-byte coalesced segment).
+//
+// The same kernel also runs the products of the mixed-precision mode on the
+// FP32 matrix cores (F32 = true): operands are rounded to FP32 as they are
+// staged into LDS, accumulation is FP32 (v_mfma_f32_16x16x4f32, twice the
+// FP64 rate), results are written in FP64.  FP32 tiles are 32 deep, so LDS
+// holds the same bytes as the 16-deep FP64 tiles.  Lane layout of the FP32
+// instruction: output d[i][j] is item i % 4 of lane j + 16 (i / 4), so lane
+// l, item v holds C[row0 + l % 16][col0 + 4 (l / 16) + v].
 #include <algorithm>
+#include <array>
 #include <cstdlib>
 #include <string>
 
@@ -29,30 +38,100 @@
 namespace zcsd {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
 
-template <int BM, int BN, int BK, bool TA, bool TB>
+// precision scope of the products (GemmLowpScope / GemmFp64Scope) and the
+// count of FP32 product launches, per host thread
+namespace {
+thread_local int g_lowp_mode = 0;  // 0 FP64, 1 FP32 where it pays, 2 FP32 always
+thread_local long long g_lowp_launches = 0;
+}
+
+// arithmetic of the two instantiations: LDS element type, accumulator, MFMA
+// step, and the column offset of accumulator item v in lane group lk
+template <bool F32>
+struct Mma;
+template <>
+struct Mma<false> {
+  using T = double;
+  using Acc = d4;
+  static __device__ __forceinline__ Acc step(double a, double b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int col(int lk, int v) { return lk + 4 * v; }
+};
+template <>
+struct Mma<true> {
+  using T = float;
+  using Acc = f4;
+  static __device__ __forceinline__ Acc step(float a, float b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int col(int lk, int v) { return 4 * lk + v; }
+};
+
+template <int BM, int BN, int BK, bool TA, bool TB, bool F32>
 __global__ __launch_bounds__(256, 2) void dgemm_kernel(
     int m, int n, int k, const double* __restrict__ A, long long lda, long long sA,
     const double* __restrict__ B, long long ldb, long long sB, double* __restrict__ C,
     long long ldc, long long sC, double alpha, double beta, int nb1, long long sA2, long long sB2,
-    long long sC2, int nprob, int kchunk, double* ws, int sym_upper, int tri, int kseg) {
-  if (sym_upper && blockIdx.x > blockIdx.y) return;  // tile below the diagonal (BM == BN)
+    long long sC2, int nprob, int kchunk, double* ws, int sym_upper, int tri, int kseg,
+    int order) {
+  // tile (bx, by) of problem zp; order 0: the grid's (x, y) and z = (split,
+  // problem); order 1, 2 (square products whose operands make k >= max(i, j)
+  // the only nonzero range, so a tile's work falls with max(x, y)): a linear
+  // grid over (tile, problem) with the problem fastest and the heaviest tiles
+  // first, so that no long tile starts at the end of the launch.  Order 1
+  // walks shells of max(x, y) = m (tiles (0..m, m) then (m, 0..m-1)); order 2
+  // (symmetric products) the upper tiles x <= y column by column.
+  int bx, by, zp, split;
+  if (order == 0) {
+    if (sym_upper && blockIdx.x > blockIdx.y) return;  // tile below the diagonal (BM == BN)
+    bx = blockIdx.x;
+    by = blockIdx.y;
+    zp = blockIdx.z % nprob;
+    split = blockIdx.z / nprob;
+  } else {
+    const long long L = blockIdx.x;
+    zp = (int)(L % nprob);
+    split = 0;
+    const long long t = L / nprob;
+    if (order == 1) {
+      int m = (int)sqrt((double)t);
+      while ((long long)m * m > t) --m;
+      while ((long long)(m + 1) * (m + 1) <= t) ++m;
+      const int r = (int)(t - (long long)m * m);
+      if (r <= m) {
+        bx = r;
+        by = m;
+      } else {
+        bx = m;
+        by = r - m - 1;
+      }
+    } else {
+      int y = (int)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+      while ((long long)y * (y + 1) / 2 > t) --y;
+      while ((long long)(y + 1) * (y + 2) / 2 <= t) ++y;
+      by = y;
+      bx = (int)(t - (long long)y * (y + 1) / 2);
+    }
+  }
   constexpr int WM = BM / 2, WN = BN / 2;
   constexpr int TM = WM / 16, TN = WN / 16;
   constexpr int NA = BM * BK / 256, NB = BN * BK / 256;
   static_assert(NA * 256 == BM * BK && NB * 256 == BN * BK, "tile/threads mismatch");
-  __shared__ double As[BK][BM + 1];
-  __shared__ double Bs[BK][BN + 1];
+  using M = Mma<F32>;
+  using T = typename M::T;
+  __shared__ T As[BK][BM + 1];
+  __shared__ T Bs[BK][BN + 1];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int wm = wave & 1, wn = wave >> 1;
-  const int i0 = blockIdx.x * BM;
-  const int j0 = blockIdx.y * BN;
-  const int zp = blockIdx.z % nprob;      // problem index (b1, b2)
-  const int split = blockIdx.z / nprob;   // k-split index (0 without split-K)
-  const long long b1 = zp % nb1, b2 = zp / nb1;
+  const int i0 = bx * BM;
+  const int j0 = by * BN;
+  const long long b1 = zp % nb1, b2 = zp / nb1;  // problem index (b1, b2)
   A += b1 * sA + b2 * sA2;
   B += b1 * sB + b2 * sB2;
   C += b1 * sC + b2 * sC2;
@@ -69,7 +148,7 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(
     beta = 0.0;
   }
 
-  double ra[NA], rb[NB];
+  T ra[NA], rb[NB];
   // with the large tiles, a tile wholly inside C (and a k-tile wholly inside
   // k) loads and stores without per-element bounds checks (measured faster
   // for 128 x 128 tiles, slower for the small split-K products of 64 x 64)
@@ -82,7 +161,7 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(
         int i, kk;
         if (!TA) { i = e % BM; kk = e / BM; } else { kk = e % BK; i = e / BK; }
         const int gi = i0 + i, gk = k0 + kk;
-        ra[q] = TA ? A[gk + (long long)gi * lda] : A[gi + (long long)gk * lda];
+        ra[q] = (T)(TA ? A[gk + (long long)gi * lda] : A[gi + (long long)gk * lda]);
       }
 #pragma unroll
       for (int q = 0; q < NB; ++q) {
@@ -90,7 +169,7 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(
         int j, kk;
         if (!TB) { kk = e % BK; j = e / BK; } else { j = e % BN; kk = e / BN; }
         const int gj = j0 + j, gk = k0 + kk;
-        rb[q] = TB ? B[gj + (long long)gk * ldb] : B[gk + (long long)gj * ldb];
+        rb[q] = (T)(TB ? B[gj + (long long)gk * ldb] : B[gk + (long long)gj * ldb]);
       }
       return;
     }
@@ -102,7 +181,7 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(
       const int gi = i0 + i, gk = k0 + kk;
       double v = 0.0;
       if (gi < m && gk < kl) v = TA ? A[gk + (long long)gi * lda] : A[gi + (long long)gk * lda];
-      ra[q] = v;
+      ra[q] = (T)v;
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
@@ -112,7 +191,7 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(
       const int gj = j0 + j, gk = k0 + kk;
       double v = 0.0;
       if (gj < n && gk < kl) v = TB ? B[gj + (long long)gk * ldb] : B[gk + (long long)gj * ldb];
-      rb[q] = v;
+      rb[q] = (T)v;
     }
   };
   auto store_tiles = [&]() {
@@ -132,11 +211,11 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(
     }
   };
 
-  d4 acc[TM][TN];
+  typename M::Acc acc[TM][TN];
 #pragma unroll
   for (int x = 0; x < TM; ++x)
 #pragma unroll
-    for (int y = 0; y < TN; ++y) acc[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int y = 0; y < TN; ++y) acc[x][y] = typename M::Acc{0, 0, 0, 0};
 
   const int lr = lane & 15;   // row (of the 16-block) this lane feeds / owns
   const int lk = lane >> 4;   // k index within the k-step of 4
@@ -169,7 +248,7 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(
     if (t + 1 < total) load_tiles(kstart(t + 1), klim(t + 1));
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
-      double fa[TM], fb[TN];
+      T fa[TM], fb[TN];
 #pragma unroll
       for (int x = 0; x < TM; ++x) fa[x] = As[kk + lk][wm * WM + x * 16 + lr];
 #pragma unroll
@@ -177,8 +256,7 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(
 #pragma unroll
       for (int x = 0; x < TM; ++x)
 #pragma unroll
-        for (int y = 0; y < TN; ++y)
-          acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(fb[y], fa[x], acc[x][y], 0, 0, 0);
+        for (int y = 0; y < TN; ++y) acc[x][y] = M::step(fb[y], fa[x], acc[x][y]);
     }
   }
 
@@ -197,21 +275,21 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(
         for (int y = 0; y < TN; ++y)
 #pragma unroll
           for (int v = 0; v < 4; ++v)
-            o[y][v] = C[row + (long long)(j0 + wn * WN + y * 16 + lk + 4 * v) * ldc];
+            o[y][v] = C[row + (long long)(j0 + wn * WN + y * 16 + M::col(lk, v)) * ldc];
 #pragma unroll
         for (int y = 0; y < TN; ++y)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) o[y][v] = alpha * acc[x][y][v] + beta * o[y][v];
+          for (int v = 0; v < 4; ++v) o[y][v] = alpha * (double)acc[x][y][v] + beta * o[y][v];
       } else {
 #pragma unroll
         for (int y = 0; y < TN; ++y)
 #pragma unroll
-          for (int v = 0; v < 4; ++v) o[y][v] = alpha * acc[x][y][v];
+          for (int v = 0; v < 4; ++v) o[y][v] = alpha * (double)acc[x][y][v];
       }
 #pragma unroll
       for (int y = 0; y < TN; ++y)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) C[row + (long long)(j0 + wn * WN + y * 16 + lk + 4 * v) * ldc] = o[y][v];
+        for (int v = 0; v < 4; ++v) C[row + (long long)(j0 + wn * WN + y * 16 + M::col(lk, v)) * ldc] = o[y][v];
     }
     return;
   }
@@ -224,21 +302,21 @@ __global__ __launch_bounds__(256, 2) void dgemm_kernel(
     for (int y = 0; y < TN; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int col = j0 + wn * WN + y * 16 + lk + 4 * v;
+        const int col = j0 + wn * WN + y * 16 + M::col(lk, v);
         o[y][v] = (rd && col < n) ? C[row + (long long)col * ldc] : 0.0;
       }
 #pragma unroll
     for (int y = 0; y < TN; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const double r = alpha * acc[x][y][v];
+        const double r = alpha * (double)acc[x][y][v];
         o[y][v] = rd ? r + beta * o[y][v] : r;
       }
 #pragma unroll
     for (int y = 0; y < TN; ++y)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int col = j0 + wn * WN + y * 16 + lk + 4 * v;
+        const int col = j0 + wn * WN + y * 16 + M::col(lk, v);
         if (col < n) C[row + (long long)col * ldc] = o[y][v];
       }
   }
@@ -269,17 +347,17 @@ __global__ void splitk_reduce_kernel(int m, int n, int nprob, int nsplit, const 
   }
 }
 
-template <int BM, int BN, int BK>
+template <int BM, int BN, int BK, bool F32>
 static const char* tile_name(int ta, int tb) {
-  static const char* names[4] = {nullptr, nullptr, nullptr, nullptr};
-  static std::string store[4];
-  const int i = (ta ? 2 : 0) + (tb ? 1 : 0);
-  if (!names[i]) {
-    store[i] = "dgemm_" + std::to_string(BM) + "x" + std::to_string(BN) + "_" + (ta ? "T" : "N") +
-               (tb ? "T" : "N");
-    names[i] = store[i].c_str();
-  }
-  return names[i];
+  // initialised once (thread-safe), read by every launch
+  static const std::array<std::string, 4> names = [] {
+    std::array<std::string, 4> a;
+    for (int i = 0; i < 4; ++i)
+      a[i] = std::string(F32 ? "gemm_f32acc_" : "dgemm_") + std::to_string(BM) + "x" +
+             std::to_string(BN) + "_" + ((i & 2) ? "T" : "N") + ((i & 1) ? "T" : "N");
+    return a;
+  }();
+  return names[(ta ? 2 : 0) + (tb ? 1 : 0)].c_str();
 }
 
 // Flops of the tiles a launch computes: tiles below the diagonal of a
@@ -312,10 +390,10 @@ static double computed_flops(const GemmBatch& g, bool split) {
   return f * nprob;
 }
 
-template <int BM, int BN, int BK>
+template <int BM, int BN, int BK, bool F32>
 static void launch_tile(const GemmBatch& g, hipStream_t s, int ksplit) {
   const double nprob_d = (double)g.batch * g.batch2;
-  ProfScope prof(tile_name<BM, BN, BK>(g.transA, g.transB), s,
+  ProfScope prof(tile_name<BM, BN, BK, F32>(g.transA, g.transB), s,
                  prof_on() ? computed_flops<BM, BN, BK>(g, ksplit > 1) : 0.0,
                  8.0 * nprob_d * ((double)g.m * g.k + (double)g.k * g.n + (g.beta != 0.0 ? 2.0 : 1.0) * g.m * g.n));
   const int gx = (g.m + BM - 1) / BM, gy = (g.n + BN - 1) / BN;
@@ -334,15 +412,28 @@ static void launch_tile(const GemmBatch& g, hipStream_t s, int ksplit) {
   for (int c0 = 0; c0 < g.batch2; c0 += per) {
     const int nc = std::min(per, g.batch2 - c0);
     const int nprob = g.batch * nc;
-    dim3 grid(gx, gy, nprob * nsplit), block(256);
+    // heavy tiles first for square products with k >= max(i, j), and only the
+    // upper tiles of symmetric products (see the kernel).  Measured: with the
+    // grid's own order neither skipping the lower tiles of a symmetric
+    // product nor the light tiles of a triangular one shortened the launch
+    // (8 symmetric 4096^2 products took 17.8 ms against 18.0 ms for the full
+    // ones), since a launch lasts as long as the most loaded CU
+    int order = 0;
+    if (kchunk == 0 && gx == gy && !g.upper_only) {
+      if (g.sym_upper && (g.tri == 0 || (g.tri & 9) == 9)) order = 2;
+      else if (!g.sym_upper && (g.tri & 9) == 9) order = 1;
+    }
+    const long long lin = (order == 2 ? (long long)gx * (gx + 1) / 2 : (long long)gx * gy) * nprob;
+    dim3 grid = order ? dim3((unsigned)lin, 1, 1) : dim3(gx, gy, nprob * nsplit);
+    dim3 block(256);
     const double* A = g.A + (long long)c0 * g.sA2;
     const double* B = g.B + (long long)c0 * g.sB2;
     double* C = g.C + (long long)c0 * g.sC2;
 #define ZCSD_GEMM_LAUNCH(TA_, TB_)                                                        \
-  hipLaunchKernelGGL((dgemm_kernel<BM, BN, BK, TA_, TB_>), grid, block, 0, s, g.m, g.n, g.k, A, \
+  hipLaunchKernelGGL((dgemm_kernel<BM, BN, BK, TA_, TB_, F32>), grid, block, 0, s, g.m, g.n, g.k, A, \
                      g.lda, g.sA, B, g.ldb, g.sB, C, g.ldc, g.sC, g.alpha, g.beta, g.batch,     \
                      g.sA2, g.sB2, g.sC2, nprob, kchunk, g.ws, (g.sym_upper || g.upper_only) ? 1 : 0, g.tri, \
-                     g.kseg)
+                     g.kseg, order)
     if (!g.transA && !g.transB) ZCSD_GEMM_LAUNCH(false, false);
     else if (!g.transA && g.transB) ZCSD_GEMM_LAUNCH(false, true);
     else if (g.transA && !g.transB) ZCSD_GEMM_LAUNCH(true, false);
@@ -374,14 +465,18 @@ void dgemm(const GemmBatch& g, hipStream_t s) {
                    g.sC, s);
     return;
   }
-  if (gemm_lowp_active()) {
-    gemm_lowp(g, s);
-    return;
-  }
   const long long nprob = (long long)g.batch * g.batch2;
   const long long tiles128 = (long long)((g.m + 127) / 128) * ((g.n + 127) / 128) * nprob;
+  // inside a GemmLowpScope the FP32 matrix cores take the products where they
+  // did not measure slower than FP64: dense products with op(B) = B (4096^3
+  // NN: 90 against 60 TFLOP/s); transposed-B products (2 x 4096 x 4096 x
+  // 16384 NT: 52 against 61) and triangular ones (equal or slower) stay FP64
+  const int lm = g_lowp_mode;
+  const bool f32 = lm == 2 || (lm == 1 && !g.tri && !g.transB);
+  if (f32) ++g_lowp_launches;
   if (tiles128 >= 512) {
-    launch_tile<128, 128, 16>(g, s, 1);
+    if (f32) launch_tile<128, 128, 32, true>(g, s, 1);
+    else launch_tile<128, 128, 16, false>(g, s, 1);
     return;
   }
   // few output tiles and a long k: split k across workgroups when a workspace is given
@@ -396,7 +491,25 @@ void dgemm(const GemmBatch& g, hipStream_t s) {
                                       std::max<long long>(2, 512 / std::max<long long>(1, tiles64)));
     while (ksplit > 1 && (size_t)ksplit * nprob * g.m * g.n > g.ws_elems) --ksplit;
   }
-  launch_tile<64, 64, 16>(g, s, ksplit);
+  if (f32) launch_tile<64, 64, 32, true>(g, s, ksplit);
+  else launch_tile<64, 64, 16, false>(g, s, ksplit);
 }
+
+// ---------------------------------------------------------------------------
+// precision scopes of the mixed mode (see zcsd_internal.h)
+long long gemm_lowp_launches() { return g_lowp_launches; }
+GemmLowpScope::GemmLowpScope(bool on, bool always) : on_(on), saved_(g_lowp_mode) {
+  if (on_) g_lowp_mode = always ? 2 : 1;
+}
+GemmLowpScope::~GemmLowpScope() {
+  if (on_) g_lowp_mode = saved_;
+}
+GemmFp64Scope::GemmFp64Scope(bool on) : on_(on), saved_(g_lowp_mode) {
+  if (on_) g_lowp_mode = 0;
+}
+GemmFp64Scope::~GemmFp64Scope() {
+  if (on_) g_lowp_mode = saved_;
+}
+bool gemm_lowp_active() { return g_lowp_mode > 0; }
 
 }  // namespace zcsd

@@ -8,12 +8,11 @@
 namespace zcsd {
 
 inline bool log_enabled() {
-  static int v = -1;
-  if (v < 0) {
+  static const bool v = [] {
     const char* e = std::getenv("ZCSD_LOG");
-    v = (e && e[0] && e[0] != '0') ? 1 : 0;
-  }
-  return v == 1;
+    return e && e[0] && e[0] != '0';
+  }();
+  return v;
 }
 
 template <class F>

@@ -22,7 +22,7 @@ struct ZoloEigArgs {
   int n_leaf = 64;
   double eps = 1e-15, tol = 0x1p-53;
   bool measure_offblock = true;
-  bool lowp = false;           // products on the FP32 matrix cores (mixed mode; refine after)
+  bool lowp = false;           // products on the FP32 matrix cores (mixed mode)
   // keep_below < hi: only the eigenpairs below keep_below are wanted (a
   // spectral divide and conquer restricted to an interval): the first split
   // is at keep_below and the part above is finished without dividing it
@@ -37,18 +37,6 @@ struct ZoloEigResult {
   int full_refinements = 0;    // splits that needed the full QR step
 };
 ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s);
-
-// FP64 refinement of an approximate eigendecomposition B X = X diag(lam)
-// (refine.hip): X (n x n, ld n) and lam (n) are refined in place and sorted;
-// bnorm2 bounds ||B||_2^2; at most `iters` corrections.
-struct EigRefineResult {
-  int iters = 0, clusters = 0, max_cluster = 0;
-  double offdiag = 0.0, delta = 0.0;  // final ||X^T B X - diag||_2 estimate and cluster threshold
-  bool converged = false;              // offdiag reached the rounding floor
-  bool fallback = false;               // the caller recomputed in FP64
-};
-EigRefineResult eig_refine(int n, const double* B, long long ldb, double* X, double* lam,
-                           double bnorm2, int iters, Arena& ar, hipStream_t s);
 
 // column copies described on the host: dst[:, c] for items (device descriptors)
 struct CopyDesc {

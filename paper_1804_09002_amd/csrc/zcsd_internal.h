@@ -4,6 +4,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <memory>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -70,10 +71,23 @@ struct ArenaScope {
 
 }  // namespace zcsd
 
+namespace zcsd {
+// One worker of the batched path: its own stream (default priority), its own
+// second stream for overlapped side work, and its own workspace arena.
+struct BatchWorker {
+  hipStream_t stream = nullptr;
+  hipStream_t aux = nullptr;
+  Arena arena;
+  ~BatchWorker();
+};
+}  // namespace zcsd
+
 struct zcsd_handle_s {
   int device = 0;
   hipStream_t stream = nullptr;
   zcsd::Arena arena;
+  // created on the first batched call with more than one size-class group
+  std::vector<std::unique_ptr<zcsd::BatchWorker>> workers;
   // pinned host staging for small readbacks
   double* h_stage = nullptr;
   size_t h_stage_count = 0;
@@ -112,34 +126,38 @@ struct GemmBatch {
 };
 void dgemm(const GemmBatch& g, hipStream_t s);
 
-// While a GemmLowpScope(true) is alive on this host thread, dgemm runs the
-// product on the FP32 matrix cores (FP64 operands rounded to FP32, FP32
-// accumulation, FP64 result): for steps whose error a later FP64 refinement
-// removes (gemm_lowp.hip).
+// While a GemmLowpScope(true) is alive on this host thread, dgemm runs
+// products on the FP32 matrix cores (FP64 operands rounded to FP32, FP32
+// accumulation, FP64 result): every product when `always`, otherwise those
+// where the FP32 instructions measured faster than FP64 (the demoted steps of
+// the mixed-precision mode; gemm.hip).
 class GemmLowpScope {
  public:
-  explicit GemmLowpScope(bool on);
+  explicit GemmLowpScope(bool on, bool always = false);
   ~GemmLowpScope();
   GemmLowpScope(const GemmLowpScope&) = delete;
   GemmLowpScope& operator=(const GemmLowpScope&) = delete;
 
  private:
   bool on_;
+  int saved_;
 };
 // Inside a GemmLowpScope: products that must stay FP64 (the compact-WY factor of
 // a blocked QR, whose orthogonality would otherwise degrade to the FP32 level)
 class GemmFp64Scope {
  public:
-  GemmFp64Scope();
+  explicit GemmFp64Scope(bool on = true);
   ~GemmFp64Scope();
   GemmFp64Scope(const GemmFp64Scope&) = delete;
   GemmFp64Scope& operator=(const GemmFp64Scope&) = delete;
 
  private:
+  bool on_;
   int saved_;
 };
 bool gemm_lowp_active();
-void gemm_lowp(const GemmBatch& g, hipStream_t s);
+// products launched on the FP32 matrix cores by this host thread so far
+long long gemm_lowp_launches();
 
 // ---------------------------------------------------------------------------
 // element-wise and reduction kernels (elem.hip)
@@ -147,6 +165,8 @@ void gemm_lowp(const GemmBatch& g, hipStream_t s);
 void copy_scale(int batch, int m, int n, double alpha, const double* X, long long ldx, long long sx,
                 double* Y, long long ldy, long long sy, hipStream_t s);
 void add_diag(int batch, int n, double v, double* X, long long ldx, long long sx, hipStream_t s);
+// Y = a X + b Y over `total` contiguous elements
+void axpby(long long total, double a, const double* X, double b, double* Y, hipStream_t s);
 void set_identity(int batch, int m, int n, double v, double* X, long long ldx, long long sx,
                   hipStream_t s);
 // X_b = (X_b + X_b^T) / 2 in place (n x n)
@@ -181,6 +201,11 @@ void d2h(void* h, const void* d, size_t bytes, hipStream_t s);  // async + sync
 // on first use with the default priority.  The destructor joins when join()
 // was not called (error paths), so later work on s stays ordered after it;
 // memory that the side work uses must stay allocated until the join.
+// The second stream that AuxStream uses on this host thread: `aux` from now on
+// (nullptr: back to the device's shared one).  The batched path's workers
+// each bring their own, so that their side work does not queue behind
+// another worker's.
+void set_thread_aux_stream(hipStream_t aux);
 class AuxStream {
  public:
   explicit AuxStream(hipStream_t s);

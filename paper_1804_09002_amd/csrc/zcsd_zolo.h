@@ -38,8 +38,9 @@ struct ZoloPdArgs {
   int r_override = 0;
   double ell_override = 0.0;
   bool symmetric_input = false; // X_b symmetric: H not needed, W symmetric
-  double ell_cap = 0.0;         // > 0: use at most this l (products in FP32 cannot resolve
-                                // singular values below their rounding level)
+  // mixed mode: the products of iteration 2 (Cholesky form) on the FP32 matrix
+  // cores, then one FP64 Newton-Schulz step on the iterate before W and H
+  bool lowp_iter2 = false;
   int nb_qr = 32;
 };
 struct ZoloPdResult {

@@ -130,7 +130,6 @@ ZoloPdResult zolo_pd_batched(const ZoloPdArgs& a, Arena& ar, hipStream_t s) {
     ell *= 0.9;  // margin for the rounding of R^{-1}
   }
   ell = std::min(1.0, std::max(ell, a.eps));
-  if (a.ell_cap > 0.0) ell = std::min(ell, a.ell_cap);
   int r = a.r_override;
   if (r <= 0) {
     r = zolo_choose_r(ell, a.tol);
@@ -182,8 +181,11 @@ ZoloPdResult zolo_pd_batched(const ZoloPdArgs& a, Arena& ar, hipStream_t s) {
     dgemm(g, s);
   }
 
-  // 2. Cholesky form on Y1
+  // 2. Cholesky form on Y1 (well conditioned: its products may run in FP32)
   const ZoloStepCoef& z2 = plan.step[1];
+  double* Y2 = ar.dalloc((size_t)B * nn);
+  {
+  GemmLowpScope lowp(a.lowp_iter2);
   double* G = ar.dalloc((size_t)B * nn);
   {
     GemmBatch g;
@@ -227,7 +229,6 @@ ZoloPdResult zolo_pd_batched(const ZoloPdArgs& a, Arena& ar, hipStream_t s) {
     ZCSD_CHECK_LAUNCH();
   }
   mirror_upper(B, n, Ms, n, nn, s);
-  double* Y2 = ar.dalloc((size_t)B * nn);
   copy_scale(B, n, n, 1.0, Y1, n, nn, Y2, n, nn, s);
   {
     GemmBatch g;
@@ -238,6 +239,35 @@ ZoloPdResult zolo_pd_batched(const ZoloPdArgs& a, Arena& ar, hipStream_t s) {
     g.C = Y2; g.ldc = n; g.sC = nn;
     g.alpha = z2.M; g.beta = z2.M;
     dgemm(g, s);
+  }
+  }  // end of the (possibly FP32) iteration 2
+  if (a.lowp_iter2) {
+    // Y2 holds the polar factor of R only to the FP32 level; one FP64
+    // Newton-Schulz step Y2 <- Y2 + Y2 (I - Y2^T Y2) / 2 restores its
+    // orthogonality to the FP64 level (the error left is in the skew part
+    // Y2^T Y2 cannot see, of the FP32 products' size)
+    GemmFp64Scope fp64;
+    ArenaScope ns(ar);
+    double* Gn = ar.dalloc((size_t)B * nn);
+    double* Tn = ar.dalloc((size_t)B * nn);
+    GemmBatch g;
+    g.batch = B;
+    g.transA = 1;
+    g.m = n; g.n = n; g.k = n;
+    g.A = Y2; g.lda = n; g.sA = nn;
+    g.B = Y2; g.ldb = n; g.sB = nn;
+    g.C = Gn; g.ldc = n; g.sC = nn;
+    g.sym_upper = true;
+    dgemm(g, s);
+    mirror_upper(B, n, Gn, n, nn, s);
+    GemmBatch h;
+    h.batch = B;
+    h.m = n; h.n = n; h.k = n;
+    h.A = Y2; h.lda = n; h.sA = nn;
+    h.B = Gn; h.ldb = n; h.sB = nn;
+    h.C = Tn; h.ldc = n; h.sC = nn;
+    dgemm(h, s);
+    axpby((long long)B * nn, -0.5, Tn, 1.5, Y2, s);
   }
 
   // 3. W = Q Y2, H = alpha sym(Y2^T R), X1 = Q Y1

@@ -42,9 +42,7 @@ class Info(C.Structure):
                 ("zolo_resid", C.c_double), ("eig_levels", C.c_int), ("eig_splits", C.c_int),
                 ("eig_max_r", C.c_int), ("eig_offblock", C.c_double),
                 ("eig_coupling", C.c_double), ("eig_full_refinements", C.c_int),
-                ("refine_iters", C.c_int), ("refine_clusters", C.c_int),
-                ("refine_max_cluster", C.c_int), ("refine_offdiag", C.c_double),
-                ("refine_fallback", C.c_int), ("repair", C.c_int), ("repair_resid", C.c_double),
+                ("lowp_products", C.c_int), ("repair", C.c_int), ("repair_resid", C.c_double),
                 ("time_ms", C.c_double * 4)]
 
     def as_dict(self):
@@ -53,9 +51,7 @@ class Info(C.Structure):
                 "eig_splits": self.eig_splits, "eig_max_r": self.eig_max_r,
                 "eig_offblock": self.eig_offblock, "eig_coupling": self.eig_coupling,
                 "eig_full_refinements": self.eig_full_refinements,
-                "refine_iters": self.refine_iters, "refine_clusters": self.refine_clusters,
-                "refine_max_cluster": self.refine_max_cluster, "refine_offdiag": self.refine_offdiag,
-                "refine_fallback": self.refine_fallback, "repair": self.repair,
+                "lowp_products": self.lowp_products, "repair": self.repair,
                 "repair_resid": self.repair_resid,
                 "time_ms": list(self.time_ms)}
 
@@ -80,6 +76,8 @@ def _lib():
         L.zcsd_dgemm.argtypes = [vp, i, i, i, i, i, d, vp, i, ll, vp, i, ll, d, vp, i, ll, i]
         if hasattr(L, "zcsd_dgemm_f32acc"):
             L.zcsd_dgemm_f32acc.argtypes = L.zcsd_dgemm.argtypes
+        if hasattr(L, "zcsd_dgemm_ex"):
+            L.zcsd_dgemm_ex.argtypes = L.zcsd_dgemm.argtypes + [i, i, i, vp, C.c_size_t]
         for name, args in {
             "zcsd_dcsd": [vp, i, vp, i, vp, i, vp, i, vp, i, vp, i, vp, vp, vp,
                           C.POINTER(Opts), C.POINTER(Info)],
@@ -105,6 +103,14 @@ def _lib():
                 getattr(L, name).argtypes = args
         if hasattr(L, "zcsd_zolo_choose_r"):
             L.zcsd_zolo_choose_r.restype = C.c_int
+        # the struct layouts above must be the library's: a smaller Info would
+        # let the library write past it
+        L.zcsd_sizeof_opts.restype = C.c_size_t
+        L.zcsd_sizeof_info.restype = C.c_size_t
+        if (L.zcsd_sizeof_opts() != C.sizeof(Opts) or L.zcsd_sizeof_info() != C.sizeof(Info)):
+            raise RuntimeError(f"{_LIB_PATH} was built with other zcsd_opts/zcsd_info layouts "
+                               f"({L.zcsd_sizeof_opts()}/{L.zcsd_sizeof_info()} bytes, binding "
+                               f"{C.sizeof(Opts)}/{C.sizeof(Info)}); rebuild it")
         _L = L
     return _L
 
@@ -193,6 +199,33 @@ def dgemm(A, B, transA=False, transB=False, alpha=1.0, beta=0.0, C_=None, f32acc
             _ptr(out), n_, m_ * n_, bs)
     _check(st, "zcsd_dgemm")
     return out if batched else out[0]
+
+
+GEMM_SYM_UPPER, GEMM_UPPER_ONLY, GEMM_F32ACC = 1, 2, 4
+
+
+def dgemm_ex(A, B, C_, transA, transB, m, n, k, alpha=1.0, beta=0.0, flags=0, tri=0, kseg=0,
+             ws=None):
+    """zcsd_dgemm_ex on column-major buffers (the library's own layout).
+
+    A, B, C_ are contiguous float64 device tensors of shape (batch, cols, rows):
+    each [b] is the transpose of a column-major rows x cols matrix with
+    leading dimension rows.  op(A) is m x k, op(B) k x n, C_ m x n.  ws is an
+    optional flat float64 device tensor (split-K workspace)."""
+    for X, nm in ((A, "A"), (B, "B"), (C_, "C")):
+        if not (X.is_cuda and X.dtype == torch.float64 and X.dim() == 3 and X.is_contiguous()):
+            raise TypeError(f"dgemm_ex: {nm} must be a contiguous (batch, cols, rows) float64 tensor")
+    bs = C_.shape[0]
+    h = handle(C_.device.index)
+    st = _lib().zcsd_dgemm_ex(h, 1 if transA else 0, 1 if transB else 0, m, n, k, float(alpha),
+                              _ptr(A), A.shape[2], A.shape[1] * A.shape[2],
+                              _ptr(B), B.shape[2], B.shape[1] * B.shape[2], float(beta),
+                              _ptr(C_), C_.shape[2], C_.shape[1] * C_.shape[2], bs,
+                              int(flags), int(tri), int(kseg),
+                              _ptr(ws) if ws is not None else None,
+                              0 if ws is None else ws.numel())
+    _check(st, "zcsd_dgemm_ex")
+    return C_
 
 
 def zolo_coeffs(ell, r):

@@ -39,6 +39,15 @@ def _tol(theta):
     return 2e-12 * len(theta) / smin
 
 
+def _elementwise(got, ref, tol):
+    """Every entry within 8 tol times the root-mean-square entry of the oracle
+    gradient: a Frobenius-relative error tol spread over the n^2 entries puts
+    each near tol rms(ref); the factor 8 covers the largest of them."""
+    rms = float(np.linalg.norm(ref)) / np.sqrt(ref.size)
+    err = float(np.max(np.abs(got - ref)))
+    assert err <= 8.0 * tol * rms, (err, 8.0 * tol * rms)
+
+
 @pytest.mark.parametrize("n,seed", [(1, 60), (16, 61), (100, 62), (257, 63)])
 def test_backward_matches_oracle_gradient(n, seed):
     from paper_1804_09002_amd import zcsd
@@ -54,6 +63,8 @@ def test_backward_matches_oracle_gradient(n, seed):
     tol = _tol(o["theta"])
     assert _rel(gA1, gA1_o) <= tol, (_rel(gA1, gA1_o), tol)
     assert _rel(gA2, gA2_o) <= tol, (_rel(gA2, gA2_o), tol)
+    _elementwise(gA1, gA1_o, tol)
+    _elementwise(gA2, gA2_o, tol)
 
 
 @pytest.mark.parametrize("which", ["theta", "W1", "W2"])
@@ -146,3 +157,77 @@ def test_backward_batched_64_by_512():
         tol = _tol(o["theta"])
         assert _rel(gA1[b].cpu().numpy(), r1) <= tol
         assert _rel(gA2[b].cpu().numpy(), r2) <= tol
+        _elementwise(gA1[b].cpu().numpy(), r1, tol)
+        _elementwise(gA2[b].cpu().numpy(), r2, tol)
+
+
+@pytest.mark.parametrize("member", [0, 37])
+def test_backward_central_differences_n512(member):
+    """The differentiation workload's instances (n = 512, uniform angles, seed
+    6): directional derivatives of L from the hand-written backward against
+    central differences (L(A + hD) - L(A - hD)) / 2h of the GPU forward along
+    8 seeded unit directions (||D1||_F^2 + ||D2||_F^2 = 1) per part of L:
+
+    * polar factors (L = <G1, W1> + <G2, W2>): Gaussian D1, D2, steps h in
+      {1e-3, 3e-4, 1e-4, 1e-5}.  The polar factor is smooth (radius about
+      sigma_min(A_i) ~ 3e-3 against h ||D||_2 <= 6e-5), so where the error
+      at 1e-3 is above the rounding floor (3e-8) it must fall as h^2 to 1e-4
+      (by 30x at least; 100x in exact arithmetic), and the best step must
+      reach 3e-8, where the rounding of L divided by h takes over.
+    * angles (L = g.theta): D1 = U1 diag(a) V1^T, D2 = U2 diag(b) V1^T with
+      a = -S kappa + C rho, b = C kappa + S rho, kappa = z theta (z a scalar)
+      and Gaussian rho: along it each angle moves by h kappa_i, which keeps
+      their order, and rho only scales (cos, sin).  A general direction would
+      mix eigenvectors of pairs of eigenvalues of B closer than h ||D|| (the
+      smallest gaps are ~1e-5 at n = 512), and the angles would change order
+      (the loss is a function of the sorted angles), so its differences
+      carry no O(h^2) remainder at these steps.  Steps {1e-3, 1e-4, 1e-5}; the
+      best must agree to 3e-8.
+    Calibrated on the CPU oracle's forward for the same inputs: polar errors
+    2-4e-7, 2-4e-8, 2-4e-9, 1e-8 for the four steps; angle errors 1e-10 to
+    1.5e-8."""
+    from paper_1804_09002_amd import zcsd
+    n, seed = 512, 6
+    rng = np.random.default_rng(seed)
+    for b in range(member + 1):  # the workload's draws, in its order
+        A1, A2, _ = WL.uniform_pair(n, int(rng.integers(1 << 31)))
+        g, G1, G2 = rng.standard_normal(n), rng.standard_normal((n, n)), rng.standard_normal((n, n))
+    U1, U2, V1, th, info = zcsd.csd(_t(A1), _t(A2))
+    u1, u2, v1, t0 = U1.cpu().numpy(), U2.cpu().numpy(), V1.cpu().numpy(), th.cpu().numpy()
+    c, s = np.cos(t0), np.sin(t0)
+
+    def grads(gg, GG1, GG2):
+        a, b = zcsd.csd_backward(U1, U2, V1, th, None if gg is None else _t(gg),
+                                 None if GG1 is None else _t(GG1), None if GG2 is None else _t(GG2))
+        return a.cpu().numpy(), b.cpu().numpy()
+
+    def L(B1, B2, part):
+        uu1, uu2, vv1, t, inf = zcsd.csd(_t(B1), _t(B2), rank_mode="full", want_polar=True)
+        if part == "angles":
+            return float((t.cpu().numpy() * g).sum())
+        return float((inf["W1"].cpu().numpy() * G1).sum() + (inf["W2"].cpu().numpy() * G2).sum())
+
+    drng = np.random.default_rng(seed + 2000 + member)
+    for part, hs in (("polar", (1e-3, 3e-4, 1e-4, 1e-5)), ("angles", (1e-3, 1e-4, 1e-5))):
+        gA1, gA2 = grads(g, None, None) if part == "angles" else grads(None, G1, G2)
+        for d in range(8):
+            if part == "angles":
+                kap = drng.standard_normal() * t0
+                rho = drng.standard_normal(n)
+                D1 = (u1 * (-s * kap + c * rho)) @ v1.T
+                D2 = (u2 * (c * kap + s * rho)) @ v1.T
+            else:
+                D1, D2 = drng.standard_normal((n, n)), drng.standard_normal((n, n))
+            nrm = np.sqrt((D1 ** 2).sum() + (D2 ** 2).sum())
+            D1, D2 = D1 / nrm, D2 / nrm
+            an = float((gA1 * D1).sum() + (gA2 * D2).sum())
+            err = {}
+            for h in hs:
+                fd = (L(A1 + h * D1, A2 + h * D2, part) - L(A1 - h * D1, A2 - h * D2, part)) / (2 * h)
+                err[h] = abs(fd - an) / abs(an)
+            print(f"{part} direction {d}: derivative {an:.6e}, relative errors "
+                  + ", ".join(f"h={h:g}: {e:.2e}" for h, e in err.items()), flush=True)
+            assert min(err.values()) <= 3e-8, err
+            if part == "polar" and err[1e-3] > 3e-8:
+                # above the rounding floor the truncation error falls as h^2
+                assert err[1e-3] >= 30 * err[1e-4], err

@@ -124,7 +124,7 @@ def test_batched_member_below_eps_takes_algorithm2():
     path with Algorithm 2 (Sec. 5.1), and every member meets the FP64 targets
     and the oracle's angles."""
     from paper_1804_09002_amd import zcsd
-    rng = np.random.default_rng(47)
+    rng = np.random.default_rng(41)
     n_bad = 44
     theta = WL.angles_cumsum_clustered(n_bad, rng)
     assert min(np.min(theta), np.min(np.pi / 2 - theta)) < 1e-15

@@ -207,6 +207,19 @@ def backward_leg(count=64, n=512, seed=6):
             "backward_tflops_16n3": round(16.0 * n ** 3 * count / (t2 - t1) / 1e12, 3)}
 
 
+def cpu_model():
+    """The host CPU's model name (Linux /proc/cpuinfo), or the platform string."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or platform.machine()
+
+
 def cpu_baseline(n, reps, seed):
     """The oracle (numpy/LAPACK FP64, test infrastructure) on a bounded sample."""
     import numpy as np
@@ -291,6 +304,7 @@ def main():
         dt, threads = cpu_baseline(args.cpu_n, args.cpu_reps, args.seed)
         scale = (args.cpu_n / n) ** 3
         cpu = {"value": round(scale / dt, 6), "unit": "CSD/s", "cores": threads, "kind": "oracle",
+               "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
                "sample": f"{args.cpu_reps} oracle CSDs at n={args.cpu_n} (same construction), "
                          f"{dt:.2f} s each, scaled by (n_sample/n)^3 to n={n}"}
 

@@ -37,10 +37,15 @@ constexpr int JNT = 256;
 __global__ __launch_bounds__(JNT) void jacobi_kernel(const int* __restrict__ sizes, const double* A,
                                                      long long lda, long long sA, double* V,
                                                      long long ldv, long long sV, double* lam) {
-  __shared__ double S[JB][JB + 1];
+  // the matrix in two buffers: a round reads one and writes J^T S J into the other
+  __shared__ double Sbuf[2][JB][JB + 1];
   __shared__ double Q[JB][JB + 1];
   __shared__ double cs[JB / 2][2];
   __shared__ int pq[JB / 2][2];
+  // per index i of a round: row/column i of J^T S J is al[i] (row/column i) +
+  // be[i] (row/column pt[i]) of S (al = 1, be = 0 for an index not rotated)
+  __shared__ double al[JB], be[JB];
+  __shared__ int pt[JB];
   __shared__ double red2[JNT / 64];
   __shared__ double lt[JB];
   __shared__ int rotated;
@@ -53,6 +58,8 @@ __global__ __launch_bounds__(JNT) void jacobi_kernel(const int* __restrict__ siz
   if (n <= 0) return;
   // element e = tid + JNT q of the n x n block: row e % n, column e / n
   constexpr int NL = JB * JB / JNT;
+  int cur = 0;
+  double(*S)[JB + 1] = Sbuf[0];
   // symmetrised input into S (all loads of a thread in flight at once, then
   // the LDS stores); with_basis also resets Q to I
   auto load_input = [&](bool with_basis) {
@@ -102,6 +109,7 @@ __global__ __launch_bounds__(JNT) void jacobi_kernel(const int* __restrict__ siz
           q = t;
         }
         double c = 1.0, s = 0.0;
+        const int q0 = q;
         if (q < n && fabs(S[p][q]) > thr) {
           const double apq = S[p][q];
           const double tau = (S[q][q] - S[p][p]) / (2.0 * apq);
@@ -116,41 +124,49 @@ __global__ __launch_bounds__(JNT) void jacobi_kernel(const int* __restrict__ siz
         pq[tid][1] = q;
         cs[tid][0] = c;
         cs[tid][1] = s;
-      }
-      __syncthreads();
-      // columns: A <- A J, V <- V J
-      for (int e = tid; e < (m / 2) * n; e += JNT) {
-        const int k = e / n, i = e % n;
-        const int p = pq[k][0], q = pq[k][1];
-        if (p == q) continue;
-        const double c = cs[k][0], s = cs[k][1];
-        const double ap = S[i][p], aq = S[i][q];
-        S[i][p] = c * ap - s * aq;
-        S[i][q] = s * ap + c * aq;
-        const double vp = Q[i][p], vq = Q[i][q];
-        Q[i][p] = c * vp - s * vq;
-        Q[i][q] = s * vp + c * vq;
-      }
-      __syncthreads();
-      // rows: A <- J^T A
-      for (int e = tid; e < (m / 2) * n; e += JNT) {
-        const int k = e / n, j = e % n;
-        const int p = pq[k][0], q = pq[k][1];
-        if (p == q) continue;
-        const double c = cs[k][0], s = cs[k][1];
-        const double ap = S[p][j], aq = S[q][j];
-        S[p][j] = c * ap - s * aq;
-        S[q][j] = s * ap + c * aq;
-      }
-      __syncthreads();
-      if (tid < m / 2) {
-        const int p = pq[tid][0], q = pq[tid][1];
+        // new column p = c col_p - s col_q, new column q = s col_p + c col_q
+        // (rows alike); an index without a rotation keeps its row and column
         if (p != q) {
-          S[p][q] = 0.0;
-          S[q][p] = 0.0;
+          al[p] = c; be[p] = -s; pt[p] = q;
+          al[q] = c; be[q] = s; pt[q] = p;
+        } else {
+          al[p] = 1.0; be[p] = 0.0; pt[p] = p;
+          if (q0 < n) {
+            al[q0] = 1.0; be[q0] = 0.0; pt[q0] = q0;
+          }
         }
       }
       __syncthreads();
+      // S' = J^T S J into the other buffer (a column combination, then the
+      // row combination of the two columns: the arithmetic of applying J on
+      // the right, then J^T on the left), the rotated pairs' entries set to
+      // zero; V <- V J in place (each pair's two columns by one thread)
+      {
+        double(*Sn)[JB + 1] = Sbuf[cur ^ 1];
+#pragma unroll
+        for (int qq = 0; qq < NL; ++qq) {
+          const int e = tid + JNT * qq, i = e % n, j = e / n;
+          if (e < n * n) {
+            const int pi = pt[i], pj = pt[j];
+            const double ai = al[i], bi = be[i], aj = al[j], bj = be[j];
+            const double t1 = aj * S[i][j] + bj * S[i][pj];
+            const double t2 = aj * S[pi][j] + bj * S[pi][pj];
+            Sn[i][j] = (pi == j && pi != i) ? 0.0 : ai * t1 + bi * t2;
+          }
+        }
+        for (int e = tid; e < (m / 2) * n; e += JNT) {
+          const int k = e / n, i = e % n;
+          const int p = pq[k][0], q = pq[k][1];
+          if (p == q) continue;
+          const double c = cs[k][0], s = cs[k][1];
+          const double vp = Q[i][p], vq = Q[i][q];
+          Q[i][p] = c * vp - s * vq;
+          Q[i][q] = s * vp + c * vq;
+        }
+      }
+      __syncthreads();
+      cur ^= 1;
+      S = Sbuf[cur];
     }
     if (!rotated) break;
     __syncthreads();  // every thread has read `rotated` before it is reset

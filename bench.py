@@ -29,8 +29,8 @@ PEAKS = {"f64_mfma_tflops": 78.6, "f64_vector_tflops": 78.6, "hbm_gbs": 8000.0}
 TRAFFIC = {
     "tsqr_tree": {"bytes": 1296313.7, "src": "paper_1804_09002_amd/csrc/qr_tsqr.hip",
                  "sha": "566b053691d975b3", "summary": "profiles/tsqr_tree_kernel_csd4096_traffic.md"},
-    "dgemm_128x128_NN": {"bytes": 583020874.9, "src": "paper_1804_09002_amd/csrc/gemm.hip",
-                        "sha": "e9980925ba50f1f4", "summary": "profiles/dgemm_kernel_128x128_NN_csd4096_traffic.md"},
+    "dgemm_128x128_NN": {"bytes": 581227567.5, "src": "paper_1804_09002_amd/csrc/gemm.hip",
+                        "sha": "4d3b20a3075eda43", "summary": "profiles/dgemm_kernel_128x128_NN_csd4096_traffic.md"},
     "dgemm_64x64_TN": {"bytes": 82392906.6, "src": "paper_1804_09002_amd/csrc/gemm.hip",
                       "sha": "e9980925ba50f1f4", "summary": "profiles/dgemm_kernel_64x64_TN_csd4096_traffic.md"},
 }

@@ -3,12 +3,13 @@
  * decomposition of Gawlik, Nakatsukasa & Sutton, "A Backward Stable Algorithm
  * for Computing the CS Decomposition via the Polar Decomposition"
  * (arXiv 1804.09002): Zolo-csd = two Zolotarev polar decompositions (Zolo-pd,
- * Sec. 5), the Hermitian matrix B = H2 - H1 + mu (I - A^T A) (Algorithm 1,
- * line 4) and a Zolotarev spectral divide-and-conquer eigendecomposition of B
+ * Sec. 5), the Hermitian matrix B = H2 - H1 + mu (I - A^T A) (Algorithm 1)
+ * and a Zolotarev spectral divide-and-conquer eigendecomposition of B
  * (Zolo-eig, Sec. 5), assembled into U1, U2, V1 and the angles theta.
  *
  * Conventions for every entry point
- *  - Matrices are real FP64, column-major, with a leading dimension ld >= rows.
+ *  - Matrices are real FP64, column-major, with a leading dimension ld >= rows
+ *    (zcsd_zcsd: interleaved complex FP64, ld counted in complex elements).
  *  - Pointers named d_* are device pointers (HIP memory on the handle's device);
  *    h_* are host pointers.  The caller owns all input and output buffers.
  *  - Work is enqueued on the handle's stream.  Entry points that need host
@@ -75,12 +76,12 @@ typedef struct {
   zcsd_precision prec;     /* ZCSD_FP64 (default) or ZCSD_MIXED_FP32 (above) */
   zcsd_rank_mode rank_mode;
   double eps;              /* floor of the Zolo-pd interval [eps, 1]; 1e-15 (Sec. 5.1) */
-  double mu;               /* shift of the null space in B; 2 (Algorithm 3 line 3) */
+  double mu;               /* shift of the null space in B; 2 (Algorithm 3) */
   double tol;              /* Zolo-pd target 1 - l_2 <= tol; 2^-53 */
   int r_override;          /* 0 = choose r from the l estimate; 1..8 forces r */
   double ell_override;     /* 0 = estimate l = sigma_min lower bound; > 0 forces l */
   int n_leaf;              /* Zolo-eig blocks of at most this size go to Jacobi (<= 64) */
-  int postprocess;         /* 0, 1: C_ii = v_i^T H1 v_i, S_ii = v_i^T H2 v_i (Alg. 1 lines 8-9),
+  int postprocess;         /* 0, 1: C_ii = v_i^T H1 v_i, S_ii = v_i^T H2 v_i (Algorithm 1),
                               theta = atan2(S_ii, C_ii), C = cos, S = sin (Remark (iii));
                               2: theta_i solves sin(theta) - cos(theta) = Lambda_ii, the
                               cheaper and less accurate alternative of Remark (iv) (no
@@ -179,6 +180,36 @@ zcsd_status zcsd_dcsd_mn(zcsd_handle* handle, int m1, int m2, int n,
                          const zcsd_opts* opts, zcsd_info* info);
 
 /*
+ * CS decomposition of a complex partial isometry A = [A1; A2], A1, A2 in
+ * C^{n x n} (the setting of Sec. 1 and Theorem 2.1):
+ *    A1 = U1 diag(cos theta) V1^*,  A2 = U2 diag(sin theta) V1^*,
+ * U1, U2, V1 with orthonormal (complex) columns, theta ascending in
+ * [0, pi/2].  Computed through the real embedding X + iY -> [X -Y; Y X]:
+ * Algorithm 1 / 3 on the 2n x 2n real blocks, whose angles are those of A
+ * twice; the complex columns are read from one real column of each pair,
+ * repeated complex angles get a complex-orthonormal basis of their cluster,
+ * and Newton-Schulz steps on the embedded V1 (the same right factor on U1
+ * and U2) make the columns complex-orthonormal to rounding.
+ * Memory: column-major device arrays of interleaved complex doubles
+ * (re, im), as std::complex<double> / hipDoubleComplex; leading dimensions
+ * count complex elements (>= n).  d_A1, d_A2 are read only; d_U1, d_U2,
+ * d_V1 (n x n) and d_theta (n reals) are written, with only the first
+ * info->rank columns / entries valid (the rest zero).  opts may be NULL;
+ * only prec = ZCSD_FP64 is accepted.  info may be NULL; it reports the rank
+ * and whether Algorithm 2 replaced a polar factor.  Errors: ZCSD_EINVAL for
+ * n < 1, NULL pointers, short leading dimensions or another precision;
+ * ZCSD_ENOCONV as zcsd_dcsd, or when a real angle has no partner within the
+ * pairing gap; ZCSD_ENOMEM when the workspace (11 (2n)^2 doubles plus what
+ * zcsd_workspace_size reports for the real path at size 2n) cannot be
+ * allocated.  Returns after the stream has finished the call.
+ */
+zcsd_status zcsd_zcsd(zcsd_handle* handle, int n,
+                      const double* d_A1, int lda1, const double* d_A2, int lda2,
+                      double* d_U1, int ldu1, double* d_U2, int ldu2,
+                      double* d_V1, int ldv1, double* d_theta,
+                      const zcsd_opts* opts, zcsd_info* info);
+
+/*
  * Complete 2 x 2 CS decomposition of an orthogonal 2n x 2n matrix
  * A = [A1 A3; A2 A4] (Remark (viii) of Sec. 3):
  *    A = diag(U1, U2) [C -S; S C] diag(V1, V2)^T,  C = diag(cos theta),
@@ -232,8 +263,8 @@ zcsd_status zcsd_dcsd_batched(zcsd_handle* handle, int batch, const int* n_host,
 /*
  * Backward of `batch` full-rank CS decompositions of size n: the gradients
  * gA1, gA2 of L = sum_i g_theta[i] theta_i + <G_W1, W1> + <G_W2, W2> with
- * respect to A1 and A2, where W_i = U_i V1^T are the polar factors (Alg. 1
- * lines 1-2) and theta the angles (Alg. 1 lines 8-9 with Remark (iii)).
+ * respect to A1 and A2, where W_i = U_i V1^T are the polar factors of
+ * Algorithm 1 and theta its angles (with Remark (iii)).
  * First-order perturbation of c_i = v_i^T H1 v_i and s_i = v_i^T H2 v_i gives
  * d theta_i = -s_i u1_i^T dA1 v_i + c_i u2_i^T dA2 v_i; the polar factor of
  * A = U Sigma V^T moves by U [(E - E^T)/(sigma_j + sigma_k)] V^T, E = U^T dA V.

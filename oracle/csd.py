@@ -8,18 +8,18 @@ through the classical backward-stable route the paper names in Remark (v) and
 Sec. 5.1: polar decompositions through the SVD and a LAPACK symmetric
 eigensolver, with the steps of Algorithm 1 in the paper's order:
 
-  1-2  W_i H_i = A_i                       (polar, via SVD: W = P Q^T, H = Q Sigma Q^T)
-  3    mu = 0 if rank(A) = n else 2        (rank from ||A||_F^2, Remark (vi))
-  4    B = H2 - H1 + mu (I - A^T A)
-  5    V1 Lambda V1^T = B                  (numpy.linalg.eigh)
-       rank-deficient: keep the eigenpairs with Lambda in [-1, 1] (Alg. 3, Remark (vii))
-  6-7  U_i = W_i V1
-  8-9  C = diag(V1^T H1 V1), S = diag(V1^T H2 V1)
-  post theta = arctan(S_ii / C_ii), C = cos theta, S = sin theta (Remark (iii)),
-       columns ordered by ascending theta (Sec. 1).
-       With theta_from="lambda" lines 8-9 are replaced by the cheaper route of
-       Remark (iv): Lambda_ii = sin theta_i - cos theta_i = sqrt(2) sin(theta_i - pi/4),
-       so theta_i = pi/4 + arcsin(Lambda_ii / sqrt(2)).
+  polar   W_i H_i = A_i                     (via SVD: W = P Q^T, H = Q Sigma Q^T)
+  rank    mu = 0 if rank(A) = n else 2      (rank from ||A||_F^2, Remark (vi))
+  B       B = H2 - H1 + mu (I - A^T A)
+  eig     V1 Lambda V1^T = B                (numpy.linalg.eigh)
+          rank-deficient: keep the eigenpairs with Lambda in [-1, 1] (Alg. 3, Remark (vii))
+  U       U_i = W_i V1
+  C, S    C = diag(V1^T H1 V1), S = diag(V1^T H2 V1)
+  angles  theta = arctan(S_ii / C_ii), C = cos theta, S = sin theta (Remark (iii)),
+          columns ordered by ascending theta (Sec. 1).
+          With theta_from="lambda" C and S come instead from the cheaper route of
+          Remark (iv): Lambda_ii = sin theta_i - cos theta_i = sqrt(2) sin(theta_i - pi/4),
+          so theta_i = pi/4 + arcsin(Lambda_ii / sqrt(2)).
 
 Readings taken where the paper is silent: H and B are symmetrised by
 (X + X^T)/2; arctan(S/C) is evaluated as atan2(S, C) and clamped to [0, pi/2].
@@ -51,7 +51,7 @@ def csd(A1, A2, rank_mode="auto", mu=2.0, b_choice="H2-H1", theta_from="diag"):
     b_choice : "H2-H1" (the paper's choice).  "H1" is accepted only so the
                tests can reproduce the unstable variant of the worked example
                in Sec. 3; it is never the default.
-    theta_from: "diag" (Alg. 1 lines 8-9, the default) or "lambda" (Remark (iv)).
+    theta_from: "diag" (C, S = diag(V1^T H_i V1), the default) or "lambda" (Remark (iv)).
     Returns a dict with U1, U2, V1, theta (economical in the rank-deficient
     case) and the intermediates W1, W2, H1, H2, B, Lambda, rank, mu.
     """
@@ -83,7 +83,7 @@ def csd(A1, A2, rank_mode="auto", mu=2.0, b_choice="H2-H1", theta_from="diag"):
     B = 0.5 * (B + B.T)
     lam, V = np.linalg.eigh(B)
     if deficient:
-        # Alg. 3 line 5: the eigenvectors whose eigenvalues lie in [-1, 1];
+        # Algorithm 3: the eigenvectors whose eigenvalues lie in [-1, 1];
         # the n - r others sit at mu.  eigh sorts ascending, so they are the
         # r_A smallest (r_A from Remark (vi) unless the caller forced the mode).
         keep = int(np.sum(lam <= 0.5 * (1.0 + mu_used)))

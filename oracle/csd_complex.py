@@ -8,15 +8,15 @@ U1, U2, V1 unitary, C = diag(cos theta), S = diag(sin theta),
 Algorithm 3 in complex arithmetic, through the classical route the paper
 names (polar via the SVD, Hermitian eigensolver), in the paper's order:
 
-  1-2  W_i H_i = A_i        W = P Q^*, H = Q Sigma Q^* from A_i = P Sigma Q^*
-  3    mu = 0 if rank(A) = n else 2 (rank = round(||A||_F^2), Remark (vi))
-  4    B = H2 - H1 + mu (I - A^* A), made Hermitian by (B + B^*) / 2
-  5    V1 Lambda V1^* = B   (numpy.linalg.eigh); rank deficient: keep the
-       eigenpairs with Lambda <= (1 + mu) / 2 (Alg. 3, Remark (vii))
-  6-7  U_i = W_i V1
-  8-9  C_ii = Re(v_i^* H1 v_i), S_ii = Re(v_i^* H2 v_i) (real: H_i Hermitian)
-  post theta = atan2(S_ii, C_ii) clamped to [0, pi/2] (Remark (iii)),
-       columns ordered by ascending theta.
+  polar   W_i H_i = A_i        W = P Q^*, H = Q Sigma Q^* from A_i = P Sigma Q^*
+  rank    mu = 0 if rank(A) = n else 2 (rank = round(||A||_F^2), Remark (vi))
+  B       B = H2 - H1 + mu (I - A^* A), made Hermitian by (B + B^*) / 2
+  eig     V1 Lambda V1^* = B   (numpy.linalg.eigh); rank deficient: keep the
+          eigenpairs with Lambda <= (1 + mu) / 2 (Alg. 3, Remark (vii))
+  U       U_i = W_i V1
+  C, S    C_ii = Re(v_i^* H1 v_i), S_ii = Re(v_i^* H2 v_i) (real: H_i Hermitian)
+  angles  theta = atan2(S_ii, C_ii) clamped to [0, pi/2] (Remark (iii)),
+          columns ordered by ascending theta.
 Shares no code with the real oracle or the device path.
 """
 from __future__ import annotations

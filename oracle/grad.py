@@ -4,7 +4,7 @@ With A1 = U1 C V1^T, A2 = U2 S V1^T (C = diag(c), S = diag(s), distinct angles):
 
 * angles: theta_i = atan2(s_i, c_i) with dc_i = u1_i^T dA1 v_i and
   ds_i = u2_i^T dA2 v_i (first-order perturbation of the diagonal of
-  V1^T H_i V1, Algorithm 1 lines 8-9), so
+  V1^T H_i V1 that gives C and S in Algorithm 1), so
       d theta_i / d A1 = -s_i u1_i v_i^T,   d theta_i / d A2 = c_i u2_i v_i^T;
 * polar factor W = U V^T of A = U Sigma V^T: for E = U^T dA V,
   dW = U [(E - E^T) / (sigma_j + sigma_k)] V^T, so

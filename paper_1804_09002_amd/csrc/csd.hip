@@ -1,16 +1,16 @@
 // Zolo-csd driver: Algorithm 1 (full rank) and Algorithm 3 (rank-deficient
 // partial isometry) on the device, with Remarks (iii), (vi) and (vii).
 //
-//   a1  rank: r_A = round(||A||_F^2) (Remark (vi)); mu = 0 if r_A = n else 2
-//   a2-a5  W_i H_i = A_i for i = 1, 2 in one batched Zolo-pd (lines 1-2; the two
-//       polars run side by side, Remark (ii)); rank-deficient inputs use the
-//       modified Zolo-pd on [eps, 1] with r = 8 (Sec. 5.1, Algorithm 3 line 1)
-//   a6  B = H2 - H1 + mu (I - A1^T A1 - A2^T A2), symmetrised (line 4)
-//   a7  V1 Lambda V1^T = B by Zolo-eig (line 5)
-//   a8  rank-deficient: keep the eigenvectors with Lambda in [-1, 1] (Alg. 3 line 5)
-//   a9  U_i = W_i V1 (lines 6-7)
-//   a10 C = diag(V1^T H1 V1), S = diag(V1^T H2 V1) (lines 8-9)
-//   a11 theta = atan2(S_ii, C_ii) clamped to [0, pi/2] (Remark (iii)), columns
+//   rank: r_A = round(||A||_F^2) (Remark (vi)); mu = 0 if r_A = n else 2
+//   polars: W_i H_i = A_i for i = 1, 2 in one batched Zolo-pd (the two polars
+//       run side by side, Remark (ii)); rank-deficient inputs use the modified
+//       Zolo-pd on [eps, 1] with r = 8 (Sec. 5.1, Algorithm 3)
+//   B = H2 - H1 + mu (I - A1^T A1 - A2^T A2), symmetrised
+//   V1 Lambda V1^T = B by Zolo-eig
+//   rank-deficient: keep the eigenvectors with Lambda in [-1, 1] (Algorithm 3)
+//   U_i = W_i V1
+//   C = diag(V1^T H1 V1), S = diag(V1^T H2 V1)
+//   theta = atan2(S_ii, C_ii) clamped to [0, pi/2] (Remark (iii)), columns
 //       sorted by ascending theta.
 #include <algorithm>
 #include <chrono>
@@ -55,7 +55,7 @@ __global__ void theta_kernel(int r, const double* __restrict__ c, const double* 
   }
 }
 
-// Remark (iv), the cheaper alternative to lines 8-9: theta_j solves
+// Remark (iv), the cheaper alternative to C, S from V1^T H_i V1: theta_j solves
 // sin(theta) - cos(theta) = Lambda_jj, i.e. theta = pi/4 + asin(Lambda_jj / sqrt(2))
 __global__ void theta_from_lambda_kernel(int r, const double* __restrict__ lam, double* th) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -217,7 +217,7 @@ static CsdOut csd_run(int n, const double* A1, long long lda1, const double* A2,
   const double ztol = o.tol;
   const long long lowp0 = gemm_lowp_launches();
 
-  // a1: rank from ||A||_F^2 (Remark (vi))
+  // rank from ||A||_F^2 (Remark (vi))
   double* X = ar.dalloc(2 * (size_t)nn);
   copy_scale(1, n, n, 1.0, A1, lda1, 0, X, n, 0, s);
   copy_scale(1, n, n, 1.0, A2, lda2, 0, X + nn, n, 0, s);
@@ -238,7 +238,7 @@ static CsdOut csd_run(int n, const double* A1, long long lda1, const double* A2,
   }
   const double mu = deficient ? o.mu : 0.0;
 
-  // a2-a5: the two polar decompositions, batched
+  // the two polar decompositions, batched
   double* W = ar.dalloc(2 * (size_t)nn);
   double* H = ar.dalloc(2 * (size_t)nn);
   {
@@ -291,7 +291,7 @@ static CsdOut csd_run(int n, const double* A1, long long lda1, const double* A2,
   double t1 = now_ms();
   out.t_polar = t1 - t0;
 
-  // a6: B = H2 - H1 + mu (I - A^T A)
+  // B = H2 - H1 + mu (I - A^T A)
   double* B = ar.dalloc(nn);
   copy_scale(1, n, n, 1.0, H + nn, n, 0, B, n, 0, s);
   axpby(nn, -1.0, H, 1.0, B, s);
@@ -312,7 +312,7 @@ static CsdOut csd_run(int n, const double* A1, long long lda1, const double* A2,
   double t2 = now_ms();
   out.t_B = t2 - t1;
 
-  // a7: Zolo-eig of B
+  // Zolo-eig of B
   double* V = ar.dalloc(nn);
   double* lam = ar.dalloc(n);
   {
@@ -338,7 +338,7 @@ static CsdOut csd_run(int n, const double* A1, long long lda1, const double* A2,
   double t3 = now_ms();
   out.t_eig = t3 - t2;
 
-  // a8: rank-deficient selection (eigenvalues ascending: the kept ones come first)
+  // rank-deficient selection (eigenvalues ascending: the kept ones come first)
   int r = n;
   if (deficient) {
     std::vector<double> lh(n);
@@ -349,7 +349,7 @@ static CsdOut csd_run(int n, const double* A1, long long lda1, const double* A2,
   }
   out.rank = r;
 
-  // a9, a10: U_i = W_i V, c = diag(V^T H1 V), s = diag(V^T H2 V)
+  // U_i = W_i V, c = diag(V^T H1 V), s = diag(V^T H2 V)
   double* Ut = ar.dalloc(2 * (size_t)nn);
   double* T = ar.dalloc(2 * (size_t)nn);
   double* cs = ar.dalloc(2 * (size_t)n);
@@ -441,7 +441,7 @@ static CsdOut csd_run(int n, const double* A1, long long lda1, const double* A2,
       ZCSD_CHECK_LAUNCH();
     }
   }
-  // a11: order by ascending theta and write the outputs (columns r..n-1 zero)
+  // order by ascending theta and write the outputs (columns r..n-1 zero)
   std::vector<double> thh(r);
   if (r > 0) d2h(thh.data(), th, r * sizeof(double), s);
   std::vector<int> perm(r);

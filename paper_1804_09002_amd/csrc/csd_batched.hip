@@ -4,19 +4,19 @@
 // embedded in the class size N with padding that cannot mix with its
 // spectrum, and the class runs through the batched kernels of the single
 // path as one problem set:
-//   polar (Alg. 1 lines 1-2): X = diag(A_i, I).  The padding has singular
+//   polar (Algorithm 1): X = diag(A_i, I).  The padding has singular
 //       value 1, which Z maps to 1, so W = diag(W_i, I), H = diag(H_i, I)
 //       (up to rounding-level coupling that is discarded);
-//   B (line 4): built on the real n x n part, the padding set to exactly 3 I
+//   B: built on the real n x n part, the padding set to exactly 3 I
 //       with exactly zero coupling.  The real spectrum lies in [-1, 1] (plus
 //       mu = 2 on the null space of a rank-deficient input, Alg. 3), so the
 //       padding is an isolated eigenvalue and every eigenvector of the real
 //       part has zero padding rows up to rounding;
-//   eig (line 5): one batched Zolo-eig over the class;
+//   eig: one batched Zolo-eig over the class;
 //   selection: the eigenpairs with lambda <= 2 (full rank) or <= (1 + mu)/2
-//       (Alg. 3 line 5, null space at mu) are the real ones; the padding at 3
+//       (Algorithm 3, null space at mu) are the real ones; the padding at 3
 //       is dropped the same way;
-//   assembly (lines 6-9, Remark (iii)): U_i = W_i V1, c = diag(V1^T H1 V1),
+//   assembly (Algorithm 1, Remark (iii)): U_i = W_i V1, c = diag(V1^T H1 V1),
 //       s = diag(V1^T H2 V1), theta = atan2(s, c), sorted per problem.
 // Full-rank and rank-deficient problems of a class are separate sub-batches
 // (the latter use the modified Zolo-pd with l = eps, r = 8).
@@ -343,7 +343,7 @@ static bool csd_group(int N, const std::vector<int>& mem, bool deficient, const 
   }
   // selection (ascending, so the kept pairs come first): lambda <= 2 keeps the
   // real spectrum [-1, 1] and drops the padding at 3; with the null space at mu
-  // the threshold is (1 + mu) / 2 (Alg. 3 line 5)
+  // the threshold is (1 + mu) / 2 (Algorithm 3)
   const double keep_max = deficient ? 0.5 * (1.0 + mu) : 2.0;
   std::vector<double> lh((size_t)K * N);
   d2h(lh.data(), lam, lh.size() * sizeof(double), s);

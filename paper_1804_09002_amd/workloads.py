@@ -18,6 +18,11 @@ Recipes (the paper's test classes of Sec. 6, real analogues):
                    partial isometry, test class 4).
 * ``paper_test_class``  the eight test classes of Sec. 6 (1-4 and the noisy
                    1'-4'), real analogues.
+* ``complex_pair`` complex blocks A1 = U1 diag(cos t) V1^H, A2 = U2 diag(sin t) V1^H
+                   with Haar unitary factors (Q of a complex Gaussian, phases of
+                   diag(R) divided out): uniform or clustered angles, repeated
+                   angles of a given multiplicity, zeroed pairs (rank deficient),
+                   or a Haar 2n x n matrix with orthonormal columns.
 """
 from __future__ import annotations
 
@@ -120,6 +125,52 @@ def uniform_pair(n, seed):
     rng = np.random.default_rng(seed)
     theta = angles_uniform(n, rng)
     return from_angles(theta, rng)
+
+
+def haar_unitary(m, n, rng):
+    """m x n (m >= n) with orthonormal complex columns, Haar distributed."""
+    G = rng.standard_normal((m, n)) + 1j * rng.standard_normal((m, n))
+    Q, R = np.linalg.qr(G)
+    d = np.diag(R)
+    ph = np.where(np.abs(d) > 0, d / np.where(np.abs(d) > 0, np.abs(d), 1.0), 1.0)
+    return Q * ph
+
+
+def complex_pair(n, seed, kind="uniform", rank_deficient=0, mult=1):
+    """Complex128 blocks (A1, A2, meta).  kind: "uniform" (angles uniform in
+    [0, pi/2]), "clustered" (as clustered_pair), "repeated" (n / mult distinct
+    uniform angles, each `mult` times), "exact_ends" (n // 8 angles exactly 0
+    and n // 8 exactly pi/2, the rest uniform), "haar" (a Haar 2n x n matrix
+    with orthonormal columns split into its halves).  rank_deficient = k
+    zeroes k random (C_ii, S_ii) pairs."""
+    rng = np.random.default_rng(seed)
+    if kind == "haar":
+        A = haar_unitary(2 * n, n, rng)
+        return np.ascontiguousarray(A[:n]), np.ascontiguousarray(A[n:]), {}
+    if kind == "uniform":
+        theta = angles_uniform(n, rng)
+    elif kind == "clustered":
+        theta = angles_clustered_ends(n, rng)
+    elif kind == "exact_ends":
+        e = n // 8
+        theta = np.concatenate([np.zeros(e), np.sort(rng.uniform(0.0, np.pi / 2, n - 2 * e)),
+                                np.full(e, np.pi / 2)])
+    elif kind == "repeated":
+        if n % mult:
+            raise ValueError("complex_pair: n must be a multiple of mult")
+        theta = np.sort(np.repeat(rng.uniform(0.0, np.pi / 2, n // mult), mult))
+    else:
+        raise ValueError(f"unknown kind {kind!r}")
+    zero_idx = np.sort(rng.choice(n, size=rank_deficient, replace=False)) if rank_deficient else None
+    U1, U2, V1 = (haar_unitary(n, n, rng) for _ in range(3))
+    c, s = np.cos(theta), np.sin(theta)
+    if zero_idx is not None:
+        c[zero_idx] = 0.0
+        s[zero_idx] = 0.0
+    Vh = V1.conj().T
+    A1 = (U1 * c) @ Vh
+    A2 = (U2 * s) @ Vh
+    return A1, A2, {"U1": U1, "U2": U2, "V1": V1, "theta": theta, "zero_idx": zero_idx}
 
 
 PAPER_CLASSES = ("1", "2", "3", "4", "1'", "2'", "3'", "4'")

@@ -85,6 +85,8 @@ def _lib():
                              C.POINTER(Opts), C.POINTER(Info)],
             "zcsd_dcsd_mn": [vp, i, i, i, vp, i, vp, i, vp, i, vp, i, vp, i, vp,
                              C.POINTER(Opts), C.POINTER(Info)],
+            "zcsd_zcsd": [vp, i, vp, i, vp, i, vp, i, vp, i, vp, i, vp,
+                          C.POINTER(Opts), C.POINTER(Info)],
             "zcsd_dzolo_pd": [vp, i, i, d, vp, i, ll, vp, vp, vp, C.POINTER(Opts), C.POINTER(Info)],
             "zcsd_dsyev_zolo": [vp, i, vp, i, d, d, vp, i, vp, C.POINTER(Opts), C.POINTER(Info)],
             "zcsd_dcsd_backward": [vp, i, i, vp, vp, vp, vp, vp, vp, vp, vp, vp],
@@ -356,6 +358,36 @@ def csd(A1, A2, rank_mode="auto", r=None, ell=None, want_polar=False, **opts):
     if want_polar:
         d["W1"], d["W2"] = W1.t(), W2.t()
     return U1.t(), U2.t(), V1.t(), th, d
+
+
+def csd_complex(A1, A2, rank_mode="auto", **opts):
+    """CS decomposition of a complex [A1; A2] (n x n complex128 HIP tensors).
+
+    Returns (U1, U2, V1, theta, info) with A1 = U1 diag(cos theta) V1^H and
+    A2 = U2 diag(sin theta) V1^H (complex128 factors, float64 theta); in the
+    rank-deficient case only the first info['rank'] columns / entries are
+    valid.  Computed by zcsd_zcsd through the real embedding of the blocks.
+    """
+    for X, name in ((A1, "A1"), (A2, "A2")):
+        if not (isinstance(X, torch.Tensor) and X.is_cuda and X.dtype == torch.complex128
+                and X.dim() == 2 and X.shape[0] == X.shape[1]):
+            raise TypeError(f"csd_complex: {name} must be a square complex128 tensor on a HIP device")
+    n = A1.shape[0]
+    if A2.shape != A1.shape:
+        raise ValueError("csd_complex: A1 and A2 must have the same shape")
+    a1 = A1.t().contiguous()
+    a2 = A2.t().contiguous()
+    U1 = torch.empty_like(a1)
+    U2 = torch.empty_like(a1)
+    V1 = torch.empty_like(a1)
+    th = torch.empty(n, dtype=torch.float64, device=A1.device)
+    o = default_opts(rank_mode=rank_mode, **opts)
+    info = Info()
+    h = handle(A1.device.index)
+    st = _lib().zcsd_zcsd(h, n, _ptr(a1), n, _ptr(a2), n, _ptr(U1), n, _ptr(U2), n, _ptr(V1), n,
+                          _ptr(th), C.byref(o), C.byref(info))
+    _check(st, "zcsd_zcsd")
+    return U1.t(), U2.t(), V1.t(), th, info.as_dict()
 
 
 def csd2x2(A1, A2, A3, A4, **opts):

@@ -1,0 +1,131 @@
+"""Complex CS decomposition on the GPU (zcsd_zcsd) against the complex oracle.
+
+The paper's setting is complex (Sec. 1, Theorem 2.1).  Inputs are complex
+partial isometries with Haar unitary factors and uniform, clustered or exactly
+repeated angles, a Haar 2n x n matrix, and rank-deficient ones; sizes span one
+and several Jacobi leaves and ragged n.  Checked: the rank, the angles
+against oracle.csd_complex (and against the angles of the construction), the
+2-norm backward error and the complex orthogonality ||X^H X - I||_2 of U1,
+U2, V1 -- the decomposition itself is not unique (column phases, bases of
+repeated angles), so the factors are compared through what is unique.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import csd_complex as OC
+from paper_1804_09002_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -53
+DEV = torch.device("cuda:0")
+
+
+def _t(x):
+    return torch.tensor(np.ascontiguousarray(x), dtype=torch.complex128, device=DEV)
+
+
+def _measures(A1, A2, U1, U2, V1, th, r):
+    U1, U2, V1, th = U1[:, :r], U2[:, :r], V1[:, :r], th[:r]
+    A = np.vstack([A1, A2])
+    Vh = V1.conj().T
+    R = np.vstack([(U1 * np.cos(th)) @ Vh - A1, (U2 * np.sin(th)) @ Vh - A2])
+    res = np.linalg.norm(R, 2) / max(np.linalg.norm(A, 2), 1e-300)
+    orth = [np.linalg.norm(X.conj().T @ X - np.eye(r), 2) for X in (U1, U2, V1)]
+    return res, orth
+
+
+CASES = [
+    ("uniform", 1, 0, 1), ("uniform", 7, 0, 1), ("uniform", 64, 0, 1), ("uniform", 130, 0, 1),
+    ("haar", 257, 0, 1), ("clustered", 200, 0, 1), ("repeated", 96, 0, 4), ("repeated", 48, 0, 48),
+    ("uniform", 100, 10, 1), ("clustered", 120, 9, 1), ("exact_ends", 80, 0, 1),
+    ("exact_ends", 72, 6, 1),
+]
+
+
+@pytest.mark.parametrize("kind,n,k,mult", CASES)
+def test_complex_csd_against_oracle(kind, n, k, mult):
+    from paper_1804_09002_amd import zcsd
+    A1, A2, meta = WL.complex_pair(n, 1000 + n + k, kind=kind, rank_deficient=k, mult=mult)
+    U1, U2, V1, th, info = zcsd.csd_complex(_t(A1), _t(A2))
+    U1, U2, V1, th = (x.cpu().numpy() for x in (U1, U2, V1, th))
+    o = OC.csd(A1, A2)
+    r = info["rank"]
+    assert r == o["rank"] == n - k
+    assert np.all(np.diff(th[:r]) >= 0) and np.all(th[r:] == 0)
+    assert np.all(U1[:, r:] == 0) and np.all(V1[:, r:] == 0)
+    dth = float(np.max(np.abs(th[:r] - o["theta"]))) if r else 0.0
+    res, orth = _measures(A1, A2, U1, U2, V1, th, r)
+    print(f"complex {kind} n={n} k={k} mult={mult}: |dtheta| {dth:.1e} backward {res:.1e} "
+          f"orth {max(orth):.1e}", flush=True)
+    assert dth <= 10 * max(n, 8) * U
+    if "theta" in meta:
+        keep = np.ones(n, bool)
+        if meta["zero_idx"] is not None:
+            keep[meta["zero_idx"]] = False
+        truth = np.sort(meta["theta"][keep])
+        assert np.max(np.abs(th[:r] - truth)) <= 10 * max(n, 8) * U
+    assert res <= 2e-13
+    assert max(orth) <= 2e-13
+
+
+def test_one_block_zero():
+    """A2 = 0: every angle is 0 and U2 is any unitary matrix; A1 = 0 likewise."""
+    from paper_1804_09002_amd import zcsd
+    rng = np.random.default_rng(8)
+    Q = WL.haar_unitary(40, 40, rng)
+    Z = np.zeros((40, 40), complex)
+    for A1, A2, ref in ((Q, Z, 0.0), (Z, Q, np.pi / 2)):
+        U1, U2, V1, th, info = zcsd.csd_complex(_t(A1), _t(A2))
+        U1, U2, V1, th = (x.cpu().numpy() for x in (U1, U2, V1, th))
+        assert info["rank"] == 40
+        assert np.max(np.abs(th - ref)) <= 1e-14
+        res, orth = _measures(A1, A2, U1, U2, V1, th, 40)
+        assert res <= 2e-13 and max(orth) <= 2e-13
+
+
+def test_real_input_gives_real_angles():
+    """A real input through the complex path: the angles of the real path."""
+    from paper_1804_09002_amd import zcsd
+    A1, A2, _ = WL.uniform_pair(90, 5)
+    th_c = zcsd.csd_complex(_t(A1), _t(A2))[3]
+    th_r = zcsd.csd(torch.tensor(A1, device=DEV), torch.tensor(A2, device=DEV))[3]
+    assert float((th_c - th_r).abs().max()) <= 10 * 90 * U
+
+
+def test_phase_and_column_invariance():
+    """Scaling A by a unimodular e^{i phi} and permuting its columns change
+    neither the angles nor the reconstruction error."""
+    from paper_1804_09002_amd import zcsd
+    A1, A2, _ = WL.complex_pair(70, 6)
+    ph = np.exp(0.7j)
+    p = np.random.default_rng(6).permutation(70)
+    th0 = zcsd.csd_complex(_t(A1), _t(A2))[3].cpu().numpy()
+    B1, B2 = ph * A1[:, p], ph * A2[:, p]
+    U1, U2, V1, th, info = zcsd.csd_complex(_t(B1), _t(B2))
+    U1, U2, V1, th = (x.cpu().numpy() for x in (U1, U2, V1, th))
+    assert np.max(np.abs(th - th0)) <= 10 * 70 * U
+    res, orth = _measures(B1, B2, U1, U2, V1, th, info["rank"])
+    assert res <= 2e-13 and max(orth) <= 2e-13
+
+
+def test_complex_n1024_known_angles():
+    """n = 1024 (a 2048 real embedding, several Zolo-eig levels): the angles
+    of the construction, backward error and orthogonality on the device."""
+    from paper_1804_09002_amd import zcsd
+    n = 1024
+    A1, A2, meta = WL.complex_pair(n, 7)
+    a1, a2 = _t(A1), _t(A2)
+    U1, U2, V1, th, info = zcsd.csd_complex(a1, a2)
+    assert info["rank"] == n
+    truth = torch.tensor(np.sort(meta["theta"]), device=DEV)
+    assert float((th - truth).abs().max()) <= 10 * n * U
+    c = torch.cos(th).to(torch.complex128)
+    s = torch.sin(th).to(torch.complex128)
+    Vh = V1.conj().T.contiguous()
+    R = torch.cat([(U1 * c) @ Vh - a1, (U2 * s) @ Vh - a2]).cpu().numpy()
+    res = np.linalg.norm(R, 2) / np.linalg.norm(np.vstack([A1, A2]), 2)
+    I = torch.eye(n, dtype=torch.complex128, device=DEV)
+    orth = [np.linalg.norm((X.conj().T.contiguous() @ X - I).cpu().numpy(), 2) for X in (U1, U2, V1)]
+    print(f"complex n=1024: backward {res:.1e} orth {max(orth):.1e}", flush=True)
+    assert res <= 1e-13 and max(orth) <= 1e-13

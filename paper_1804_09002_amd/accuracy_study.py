@@ -66,13 +66,19 @@ def load_paper(path):
 
 def table(rows, paper=None):
     """Markdown table; with `paper` (load_paper) each measure is followed by the
-    paper's Zolo-csd value for the same class and n in parentheses."""
+    paper's figures for the same class and n in parentheses: Zolo-csd's, and
+    LAPACK's csd after a slash where Table 1 has them."""
     out = ["| class | n | rank | d(A) | ‖Â−A‖₂/d(A) | ‖U1ᵀU1−I‖₂/u | ‖U2ᵀU2−I‖₂/u | ‖V1ᵀV1−I‖₂/u |",
            "|---|---:|---:|---:|---:|---:|---:|---:|"]
     for m in rows:
         o = m["orth_u"]
         p = paper.get((m["cls"], m["n"])) if paper else None
-        z = (lambda k, f: f" ({p[k]:{f}})") if p else (lambda k, f: "")
+
+        def z(k, f):
+            if not p:
+                return ""
+            lap = p.get("lapack")
+            return f" ({p[k]:{f}} / {lap[k]:{f}})" if lap else f" ({p[k]:{f}})"
         out.append(f"| {m['cls']} | {m['n']} | {m['rank']} | {m['dA']:.1e} | {m['res_dA']:.2f}{z('res', '.2f')} | "
                    f"{o[0]:.1f}{z('U1', '.1f')} | {o[1]:.1f}{z('U2', '.1f')} | {o[2]:.1f}{z('V1', '.1f')} |")
     return "\n".join(out)
@@ -83,7 +89,7 @@ def main(argv=None):
     p.add_argument("--jmax", type=int, default=9)
     p.add_argument("--seed", type=int, default=11)
     p.add_argument("--paper", default=None,
-                   help="JSON of the paper's Zolo-csd columns (tests/golden/paper_tables_sec6.json)"
+                   help="JSON of the paper's Zolo-csd and LAPACK columns (tests/golden/paper_tables_sec6.json)"
                         " to print beside the measured values")
     a = p.parse_args(argv)
     rows = run(a.jmax, a.seed)

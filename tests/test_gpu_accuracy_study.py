@@ -7,8 +7,18 @@ residual ||A_hat - A||_2 / d(A) within a small factor of the oracle's (the
 backward stability of Theorem 4.1: the error is a modest multiple of the
 distance d(A) to the partial isometries, plus rounding), orthonormal factors
 to 1e-13, and, on the exact partial isometries (classes 1-4), the oracle's
-angles to 10 n u.
+angles to 10 n u.  Against the paper's own figures for the same class and n
+(Tables 1 and 2 of Sec. 6, tests/golden/paper_tables_sec6.json; its matrices
+are complex and random, so the comparison is of magnitudes): on the
+full-rank classes the orthogonality of U1, U2, V1 stays within 1.5x of what
+the paper measured for LAPACK's csd (the comparison system of Table 1), and
+the scaled residual within 3x of Zolo-csd's or below LAPACK's; on the
+rank-deficient classes (Table 2 has no LAPACK column) the orthogonality stays
+within 6x and the residual within 3x of Zolo-csd's figures.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 import torch
@@ -20,6 +30,8 @@ from paper_1804_09002_amd import workloads as WL
 pytestmark = pytest.mark.gpu
 U = 2.0 ** -53
 DEV = torch.device("cuda:0")
+with open(os.path.join(os.path.dirname(__file__), "golden", "paper_tables_sec6.json")) as _f:
+    PAPER = {(r["class"], r["n"]): r for r in json.load(_f)["rows"]}
 
 
 @pytest.mark.parametrize("n", [30, 85, 240])
@@ -50,3 +62,13 @@ def test_paper_class_against_oracle(cls, n):
     assert max(g["orth_u"]) * U <= 1e-13
     if not cls.endswith("'"):
         assert np.max(np.abs(th[:r] - o["theta"])) <= 10 * n * U
+    p = PAPER[(cls, n)]
+    if "lapack" in p:
+        L = p["lapack"]
+        for got, k in zip(g["orth_u"], ("U1", "U2", "V1")):
+            assert got <= 1.5 * L[k], (k, got, L[k])
+        assert g["res_dA"] <= max(3.0 * p["res"], L["res"]), (g["res_dA"], p["res"], L["res"])
+    else:
+        for got, k in zip(g["orth_u"], ("U1", "U2", "V1")):
+            assert got <= 6.0 * p[k], (k, got, p[k])
+        assert g["res_dA"] <= 3.0 * p["res"], (g["res_dA"], p["res"])

@@ -207,6 +207,38 @@ def backward_leg(count=64, n=512, seed=6):
             "backward_tflops_16n3": round(16.0 * n ** 3 * count / (t2 - t1) / 1e12, 3)}
 
 
+def complex_leg(n=2048, seed=7, reps=2):
+    """The complex CSD (zcsd_zcsd) at n = 2048, uniform angles and Haar unitary
+    factors: its real embedding has the size of the bench's real input."""
+    import numpy as np
+    import torch
+    from paper_1804_09002_amd import workloads as WL
+    from paper_1804_09002_amd import zcsd
+    A1, A2, meta = WL.complex_pair(n, seed)
+    a1 = torch.tensor(A1, dtype=torch.complex128, device="cuda:0")
+    a2 = torch.tensor(A2, dtype=torch.complex128, device="cuda:0")
+    zcsd.csd_complex(a1, a2)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        U1, U2, V1, th, info = zcsd.csd_complex(a1, a2)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    truth = torch.tensor(np.sort(meta["theta"]), device="cuda:0")
+    c = torch.cos(th).to(torch.complex128)
+    s = torch.sin(th).to(torch.complex128)
+    Vh = V1.conj().T.contiguous()
+    R = torch.cat([(U1 * c) @ Vh - a1, (U2 * s) @ Vh - a2])
+    I = torch.eye(n, dtype=torch.complex128, device="cuda:0")
+    fro = lambda X: float(torch.linalg.vector_norm(X))
+    return {"workload": f"csd_complex_fp64_n{n}_uniform_angles", "real_embedding_n": 2 * n,
+            "ms_per_csd": round(ms, 3), "rank": info["rank"],
+            "accuracy": {"max_abs_theta_err": float((th - truth).abs().max()),
+                         "backward_rel_fro": fro(R) / fro(torch.cat([a1, a2])),
+                         "orth_fro": {k: fro(X.conj().T.contiguous() @ X - I)
+                                      for k, X in (("U1", U1), ("U2", U2), ("V1", V1))}}}
+
+
 def cpu_model():
     """The host CPU's model name (Linux /proc/cpuinfo), or the platform string."""
     try:
@@ -338,6 +370,8 @@ def main():
         extra = {"mixed": mixed, "batched": batched_leg(args.batched_count, args.single_sample)}
         log("forward+backward leg: 64 x n=512")
         extra["backward"] = backward_leg()
+        log("complex leg: n=2048")
+        extra["complex"] = complex_leg()
 
     flops_model = 198.0 * n ** 3  # 67(m1+m2)n^2 + 64n^3 with m1 = m2 = n (Remark (v))
     rec = {

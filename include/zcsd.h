@@ -197,7 +197,8 @@ zcsd_status zcsd_dcsd_mn(zcsd_handle* handle, int m1, int m2, int n,
  * info->rank columns / entries valid (the rest zero).  opts may be NULL;
  * only prec = ZCSD_FP64 is accepted.  info may be NULL; it reports the rank
  * and whether Algorithm 2 replaced a polar factor.  Errors: ZCSD_EINVAL for
- * n < 1, NULL pointers, short leading dimensions or another precision;
+ * n outside [1, 32767], NULL pointers, short leading dimensions or another
+ * precision;
  * ZCSD_ENOCONV as zcsd_dcsd, or when a real angle has no partner within the
  * pairing gap; ZCSD_ENOMEM when the workspace (11 (2n)^2 doubles plus what
  * zcsd_workspace_size reports for the real path at size 2n) cannot be

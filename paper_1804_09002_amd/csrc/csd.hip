@@ -173,8 +173,11 @@ struct CsdOut {
   double t_polar = 0, t_B = 0, t_eig = 0, t_asm = 0;
 };
 
-// X <- X + X (I - X^T X) / 2 in FP64 (n x m, ld n): one Newton-Schulz step
-// towards the nearest matrix with orthonormal columns
+// X <- X - X (X^T X - I) / 2 in FP64 (n x m, ld n): one Newton-Schulz step
+// towards the nearest matrix with orthonormal columns.  The correction is
+// formed from E = X^T X - I and added to X, so that only it (not X itself)
+// carries the product's rounding: the result is orthonormal to about the
+// rounding of X^T X
 static void newton_schulz(int n, int m, double* X, Arena& ar, hipStream_t s) {
   GemmFp64Scope fp64;
   ArenaScope sc(ar);
@@ -189,13 +192,14 @@ static void newton_schulz(int n, int m, double* X, Arena& ar, hipStream_t s) {
   g.sym_upper = true;
   dgemm(g, s);
   mirror_upper(1, m, G, m, 0, s);
+  add_diag(1, m, -1.0, G, m, 0, s);
   GemmBatch h;
   h.m = n; h.n = m; h.k = m;
   h.A = X; h.lda = n;
   h.B = G; h.ldb = m;
   h.C = T; h.ldc = n;
   dgemm(h, s);
-  axpby((long long)n * m, -0.5, T, 1.5, X, s);
+  axpby((long long)n * m, -0.5, T, 1.0, X, s);
 }
 
 static CsdOut csd_run(int n, const double* A1, long long lda1, const double* A2, long long lda2,

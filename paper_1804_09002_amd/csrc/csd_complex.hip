@@ -244,7 +244,7 @@ extern "C" zcsd_status zcsd_zcsd(zcsd_handle* handle, int n, const double* d_A1,
                                  const zcsd_opts* opts, zcsd_info* info) {
   if (!handle) return ZCSD_EINVAL;
   return guarded([&] {
-    ZCSD_REQUIRE(n >= 1, "zcsd: n must be positive");
+    ZCSD_REQUIRE(n >= 1 && n <= 32767, "zcsd: n must lie in [1, 32767]");
     ZCSD_REQUIRE(d_A1 && d_A2 && d_U1 && d_U2 && d_V1 && d_theta, "zcsd: NULL pointer");
     ZCSD_REQUIRE(lda1 >= n && lda2 >= n && ldu1 >= n && ldu2 >= n && ldv1 >= n,
                  "zcsd: leading dimension < n");

@@ -121,6 +121,28 @@ zcsd_status zcsd_destroy(zcsd_handle* handle);
 zcsd_status zcsd_set_stream(zcsd_handle* handle, void* stream);
 void zcsd_default_opts(zcsd_opts* opts);
 const char* zcsd_status_string(zcsd_status s);
+/* Tuning of the batched path (zcsd_dcsd_batched), per handle; not in the
+ * paper.  The problems of a batch are grouped into size classes padded to
+ * the next multiple of a step (ZCSD_TUNE_CLASS_STEP_SMALL for n <= 64,
+ * default 8; _MID for 64 < n <= 256, default 16; _LARGE beyond, default 64),
+ * and the groups run on ZCSD_TUNE_BATCHED_WORKERS concurrent host threads,
+ * each with its own stream and workspace (default 4).  Smaller steps pad less
+ * but make more groups; more workers overlap more latency-bound chains but
+ * hold more workspace and compete for the device.  The defaults are the best
+ * measured on 2048 problems with n log-uniform in [8, 256];
+ * paper_1804_09002_amd/autotune.py measures the settings for another
+ * workload.  zcsd_set_tuning returns ZCSD_EINVAL for an unknown key, workers
+ * outside [1, 16] or a step outside [1, 256]; it takes effect on the next
+ * batched call of the handle. */
+typedef enum {
+  ZCSD_TUNE_BATCHED_WORKERS = 0,
+  ZCSD_TUNE_CLASS_STEP_SMALL = 1,
+  ZCSD_TUNE_CLASS_STEP_MID = 2,
+  ZCSD_TUNE_CLASS_STEP_LARGE = 3
+} zcsd_tune_key;
+zcsd_status zcsd_set_tuning(zcsd_handle* handle, int key, int value);
+zcsd_status zcsd_get_tuning(zcsd_handle* handle, int key, int* value);
+
 /* sizeof(zcsd_opts) and sizeof(zcsd_info) as this library was built: a
  * binding that lays the structs out itself checks them before any call that
  * reads or writes one (a mismatch would make the library write past the
@@ -188,8 +210,12 @@ zcsd_status zcsd_dcsd_mn(zcsd_handle* handle, int m1, int m2, int n,
  * Algorithm 1 / 3 on the 2n x 2n real blocks, whose angles are those of A
  * twice; the complex columns are read from one real column of each pair,
  * repeated complex angles get a complex-orthonormal basis of their cluster,
- * and Newton-Schulz steps on the embedded V1 (the same right factor on U1
- * and U2) make the columns complex-orthonormal to rounding.
+ * Newton-Schulz steps on the embedded V1 (the same right factor on U1 and
+ * U2) make the columns complex-orthonormal, U1 and U2 then get correction
+ * steps of their own that change each column only by better-determined ones
+ * (larger cos theta for U1, sin theta for U2), columns that A leaves
+ * undetermined (cos or sin below 2^-46) are completed orthonormally, and the
+ * angles are recomputed from the final factors.
  * Memory: column-major device arrays of interleaved complex doubles
  * (re, im), as std::complex<double> / hipDoubleComplex; leading dimensions
  * count complex elements (>= n).  d_A1, d_A2 are read only; d_U1, d_U2,

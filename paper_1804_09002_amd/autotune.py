@@ -1,0 +1,112 @@
+"""Autotuner of the batched path (zcsd_dcsd_batched) for a workload.
+
+    python -m paper_1804_09002_amd.autotune [--count 2048] [--lo 8] [--hi 256]
+        [--seed 5] [--reps 3] [--out tuning.json]
+
+The batched path groups problems into size classes padded to a multiple of a
+step and runs the groups on several worker streams (include/zcsd.h,
+zcsd_set_tuning).  For a synthetic workload with the given size distribution
+(n log-uniform in [lo, hi], uniform angles, as the bench's batched leg), this
+times one batched call per candidate setting after two warm-up calls (mean of
+`reps` calls): first the number of workers at the default steps, then the
+class steps at the best number of workers (coordinate descent).  It prints
+the timings and writes the best setting with them to `--out` as JSON;
+`apply(path)` sets a written file's setting on the current device's handle.
+The library's defaults are this search's result for the bench workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import time
+
+WORKERS = (1, 2, 3, 4, 6, 8)
+STEPS = ((4, 8, 32), (8, 16, 64), (8, 32, 64), (16, 16, 64), (16, 32, 64))
+
+
+def workload(count, lo, hi, seed):
+    import numpy as np
+    import torch
+
+    from . import workloads as WL
+    from . import zcsd
+    sizes = [int(n) for n in WL.batched_sizes(count, seed, lo, hi)]
+    rng = np.random.default_rng(seed)
+    A1s, A2s = [], []
+    for n in sizes:
+        A1, A2, _ = WL.uniform_pair(n, int(rng.integers(1 << 31)))
+        A1s.append(torch.tensor(A1, device="cuda:0"))
+        A2s.append(torch.tensor(A2, device="cuda:0"))
+    a1, sizes, offs = zcsd.pack_ragged(A1s)
+    a2, _, _ = zcsd.pack_ragged(A2s)
+    return a1, a2, sizes, offs
+
+
+def time_setting(data, setting, reps):
+    import torch
+
+    from . import zcsd
+    zcsd.set_tuning(**setting)
+    a1, a2, sizes, offs = data
+    for _ in range(2):
+        zcsd.csd_batched_packed(a1, a2, sizes, offs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        zcsd.csd_batched_packed(a1, a2, sizes, offs)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def search(count=2048, lo=8, hi=256, seed=5, reps=3, workers=WORKERS, steps=STEPS, log=print):
+    from . import zcsd
+    data = workload(count, lo, hi, seed)
+    start = zcsd.get_tuning()
+    timings = []
+
+    def run(setting):
+        t = time_setting(data, setting, reps)
+        timings.append({**setting, "seconds": round(t, 5)})
+        log(f"{setting}: {t * 1e3:.2f} ms")
+        return t
+
+    base_steps = dict(class_step_small=start["class_step_small"], class_step_mid=start["class_step_mid"],
+                      class_step_large=start["class_step_large"])
+    best_w = min(workers, key=lambda w: run(dict(batched_workers=w, **base_steps)))
+    best = None
+    for st in steps:
+        setting = dict(batched_workers=best_w, class_step_small=st[0], class_step_mid=st[1],
+                       class_step_large=st[2])
+        t = run(setting)
+        if best is None or t < best[1]:
+            best = (setting, t)
+    zcsd.set_tuning(**start)
+    return {"workload": {"count": count, "lo": lo, "hi": hi, "seed": seed},
+            "best": best[0], "best_seconds": round(best[1], 5), "timings": timings}
+
+
+def apply(path, device=None):
+    """Set the best setting of a file written by this tool on the device's handle."""
+    from . import zcsd
+    with open(path) as f:
+        zcsd.set_tuning(device, **json.load(f)["best"])
+
+
+def main(argv=None):
+    p = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    p.add_argument("--count", type=int, default=2048)
+    p.add_argument("--lo", type=int, default=8)
+    p.add_argument("--hi", type=int, default=256)
+    p.add_argument("--seed", type=int, default=5)
+    p.add_argument("--reps", type=int, default=3)
+    p.add_argument("--out", default=None)
+    a = p.parse_args(argv)
+    res = search(a.count, a.lo, a.hi, a.seed, a.reps)
+    print(json.dumps({"best": res["best"], "best_seconds": res["best_seconds"]}))
+    if a.out:
+        with open(a.out, "w") as f:
+            json.dump(res, f, indent=1)
+
+
+if __name__ == "__main__":
+    main()

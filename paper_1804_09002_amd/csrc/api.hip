@@ -55,6 +55,40 @@ zcsd_status zcsd_set_stream(zcsd_handle* handle, void* stream) {
   return ZCSD_OK;
 }
 
+zcsd_status zcsd_set_tuning(zcsd_handle* handle, int key, int value) {
+  if (!handle) return ZCSD_EINVAL;
+  switch (key) {
+    case ZCSD_TUNE_BATCHED_WORKERS:
+      if (value < 1 || value > 16) return ZCSD_EINVAL;
+      handle->tune_workers = value;
+      return ZCSD_OK;
+    case ZCSD_TUNE_CLASS_STEP_SMALL:
+    case ZCSD_TUNE_CLASS_STEP_MID:
+    case ZCSD_TUNE_CLASS_STEP_LARGE:
+      if (value < 1 || value > 256) return ZCSD_EINVAL;
+      handle->tune_step[key - ZCSD_TUNE_CLASS_STEP_SMALL] = value;
+      return ZCSD_OK;
+    default:
+      return ZCSD_EINVAL;
+  }
+}
+
+zcsd_status zcsd_get_tuning(zcsd_handle* handle, int key, int* value) {
+  if (!handle || !value) return ZCSD_EINVAL;
+  switch (key) {
+    case ZCSD_TUNE_BATCHED_WORKERS:
+      *value = handle->tune_workers;
+      return ZCSD_OK;
+    case ZCSD_TUNE_CLASS_STEP_SMALL:
+    case ZCSD_TUNE_CLASS_STEP_MID:
+    case ZCSD_TUNE_CLASS_STEP_LARGE:
+      *value = handle->tune_step[key - ZCSD_TUNE_CLASS_STEP_SMALL];
+      return ZCSD_OK;
+    default:
+      return ZCSD_EINVAL;
+  }
+}
+
 size_t zcsd_sizeof_opts(void) { return sizeof(zcsd_opts); }
 size_t zcsd_sizeof_info(void) { return sizeof(zcsd_info); }
 

@@ -198,12 +198,11 @@ T* upload_vec(Arena& ar, const std::vector<T>& v, hipStream_t s) {
 
 }  // namespace
 
-// padded size of a problem of size n: multiples of 8 up to 64, of 16 up to 256,
-// of 64 beyond
-int batched_class_size(int n) {
-  if (n <= 64) return std::max(8, (n + 7) / 8 * 8);
-  if (n <= 256) return (n + 15) / 16 * 16;
-  return (n + 63) / 64 * 64;
+// padded size of a problem of size n: the next multiple of step[0] up to 64
+// (8 by default), of step[1] up to 256 (16), of step[2] beyond (64)
+int batched_class_size(int n, const int step[3]) {
+  const int st = n <= 64 ? step[0] : (n <= 256 ? step[1] : step[2]);
+  return (n + st - 1) / st * st;
 }
 
 // arena bytes of one group of K problems of class size N: the iterates and
@@ -244,7 +243,6 @@ struct BatchedStats {
 // launches and host decisions that leaves much of the GPU idle for the small
 // classes: up to this many run at once, each on its own host thread, stream
 // and arena (the box's hardware queues per process: 4).
-constexpr int kBatchedWorkers = 4;
 
 // One group: members of one size class with the same rank mode.  Returns
 // false, having written nothing, when a full-rank group's shared lower bound
@@ -474,9 +472,11 @@ extern "C" zcsd_status zcsd_dcsd_batched(zcsd_handle* handle, int batch, const i
     ar.reset();
     // classes and the workspace of the largest chunk
     std::map<int, std::vector<int>> cls;
-    for (int k = 0; k < batch; ++k) cls[batched_class_size(n_host[k])].push_back(k);
+    for (int k = 0; k < batch; ++k)
+      cls[batched_class_size(n_host[k], handle->tune_step)].push_back(k);
     // workspace ceiling per chunk (each of the concurrent workers holds one)
-    const size_t cap_bytes = ((size_t)48 << 30) / kBatchedWorkers;
+    const int n_workers = std::max(1, handle->tune_workers);
+    const size_t cap_bytes = ((size_t)48 << 30) / n_workers;
     // members per chunk: the workspace ceiling, and the launch grids of the
     // polars, whose second dimension (<= 65535) enumerates 2 polars x r <= 8
     // terms per member
@@ -543,7 +543,7 @@ extern "C" zcsd_status zcsd_dcsd_batched(zcsd_handle* handle, int batch, const i
       }
     }
     // largest cost first onto the least loaded worker
-    const int W = std::max(1, std::min<int>(kBatchedWorkers, (int)groups.size()));
+    const int W = std::max(1, std::min<int>(n_workers, (int)groups.size()));
     std::vector<int> order(groups.size());
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(),

@@ -91,6 +91,10 @@ struct zcsd_handle_s {
   // pinned host staging for small readbacks
   double* h_stage = nullptr;
   size_t h_stage_count = 0;
+  // batched-path tuning (zcsd_set_tuning): concurrent worker streams, and the
+  // size-class steps for n <= 64, 64 < n <= 256 and n > 256
+  int tune_workers = 4;
+  int tune_step[3] = {8, 16, 64};
 };
 
 namespace zcsd {

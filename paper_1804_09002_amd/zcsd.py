@@ -94,6 +94,8 @@ def _lib():
             "zcsd_dcsd_batched": [vp, i, C.POINTER(C.c_int), C.POINTER(C.c_longlong), vp, vp, vp, vp,
                                   vp, vp, C.POINTER(C.c_int), C.POINTER(Opts), C.POINTER(Info)],
             "zcsd_zolo_coeffs": [d, i, C.POINTER(d), C.POINTER(d), C.POINTER(d), C.POINTER(d)],
+            "zcsd_set_tuning": [vp, i, i],
+            "zcsd_get_tuning": [vp, i, C.POINTER(C.c_int)],
             "zcsd_zolo_choose_r": [d, d],
             "zcsd_workspace_size": [vp, i, C.POINTER(Opts), C.POINTER(C.c_size_t)],
             "zcsd_dqr": [vp, i, i, i, i, vp, i, ll, vp, i, ll],
@@ -149,6 +151,30 @@ def handle(device=None):
         _HANDLES[dev] = h
     _lib().zcsd_set_stream(h, C.c_void_p(torch.cuda.current_stream(dev).cuda_stream))
     return h
+
+
+TUNE_BATCHED_WORKERS, TUNE_CLASS_STEP_SMALL, TUNE_CLASS_STEP_MID, TUNE_CLASS_STEP_LARGE = range(4)
+TUNE_KEYS = {"batched_workers": TUNE_BATCHED_WORKERS, "class_step_small": TUNE_CLASS_STEP_SMALL,
+             "class_step_mid": TUNE_CLASS_STEP_MID, "class_step_large": TUNE_CLASS_STEP_LARGE}
+
+
+def set_tuning(device=None, **values):
+    """Batched-path tuning of the device's handle (zcsd_set_tuning), e.g.
+    set_tuning(batched_workers=4, class_step_small=8, class_step_mid=16)."""
+    h = handle(device)
+    for k, v in values.items():
+        _check(_lib().zcsd_set_tuning(h, TUNE_KEYS[k], int(v)), f"zcsd_set_tuning({k}={v})")
+
+
+def get_tuning(device=None):
+    """The batched-path tuning of the device's handle, as a dict."""
+    h = handle(device)
+    out = {}
+    for k, key in TUNE_KEYS.items():
+        v = C.c_int(0)
+        _check(_lib().zcsd_get_tuning(h, key, C.byref(v)), "zcsd_get_tuning")
+        out[k] = v.value
+    return out
 
 
 def default_opts(**kw):

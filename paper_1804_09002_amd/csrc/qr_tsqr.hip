@@ -69,14 +69,6 @@ __device__ __forceinline__ double swizzle_f64(double v) {
   return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
 }
 
-// lane l reads lane src (0..63)
-__device__ __forceinline__ double bperm_f64(double v, int src) {
-  const long long b = __double_as_longlong(v);
-  const int lo = __builtin_amdgcn_ds_bpermute(src << 2, (int)b);
-  const int hi = __builtin_amdgcn_ds_bpermute(src << 2, (int)(b >> 32));
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
-
 __device__ __forceinline__ double readlane_f64(double v, int l) {
   const long long b = __double_as_longlong(v);
   const int lo = __builtin_amdgcn_readlane((int)b, l);
@@ -238,13 +230,15 @@ __device__ __forceinline__ void ql_householder_step(double (&a)[RQ][4], double (
     for (int q = 0; q < 4; ++q) pr[4 * g + q] = a[rt][q];  // the pivot row a(t, :)
   }
   __syncthreads();
-  double dsel = (rb[jsel] + rb[TS_W + jsel]) + (rb[2 * TS_W + jsel] + rb[3 * TS_W + jsel]);
-  if constexpr (NW == 8)
-    dsel += (rb[4 * TS_W + jsel] + rb[5 * TS_W + jsel]) + (rb[6 * TS_W + jsel] + rb[7 * TS_W + jsel]);
+  // the totals of the lane's own four columns, read straight from the waves'
+  // partial sums (one LDS round trip; summed in the same order as before)
   double d[4], at[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    d[q] = bperm_f64(dsel, g + 16 * q);  // lane g + 16 q holds column 4g + q
+    const double* c = rb + 4 * g + q;
+    double v = (c[0] + c[TS_W]) + (c[2 * TS_W] + c[3 * TS_W]);
+    if constexpr (NW == 8) v += (c[4 * TS_W] + c[5 * TS_W]) + (c[6 * TS_W] + c[7 * TS_W]);
+    d[q] = v;
     at[q] = pr[4 * g + q];
   }
   const double dt = readlane_f64(d[qt], gt), alpha = readlane_f64(at[qt], gt);

@@ -237,6 +237,25 @@ zcsd_status zcsd_zcsd(zcsd_handle* handle, int n,
                       const zcsd_opts* opts, zcsd_info* info);
 
 /*
+ * zcsd_zcsd with rectangular complex blocks, A1 m1 x n and A2 m2 x n,
+ * m1, m2 >= n (the paper's general setting, Sec. 1): U1 (m1 x n) and U2
+ * (m2 x n) with orthonormal columns, V1 (n x n).  The real embeddings
+ * (2 m_i x 2n) are reduced by Householder QRs E_i = Q_i R_i, the square real
+ * path runs on [R1; R2] and U_i = Q_i U_i', then the complex factors are read
+ * back as for zcsd_zcsd.  Interleaved complex column-major arrays as there:
+ * d_A1 (ld >= m1), d_A2 (ld >= m2) read only; d_U1 (ld >= m1), d_U2
+ * (ld >= m2), d_V1 (ld >= n), d_theta (n reals) written, the first
+ * info->rank columns / entries valid.  Errors: ZCSD_EINVAL for n < 1,
+ * m_i < n, m_i > 32767, NULL pointers, short leading dimensions or another
+ * precision; otherwise as zcsd_zcsd.
+ */
+zcsd_status zcsd_zcsd_mn(zcsd_handle* handle, int m1, int m2, int n,
+                         const double* d_A1, int lda1, const double* d_A2, int lda2,
+                         double* d_U1, int ldu1, double* d_U2, int ldu2,
+                         double* d_V1, int ldv1, double* d_theta,
+                         const zcsd_opts* opts, zcsd_info* info);
+
+/*
  * Complete 2 x 2 CS decomposition of an orthogonal 2n x 2n matrix
  * A = [A1 A3; A2 A4] (Remark (viii) of Sec. 3):
  *    A = diag(U1, U2) [C -S; S C] diag(V1, V2)^T,  C = diag(cos theta),

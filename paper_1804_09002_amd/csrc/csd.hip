@@ -559,8 +559,8 @@ extern "C" zcsd_status zcsd_workspace_size(zcsd_handle* handle, int n, const zcs
 
 // Householder QR of the m x n block A (m >= n): Q (m x n, ld m) and the n x n
 // triangular factor R (ld n; geqrf leaves zeros below the diagonal)
-static void tall_qr(int m, int n, const double* A, long long lda, double* Q, double* R, Arena& ar,
-                    hipStream_t s) {
+void zcsd::tall_qr(int m, int n, const double* A, long long lda, double* Q, double* R, Arena& ar,
+                   hipStream_t s) {
   ArenaScope sc(ar);
   const long long mn = (long long)m * n;
   double* M = ar.dalloc((size_t)mn);

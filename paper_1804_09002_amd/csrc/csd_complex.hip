@@ -54,20 +54,21 @@
 #include "zcsd_api_guard.h"
 #include "zcsd_eig.h"
 #include "zcsd_internal.h"
+#include "zcsd_la.h"
 
 namespace zcsd {
 namespace {
 
-// E (2n x 2n, ld 2n) = [Re A  -Im A; Im A  Re A], A interleaved complex (ld lda)
-__global__ void complex_embed_kernel(int n, const double* __restrict__ A, long long lda,
+// E (2m x 2n, ld 2m) = [Re A  -Im A; Im A  Re A], A m x n interleaved complex (ld lda)
+__global__ void complex_embed_kernel(int m, int n, const double* __restrict__ A, long long lda,
                                      double* __restrict__ E) {
-  const long long N = 2LL * n;
-  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < N * N;
+  const long long M2 = 2LL * m, total = M2 * 2 * n;
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < total;
        e += (long long)gridDim.x * blockDim.x) {
-    const int r = (int)(e % N), c = (int)(e / N);
-    const long long src = 2 * ((r % n) + (long long)(c % n) * lda);
+    const int r = (int)(e % M2), c = (int)(e / M2);
+    const long long src = 2 * ((r % m) + (long long)(c % n) * lda);
     const double re = A[src], im = A[src + 1];
-    const bool top = r < n, left = c < n;
+    const bool top = r < m, left = c < n;
     E[e] = (top == left) ? re : (top ? -im : im);
   }
 }
@@ -83,10 +84,10 @@ __global__ void gather_columns_kernel(long long rows, const double* __restrict__
     dst[i] = src[i];
 }
 
-// P = [Y, J Y]: Y is 2n x r (ld 2n), P is 2n x 2r (ld 2n), J [a; b] = [-b; a]
-__global__ void with_j_image_kernel(int n, int r, const double* __restrict__ Y,
+// P = [Y, J Y]: Y is 2h x r (ld 2h), P is 2h x 2r (ld 2h), J [a; b] = [-b; a]
+__global__ void with_j_image_kernel(int h, int r, const double* __restrict__ Y,
                                     double* __restrict__ P) {
-  const long long N = 2LL * n;
+  const long long N = 2LL * h;
   const int k = blockIdx.y;
   const double* y = Y + (long long)k * N;
   double* p0 = P + (long long)k * N;
@@ -94,21 +95,21 @@ __global__ void with_j_image_kernel(int n, int r, const double* __restrict__ Y,
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < N;
        i += (long long)gridDim.x * blockDim.x) {
     p0[i] = y[i];
-    p1[i] = (i < n) ? -y[i + n] : y[i - n];
+    p1[i] = (i < h) ? -y[i + h] : y[i - h];
   }
 }
 
-// complex column k of Z (interleaved, ld ldz) = Y(0:n, j) + i Y(n:2n, j) with
-// j = perm[k] for k < r, zero for r <= k < n; k = blockIdx.y
-__global__ void to_complex_kernel(int n, int r, const double* __restrict__ Y,
+// complex column k of Z (h rows, interleaved, ld ldz) = Y(0:h, j) + i Y(h:2h, j)
+// with j = perm[k] for k < r, zero for k >= r; Y is 2h x r (ld 2h); k = blockIdx.y
+__global__ void to_complex_kernel(int h, int r, const double* __restrict__ Y,
                                   const int* __restrict__ perm, double* __restrict__ Z,
                                   long long ldz) {
   const int k = blockIdx.y;
   double* z = Z + 2LL * k * ldz;
-  const double* y = Y + 2LL * (k < r ? perm[k] : 0) * n;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+  const double* y = Y + 2LL * (k < r ? perm[k] : 0) * h;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < h; i += gridDim.x * blockDim.x) {
     z[2 * i] = k < r ? y[i] : 0.0;
-    z[2 * i + 1] = k < r ? y[n + i] : 0.0;
+    z[2 * i + 1] = k < r ? y[h + i] : 0.0;
   }
 }
 
@@ -225,12 +226,344 @@ std::vector<double> distinct_diagonal(int p) {
   return d;
 }
 
-// embedding 2NN, real factors 3NN, selected columns 3NN/2, Newton-Schulz Gram
-// NN/2, cluster matrices up to 4NN (2m <= 2n), the real path's workspace
-size_t complex_workspace_bytes(int n) {
-  const long long N = 2LL * n, NN = N * N;
-  return csd_workspace_bytes((int)N) + (size_t)(11 * NN + 16 * N) * sizeof(double) +
+// doubles held at once: the embeddings, the real factors, the selected
+// columns and the angles for the whole call; then, one phase at a time, the
+// blocks' QR reduction (rectangular blocks), the cluster matrices (up to
+// four (2n)^2), the re-orthonormalisation and completion temporaries and the
+// angle products (all below 8 (2n)^2 + 6 (2 max(m1, m2)) (2n)); plus the real
+// path's workspace at 2n and the QR workspace
+size_t complex_workspace_bytes(int m1, int m2, int n) {
+  const long long N = 2LL * n, NN = N * N, mx = 2LL * std::max(m1, m2);
+  const long long rows = 2LL * m1 + 2LL * m2 + N;
+  const long long held = (2LL * m1 + 2LL * m2) * N + rows * N + rows * n + 2 * N;
+  const long long qr = (m1 == n && m2 == n) ? 0 : (2LL * m1 + 2LL * m2) * N + 4 * NN + mx * N;
+  const long long phase = std::max(qr, 8 * NN + 6 * mx * N);
+  return csd_workspace_bytes((int)N) + (size_t)(held + phase) * sizeof(double) +
+         ((m1 == n && m2 == n) ? 0 : qr_work_bytes(QRShape::General, 1, (int)mx, (int)N, 32)) +
          ((size_t)64 << 20);
+}
+
+}  // namespace
+}  // namespace zcsd
+
+using namespace zcsd;
+
+namespace zcsd {
+namespace {
+
+// Algorithm 1 / 3 on the real embedding of complex A1 (m1 x n), A2 (m2 x n),
+// m1, m2 >= n, and the read-back of the complex factors (see the top of the file)
+void complex_csd(zcsd_handle* handle, int m1, int m2, int n, const double* d_A1, long long lda1,
+                 const double* d_A2, long long lda2, double* d_U1, long long ldu1, double* d_U2,
+                 long long ldu2, double* d_V1, long long ldv1, double* d_theta, const zcsd_opts& o,
+                 zcsd_info* info) {
+  ZCSD_REQUIRE(o.prec == ZCSD_FP64, "zcsd: complex input is computed in the FP64 mode only");
+  ZCSD_HIP(hipSetDevice(handle->device));
+  const int N = 2 * n;
+  const long long NN = (long long)N * N;
+  // factors q = 0 (U1), 1 (U2), 2 (V1): rows of the real factor, half of them
+  const long long rows[3] = {2LL * m1, 2LL * m2, N};
+  const int half[3] = {m1, m2, n};
+  Arena& ar = handle->arena;
+  ar.reset();
+  ar.reserve(complex_workspace_bytes(m1, m2, n));
+  hipStream_t s = handle->stream;
+  double* E[2] = {ar.dalloc((size_t)rows[0] * N), ar.dalloc((size_t)rows[1] * N)};
+  double* R[3];  // the real factors (rows[q] x N), later scratch for [Y, JY]
+  double* Y[3];  // the selected columns (rows[q] x n)
+  for (int q = 0; q < 3; ++q) R[q] = ar.dalloc((size_t)rows[q] * N);
+  for (int q = 0; q < 3; ++q) Y[q] = ar.dalloc((size_t)rows[q] * n);
+  double* th = ar.dalloc(N);
+  const double* A[2] = {d_A1, d_A2};
+  const long long lda[2] = {lda1, lda2};
+  for (int i = 0; i < 2; ++i) {
+    hipLaunchKernelGGL(complex_embed_kernel, dim3(grid_for(rows[i] * N)), dim3(256), 0, s, half[i],
+                       n, A[i], lda[i], E[i]);
+    ZCSD_CHECK_LAUNCH();
+  }
+  bool repaired = false;
+  int rank2;
+  if (m1 == n && m2 == n) {
+    rank2 = csd_single_member(N, E[0], E[1], R[0], R[1], R[2], th, o, ar, s, &repaired);
+  } else {
+    // rectangular blocks: E_i = Q_i R_i, the square path on [R_1; R_2] (a
+    // partial isometry with the same angles and V1), U_i = Q_i U_i'
+    ArenaScope sc(ar);
+    double* Qt[2] = {ar.dalloc((size_t)rows[0] * N), ar.dalloc((size_t)rows[1] * N)};
+    double* Rt = ar.dalloc(2 * (size_t)NN);
+    double* Up = ar.dalloc(2 * (size_t)NN);
+    for (int i = 0; i < 2; ++i) tall_qr((int)rows[i], N, E[i], rows[i], Qt[i], Rt + i * NN, ar, s);
+    rank2 = csd_single_member(N, Rt, Rt + NN, Up, Up + NN, R[2], th, o, ar, s, &repaired);
+    for (int i = 0; i < 2; ++i)
+      gemm(0, 0, (int)rows[i], N, N, 1.0, Qt[i], rows[i], Up + i * NN, N, 0.0, R[i], rows[i], s);
+  }
+  if (rank2 % 2) throw NumError(ZCSD_ENOCONV, "zcsd: odd rank of the real embedding");
+  const int r = rank2 / 2;
+  std::vector<double> thh(std::max(1, rank2));
+  if (rank2) d2h(thh.data(), th, rank2 * sizeof(double), s);
+
+  // 1. clusters of real angles: consecutive gaps within the pairing gap
+  const double pair_gap = 0x1p-40 * (1.0 + N / 1024.0);
+  struct Cluster { int begin, end; };
+  std::vector<Cluster> cl;
+  for (int j = 0; j < rank2;) {
+    int e = j + 1;
+    while (e < rank2 && thh[e] - thh[e - 1] <= pair_gap) ++e;
+    if ((e - j) % 2)
+      throw NumError(ZCSD_ENOCONV, "zcsd: an angle of the real embedding without its pair");
+    cl.push_back({j, e});
+    j = e;
+  }
+  // 2. the first real column of every pair
+  std::vector<int> col(std::max(1, r), 0);
+  {
+    int k = 0;
+    for (const Cluster& c : cl)
+      for (int j = c.begin; j < c.end; j += 2) col[k++] = j;
+  }
+  if (r > 0) {
+    int* d_col = ar.ialloc(r);
+    h2d(d_col, col.data(), r * sizeof(int), s);
+    for (int q = 0; q < 3; ++q) {
+      hipLaunchKernelGGL(gather_columns_kernel, dim3(grid_for(rows[q]), r), dim3(256), 0, s,
+                         rows[q], R[q], d_col, Y[q]);
+      ZCSD_CHECK_LAUNCH();
+    }
+  }
+  // 3. clusters of complex multiplicity m > 1: a complex-orthonormal basis
+  {
+    int k = 0;
+    for (const Cluster& c : cl) {
+      const int p = c.end - c.begin, m = p / 2;
+      if (m > 1) {
+        ArenaScope scope(ar);
+        const long long pp = (long long)p * p;
+        double* M = ar.dalloc(pp);
+        double* P = ar.dalloc(pp);
+        double* T = ar.dalloc(pp);
+        double* Q = ar.dalloc(pp);
+        double* lam = ar.dalloc(p);
+        double* dd = ar.dalloc(p);
+        const double* X = R[2] + (long long)c.begin * N;  // V1 columns of the cluster
+        // M = X^T J X = Xb^T Xt - Xt^T Xb  (X = [Xt; Xb])
+        gemm(1, 0, p, p, n, 1.0, X + n, N, X, N, 0.0, M, p, s);
+        gemm(1, 0, p, p, n, -1.0, X, N, X + n, N, 1.0, M, p, s);
+        // T = M^T (D M) + D
+        const std::vector<double> d = distinct_diagonal(p);
+        h2d(dd, d.data(), p * sizeof(double), s);
+        hipLaunchKernelGGL(row_scale_kernel, dim3(grid_for(pp)), dim3(256), 0, s, p, dd, M, P);
+        ZCSD_CHECK_LAUNCH();
+        gemm(1, 0, p, p, p, 1.0, M, p, P, p, 0.0, T, p, s);
+        hipLaunchKernelGGL(add_diag_vec_kernel, dim3((p + 255) / 256), dim3(256), 0, s, p, dd, T);
+        ZCSD_CHECK_LAUNCH();
+        symmetrize(1, p, T, p, 0, s);
+        // D and M^T D M both have their spectrum in [1, 2]
+        ZoloEigArgs ea;
+        ea.n = p;
+        ea.B = T;
+        ea.ldb = p;
+        ea.lo = 1.99;
+        ea.hi = 4.01;
+        ea.V = Q;
+        ea.ldv = p;
+        ea.lam = lam;
+        ea.n_leaf = o.n_leaf;
+        ea.eps = o.eps;
+        ea.tol = o.tol;
+        ea.measure_offblock = false;
+        zolo_eig(ea, ar, s);
+        // one eigenvector of each pair: columns 0, 2, 4, ... (ld 2p)
+        for (int q = 0; q < 3; ++q)
+          gemm(0, 0, (int)rows[q], m, p, 1.0, R[q] + (long long)c.begin * rows[q], rows[q], Q,
+               2LL * p, 0.0, Y[q] + (long long)k * rows[q], rows[q], s);
+      }
+      k += m;
+    }
+  }
+  // 4. complex orthonormality of the factors (items 4 and 5 above)
+  if (r > 0) {
+    // angle of each complex column: its cluster's mean (ascending)
+    std::vector<double> thk(r);
+    {
+      int k = 0;
+      for (const Cluster& c : cl) {
+        double mean = 0.0;
+        for (int j = c.begin; j < c.end; ++j) mean += thh[j];
+        mean /= (c.end - c.begin);
+        for (int j = c.begin; j < c.end; j += 2) thk[k++] = mean;
+      }
+    }
+    // columns whose U1 (cos below tau: a suffix) or U2 (sin below tau: a
+    // prefix) column A leaves undetermined
+    const double tau = 0x1p-46;
+    int t1 = 0, t2 = 0;
+    for (int k = 0; k < r; ++k) {
+      if (std::cos(thk[k]) < tau) ++t1;
+      if (std::sin(thk[k]) < tau) ++t2;
+    }
+    ArenaScope scope(ar);
+    double* G = ar.dalloc(2LL * r * r);  // 2 cnt x cnt, ld 2 cnt
+    double* ss = ar.dalloc(1);
+    // Correction steps on columns [c0, c0 + cnt) of the factors in `apply`,
+    // from the complex Gram matrix of factor gq on those columns, G = I + E:
+    // mode 0 multiplies by I - E/2 (Newton-Schulz), mode 1 by
+    // I - diag(E)/2 - triu(E, 1) and mode 2 by I - diag(E)/2 - tril(E, -1)
+    // (first-order inverse Cholesky factors: a column is corrected only by
+    // the columns before it, resp. after it).  Returns the last ||E||_F, or 0
+    // once a step was taken from ||E||_F < 1e-8 (leaving O(||E||^2)).
+    auto correct = [&](int gq, std::initializer_list<int> apply, int c0, int cnt, int mode,
+                       int max_steps) {
+      double eta = 0.0;
+      const long long ldg = 2LL * cnt;
+      for (int step = 0; step < max_steps; ++step) {
+        for (int q : apply) {
+          hipLaunchKernelGGL(with_j_image_kernel, dim3(grid_for(rows[q]), cnt), dim3(256), 0, s,
+                             half[q], cnt, Y[q] + (long long)c0 * rows[q], R[q]);
+          ZCSD_CHECK_LAUNCH();
+        }
+        gemm(1, 0, 2 * cnt, cnt, (int)rows[gq], 1.0, R[gq], rows[gq],
+             Y[gq] + (long long)c0 * rows[gq], rows[gq], 0.0, G, ldg, s);
+        add_diag(1, cnt, -1.0, G, ldg, 0, s);
+        sumsq(1, 2 * cnt, cnt, G, ldg, 0, ss, ar, s);
+        double eta2 = 0.0;
+        d2h(&eta2, ss, sizeof(double), s);
+        if (!std::isfinite(eta2)) throw NumError(ZCSD_ENOCONV, "zcsd: non-finite factor");
+        eta = std::sqrt(eta2);
+        hipLaunchKernelGGL(correction_factor_kernel, dim3(grid_for(2LL * cnt * cnt)), dim3(256), 0,
+                           s, cnt, mode, G);
+        ZCSD_CHECK_LAUNCH();
+        for (int q : apply)
+          gemm(0, 0, (int)rows[q], cnt, 2 * cnt, 1.0, R[q], rows[q], G, ldg, 0.0,
+               Y[q] + (long long)c0 * rows[q], rows[q], s);
+        if (eta < 1e-8) return 0.0;
+      }
+      return eta;
+    };
+    // any complex-orthonormal basis of t columns orthogonal to the cnt
+    // columns at cg of factor q, written at cb: the polar factor of the
+    // projection of complex Gaussian columns, through the eigendecomposition
+    // of the embedded Gram matrix (a function of it, hence itself embedded)
+    auto complete = [&](int q, int cb, int t, int cg, int cnt) {
+      ArenaScope sc(ar);
+      const long long rq = rows[q];
+      double* Om = ar.dalloc((size_t)rq * t);
+      hipLaunchKernelGGL(gaussian_fill_kernel, dim3(grid_for(rq * t)), dim3(256), 0, s, rq * t,
+                         0x5eedULL + 977ULL * q, Om);
+      ZCSD_CHECK_LAUNCH();
+      if (cnt > 0) {
+        double* Tm = ar.dalloc(2LL * cnt * t);
+        hipLaunchKernelGGL(with_j_image_kernel, dim3(grid_for(rq), cnt), dim3(256), 0, s, half[q],
+                           cnt, Y[q] + (long long)cg * rq, R[q]);
+        ZCSD_CHECK_LAUNCH();
+        for (int pass = 0; pass < 2; ++pass) {
+          gemm(1, 0, 2 * cnt, t, (int)rq, 1.0, R[q], rq, Om, rq, 0.0, Tm, 2LL * cnt, s);
+          gemm(0, 0, (int)rq, t, 2 * cnt, -1.0, R[q], rq, Tm, 2LL * cnt, 1.0, Om, rq, s);
+        }
+      }
+      const int p = 2 * t;
+      const long long pp = (long long)p * p;
+      double* PJ = ar.dalloc((size_t)rq * p);
+      double* G2 = ar.dalloc(pp);
+      double* Q = ar.dalloc(pp);
+      double* Qs = ar.dalloc(pp);
+      double* lam = ar.dalloc(p);
+      double* Mt = ar.dalloc((size_t)p * t);
+      double* nrm = ar.dalloc(1);
+      hipLaunchKernelGGL(with_j_image_kernel, dim3(grid_for(rq), t), dim3(256), 0, s, half[q], t, Om,
+                         PJ);
+      ZCSD_CHECK_LAUNCH();
+      gemm(1, 0, p, p, (int)rq, 1.0, PJ, rq, PJ, rq, 0.0, G2, p, s);
+      symmetrize(1, p, G2, p, 0, s);
+      sumsq(1, p, p, G2, p, 0, nrm, ar, s);
+      double f2 = 0.0;
+      d2h(&f2, nrm, sizeof(double), s);
+      const double hi = 1.01 * std::sqrt(f2) + 1e-300;
+      if (!std::isfinite(hi)) throw NumError(ZCSD_ENOCONV, "zcsd: non-finite completion");
+      ZoloEigArgs ea;
+      ea.n = p;
+      ea.B = G2;
+      ea.ldb = p;
+      ea.lo = -0.01 * hi;
+      ea.hi = hi;
+      ea.V = Q;
+      ea.ldv = p;
+      ea.lam = lam;
+      ea.n_leaf = o.n_leaf;
+      ea.eps = o.eps;
+      ea.tol = o.tol;
+      ea.measure_offblock = false;
+      zolo_eig(ea, ar, s);
+      // M(:, 0:t) = Q diag(lam)^(-1/2) Q(0:t, :)^T
+      hipLaunchKernelGGL(scale_columns_kernel, dim3(grid_for(pp)), dim3(256), 0, s, p, Q, lam,
+                         1e-30 * hi, Qs);
+      ZCSD_CHECK_LAUNCH();
+      gemm(0, 1, p, t, p, 1.0, Qs, p, Q, p, 0.0, Mt, p, s);
+      gemm(0, 0, (int)rq, t, p, 1.0, PJ, rq, Mt, p, 0.0, Y[q] + (long long)cb * rq, rq, s);
+    };
+    // V1 (and U1, U2 with V1's factor, which keeps U_i = W_i V1)
+    if (correct(2, {0, 1, 2}, 0, r, 0, 3) > 0.0)
+      throw NumError(ZCSD_ENOCONV, "zcsd: V1 did not become orthonormal");
+    // U1 and U2 on their own, each column corrected only by the columns of
+    // larger cos (U1) or sin (U2): those are at least as well determined
+    if (r - t1 > 0 && correct(0, {0}, 0, r - t1, 1, 4) > 0.0)
+      throw NumError(ZCSD_ENOCONV, "zcsd: U1 did not become orthonormal");
+    if (r - t2 > 0 && correct(1, {1}, t2, r - t2, 2, 4) > 0.0)
+      throw NumError(ZCSD_ENOCONV, "zcsd: U2 did not become orthonormal");
+    if (t1 > 0) {
+      complete(0, r - t1, t1, 0, r - t1);
+      if (correct(0, {0}, 0, r, 0, 3) > 0.0)
+        throw NumError(ZCSD_ENOCONV, "zcsd: U1 did not become orthonormal");
+    }
+    if (t2 > 0) {
+      complete(1, 0, t2, t2, r - t2);
+      if (correct(1, {1}, 0, r, 0, 3) > 0.0)
+        throw NumError(ZCSD_ENOCONV, "zcsd: U2 did not become orthonormal");
+    }
+  }
+  // 5. angles from the final factors, C_kk = Re(u1_k^* A1 v_k) and
+  //    S_kk = Re(u2_k^* A2 v_k): Algorithm 1's diagonals of V1^* H_i V1,
+  //    since U_i^* A_i = V1^* W_i^* W_i H_i = V1^* H_i.  For embedded
+  //    columns that is the real dot product [Re u; Im u] . (embedded A_i)
+  //    [Re v; Im v]; columns in ascending order of theta
+  std::vector<double> thc(n, 0.0);
+  std::vector<int> perm(n);
+  for (int k = 0; k < n; ++k) perm[k] = k;
+  if (r > 0) {
+    ArenaScope scope(ar);
+    double* P = ar.dalloc((size_t)std::max(rows[0], rows[1]) * r);
+    double* cs = ar.dalloc(2LL * r);
+    for (int i = 0; i < 2; ++i) {
+      gemm(0, 0, (int)rows[i], r, N, 1.0, E[i], rows[i], Y[2], N, 0.0, P, rows[i], s);
+      hipLaunchKernelGGL(column_dots_kernel, dim3(r), dim3(256), 0, s, rows[i], Y[i], P,
+                         cs + (long long)i * r);
+      ZCSD_CHECK_LAUNCH();
+    }
+    std::vector<double> h(2 * (size_t)r);
+    d2h(h.data(), cs, h.size() * sizeof(double), s);
+    for (int k = 0; k < r; ++k)
+      thc[k] = std::min(std::max(std::atan2(h[r + k], h[k]), 0.0), 0.5 * M_PI);
+    std::stable_sort(perm.begin(), perm.begin() + r, [&](int a, int b) { return thc[a] < thc[b]; });
+    std::vector<double> sorted(n, 0.0);
+    for (int k = 0; k < r; ++k) sorted[k] = thc[perm[k]];
+    thc.swap(sorted);
+  }
+  // 6. complex columns
+  int* d_perm = ar.ialloc(n);
+  h2d(d_perm, perm.data(), n * sizeof(int), s);
+  double* outs[3] = {d_U1, d_U2, d_V1};
+  const long long lds[3] = {ldu1, ldu2, ldv1};
+  for (int q = 0; q < 3; ++q) {
+    hipLaunchKernelGGL(to_complex_kernel, dim3(grid_for(half[q]), n), dim3(256), 0, s, half[q], r,
+                       Y[q], d_perm, outs[q], lds[q]);
+    ZCSD_CHECK_LAUNCH();
+  }
+  h2d(d_theta, thc.data(), n * sizeof(double), s);
+  ZCSD_HIP(hipStreamSynchronize(s));
+  if (info) {
+    *info = zcsd_info{};
+    info->rank = r;
+    info->repair = repaired ? 1 : 0;
+  }
 }
 
 }  // namespace
@@ -251,294 +584,27 @@ extern "C" zcsd_status zcsd_zcsd(zcsd_handle* handle, int n, const double* d_A1,
     zcsd_opts o;
     zcsd_default_opts(&o);
     if (opts) o = *opts;
-    ZCSD_REQUIRE(o.prec == ZCSD_FP64, "zcsd: complex input is computed in the FP64 mode only");
-    ZCSD_HIP(hipSetDevice(handle->device));
-    const int N = 2 * n;
-    const long long NN = (long long)N * N;
-    Arena& ar = handle->arena;
-    ar.reset();
-    ar.reserve(complex_workspace_bytes(n));
-    hipStream_t s = handle->stream;
-    double* E = ar.dalloc(2 * (size_t)NN);
-    double* R = ar.dalloc(3 * (size_t)NN);      // real U1, U2, V1 (N x N each)
-    double* Y = ar.dalloc(3 * (size_t)NN / 2);  // selected columns, N x r each (r <= n)
-    double* th = ar.dalloc(N);
-    const long long Ysz = (long long)N * n;
+    complex_csd(handle, n, n, n, d_A1, lda1, d_A2, lda2, d_U1, ldu1, d_U2, ldu2, d_V1, ldv1,
+                d_theta, o, info);
+  });
+}
 
-    hipLaunchKernelGGL(complex_embed_kernel, dim3(grid_for(NN)), dim3(256), 0, s, n, d_A1,
-                       (long long)lda1, E);
-    ZCSD_CHECK_LAUNCH();
-    hipLaunchKernelGGL(complex_embed_kernel, dim3(grid_for(NN)), dim3(256), 0, s, n, d_A2,
-                       (long long)lda2, E + NN);
-    ZCSD_CHECK_LAUNCH();
-    bool repaired = false;
-    const int rank2 = csd_single_member(N, E, E + NN, R, R + NN, R + 2 * NN, th, o, ar, s,
-                                        &repaired);
-    if (rank2 % 2) throw NumError(ZCSD_ENOCONV, "zcsd: odd rank of the real embedding");
-    const int r = rank2 / 2;
-    std::vector<double> thh(std::max(1, rank2));
-    if (rank2) d2h(thh.data(), th, rank2 * sizeof(double), s);
-
-    // 1. clusters of real angles: consecutive gaps within the pairing gap
-    const double pair_gap = 0x1p-40 * (1.0 + N / 1024.0);
-    struct Cluster { int begin, end; };
-    std::vector<Cluster> cl;
-    for (int j = 0; j < rank2;) {
-      int e = j + 1;
-      while (e < rank2 && thh[e] - thh[e - 1] <= pair_gap) ++e;
-      if ((e - j) % 2)
-        throw NumError(ZCSD_ENOCONV, "zcsd: an angle of the real embedding without its pair");
-      cl.push_back({j, e});
-      j = e;
-    }
-    // 2. the first real column of every pair
-    std::vector<double> thc(n, 0.0);
-    std::vector<int> col(std::max(1, r), 0);
-    {
-      int k = 0;
-      for (const Cluster& c : cl)
-        for (int j = c.begin; j < c.end; j += 2) col[k++] = j;
-    }
-    if (r > 0) {
-      int* d_col = ar.ialloc(r);
-      h2d(d_col, col.data(), r * sizeof(int), s);
-      for (int q = 0; q < 3; ++q) {
-        hipLaunchKernelGGL(gather_columns_kernel, dim3(grid_for(N), r), dim3(256), 0, s,
-                           (long long)N, R + q * NN, d_col, Y + q * Ysz);
-        ZCSD_CHECK_LAUNCH();
-      }
-    }
-    // 3. clusters of complex multiplicity m > 1: a complex-orthonormal basis
-    {
-      int k = 0;
-      for (const Cluster& c : cl) {
-        const int p = c.end - c.begin, m = p / 2;
-        if (m > 1) {
-          ArenaScope scope(ar);
-          const long long pp = (long long)p * p;
-          double* M = ar.dalloc(pp);
-          double* P = ar.dalloc(pp);
-          double* T = ar.dalloc(pp);
-          double* Q = ar.dalloc(pp);
-          double* lam = ar.dalloc(p);
-          double* dd = ar.dalloc(p);
-          const double* X = R + 2 * NN + (long long)c.begin * N;  // V1 columns of the cluster
-          // M = X^T J X = Xb^T Xt - Xt^T Xb  (X = [Xt; Xb])
-          gemm(1, 0, p, p, n, 1.0, X + n, N, X, N, 0.0, M, p, s);
-          gemm(1, 0, p, p, n, -1.0, X, N, X + n, N, 1.0, M, p, s);
-          // T = M^T (D M) + D
-          const std::vector<double> d = distinct_diagonal(p);
-          h2d(dd, d.data(), p * sizeof(double), s);
-          hipLaunchKernelGGL(row_scale_kernel, dim3(grid_for(pp)), dim3(256), 0, s, p, dd, M, P);
-          ZCSD_CHECK_LAUNCH();
-          gemm(1, 0, p, p, p, 1.0, M, p, P, p, 0.0, T, p, s);
-          hipLaunchKernelGGL(add_diag_vec_kernel, dim3((p + 255) / 256), dim3(256), 0, s, p, dd,
-                             T);
-          ZCSD_CHECK_LAUNCH();
-          symmetrize(1, p, T, p, 0, s);
-          // D and M^T D M both have their spectrum in [1, 2]
-          ZoloEigArgs ea;
-          ea.n = p;
-          ea.B = T;
-          ea.ldb = p;
-          ea.lo = 1.99;
-          ea.hi = 4.01;
-          ea.V = Q;
-          ea.ldv = p;
-          ea.lam = lam;
-          ea.n_leaf = o.n_leaf;
-          ea.eps = o.eps;
-          ea.tol = o.tol;
-          ea.measure_offblock = false;
-          zolo_eig(ea, ar, s);
-          // one eigenvector of each pair: columns 0, 2, 4, ... (ld 2p)
-          for (int q = 0; q < 3; ++q)
-            gemm(0, 0, N, m, p, 1.0, R + q * NN + (long long)c.begin * N, N, Q, 2LL * p, 0.0,
-                 Y + q * Ysz + (long long)k * N, N, s);
-        }
-        k += m;
-      }
-    }
-    // 4. complex orthonormality of the factors (items 4 and 5 above)
-    if (r > 0) {
-      // angle of each complex column: its cluster's mean (ascending)
-      std::vector<double> thk(r);
-      {
-        int k = 0;
-        for (const Cluster& c : cl) {
-          double mean = 0.0;
-          for (int j = c.begin; j < c.end; ++j) mean += thh[j];
-          mean /= (c.end - c.begin);
-          for (int j = c.begin; j < c.end; j += 2) thk[k++] = mean;
-        }
-      }
-      // columns whose U1 (cos below tau: a suffix) or U2 (sin below tau: a
-      // prefix) column A leaves undetermined
-      const double tau = 0x1p-46;
-      int t1 = 0, t2 = 0;
-      for (int k = 0; k < r; ++k) {
-        if (std::cos(thk[k]) < tau) ++t1;
-        if (std::sin(thk[k]) < tau) ++t2;
-      }
-      ArenaScope scope(ar);
-      double* G = ar.dalloc(2LL * r * r);  // 2 cnt x cnt, ld 2 cnt
-      double* ss = ar.dalloc(1);
-      // Correction steps on columns [c0, c0 + cnt) of the factors in `apply`,
-      // from the complex Gram matrix of factor gq on those columns, G = I + E:
-      // mode 0 multiplies by I - E/2 (Newton-Schulz), mode 1 by
-      // I - diag(E)/2 - triu(E, 1) and mode 2 by I - diag(E)/2 - tril(E, -1)
-      // (first-order inverse Cholesky factors: a column is corrected only by
-      // the columns before it, resp. after it).  Returns the last ||E||_F.
-      auto correct = [&](int gq, std::initializer_list<int> apply, int c0, int cnt, int mode,
-                         int max_steps) {
-        double eta = 0.0;
-        const long long ldg = 2LL * cnt;
-        for (int step = 0; step < max_steps; ++step) {
-          for (int q : apply) {
-            hipLaunchKernelGGL(with_j_image_kernel, dim3(grid_for(N), cnt), dim3(256), 0, s, n,
-                               cnt, Y + q * Ysz + (long long)c0 * N, R + q * NN);
-            ZCSD_CHECK_LAUNCH();
-          }
-          gemm(1, 0, 2 * cnt, cnt, N, 1.0, R + gq * NN, N, Y + gq * Ysz + (long long)c0 * N, N,
-               0.0, G, ldg, s);
-          add_diag(1, cnt, -1.0, G, ldg, 0, s);
-          sumsq(1, 2 * cnt, cnt, G, ldg, 0, ss, ar, s);
-          double eta2 = 0.0;
-          d2h(&eta2, ss, sizeof(double), s);
-          if (!std::isfinite(eta2)) throw NumError(ZCSD_ENOCONV, "zcsd: non-finite factor");
-          eta = std::sqrt(eta2);
-          hipLaunchKernelGGL(correction_factor_kernel, dim3(grid_for(2LL * cnt * cnt)), dim3(256),
-                             0, s, cnt, mode, G);
-          ZCSD_CHECK_LAUNCH();
-          for (int q : apply)
-            gemm(0, 0, N, cnt, 2 * cnt, 1.0, R + q * NN, N, G, ldg, 0.0,
-                 Y + q * Ysz + (long long)c0 * N, N, s);
-          if (eta < 1e-8) return 0.0;  // the step left O(eta^2) + rounding
-        }
-        return eta;
-      };
-      // any complex-orthonormal basis of t columns orthogonal to the cnt
-      // columns at cg of factor q, written at cb: the polar factor of the
-      // projection of complex Gaussian columns, through the eigendecomposition
-      // of the embedded Gram matrix (a function of it, hence itself embedded)
-      auto complete = [&](int q, int cb, int t, int cg, int cnt) {
-        ArenaScope sc(ar);
-        double* Om = ar.dalloc((size_t)N * t);
-        hipLaunchKernelGGL(gaussian_fill_kernel, dim3(grid_for((long long)N * t)), dim3(256), 0, s,
-                           (long long)N * t, 0x5eedULL + 977ULL * q, Om);
-        ZCSD_CHECK_LAUNCH();
-        if (cnt > 0) {
-          double* Tm = ar.dalloc(2LL * cnt * t);
-          hipLaunchKernelGGL(with_j_image_kernel, dim3(grid_for(N), cnt), dim3(256), 0, s, n, cnt,
-                             Y + q * Ysz + (long long)cg * N, R + q * NN);
-          ZCSD_CHECK_LAUNCH();
-          for (int pass = 0; pass < 2; ++pass) {
-            gemm(1, 0, 2 * cnt, t, N, 1.0, R + q * NN, N, Om, N, 0.0, Tm, 2LL * cnt, s);
-            gemm(0, 0, N, t, 2 * cnt, -1.0, R + q * NN, N, Tm, 2LL * cnt, 1.0, Om, N, s);
-          }
-        }
-        const int p = 2 * t;
-        const long long pp = (long long)p * p;
-        double* PJ = ar.dalloc((size_t)N * p);
-        double* G2 = ar.dalloc(pp);
-        double* Q = ar.dalloc(pp);
-        double* Qs = ar.dalloc(pp);
-        double* lam = ar.dalloc(p);
-        double* Mt = ar.dalloc((size_t)p * t);
-        double* nrm = ar.dalloc(1);
-        hipLaunchKernelGGL(with_j_image_kernel, dim3(grid_for(N), t), dim3(256), 0, s, n, t, Om, PJ);
-        ZCSD_CHECK_LAUNCH();
-        gemm(1, 0, p, p, N, 1.0, PJ, N, PJ, N, 0.0, G2, p, s);
-        symmetrize(1, p, G2, p, 0, s);
-        sumsq(1, p, p, G2, p, 0, nrm, ar, s);
-        double f2 = 0.0;
-        d2h(&f2, nrm, sizeof(double), s);
-        const double hi = 1.01 * std::sqrt(f2) + 1e-300;
-        if (!std::isfinite(hi)) throw NumError(ZCSD_ENOCONV, "zcsd: non-finite completion");
-        ZoloEigArgs ea;
-        ea.n = p;
-        ea.B = G2;
-        ea.ldb = p;
-        ea.lo = -0.01 * hi;
-        ea.hi = hi;
-        ea.V = Q;
-        ea.ldv = p;
-        ea.lam = lam;
-        ea.n_leaf = o.n_leaf;
-        ea.eps = o.eps;
-        ea.tol = o.tol;
-        ea.measure_offblock = false;
-        zolo_eig(ea, ar, s);
-        // M(:, 0:t) = Q diag(lam)^(-1/2) Q(0:t, :)^T
-        hipLaunchKernelGGL(scale_columns_kernel, dim3(grid_for(pp)), dim3(256), 0, s, p, Q, lam,
-                           1e-30 * hi, Qs);
-        ZCSD_CHECK_LAUNCH();
-        gemm(0, 1, p, t, p, 1.0, Qs, p, Q, p, 0.0, Mt, p, s);
-        gemm(0, 0, N, t, p, 1.0, PJ, N, Mt, p, 0.0, Y + q * Ysz + (long long)cb * N, N, s);
-      };
-      // V1 (and U1, U2 with V1's factor, which keeps U_i = W_i V1)
-      if (correct(2, {0, 1, 2}, 0, r, 0, 3) > 0.0)
-        throw NumError(ZCSD_ENOCONV, "zcsd: V1 did not become orthonormal");
-      // U1 and U2 on their own, each column corrected only by the columns of
-      // larger cos (U1) or sin (U2): those are at least as well determined
-      if (r - t1 > 0 && correct(0, {0}, 0, r - t1, 1, 4) > 0.0)
-        throw NumError(ZCSD_ENOCONV, "zcsd: U1 did not become orthonormal");
-      if (r - t2 > 0 && correct(1, {1}, t2, r - t2, 2, 4) > 0.0)
-        throw NumError(ZCSD_ENOCONV, "zcsd: U2 did not become orthonormal");
-      if (t1 > 0) {
-        complete(0, r - t1, t1, 0, r - t1);
-        if (correct(0, {0}, 0, r, 0, 3) > 0.0)
-          throw NumError(ZCSD_ENOCONV, "zcsd: U1 did not become orthonormal");
-      }
-      if (t2 > 0) {
-        complete(1, 0, t2, t2, r - t2);
-        if (correct(1, {1}, 0, r, 0, 3) > 0.0)
-          throw NumError(ZCSD_ENOCONV, "zcsd: U2 did not become orthonormal");
-      }
-    }
-    // 5. angles from the final factors, C_kk = Re(u1_k^* A1 v_k) and
-    //    S_kk = Re(u2_k^* A2 v_k): Algorithm 1's diagonals of V1^* H_i V1,
-    //    since U_i^* A_i = V1^* W_i^* W_i H_i = V1^* H_i.  For embedded
-    //    columns that is the real dot product [Re u; Im u] . (embedded A_i)
-    //    [Re v; Im v]; columns in ascending order of theta
-    std::vector<int> perm(std::max(1, n));
-    for (int k = 0; k < n; ++k) perm[k] = k;
-    if (r > 0) {
-      ArenaScope scope(ar);
-      double* P = ar.dalloc((size_t)N * r);
-      double* cs = ar.dalloc(2LL * r);
-      for (int i = 0; i < 2; ++i) {
-        gemm(0, 0, N, r, N, 1.0, E + i * NN, N, Y + 2 * Ysz, N, 0.0, P, N, s);
-        hipLaunchKernelGGL(column_dots_kernel, dim3(r), dim3(256), 0, s, (long long)N,
-                           Y + i * Ysz, P, cs + (long long)i * r);
-        ZCSD_CHECK_LAUNCH();
-      }
-      std::vector<double> h(2 * (size_t)r);
-      d2h(h.data(), cs, h.size() * sizeof(double), s);
-      for (int k = 0; k < r; ++k)
-        thc[k] = std::min(std::max(std::atan2(h[r + k], h[k]), 0.0), 0.5 * M_PI);
-      std::stable_sort(perm.begin(), perm.begin() + r,
-                       [&](int a, int b) { return thc[a] < thc[b]; });
-      std::vector<double> sorted(n, 0.0);
-      for (int k = 0; k < r; ++k) sorted[k] = thc[perm[k]];
-      thc.swap(sorted);
-    }
-    // 6. complex columns
-    int* d_perm = ar.ialloc(std::max(1, n));
-    h2d(d_perm, perm.data(), n * sizeof(int), s);
-    double* outs[3] = {d_U1, d_U2, d_V1};
-    const int lds[3] = {ldu1, ldu2, ldv1};
-    for (int q = 0; q < 3; ++q) {
-      hipLaunchKernelGGL(to_complex_kernel, dim3(grid_for(n), n), dim3(256), 0, s, n, r,
-                         Y + q * Ysz, d_perm, outs[q], (long long)lds[q]);
-      ZCSD_CHECK_LAUNCH();
-    }
-    h2d(d_theta, thc.data(), n * sizeof(double), s);
-    ZCSD_HIP(hipStreamSynchronize(s));
-    if (info) {
-      *info = zcsd_info{};
-      info->rank = r;
-      info->repair = repaired ? 1 : 0;
-    }
+extern "C" zcsd_status zcsd_zcsd_mn(zcsd_handle* handle, int m1, int m2, int n,
+                                    const double* d_A1, int lda1, const double* d_A2, int lda2,
+                                    double* d_U1, int ldu1, double* d_U2, int ldu2, double* d_V1,
+                                    int ldv1, double* d_theta, const zcsd_opts* opts,
+                                    zcsd_info* info) {
+  if (!handle) return ZCSD_EINVAL;
+  return guarded([&] {
+    ZCSD_REQUIRE(n >= 1 && m1 >= n && m2 >= n && m1 <= 32767 && m2 <= 32767,
+                 "zcsd_mn: need 1 <= n <= m1, m2 <= 32767");
+    ZCSD_REQUIRE(d_A1 && d_A2 && d_U1 && d_U2 && d_V1 && d_theta, "zcsd_mn: NULL pointer");
+    ZCSD_REQUIRE(lda1 >= m1 && lda2 >= m2 && ldu1 >= m1 && ldu2 >= m2 && ldv1 >= n,
+                 "zcsd_mn: leading dimension too small");
+    zcsd_opts o;
+    zcsd_default_opts(&o);
+    if (opts) o = *opts;
+    complex_csd(handle, m1, m2, n, d_A1, lda1, d_A2, lda2, d_U1, ldu1, d_U2, ldu2, d_V1, ldv1,
+                d_theta, o, info);
   });
 }

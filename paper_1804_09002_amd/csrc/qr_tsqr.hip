@@ -231,7 +231,7 @@ __device__ __forceinline__ void ql_householder_step(double (&a)[RQ][4], double (
   }
   __syncthreads();
   // the totals of the lane's own four columns, read straight from the waves'
-  // partial sums (one LDS round trip; summed in the same order as before)
+  // partial sums (one LDS round trip; pairwise sums in a fixed order)
   double d[4], at[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {

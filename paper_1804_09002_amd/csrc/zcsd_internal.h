@@ -234,6 +234,10 @@ int csd_single_member(int n, const double* A1, const double* A2, double* U1, dou
                       double* V1, double* theta, const zcsd_opts& o, Arena& ar, hipStream_t s,
                       bool* repaired);
 size_t csd_workspace_bytes(int n);
+// Householder QR of the m x n block A (m >= n, ld lda): Q (m x n, ld m) and
+// the triangular R (n x n, ld n, zeros below the diagonal) (csd.hip)
+void tall_qr(int m, int n, const double* A, long long lda, double* Q, double* R, Arena& ar,
+             hipStream_t s);
 
 // Device address of the fixed scratch array of the allocation-free backward
 // (backward.hip) on `device`, which must be current; looked up once per device.

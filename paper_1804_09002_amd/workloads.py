@@ -173,6 +173,24 @@ def complex_pair(n, seed, kind="uniform", rank_deficient=0, mult=1):
     return A1, A2, {"U1": U1, "U2": U2, "V1": V1, "theta": theta, "zero_idx": zero_idx}
 
 
+def complex_rect_pair(m1, m2, n, seed, rank_deficient=0):
+    """Rectangular complex blocks (m1, m2 >= n): A1 = U1 C V1^H (m1 x n),
+    A2 = U2 S V1^H (m2 x n) with U_i of orthonormal columns (Haar, m_i x n),
+    Haar unitary V1 and uniform angles; rank_deficient = k zeroes k random
+    (C_ii, S_ii) pairs."""
+    rng = np.random.default_rng(seed)
+    theta = angles_uniform(n, rng)
+    U1, U2 = haar_unitary(m1, n, rng), haar_unitary(m2, n, rng)
+    V1 = haar_unitary(n, n, rng)
+    zero_idx = np.sort(rng.choice(n, size=rank_deficient, replace=False)) if rank_deficient else None
+    c, s = np.cos(theta), np.sin(theta)
+    if zero_idx is not None:
+        c[zero_idx] = 0.0
+        s[zero_idx] = 0.0
+    Vh = V1.conj().T
+    return (U1 * c) @ Vh, (U2 * s) @ Vh, {"theta": theta, "zero_idx": zero_idx}
+
+
 PAPER_CLASSES = ("1", "2", "3", "4", "1'", "2'", "3'", "4'")
 
 

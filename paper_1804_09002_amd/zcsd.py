@@ -87,6 +87,8 @@ def _lib():
                              C.POINTER(Opts), C.POINTER(Info)],
             "zcsd_zcsd": [vp, i, vp, i, vp, i, vp, i, vp, i, vp, i, vp,
                           C.POINTER(Opts), C.POINTER(Info)],
+            "zcsd_zcsd_mn": [vp, i, i, i, vp, i, vp, i, vp, i, vp, i, vp, i, vp,
+                             C.POINTER(Opts), C.POINTER(Info)],
             "zcsd_dzolo_pd": [vp, i, i, d, vp, i, ll, vp, vp, vp, C.POINTER(Opts), C.POINTER(Info)],
             "zcsd_dsyev_zolo": [vp, i, vp, i, d, d, vp, i, vp, C.POINTER(Opts), C.POINTER(Info)],
             "zcsd_dcsd_backward": [vp, i, i, vp, vp, vp, vp, vp, vp, vp, vp, vp],
@@ -387,32 +389,41 @@ def csd(A1, A2, rank_mode="auto", r=None, ell=None, want_polar=False, **opts):
 
 
 def csd_complex(A1, A2, rank_mode="auto", **opts):
-    """CS decomposition of a complex [A1; A2] (n x n complex128 HIP tensors).
+    """CS decomposition of a complex [A1; A2] (A1: (m1, n), A2: (m2, n)
+    complex128 HIP tensors, m1, m2 >= n).
 
     Returns (U1, U2, V1, theta, info) with A1 = U1 diag(cos theta) V1^H and
     A2 = U2 diag(sin theta) V1^H (complex128 factors, float64 theta); in the
     rank-deficient case only the first info['rank'] columns / entries are
-    valid.  Computed by zcsd_zcsd through the real embedding of the blocks.
+    valid.  Computed through the real embedding of the blocks: zcsd_zcsd for
+    square blocks, zcsd_zcsd_mn for rectangular ones.
     """
     for X, name in ((A1, "A1"), (A2, "A2")):
         if not (isinstance(X, torch.Tensor) and X.is_cuda and X.dtype == torch.complex128
-                and X.dim() == 2 and X.shape[0] == X.shape[1]):
-            raise TypeError(f"csd_complex: {name} must be a square complex128 tensor on a HIP device")
-    n = A1.shape[0]
-    if A2.shape != A1.shape:
-        raise ValueError("csd_complex: A1 and A2 must have the same shape")
+                and X.dim() == 2):
+            raise TypeError(f"csd_complex: {name} must be a 2-D complex128 tensor on a HIP device")
+    m1, n = A1.shape
+    m2 = A2.shape[0]
+    if A2.shape[1] != n or m1 < n or m2 < n:
+        raise ValueError("csd_complex: need A1 (m1, n), A2 (m2, n) with m1, m2 >= n")
     a1 = A1.t().contiguous()
     a2 = A2.t().contiguous()
-    U1 = torch.empty_like(a1)
-    U2 = torch.empty_like(a1)
-    V1 = torch.empty_like(a1)
-    th = torch.empty(n, dtype=torch.float64, device=A1.device)
+    dev = A1.device
+    U1 = torch.empty((n, m1), dtype=torch.complex128, device=dev)
+    U2 = torch.empty((n, m2), dtype=torch.complex128, device=dev)
+    V1 = torch.empty((n, n), dtype=torch.complex128, device=dev)
+    th = torch.empty(n, dtype=torch.float64, device=dev)
     o = default_opts(rank_mode=rank_mode, **opts)
     info = Info()
-    h = handle(A1.device.index)
-    st = _lib().zcsd_zcsd(h, n, _ptr(a1), n, _ptr(a2), n, _ptr(U1), n, _ptr(U2), n, _ptr(V1), n,
-                          _ptr(th), C.byref(o), C.byref(info))
-    _check(st, "zcsd_zcsd")
+    h = handle(dev.index)
+    if m1 == n and m2 == n:
+        st = _lib().zcsd_zcsd(h, n, _ptr(a1), n, _ptr(a2), n, _ptr(U1), n, _ptr(U2), n, _ptr(V1), n,
+                              _ptr(th), C.byref(o), C.byref(info))
+        _check(st, "zcsd_zcsd")
+    else:
+        st = _lib().zcsd_zcsd_mn(h, m1, m2, n, _ptr(a1), m1, _ptr(a2), m2, _ptr(U1), m1, _ptr(U2), m2,
+                                 _ptr(V1), n, _ptr(th), C.byref(o), C.byref(info))
+        _check(st, "zcsd_zcsd_mn")
     return U1.t(), U2.t(), V1.t(), th, info.as_dict()
 
 

@@ -129,3 +129,27 @@ def test_complex_n1024_known_angles():
     orth = [np.linalg.norm((X.conj().T.contiguous() @ X - I).cpu().numpy(), 2) for X in (U1, U2, V1)]
     print(f"complex n=1024: backward {res:.1e} orth {max(orth):.1e}", flush=True)
     assert res <= 1e-13 and max(orth) <= 1e-13
+
+
+@pytest.mark.parametrize("m1,m2,n,k", [(9, 7, 5, 0), (100, 64, 40, 0), (150, 90, 80, 6), (70, 70, 33, 0)])
+def test_complex_rectangular_against_oracle(m1, m2, n, k):
+    """zcsd_zcsd_mn: A1 (m1 x n), A2 (m2 x n) complex; the rank, the angles of
+    the oracle and of the construction, the backward error and the complex
+    orthogonality of U1 (m1 x n), U2 (m2 x n), V1."""
+    from paper_1804_09002_amd import zcsd
+    A1, A2, meta = WL.complex_rect_pair(m1, m2, n, 2000 + m1 + n + k, rank_deficient=k)
+    U1, U2, V1, th, info = zcsd.csd_complex(_t(A1), _t(A2))
+    assert U1.shape == (m1, n) and U2.shape == (m2, n) and V1.shape == (n, n)
+    U1, U2, V1, th = (x.cpu().numpy() for x in (U1, U2, V1, th))
+    o = OC.csd(A1, A2)
+    r = info["rank"]
+    assert r == o["rank"] == n - k
+    assert np.max(np.abs(th[:r] - o["theta"])) <= 10 * max(m1, m2) * U
+    keep = np.ones(n, bool)
+    if meta["zero_idx"] is not None:
+        keep[meta["zero_idx"]] = False
+    assert np.max(np.abs(th[:r] - np.sort(meta["theta"][keep]))) <= 10 * max(m1, m2) * U
+    res, orth = _measures(A1, A2, U1, U2, V1, th, r)
+    print(f"complex rect {m1}x{m2}x{n} k={k}: backward {res:.1e} orth {max(orth):.1e}", flush=True)
+    assert res <= 2e-13 and max(orth) <= 2e-13
+

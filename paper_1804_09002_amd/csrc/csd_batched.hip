@@ -205,6 +205,17 @@ int batched_class_size(int n, const int step[3]) {
   return (n + st - 1) / st * st;
 }
 
+// the first W workers of the handle, each with its stream and second stream
+// (created in this order, worker by worker)
+void ensure_batch_workers(zcsd_handle* h, int W) {
+  while ((int)h->workers.size() < W) {
+    auto bw = std::make_unique<BatchWorker>();
+    ZCSD_HIP(hipStreamCreateWithFlags(&bw->stream, hipStreamNonBlocking));
+    ZCSD_HIP(hipStreamCreateWithFlags(&bw->aux, hipStreamNonBlocking));
+    h->workers.push_back(std::move(bw));
+  }
+}
+
 // arena bytes of one group of K problems of class size N: the iterates and
 // products (216 N^2 doubles per problem), the Householder workspaces of the
 // polars (2K problems, up to 8 terms each) and of Zolo-eig's sign functions
@@ -555,12 +566,7 @@ extern "C" zcsd_status zcsd_dcsd_batched(zcsd_handle* handle, int batch, const i
       assign[w].push_back(gi);
       load[w] += groups[gi].cost;
     }
-    while ((int)handle->workers.size() < W) {
-      auto bw = std::make_unique<BatchWorker>();
-      ZCSD_HIP(hipStreamCreateWithFlags(&bw->stream, hipStreamNonBlocking));
-      ZCSD_HIP(hipStreamCreateWithFlags(&bw->aux, hipStreamNonBlocking));
-      handle->workers.push_back(std::move(bw));
-    }
+    ensure_batch_workers(handle, W);
     // the workers start after everything queued on the caller's stream
     hipEvent_t ready = nullptr;
     ZCSD_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));

@@ -86,7 +86,8 @@ struct zcsd_handle_s {
   int device = 0;
   hipStream_t stream = nullptr;
   zcsd::Arena arena;
-  // created on the first batched call with more than one size-class group
+  // the batched path's workers: the default number made with the handle,
+  // more on a batched call whose tuning asks for them
   std::vector<std::unique_ptr<zcsd::BatchWorker>> workers;
   // pinned host staging for small readbacks
   double* h_stage = nullptr;
@@ -234,6 +235,8 @@ int csd_single_member(int n, const double* A1, const double* A2, double* U1, dou
                       double* V1, double* theta, const zcsd_opts& o, Arena& ar, hipStream_t s,
                       bool* repaired);
 size_t csd_workspace_bytes(int n);
+// the batched path's first W worker streams of a handle (csd_batched.hip)
+void ensure_batch_workers(zcsd_handle_s* h, int W);
 // Householder QR of the m x n block A (m >= n, ld lda): Q (m x n, ld m) and
 // the triangular R (n x n, ld n, zeros below the diagonal) (csd.hip)
 void tall_qr(int m, int n, const double* A, long long lda, double* Q, double* R, Arena& ar,

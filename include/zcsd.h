@@ -131,14 +131,21 @@ const char* zcsd_status_string(zcsd_status s);
  * hold more workspace and compete for the device.  The defaults are the best
  * measured on 2048 problems with n log-uniform in [8, 256];
  * paper_1804_09002_amd/autotune.py measures the settings for another
- * workload.  zcsd_set_tuning returns ZCSD_EINVAL for an unknown key, workers
- * outside [1, 16] or a step outside [1, 256]; it takes effect on the next
- * batched call of the handle. */
+ * workload.  Full-rank problems with n <= ZCSD_TUNE_ONE_WORKGROUP_MAX_N
+ * (default 64, at most 64, 0 = none) skip the classes: each runs as a whole
+ * CSD inside one workgroup, all of them in one persistent launch that runs
+ * beside the class groups (the same Algorithm 1 with Zolo-pd; Zolo-eig of a
+ * block of at most 64 is its Jacobi leaf solve), unless r_override,
+ * ell_override or n_leaf < n asks for the class path.  zcsd_set_tuning
+ * returns ZCSD_EINVAL for an unknown key, workers outside [1, 16], a step
+ * outside [1, 256] or a one-workgroup limit outside [0, 64]; it takes effect
+ * on the next batched call of the handle. */
 typedef enum {
   ZCSD_TUNE_BATCHED_WORKERS = 0,
   ZCSD_TUNE_CLASS_STEP_SMALL = 1,
   ZCSD_TUNE_CLASS_STEP_MID = 2,
-  ZCSD_TUNE_CLASS_STEP_LARGE = 3
+  ZCSD_TUNE_CLASS_STEP_LARGE = 3,
+  ZCSD_TUNE_ONE_WORKGROUP_MAX_N = 4
 } zcsd_tune_key;
 zcsd_status zcsd_set_tuning(zcsd_handle* handle, int key, int value);
 zcsd_status zcsd_get_tuning(zcsd_handle* handle, int key, int* value);
@@ -299,6 +306,10 @@ zcsd_status zcsd_dcsd2x2(zcsd_handle* handle, int n,
  * when it reaches eps (a member may have sigma_min(A_i) < eps, Sec. 5.1), the
  * class's problems run one at a time through the single path of zcsd_dcsd,
  * which has the repair of Algorithm 2, instead of the batched kernels.
+ * Small full-rank problems (n <= ZCSD_TUNE_ONE_WORKGROUP_MAX_N) run instead
+ * as one workgroup each, with their own l and their Zolotarev coefficients
+ * from a table of lower bounds (0.9 * 10^(-q/8), the largest one <= l); one
+ * whose l reaches eps also goes to the single path.
  */
 zcsd_status zcsd_dcsd_batched(zcsd_handle* handle, int batch, const int* n_host,
                               const long long* off_host,

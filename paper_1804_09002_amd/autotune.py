@@ -9,7 +9,8 @@ zcsd_set_tuning).  For a synthetic workload with the given size distribution
 (n log-uniform in [lo, hi], uniform angles, as the bench's batched leg), this
 times one batched call per candidate setting after two warm-up calls (mean of
 `reps` calls): first the number of workers at the default steps, then the
-class steps at the best number of workers (coordinate descent).  It prints
+class steps at the best number of workers, then the largest size that runs
+as one-workgroup CSDs (coordinate descent).  It prints
 the timings and writes the best setting with them to `--out` as JSON;
 `apply(path)` sets a written file's setting on the current device's handle.
 The library's defaults are this search's result for the bench workload.
@@ -22,6 +23,7 @@ import time
 
 WORKERS = (1, 2, 3, 4, 6, 8)
 STEPS = ((4, 8, 32), (8, 16, 64), (8, 32, 64), (16, 16, 64), (16, 32, 64))
+ONE_WG = (64, 48, 32, 0)
 
 
 def workload(count, lo, hi, seed):
@@ -58,7 +60,8 @@ def time_setting(data, setting, reps):
     return (time.perf_counter() - t0) / reps
 
 
-def search(count=2048, lo=8, hi=256, seed=5, reps=3, workers=WORKERS, steps=STEPS, log=print):
+def search(count=2048, lo=8, hi=256, seed=5, reps=3, workers=WORKERS, steps=STEPS, one_wg=ONE_WG,
+           log=print):
     from . import zcsd
     data = workload(count, lo, hi, seed)
     start = zcsd.get_tuning()
@@ -71,14 +74,23 @@ def search(count=2048, lo=8, hi=256, seed=5, reps=3, workers=WORKERS, steps=STEP
         return t
 
     base_steps = dict(class_step_small=start["class_step_small"], class_step_mid=start["class_step_mid"],
-                      class_step_large=start["class_step_large"])
+                      class_step_large=start["class_step_large"],
+                      one_workgroup_max_n=start["one_workgroup_max_n"])
     best_w = min(workers, key=lambda w: run(dict(batched_workers=w, **base_steps)))
     best = None
     for st in steps:
         setting = dict(batched_workers=best_w, class_step_small=st[0], class_step_mid=st[1],
-                       class_step_large=st[2])
+                       class_step_large=st[2], one_workgroup_max_n=start["one_workgroup_max_n"])
         t = run(setting)
         if best is None or t < best[1]:
+            best = (setting, t)
+    # then the largest size that runs as one-workgroup CSDs
+    for lim in one_wg:
+        if lim == best[0]["one_workgroup_max_n"]:
+            continue
+        setting = {**best[0], "one_workgroup_max_n": lim}
+        t = run(setting)
+        if t < best[1]:
             best = (setting, t)
     zcsd.set_tuning(**start)
     return {"workload": {"count": count, "lo": lo, "hi": hi, "seed": seed},

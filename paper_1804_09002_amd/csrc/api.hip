@@ -81,6 +81,10 @@ zcsd_status zcsd_set_tuning(zcsd_handle* handle, int key, int value) {
       if (value < 1 || value > 256) return ZCSD_EINVAL;
       handle->tune_step[key - ZCSD_TUNE_CLASS_STEP_SMALL] = value;
       return ZCSD_OK;
+    case ZCSD_TUNE_ONE_WORKGROUP_MAX_N:
+      if (value < 0 || value > zcsd::small_csd_max_n()) return ZCSD_EINVAL;
+      handle->tune_small_max = value;
+      return ZCSD_OK;
     default:
       return ZCSD_EINVAL;
   }
@@ -96,6 +100,9 @@ zcsd_status zcsd_get_tuning(zcsd_handle* handle, int key, int* value) {
     case ZCSD_TUNE_CLASS_STEP_MID:
     case ZCSD_TUNE_CLASS_STEP_LARGE:
       *value = handle->tune_step[key - ZCSD_TUNE_CLASS_STEP_SMALL];
+      return ZCSD_OK;
+    case ZCSD_TUNE_ONE_WORKGROUP_MAX_N:
+      *value = handle->tune_small_max;
       return ZCSD_OK;
     default:
       return ZCSD_EINVAL;

@@ -481,10 +481,6 @@ extern "C" zcsd_status zcsd_dcsd_batched(zcsd_handle* handle, int batch, const i
     hipStream_t s = handle->stream;
     Arena& ar = handle->arena;
     ar.reset();
-    // classes and the workspace of the largest chunk
-    std::map<int, std::vector<int>> cls;
-    for (int k = 0; k < batch; ++k)
-      cls[batched_class_size(n_host[k], handle->tune_step)].push_back(k);
     // workspace ceiling per chunk (each of the concurrent workers holds one)
     const int n_workers = std::max(1, handle->tune_workers);
     const size_t cap_bytes = ((size_t)48 << 30) / n_workers;
@@ -496,7 +492,20 @@ extern "C" zcsd_status zcsd_dcsd_batched(zcsd_handle* handle, int batch, const i
       while (c > 1 && batched_group_bytes(N, c) > cap_bytes) c = (c + 1) / 2;
       return std::max<size_t>(1, c);
     };
-    ar.reserve(((size_t)64 << 20) + (size_t)batch * 64);
+    // small full-rank problems: whole CSDs of one workgroup each, one
+    // persistent launch beside the class groups (candidates by size here, by
+    // rank below); not when the options fix l or r, or split blocks <= 64
+    const int small_lim = (o.r_override == 0 && o.ell_override <= 0.0)
+                              ? std::min(std::min(handle->tune_small_max, small_csd_max_n()), o.n_leaf)
+                              : 0;
+    int n_small_cand = 0;
+    for (int k = 0; k < batch; ++k) n_small_cand += (n_host[k] <= small_lim) ? 1 : 0;
+    int n_cu = 1;
+    ZCSD_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, handle->device));
+    const int small_grid_max = std::max(1, std::min(n_small_cand, n_cu));
+    const size_t small_bytes =
+        n_small_cand ? small_csd_scratch_bytes(small_grid_max) + (size_t)batch * 64 + ((size_t)1 << 20) : 0;
+    ar.reserve(((size_t)64 << 20) + (size_t)batch * 64 + small_bytes);
     // ranks (Remark (vi)) for every problem
     std::vector<double> ss((size_t)2 * batch);
     {
@@ -524,6 +533,19 @@ extern "C" zcsd_status zcsd_dcsd_batched(zcsd_handle* handle, int batch, const i
         deficient[k] = rA < n_host[k];
       }
     }
+    std::vector<int> small;
+    std::vector<char> is_small(batch, 0);
+    for (int k = 0; k < batch; ++k)
+      if (!deficient[k] && n_host[k] <= small_lim) {
+        small.push_back(k);
+        is_small[k] = 1;
+      }
+    // largest first: the workgroups take the list in turn
+    std::stable_sort(small.begin(), small.end(), [&](int x, int y) { return n_host[x] > n_host[y]; });
+    // classes of the other problems
+    std::map<int, std::vector<int>> cls;
+    for (int k = 0; k < batch; ++k)
+      if (!is_small[k]) cls[batched_class_size(n_host[k], handle->tune_step)].push_back(k);
     std::vector<double> theta_host(toff[batch], 0.0);
     BatchedStats st;
     st.classes = (int)cls.size();
@@ -571,6 +593,20 @@ extern "C" zcsd_status zcsd_dcsd_batched(zcsd_handle* handle, int batch, const i
     hipEvent_t ready = nullptr;
     ZCSD_HIP(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
     ZCSD_HIP(hipEventRecord(ready, s));
+    int* d_small_status = nullptr;
+    if (!small.empty()) {
+      const int grid = std::min<int>((int)small.size(), small_grid_max);
+      std::vector<int> nv(n_host, n_host + batch);
+      std::vector<long long> ov(off_host, off_host + batch), tv(toff.begin(), toff.begin() + batch);
+      int* d_list = upload_vec(ar, small, s);
+      int* d_nv = upload_vec(ar, nv, s);
+      long long* d_ov = upload_vec(ar, ov, s);
+      long long* d_tv = upload_vec(ar, tv, s);
+      d_small_status = ar.ialloc(small.size());
+      double* scratch = ar.dalloc(small_csd_scratch_bytes(grid) / sizeof(double));
+      small_csd_launch((int)small.size(), d_list, d_nv, d_ov, d_tv, d_A1, d_A2, d_U1, d_U2, d_V1,
+                       d_theta, o.eps, o.tol, o.postprocess == 2, grid, scratch, d_small_status, ar, s);
+    }
     const int dev = handle->device;
     std::vector<BatchedStats> wst(W);
     std::vector<std::vector<int>> wsingle(W);
@@ -614,6 +650,24 @@ extern "C" zcsd_status zcsd_dcsd_batched(zcsd_handle* handle, int batch, const i
     for (int w = 0; w < W; ++w) {
       st.merge(wst[w]);
       single.insert(single.end(), wsingle[w].begin(), wsingle[w].end());
+    }
+    if (!small.empty()) {
+      // the one-workgroup CSDs: their angles are in d_theta (no class group
+      // writes there); problems whose l reached eps go to the single path
+      std::vector<int> sst(small.size());
+      d2h(sst.data(), d_small_status, sst.size() * sizeof(int), s);
+      std::vector<double> thd(toff[batch]);
+      d2h(thd.data(), d_theta, thd.size() * sizeof(double), s);
+      for (size_t i = 0; i < small.size(); ++i) {
+        const int k = small[i];
+        if ((sst[i] & 255) == 0) {
+          rank_host[k] = n_host[k];
+          std::copy(thd.begin() + toff[k], thd.begin() + toff[k + 1], theta_host.begin() + toff[k]);
+          st.max_r = std::max(st.max_r, sst[i] >> 8);
+        } else {
+          single.push_back(k);
+        }
+      }
     }
     std::sort(single.begin(), single.end());
     // the single path (with Algorithm 2) for those members, one at a time;

@@ -155,14 +155,17 @@ def handle(device=None):
     return h
 
 
-TUNE_BATCHED_WORKERS, TUNE_CLASS_STEP_SMALL, TUNE_CLASS_STEP_MID, TUNE_CLASS_STEP_LARGE = range(4)
+(TUNE_BATCHED_WORKERS, TUNE_CLASS_STEP_SMALL, TUNE_CLASS_STEP_MID, TUNE_CLASS_STEP_LARGE,
+ TUNE_ONE_WORKGROUP_MAX_N) = range(5)
 TUNE_KEYS = {"batched_workers": TUNE_BATCHED_WORKERS, "class_step_small": TUNE_CLASS_STEP_SMALL,
-             "class_step_mid": TUNE_CLASS_STEP_MID, "class_step_large": TUNE_CLASS_STEP_LARGE}
+             "class_step_mid": TUNE_CLASS_STEP_MID, "class_step_large": TUNE_CLASS_STEP_LARGE,
+             "one_workgroup_max_n": TUNE_ONE_WORKGROUP_MAX_N}
 
 
 def set_tuning(device=None, **values):
     """Batched-path tuning of the device's handle (zcsd_set_tuning), e.g.
-    set_tuning(batched_workers=4, class_step_small=8, class_step_mid=16)."""
+    set_tuning(batched_workers=4, class_step_small=8, class_step_mid=16,
+    one_workgroup_max_n=64)."""
     h = handle(device)
     for k, v in values.items():
         _check(_lib().zcsd_set_tuning(h, TUNE_KEYS[k], int(v)), f"zcsd_set_tuning({k}={v})")

@@ -15,7 +15,8 @@ from paper_1804_09002_amd import workloads as WL
 
 pytestmark = pytest.mark.gpu
 U = 2.0 ** -53
-DEFAULT = {"batched_workers": 4, "class_step_small": 8, "class_step_mid": 16, "class_step_large": 64}
+DEFAULT = {"batched_workers": 4, "class_step_small": 8, "class_step_mid": 16, "class_step_large": 64,
+           "one_workgroup_max_n": 64}
 
 
 def test_tuning_roundtrip_and_validation():
@@ -24,7 +25,7 @@ def test_tuning_roundtrip_and_validation():
     zcsd.set_tuning(batched_workers=2, class_step_mid=32)
     assert zcsd.get_tuning() == {**DEFAULT, "batched_workers": 2, "class_step_mid": 32}
     for bad in ({"batched_workers": 0}, {"batched_workers": 17}, {"class_step_small": 0},
-                {"class_step_large": 257}):
+                {"class_step_large": 257}, {"one_workgroup_max_n": 65}):
         with pytest.raises(zcsd.ZcsdError):
             zcsd.set_tuning(**bad)
     st = zcsd.lib().zcsd_set_tuning(zcsd.handle(), 99, 1)
@@ -48,7 +49,8 @@ def test_batched_results_do_not_depend_on_tuning():
     a2, _, _ = zcsd.pack_ragged(A2s)
     ref = zcsd.csd_batched_packed(a1, a2, szs, offs)[3].cpu().numpy()
     try:
-        zcsd.set_tuning(batched_workers=1, class_step_small=4, class_step_mid=32, class_step_large=64)
+        zcsd.set_tuning(batched_workers=1, class_step_small=4, class_step_mid=32, class_step_large=64,
+                        one_workgroup_max_n=24)
         got = zcsd.csd_batched_packed(a1, a2, szs, offs)[3].cpu().numpy()
     finally:
         zcsd.set_tuning(**DEFAULT)
@@ -64,8 +66,9 @@ def test_batched_results_do_not_depend_on_tuning():
 def test_autotune_search_small_workload(tmp_path):
     from paper_1804_09002_amd import autotune, zcsd
     res = autotune.search(count=48, lo=8, hi=48, seed=3, reps=1, workers=(1, 2),
-                          steps=((8, 16, 64), (16, 16, 64)), log=lambda m: None)
-    assert len(res["timings"]) == 4
+                          steps=((8, 16, 64), (16, 16, 64)), one_wg=(64, 0), log=lambda m: None)
+    assert len(res["timings"]) == 5
+    assert res["best"]["one_workgroup_max_n"] in (64, 0)
     assert res["best"]["batched_workers"] in (1, 2)
     assert (res["best"]["class_step_small"], res["best"]["class_step_mid"]) in ((8, 16), (16, 16))
     assert zcsd.get_tuning() == DEFAULT

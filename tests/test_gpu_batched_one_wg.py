@@ -1,0 +1,173 @@
+"""The one-workgroup CSDs of the batched path (small full-rank problems, one
+persistent launch) against the oracle and against the size-class path.
+
+Every problem of size n <= 64 that is full rank runs as a whole CSD inside one
+workgroup (include/zcsd.h, ZCSD_TUNE_ONE_WORKGROUP_MAX_N).  Per problem: the
+oracle's angles (Algorithm 1 through SVD polars and LAPACK's eigh) and the
+known angles of the construction to 10 max(n, 8) u, self-certifying 2-norm
+backward error and orthogonality to 1e-13, angles ascending; and, with the
+one-workgroup path switched off on the same inputs, the class path's angles to
+10 n u (both compute Algorithm 1; their rounding differs).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import csd as O
+from paper_1804_09002_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -53
+DEV = torch.device("cuda:0")
+
+
+def _t(x):
+    return torch.tensor(np.ascontiguousarray(x), device=DEV)
+
+
+def _norm2(E):
+    return float(torch.linalg.matrix_norm(E, ord=2)) if E.numel() else 0.0
+
+
+def _checks(A1, A2, U1, U2, V1, th, r):
+    c, s = torch.cos(th[:r]), torch.sin(th[:r])
+    R = torch.cat([(U1[:, :r] * c) @ V1[:, :r].T - A1, (U2[:, :r] * s) @ V1[:, :r].T - A2])
+    res = _norm2(R) / max(_norm2(torch.cat([A1, A2])), 1e-300)
+    I = torch.eye(r, dtype=torch.float64, device=DEV)
+    orth = max(_norm2(X[:, :r].T @ X[:, :r] - I) for X in (U1, U2, V1))
+    return res, orth
+
+
+@pytest.fixture
+def one_wg_limit():
+    """Restores the handle's tuning after a test that changes it."""
+    from paper_1804_09002_amd import zcsd
+    saved = zcsd.get_tuning()
+    yield zcsd
+    zcsd.set_tuning(**saved)
+
+
+def _run(zcsd, A1s, A2s, limit, **opts):
+    zcsd.set_tuning(one_workgroup_max_n=limit)
+    return zcsd.csd_batched([_t(a) for a in A1s], [_t(a) for a in A2s], **opts)
+
+
+def test_one_workgroup_matches_oracle_and_class_path(one_wg_limit):
+    zcsd = one_wg_limit
+    assert zcsd.get_tuning()["one_workgroup_max_n"] == 64
+    sizes = [1, 2, 3, 4, 5, 7, 8, 13, 16, 17, 31, 32, 33, 47, 63, 64]
+    A1s, A2s, truth = [], [], []
+    for k, n in enumerate(sizes):
+        A1, A2, meta = WL.uniform_pair(n, 900 + k)
+        A1s.append(A1); A2s.append(A2); truth.append(np.sort(meta["theta"]))
+    A1, A2, _ = WL.clustered_pair(48, 931)     # clusters of angles near 0 and pi/2
+    A1s.append(A1); A2s.append(A2); truth.append(None)
+    one = _run(zcsd, A1s, A2s, 64)
+    cls = _run(zcsd, A1s, A2s, 0)
+    for k, ((U1, U2, V1, th, r), (_, _, _, thc, rc)) in enumerate(zip(one, cls)):
+        n = A1s[k].shape[0]
+        assert r == n and rc == n
+        thh = th.cpu().numpy()
+        assert np.all(np.diff(thh) >= 0)
+        o = O.csd(A1s[k], A2s[k])
+        assert np.max(np.abs(thh - o["theta"])) <= 10 * max(n, 8) * U, (k, n)
+        if truth[k] is not None:
+            assert np.max(np.abs(thh - truth[k])) <= 10 * max(n, 8) * U, (k, n)
+        assert float((th - thc).abs().max()) <= 10 * max(n, 8) * U, (k, n)
+        res, orth = _checks(_t(A1s[k]), _t(A2s[k]), U1, U2, V1, th, r)
+        assert res <= 1e-13 and orth <= 1e-13, (k, n, res, orth)
+
+
+def test_one_workgroup_persistent_over_many_problems(one_wg_limit):
+    """700 problems with n in [1, 64]: more than one per workgroup of the
+    persistent grid (at most one workgroup per compute unit), every one with
+    its known angles and the FP64 targets (Frobenius norms, batched on the
+    device), sampled ones against the oracle."""
+    zcsd = one_wg_limit
+    zcsd.set_tuning(one_workgroup_max_n=64)
+    rng = np.random.default_rng(77)
+    sizes = [int(x) for x in rng.integers(1, 65, size=700)]
+    A1s, A2s, truth = [], [], []
+    for n in sizes:
+        A1, A2, meta = WL.uniform_pair(n, int(rng.integers(1 << 31)))
+        A1s.append(A1); A2s.append(A2); truth.append(np.sort(meta["theta"]))
+    out = zcsd.csd_batched([_t(a) for a in A1s], [_t(a) for a in A2s])
+    worst = 0.0
+    for k, (U1, U2, V1, th, r) in enumerate(out):
+        n = sizes[k]
+        assert r == n
+        worst = max(worst, float(np.max(np.abs(th.cpu().numpy() - truth[k]))) / max(n, 8))
+        c, s = torch.cos(th), torch.sin(th)
+        A1, A2 = _t(A1s[k]), _t(A2s[k])
+        R = torch.cat([(U1 * c) @ V1.T - A1, (U2 * s) @ V1.T - A2])
+        lim = 1e-13 * max(1.0, np.sqrt(n) / 4)
+        assert float(torch.linalg.norm(R)) / float(torch.linalg.norm(torch.cat([A1, A2]))) <= lim, k
+        I = torch.eye(n, dtype=torch.float64, device=DEV)
+        for X in (U1, U2, V1):
+            assert float(torch.linalg.norm(X.T @ X - I)) <= lim, k
+    assert worst <= 10 * U, worst
+    for k in (0, 350, 699):
+        o = O.csd(A1s[k], A2s[k])
+        assert np.max(np.abs(out[k][3].cpu().numpy() - o["theta"])) <= 10 * max(sizes[k], 8) * U
+
+
+def test_one_workgroup_hands_eps_members_to_algorithm2(one_wg_limit):
+    """A member with angles within 1e-18 of 0 and pi/2 (sigma_min(A_i) < eps,
+    test class 2 of Sec. 6) and one with A_1 = 0 reach l = eps in the
+    workgroup's estimate: they run through the single path with Algorithm 2,
+    the uniform members of the same sizes stay in the persistent launch, and
+    all meet the targets and the oracle's angles.  A rank-deficient member of
+    small size runs through its class (Algorithm 3)."""
+    zcsd = one_wg_limit
+    zcsd.set_tuning(one_workgroup_max_n=64)
+    rng = np.random.default_rng(43)
+    theta = WL.angles_cumsum_clustered(40, rng)
+    A1b, A2b, _ = WL.from_angles(theta, rng)
+    A1z, A2z, _ = WL.from_angles(np.full(12, np.pi / 2), rng)
+    A1z[:] = 0.0
+    A1u, A2u, _ = WL.uniform_pair(40, 44)
+    A1d, A2d, _ = WL.clustered_pair(30, 45, rank_deficient=4)
+    A1s, A2s = [A1b, A1z, A1u, A1d], [A2b, A2z, A2u, A2d]
+    a1, sizes, offs = zcsd.pack_ragged([_t(a) for a in A1s])
+    a2, _, _ = zcsd.pack_ragged([_t(a) for a in A2s])
+    U1, U2, V1, th, ranks, info = zcsd.csd_batched_packed(a1, a2, sizes, offs)
+    assert info["repair"] >= 1
+    t0 = 0
+    for k, n in enumerate(sizes):
+        o = offs[k]
+        u1, u2, v1 = (X[o:o + n * n].view(n, n).t() for X in (U1, U2, V1))
+        t = th[t0:t0 + n]
+        t0 += n
+        ref = O.csd(A1s[k], A2s[k])
+        r = ranks[k]
+        assert r == ref["rank"], (k, r, ref["rank"])
+        assert np.max(np.abs(t[:r].cpu().numpy() - ref["theta"])) <= 10 * n * U, k
+        res, orth = _checks(_t(A1s[k]), _t(A2s[k]), u1, u2, v1, t, r)
+        assert res <= 1e-13 and orth <= 1e-13, (k, n, res, orth)
+
+
+def test_one_workgroup_angles_from_lambda(one_wg_limit):
+    """Remark (iv) (postprocess = 2): the angles from the eigenvalues of B, as
+    the oracle's theta_from="lambda" computes them and as the class path does."""
+    zcsd = one_wg_limit
+    A1s, A2s = [], []
+    for k, n in enumerate([6, 25, 64]):
+        A1, A2, _ = WL.uniform_pair(n, 960 + k)
+        A1s.append(A1); A2s.append(A2)
+    one = _run(zcsd, A1s, A2s, 64, postprocess=2)
+    cls = _run(zcsd, A1s, A2s, 0, postprocess=2)
+    for k, ((U1, U2, V1, th, r), (_, _, _, thc, _)) in enumerate(zip(one, cls)):
+        n = A1s[k].shape[0]
+        ref = O.csd(A1s[k], A2s[k], theta_from="lambda")
+        assert np.max(np.abs(th.cpu().numpy() - ref["theta"])) <= 1e-8, k
+        assert float((th - thc).abs().max()) <= 1e-8, k
+
+
+def test_one_workgroup_tuning_key(one_wg_limit):
+    zcsd = one_wg_limit
+    with pytest.raises(zcsd.ZcsdError):
+        zcsd.set_tuning(one_workgroup_max_n=65)
+    with pytest.raises(zcsd.ZcsdError):
+        zcsd.set_tuning(one_workgroup_max_n=-1)
+    zcsd.set_tuning(one_workgroup_max_n=32)
+    assert zcsd.get_tuning()["one_workgroup_max_n"] == 32

@@ -172,6 +172,62 @@ def batched_leg(count, sample, seed=5):
             "worst_backward_rel_fro": worst_res, "worst_orth_fro": worst_orth}
 
 
+def small_batched_leg(count=4096, lo=4, hi=64, seed=8):
+    """4096 CSDs with n log-uniform in [4, 64] (uniform angles): one batched call
+    with the handle's default one-workgroup limit (full-rank n <= 32 as whole
+    CSDs in one persistent launch, the rest through the size classes) against
+    the same call with every problem in the classes (one_workgroup_max_n = 0),
+    both steady state (two warm-up calls, mean of three)."""
+    import numpy as np
+    import torch
+    from paper_1804_09002_amd import workloads as WL
+    from paper_1804_09002_amd import zcsd
+    sizes = [int(n) for n in WL.batched_sizes(count, seed, lo, hi)]
+    rng = np.random.default_rng(seed)
+    A1s, A2s = [], []
+    for n in sizes:
+        A1, A2, _ = WL.uniform_pair(n, int(rng.integers(1 << 31)))
+        A1s.append(torch.tensor(A1, device="cuda:0"))
+        A2s.append(torch.tensor(A2, device="cuda:0"))
+    a1, sizes, offs = zcsd.pack_ragged(A1s)
+    a2, _, _ = zcsd.pack_ragged(A2s)
+    saved = zcsd.get_tuning()
+    limit = saved["one_workgroup_max_n"]
+    times = {}
+    try:
+        for lim in (0, limit):
+            zcsd.set_tuning(one_workgroup_max_n=lim)
+            for _ in range(2):
+                zcsd.csd_batched_packed(a1, a2, sizes, offs)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                U1, U2, V1, th, ranks, info = zcsd.csd_batched_packed(a1, a2, sizes, offs)
+            torch.cuda.synchronize()
+            times[lim] = (time.perf_counter() - t0) / 3
+    finally:
+        zcsd.set_tuning(**saved)
+    worst_res = worst_orth = 0.0
+    t_off = 0
+    for k, n in enumerate(sizes):  # outputs of the last (one-workgroup) call
+        o = offs[k]
+        u1, u2, v1 = (X[o:o + n * n].view(n, n).t() for X in (U1, U2, V1))
+        t = th[t_off:t_off + n]
+        t_off += n
+        R = torch.cat([(u1 * torch.cos(t)) @ v1.T - A1s[k], (u2 * torch.sin(t)) @ v1.T - A2s[k]])
+        worst_res = max(worst_res, float(torch.linalg.norm(R) / torch.linalg.norm(torch.cat([A1s[k], A2s[k]]))))
+        I = torch.eye(n, dtype=torch.float64, device="cuda:0")
+        worst_orth = max(worst_orth, max(float(torch.linalg.norm(X.T @ X - I)) for X in (u1, u2, v1)))
+    sum_n3 = float(sum(n ** 3 for n in sizes))
+    return {"workload": f"csd_fp64_batched_{count}_n{lo}to{hi}_loguniform", "problems": count,
+            "sum_n3": sum_n3, "one_workgroup_max_n": limit, "one_workgroup_s": round(times[limit], 5),
+            "size_classes_s": round(times[0], 5),
+            "speedup_vs_size_classes": round(times[0] / times[limit], 3),
+            "one_workgroup_csd_per_s": round(count / times[limit], 1),
+            "model_tflops_one_workgroup": round(198.0 * sum_n3 / times[limit] / 1e12, 4),
+            "worst_backward_rel_fro": worst_res, "worst_orth_fro": worst_orth}
+
+
 def backward_leg(count=64, n=512, seed=6):
     """Forward (one batched call) + hand-written backward of 64 CSDs at n = 512
     (uniform angles)."""
@@ -373,6 +429,8 @@ def main():
                  "mixed": legs["mixed_fp32"], "fp64_same_tol": legs["fp64"]}
         log(f"batched leg: {args.batched_count} problems")
         extra = {"mixed": mixed, "batched": batched_leg(args.batched_count, args.single_sample)}
+        log("small batched leg: 4096 problems, n in [4, 64]")
+        extra["batched_small"] = small_batched_leg()
         log("forward+backward leg: 64 x n=512")
         extra["backward"] = backward_leg()
         log("complex leg: n=2048")

@@ -132,11 +132,12 @@ const char* zcsd_status_string(zcsd_status s);
  * measured on 2048 problems with n log-uniform in [8, 256];
  * paper_1804_09002_amd/autotune.py measures the settings for another
  * workload.  Full-rank problems with n <= ZCSD_TUNE_ONE_WORKGROUP_MAX_N
- * (default 64, at most 64, 0 = none) skip the classes: each runs as a whole
- * CSD inside one workgroup, all of them in one persistent launch that runs
- * beside the class groups (the same Algorithm 1 with Zolo-pd; Zolo-eig of a
- * block of at most 64 is its Jacobi leaf solve), unless r_override,
- * ell_override or n_leaf < n asks for the class path.  zcsd_set_tuning
+ * (default 32, at most 64, 0 = none) skip the classes: each runs as a whole
+ * CSD inside one workgroup, all of them in persistent launches (one for
+ * n <= 32, four workgroups per compute unit; one for 32 < n <= 64, one per
+ * compute unit) that run beside the class groups (the same Algorithm 1 with
+ * Zolo-pd; Zolo-eig of a block of at most 64 is its Jacobi leaf solve),
+ * unless r_override, ell_override or n_leaf < n asks for the class path.  zcsd_set_tuning
  * returns ZCSD_EINVAL for an unknown key, workers outside [1, 16], a step
  * outside [1, 256] or a one-workgroup limit outside [0, 64]; it takes effect
  * on the next batched call of the handle. */

@@ -39,10 +39,13 @@ namespace zcsd {
 
 namespace {
 
-constexpr int SN = 64;       // largest problem size
-constexpr int SL = SN + 1;   // leading dimension of the LDS matrices
-constexpr int ST = 256;      // threads per workgroup
-constexpr int SNN = SN * SN; // global scratch matrix stride (doubles)
+// Two instances of everything below (SN: largest size, ST: threads of a
+// workgroup): problems of 33..64 with 256 threads (138 KB of LDS: one
+// workgroup per compute unit), problems of at most 32 with 128 threads
+// (36 KB: four workgroups per compute unit, whose waves hide each other's
+// latency).
+constexpr int kSmallMax = 64;
+constexpr int kSmallSplit = 32;
 
 // One tabulated lower bound and the coefficients of both Zolo-pd steps
 // (c_{2j-1} and a_j of the partial fractions, M); all doubles.
@@ -52,27 +55,34 @@ struct SmallCoef {
 };
 constexpr int kCoefDoubles = (int)(sizeof(SmallCoef) / sizeof(double));
 
-// LDS of the polar phase; matrices column-major: X[col][row]
+// LDS of the polar phase; matrices column-major: X[col][row], leading
+// dimension SL
+template <int SN>
 struct PolarShared {
+  static constexpr int SL = SN + 1;
   double F[SN][SL];   // Householder QR of A_i: R on and above the diagonal, reflectors below
-  double Bw[SN][SL];  // structured QR (V2 / Q2 upper, Q1 strictly upper stored transposed); Ms; P
+  double Bw[SN][SL];  // structured QR (V2 / Q2 upper, Q1 strictly upper stored transposed);
+                      // then Ms (upper) with (G + c I) / a and L^{-1} (strictly lower); P
   double Y[SN][SL];   // Y1
-  double D[SN][SL];   // R^{-1}; G (upper) with L_j (strictly lower, diagonal in dg); Y2 / W
-  double tau0[SN], tau[SN], q1d[SN], dg[SN], vb[2][SN], xb[SN];
+  double D[SN][SL];   // G (upper) with L (strictly lower); Y2 / W
+  double tau0[SN], tau[SN], q1d[SN], dg[SN], ed[SN], xd[SN], vb[2][SN];
 };
 
 // LDS of the angle and output phase
+template <int SN>
 struct OutShared {
+  static constexpr int SL = SN + 1;
   double V[SN][SL];   // eigenvectors, V[col][row]
-  double Ha[SN][SL];  // H_1, then W_1 / W_2
-  double Hb[SN][SL];  // H_2
+  double Ha[SN][SL];  // H_1, then W_1
+  double Hb[SN][SL];  // H_2, then W_2
 };
 
+template <int SN, int ST>
 struct SmallShared {
   union {
-    PolarShared p;
-    JacobiShared j;
-    OutShared o;
+    PolarShared<SN> p;
+    JacobiShared<SN, ST> j;
+    OutShared<SN> o;
   } u;
   SmallCoef coef;
   double red[ST / 64];
@@ -82,21 +92,28 @@ struct SmallShared {
   int flag;
 };
 
-__device__ inline double wave_sum(double v) {
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+// v from the lane whose index within its group of four is given by the DPP
+// quad permutation CTRL (as two 32-bit moves)
+template <int CTRL>
+__device__ inline double quad_perm(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-// sum over the four lanes 4g .. 4g+3 of a wave
+// sum over the four lanes 4g .. 4g+3 of a wave (lanes 1,0,3,2 then 2,3,0,1);
+// every lane of the group must be active
 __device__ inline double quad_sum(double v) {
-  v += __shfl_xor(v, 1, 64);
-  v += __shfl_xor(v, 2, 64);
+  v += quad_perm<0xB1>(v);
+  v += quad_perm<0x4E>(v);
   return v;
 }
 
-// sum of v over the workgroup (every thread gets it)
+// sum of v over the workgroup (every thread gets the same value)
+template <int ST>
 __device__ inline double block_sum(double v, double* red) {
-  v = wave_sum(v);
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
@@ -105,66 +122,117 @@ __device__ inline double block_sum(double v, double* red) {
   return t;
 }
 
+// Products on n x n LDS operands (n <= SN), SN/16 x 16 SN/ST outputs per
+// thread: rows ti + 16 a, columns tl + (ST/16) b (ti = tid % 16, tl = tid /
+// 16).  term(i, l, m) is the summand, m runs over [m0(ti, tl), n).
+template <int SN, int ST, class Term, class Out>
+__device__ inline void tile_product(int n, int m0, Term term, Out out) {
+  constexpr int CT = ST / 16, RA = SN / 16, CB = SN / CT;
+  const int ti = threadIdx.x & 15, tl = threadIdx.x >> 4;
+  double acc[RA][CB] = {};
+  for (int m = m0; m < n; ++m) {
+#pragma unroll
+    for (int a = 0; a < RA; ++a)
+#pragma unroll
+      for (int b = 0; b < CB; ++b) acc[a][b] += term(ti + 16 * a, tl + CT * b, m);
+  }
+#pragma unroll
+  for (int a = 0; a < RA; ++a)
+#pragma unroll
+    for (int b = 0; b < CB; ++b) {
+      const int i = ti + 16 * a, l = tl + CT * b;
+      if (i < n && l < n) out(i, l, acc[a][b]);
+    }
+}
+
+// The rows i = p + 4 q (q < SN/4) of a thread p of a group of four: every
+// loop over them is unrolled with loads made unconditionally (all LDS
+// matrices have SN rows) and masked by a select, so that the loads of a step
+// are in flight together; stores are predicated.
+#define FOR_ROWS(q, i) _Pragma("unroll") for (int q = 0, i = p; q < SN / 4; ++q, i += 4)
+
 // One polar of the n x n block A (ld n): writes H (n x n, ld n) and W (n x n,
 // ld n) to global memory.  Returns 0, 1 (l reached eps) or 2 (a Cholesky
-// factorization broke down); every thread returns the same value.
+// factorization broke down); every thread returns the same value.  Columns
+// (or rows) g are handled by the four threads 4g .. 4g+3, thread p of them
+// on the rows i = p (mod 4); a step's reflector is computed by the group of
+// its column at the end of the previous step, so a step has one barrier.
+template <int SN, int ST>
 __device__ int small_polar(int n, const double* __restrict__ A, const SmallCoef* __restrict__ table,
-                           int ntab, double eps, double* Hout, double* Wout, SmallShared& sh,
+                           int ntab, double eps, double* Hout, double* Wout, SmallShared<SN, ST>& sh,
                            int* r_used) {
-  PolarShared& P = sh.u.p;
+  PolarShared<SN>& P = sh.u.p;
   const int tid = threadIdx.x;
-  const int g = tid >> 2, p = tid & 3;  // four threads per column (or row) g
+  const int g = tid >> 2, p = tid & 3;
   for (int e = tid; e < n * n; e += ST) P.F[e / n][e % n] = A[e];
   __syncthreads();
 
-  // 0. Householder QR of F
-  for (int k = 0; k < n; ++k) {
-    if (tid < 64) {
-      const int i = tid;
-      const double x = (i > k && i < n) ? P.F[k][i] : 0.0;
-      const double s2 = wave_sum(x * x);
-      const double x0 = P.F[k][k];
-      double tau = 0.0, scale = 0.0, beta = x0;
-      if (s2 > 0.0) {
-        beta = -copysign(sqrt(x0 * x0 + s2), x0);
-        tau = (beta - x0) / beta;
-        scale = 1.0 / (x0 - beta);
-      }
-      if (i > k && i < n) P.F[k][i] = x * scale;
-      if (i == 0) {
-        P.tau0[k] = tau;
-        P.F[k][k] = beta;
-      }
+  // 0. Householder QR of F.  house(c): the reflector of column c from its rows
+  // >= c (rows below scaled to v, the diagonal set to beta), by group c
+  auto house = [&](int c) {
+    double x[SN / 4];
+    double s2 = 0.0;
+    FOR_ROWS(q, i) {
+      x[q] = P.F[c][i];
+      s2 += (i > c && i < n) ? x[q] * x[q] : 0.0;
     }
-    __syncthreads();
+    s2 = quad_sum(s2);
+    const double x0 = P.F[c][c];
+    double tau = 0.0, scale = 0.0, beta = x0;
+    if (s2 > 0.0) {
+      beta = -copysign(sqrt(x0 * x0 + s2), x0);
+      tau = (beta - x0) / beta;
+      scale = 1.0 / (x0 - beta);
+    }
+    FOR_ROWS(q, i) {
+      if (i > c && i < n) P.F[c][i] = x[q] * scale;
+      if (i == c) P.F[c][c] = beta;
+    }
+    if (p == 0) P.tau0[c] = tau;
+  };
+  if (g == 0) house(0);
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
     const double tk = P.tau0[k];
-    if (g > k && g < n && tk != 0.0) {
-      double w = 0.0;
-      for (int i = k + ((p - k) & 3); i < n; i += 4) w += (i == k ? 1.0 : P.F[k][i]) * P.F[g][i];
-      w = quad_sum(w) * tk;
-      for (int i = k + ((p - k) & 3); i < n; i += 4) P.F[g][i] -= w * (i == k ? 1.0 : P.F[k][i]);
+    if (g > k && g < n) {
+      if (tk != 0.0) {
+        double v[SN / 4], x[SN / 4];
+        double w = 0.0;
+        FOR_ROWS(q, i) {
+          v[q] = (i == k) ? 1.0 : P.F[k][i];
+          x[q] = P.F[g][i];
+          w += (i >= k && i < n) ? v[q] * x[q] : 0.0;
+        }
+        w = quad_sum(w) * tk;
+        FOR_ROWS(q, i) {
+          if (i >= k && i < n) P.F[g][i] = x[q] - w * v[q];
+        }
+      }
+      if (g == k + 1) house(g);
     }
     __syncthreads();
   }
 
-  // l from ||R^{-1}||_F: R^{-1} into D column by column (D[j][i] = (R^{-1})_ij)
-  for (int j = 0; j < n; ++j) {
-    double x = 0.0;
-    if (tid < j) {
-      for (int m = tid; m < j; ++m) x += P.D[m][tid] * P.F[j][m];
-    }
-    const double dj = 1.0 / P.F[j][j];
-    __syncthreads();
-    if (tid < j) P.D[j][tid] = -dj * x;
-    if (tid == j) P.D[j][j] = dj;
-    __syncthreads();
-  }
+  // l = 0.9 / ||R^{-1}||_F: column c of R^{-1} by back substitution in group c
+  // (x_i kept in D[c][i] by the thread that owns row i; no barrier inside)
   double ss = 0.0;
-  for (int e = tid; e < n * n; e += ST) {
-    const int i = e % n, j = e / n;
-    if (i <= j) ss += P.D[j][i] * P.D[j][i];
+  if (g < n) {
+    const int c = g;
+    for (int i = c; i >= 0; --i) {
+      double t = 0.0;
+      FOR_ROWS(q, m) {
+        const double a = P.F[m][i], x = P.D[c][m];
+        t += (m > i && m <= c) ? a * x : 0.0;
+      }
+      t = quad_sum(t);
+      const double x = ((i == c ? 1.0 : 0.0) - t) / P.F[i][i];
+      if ((i & 3) == p) {
+        P.D[c][i] = x;
+        ss += x * x;
+      }
+    }
   }
-  ss = block_sum(ss, sh.red);
+  ss = block_sum<ST>(ss, sh.red);
   double ell = (isfinite(ss) && ss > 0.0) ? 0.9 / sqrt(ss) : 0.0;
   ell = fmin(1.0, fmax(ell, eps));
   if (ell <= eps * (1.0 + 1e-12)) return 1;  // uniform: every thread has the same ss
@@ -180,12 +248,12 @@ __device__ int small_polar(int n, const double* __restrict__ A, const SmallCoef*
     double* dst = reinterpret_cast<double*>(&sh.coef);
     for (int e = tid; e < kCoefDoubles; e += ST) dst[e] = src[e];
   }
+  for (int e = tid; e < n * n; e += ST) P.Y[e / n][e % n] = 0.0;
   __syncthreads();
   const int r = (int)sh.coef.r;
   *r_used = r;
 
   // 1. QR form on R
-  for (int e = tid; e < n * n; e += ST) P.Y[e / n][e % n] = 0.0;
   for (int j = 0; j < r; ++j) {
     const double d = sqrt(sh.coef.c1[j]);
     const double sc = sqrt(sh.coef.a1[j] / d);
@@ -194,58 +262,91 @@ __device__ int small_polar(int n, const double* __restrict__ A, const SmallCoef*
       if (i <= c) P.Bw[c][i] = (i == c) ? d : 0.0;
     }
     __syncthreads();
-    // forward: the reflector of column k acts on top row k and bottom rows 0..k
-    for (int k = 0; k < n; ++k) {
-      if (tid < 64) {
-        const int i = tid;
-        const double x = (i <= k) ? P.Bw[k][i] : 0.0;
-        const double s2 = wave_sum(x * x);  // >= d^2 > 0: row k of the bottom is still d
-        const double x0 = P.F[k][k];
-        const double beta = -copysign(sqrt(x0 * x0 + s2), x0);
-        if (i <= k) P.Bw[k][i] = x / (x0 - beta);
-        if (i == 0) P.tau[k] = (beta - x0) / beta;
+    // forward: the reflector of column c acts on top row c and bottom rows
+    // 0..c; its bottom part (rows <= c of column c, row c still d > 0)
+    // becomes v, computed by group c
+    auto shouse = [&](int c) {
+      double x[SN / 4];
+      double s2 = 0.0;
+      FOR_ROWS(q, i) {
+        x[q] = P.Bw[c][i];
+        s2 += (i <= c) ? x[q] * x[q] : 0.0;
       }
-      __syncthreads();
+      s2 = quad_sum(s2);
+      const double x0 = P.F[c][c];
+      const double beta = -copysign(sqrt(x0 * x0 + s2), x0);
+      const double scale = 1.0 / (x0 - beta);
+      FOR_ROWS(q, i) {
+        if (i <= c) P.Bw[c][i] = x[q] * scale;
+      }
+      if (p == 0) P.tau[c] = (beta - x0) / beta;
+    };
+    if (g == 0) shouse(0);
+    __syncthreads();
+    for (int k = 0; k < n; ++k) {
       if (g > k && g < n) {
         const double tk = P.tau[k];
+        double v[SN / 4], x[SN / 4];
         double w = 0.0;
-        for (int i = p; i <= k; i += 4) w += P.Bw[k][i] * P.Bw[g][i];
+        FOR_ROWS(q, i) {
+          v[q] = P.Bw[k][i];
+          x[q] = P.Bw[g][i];
+          w += (i <= k) ? v[q] * x[q] : 0.0;
+        }
         w = (quad_sum(w) + P.F[g][k]) * tk;  // top row k of column g is still R(k, g)
-        for (int i = p; i <= k; i += 4) P.Bw[g][i] -= w * P.Bw[k][i];
+        FOR_ROWS(q, i) {
+          if (i <= k) P.Bw[g][i] = x[q] - w * v[q];
+        }
+        if (g == k + 1) shouse(g);
       }
       __syncthreads();
     }
     // backward: the first n columns of Q from [sc I; 0]; Q2 overwrites V2,
-    // Q1 (k, c) for k < c goes to Bw[k][c], its diagonal to q1d
-    if (tid < 64 && tid <= n - 1) P.vb[(n - 1) & 1][tid] = P.Bw[n - 1][tid];
+    // Q1 (k, c) for k < c goes to Bw[k][c], its diagonal to q1d.  The v of
+    // step k is staged by group k at step k + 1 (its column is not touched then)
+    if (g == n - 1) {
+      FOR_ROWS(q, i) {
+        if (i <= n - 1) P.vb[(n - 1) & 1][i] = P.Bw[n - 1][i];
+      }
+    }
     __syncthreads();
     for (int k = n - 1; k >= 0; --k) {
       const double* v = P.vb[k & 1];
       const double tk = P.tau[k];
       if (g == k - 1) {
-        for (int i = p; i <= k - 1; i += 4) P.vb[(k - 1) & 1][i] = P.Bw[k - 1][i];
+        FOR_ROWS(q, i) {
+          if (i <= k - 1) P.vb[(k - 1) & 1][i] = P.Bw[k - 1][i];
+        }
       } else if (g == k) {
-        for (int i = p; i <= k; i += 4) P.Bw[k][i] = -tk * sc * v[i];
+        FOR_ROWS(q, i) {
+          if (i <= k) P.Bw[k][i] = -tk * sc * v[i];
+        }
         if (p == 0) P.q1d[k] = sc - tk * sc;
       } else if (g > k && g < n) {
+        double vv[SN / 4], x[SN / 4];
         double w = 0.0;
-        for (int i = p; i <= k; i += 4) w += v[i] * P.Bw[g][i];
+        FOR_ROWS(q, i) {
+          vv[q] = v[i];
+          x[q] = P.Bw[g][i];
+          w += (i <= k) ? vv[q] * x[q] : 0.0;
+        }
         w = quad_sum(w) * tk;
-        for (int i = p; i <= k; i += 4) P.Bw[g][i] -= w * v[i];
+        FOR_ROWS(q, i) {
+          if (i <= k) P.Bw[g][i] = x[q] - w * vv[q];
+        }
         if (p == 0) P.Bw[k][g] = -w;
       }
       __syncthreads();
     }
-    // Y += Q1 Q2^T: (i, l) sums over m >= max(i, l)
-    for (int e = tid; e < n * n; e += ST) {
-      const int i = e % n, l = e / n;
-      double acc = 0.0;
-      for (int m = max(i, l); m < n; ++m) {
-        const double q1 = (m == i) ? P.q1d[m] : P.Bw[i][m];
-        acc += q1 * P.Bw[m][l];
-      }
-      P.Y[l][i] += acc;
-    }
+    // Y += Q1 Q2^T: (i, l) sums Q1(i, m) Q2(l, m) over m >= max(i, l)
+    tile_product<SN, ST>(
+        n, max(threadIdx.x & 15, threadIdx.x >> 4),
+        [&](int i, int l, int m) -> double {
+          if (m < i || m < l || i >= n || l >= n) return 0.0;
+          const double q1 = (m == i) ? P.q1d[m] : P.Bw[i][m];
+          return q1 * P.Bw[m][l];
+        },
+        [&](int i, int l, double v) { P.Y[l][i] += v; });
     __syncthreads();
   }
   for (int e = tid; e < n * n; e += ST) {
@@ -254,86 +355,102 @@ __device__ int small_polar(int n, const double* __restrict__ A, const SmallCoef*
   }
   __syncthreads();
 
-  // 2. Cholesky form on Y1: G (upper) in D, Ms in Bw
-  for (int e = tid; e < n * n; e += ST) {
-    const int i = e % n, l = e / n;
-    if (i <= l) {
-      double acc = 0.0;
-      for (int m = 0; m < n; ++m) acc += P.Y[i][m] * P.Y[l][m];
-      P.D[l][i] = acc;
-    }
-    P.Bw[l][i] = 0.0;
-  }
+  // 2. Cholesky form on Y1: G = Y1^T Y1 (upper of D); Ms (upper of Bw)
+  tile_product<SN, ST>(
+      n, 0,
+      [&](int i, int l, int m) -> double {
+        return (i <= l && l < n) ? P.Y[i][m] * P.Y[l][m] : 0.0;
+      },
+      [&](int i, int l, double v) {
+        if (i <= l) {
+          P.D[l][i] = v;
+          P.Bw[l][i] = 0.0;
+        }
+      });
   __syncthreads();
   int status = 0;
   for (int j = 0; j < r; ++j) {
     const double c = sh.coef.c2[j], inva = 1.0 / sh.coef.a2[j];
-    // L L^T = (G + c I) / a, L(i, k) for i > k in D[k][i], L(k, k) in dg[k]
-    for (int k = 0; k < n; ++k) {
-      if (tid < 64) {
-        const int i = tid;
-        double s = 0.0;
-        if (i == k)
-          for (int m = 0; m < k; ++m) s += P.D[m][k] * P.D[m][k];
-        if (i == k) {
-          const double dkk = (P.D[k][k] + c) * inva - s;
-          if (!(dkk > 0.0)) sh.flag = 2;
-          P.dg[k] = sqrt(fmax(dkk, 0x1p-1022));
-        }
-      }
-      __syncthreads();
-      if (g > k && g < n) {
-        double s = 0.0;
-        for (int m = p; m < k; m += 4) s += P.D[m][g] * P.D[m][k];
-        s = quad_sum(s);
-        if (p == 0) P.D[k][g] = (P.D[g][k] * inva - s) / P.dg[k];
-      }
-      __syncthreads();
-    }
-    // L^{-1} in place (last column first)
-    for (int jj = n - 1; jj >= 0; --jj) {
-      const double dinv = 1.0 / P.dg[jj];
-      if (g > jj && g < n) {
-        double x = 0.0;
-        for (int m = jj + 1 + p; m <= g; m += 4) x += ((m == g) ? P.dg[g] : P.D[m][g]) * P.D[jj][m];
-        x = quad_sum(x);
-        if (p == 0) P.xb[g] = -dinv * x;
-      }
-      __syncthreads();
-      if (g > jj && g < n && p == 0) P.D[jj][g] = P.xb[g];
-      if (tid == 0) P.dg[jj] = dinv;
-      __syncthreads();
-    }
-    // Ms += L^{-T} L^{-1}: (i, l) sums over m >= max(i, l)
+    // E = (G + c I) / a: strictly lower part in Bw, diagonal in ed
     for (int e = tid; e < n * n; e += ST) {
       const int i = e % n, l = e / n;
-      double acc = 0.0;
-      for (int m = max(i, l); m < n; ++m) {
-        const double a = (m == i) ? P.dg[m] : P.D[i][m];
-        const double b = (m == l) ? P.dg[m] : P.D[l][m];
-        acc += a * b;
-      }
-      P.Bw[l][i] += acc;
+      if (i > l) P.Bw[l][i] = P.D[i][l] * inva;
+      if (i == l) P.ed[i] = (P.D[i][i] + c) * inva;
     }
+    __syncthreads();
+    // right-looking Cholesky E = L L^T: at step k, row g > k of the trailing
+    // part loses L(g, k) L(j, k) for k < j <= g (its own j = p mod 4), and
+    // L(g, k) goes to D[k][g], L(k, k) to dg[k]
+    for (int k = 0; k < n; ++k) {
+      const double ekk = P.ed[k];
+      if (!(ekk > 0.0) && tid == 0) sh.flag = 2;
+      const double dk = sqrt(fmax(ekk, 0x1p-1022));
+      if (g > k && g < n) {
+        const double rdk = 1.0 / dk;
+        const double lg = P.Bw[k][g] * rdk;
+        double ek[SN / 4], eg[SN / 4];
+        FOR_ROWS(q, jj) {
+          ek[q] = P.Bw[k][jj];
+          eg[q] = P.Bw[jj][g];
+        }
+        FOR_ROWS(q, jj) {
+          if (jj > k && jj < g) P.Bw[jj][g] = eg[q] - lg * (ek[q] * rdk);
+        }
+        if ((g & 3) == p) P.ed[g] -= lg * lg;
+        if (p == 0) P.D[k][g] = lg;
+      }
+      if (tid == 0) P.dg[k] = dk;
+      __syncthreads();
+    }
+    // L^{-1}: column c by forward substitution in group c (strictly lower part
+    // in Bw, kept by the thread that owns the row; diagonal in xd)
+    if (g < n) {
+      const int cc = g;
+      const double xc = 1.0 / P.dg[cc];
+      if (p == 0) P.xd[cc] = xc;
+      for (int i = cc + 1; i < n; ++i) {
+        double t = 0.0;
+        FOR_ROWS(q, m) {
+          const double a = P.D[m][i], x = (m == cc) ? xc : P.Bw[cc][m];
+          t += (m >= cc && m < i) ? a * x : 0.0;
+        }
+        t = quad_sum(t);
+        if ((i & 3) == p) P.Bw[cc][i] = -t / P.dg[i];
+      }
+    }
+    __syncthreads();
+    // Ms += L^{-T} L^{-1} on the upper triangle: (i, l), i <= l, sums over m >= l
+    tile_product<SN, ST>(
+        n, threadIdx.x >> 4,
+        [&](int i, int l, int m) -> double {
+          if (i > l || l >= n || m < l) return 0.0;
+          const double a = (m == i) ? P.xd[m] : P.Bw[i][m];
+          const double b = (m == l) ? P.xd[m] : P.Bw[l][m];
+          return a * b;
+        },
+        [&](int i, int l, double v) {
+          if (i <= l) P.Bw[l][i] += v;
+        });
     __syncthreads();
   }
   if (sh.flag == 2) status = 2;
-  // Y2 = M (Y1 + Y1 Ms) into D
-  for (int e = tid; e < n * n; e += ST) {
-    const int i = e % n, l = e / n;
-    double acc = 0.0;
-    for (int m = 0; m < n; ++m) acc += P.Y[m][i] * P.Bw[l][m];
-    P.D[l][i] = sh.coef.M2 * (P.Y[l][i] + acc);
-  }
+  // Y2 = M (Y1 + Y1 Ms) into D (Ms symmetric, its upper triangle stored)
+  tile_product<SN, ST>(
+      n, 0,
+      [&](int i, int l, int m) -> double {
+        if (i >= n || l >= n) return 0.0;
+        return P.Y[m][i] * (m <= l ? P.Bw[l][m] : P.Bw[m][l]);
+      },
+      [&](int i, int l, double v) { P.D[l][i] = sh.coef.M2 * (P.Y[l][i] + v); });
   __syncthreads();
 
   // 3. H = sym(Y2^T R): P = Y2^T R into Bw, then the symmetric part to global
-  for (int e = tid; e < n * n; e += ST) {
-    const int i = e % n, l = e / n;
-    double acc = 0.0;
-    for (int m = 0; m <= l; ++m) acc += P.D[i][m] * P.F[l][m];
-    P.Bw[l][i] = acc;
-  }
+  tile_product<SN, ST>(
+      n, 0,
+      [&](int i, int l, int m) -> double {
+        return (m <= l && i < n && l < n) ? P.D[i][m] * P.F[l][m] : 0.0;
+      },
+      [&](int i, int l, double v) { P.Bw[l][i] = v; });
   __syncthreads();
   for (int e = tid; e < n * n; e += ST) {
     const int i = e % n, l = e / n;
@@ -342,13 +459,23 @@ __device__ int small_polar(int n, const double* __restrict__ A, const SmallCoef*
   // W = Q Y2: the reflectors of step 0, last first, on each column of D
   // (four threads per column, each on its own rows: no barrier inside)
   if (g < n) {
+    double x[SN / 4];
+    FOR_ROWS(q, i) x[q] = P.D[g][i];
     for (int k = n - 1; k >= 0; --k) {
       const double tk = P.tau0[k];
-      if (tk == 0.0) continue;
+      double v[SN / 4];
       double w = 0.0;
-      for (int i = k + ((p - k) & 3); i < n; i += 4) w += (i == k ? 1.0 : P.F[k][i]) * P.D[g][i];
+      FOR_ROWS(q, i) {
+        v[q] = (i == k) ? 1.0 : P.F[k][i];
+        w += (i >= k && i < n) ? v[q] * x[q] : 0.0;
+      }
       w = quad_sum(w) * tk;
-      for (int i = k + ((p - k) & 3); i < n; i += 4) P.D[g][i] -= w * (i == k ? 1.0 : P.F[k][i]);
+      FOR_ROWS(q, i) {
+        if (i >= k && i < n) x[q] -= w * v[q];
+      }
+    }
+    FOR_ROWS(q, i) {
+      if (i < n) P.D[g][i] = x[q];
     }
   }
   __syncthreads();
@@ -358,14 +485,17 @@ __device__ int small_polar(int n, const double* __restrict__ A, const SmallCoef*
 }
 
 // Persistent kernel: workgroup b solves problems list[b], list[b + grid], ...
+// (MINW: waves per SIMD it must allow, which bounds its registers)
 // status[t]: 0 done, 1 l reached eps (not written), 2 Cholesky breakdown (not
 // written); bits 8.. hold the Zolotarev degree of the two polars (max).
-__global__ __launch_bounds__(ST) void csd_small_kernel(
+template <int SN, int ST, int MINW>
+__global__ __launch_bounds__(ST, MINW) void csd_small_kernel(
     int count, const int* __restrict__ list, const int* __restrict__ nq, const long long* __restrict__ off,
     const long long* __restrict__ toff, const double* __restrict__ A1, const double* __restrict__ A2,
     double* U1, double* U2, double* V1, double* theta, const SmallCoef* __restrict__ table, int ntab,
     double eps, int theta_from_lambda, double* scratch, int* status) {
-  __shared__ SmallShared sh;
+  __shared__ SmallShared<SN, ST> sh;
+  constexpr long long SNN = (long long)SN * SN;
   const int tid = threadIdx.x;
   double* Hs1 = scratch + (long long)blockIdx.x * 6 * SNN;
   double* Hs2 = Hs1 + SNN;
@@ -380,8 +510,8 @@ __global__ __launch_bounds__(ST) void csd_small_kernel(
     if (tid == 0) sh.flag = 0;
     __syncthreads();
     int r1 = 0, r2 = 0;
-    int st = small_polar(n, A1 + o, table, ntab, eps, Hs1, Ws1, sh, &r1);
-    if (st == 0) st = small_polar(n, A2 + o, table, ntab, eps, Hs2, Ws2, sh, &r2);
+    int st = small_polar<SN, ST>(n, A1 + o, table, ntab, eps, Hs1, Ws1, sh, &r1);
+    if (st == 0) st = small_polar<SN, ST>(n, A2 + o, table, ntab, eps, Hs2, Ws2, sh, &r2);
     if (st != 0) {
       if (tid == 0) status[t] = st;
       __syncthreads();
@@ -392,7 +522,7 @@ __global__ __launch_bounds__(ST) void csd_small_kernel(
     __syncthreads();
     jacobi_block(n, Bs, n, Vs, n, sh.lam, sh.u.j);
     __syncthreads();
-    OutShared& O = sh.u.o;
+    OutShared<SN>& O = sh.u.o;
     for (int e = tid; e < n * n; e += ST) {
       O.V[e / n][e % n] = Vs[e];
       O.Ha[e / n][e % n] = Hs1[e];
@@ -500,23 +630,38 @@ const std::vector<SmallCoef>& small_table(double eps, double tol) {
 
 }  // namespace
 
-size_t small_csd_scratch_bytes(int grid) { return (size_t)grid * 6 * SNN * sizeof(double); }
+int small_csd_max_n() { return kSmallMax; }
 
-int small_csd_max_n() { return SN; }
+int small_csd_split_n() { return kSmallSplit; }
 
-void small_csd_launch(int count, const int* d_list, const int* d_n, const long long* d_off,
-                      const long long* d_toff, const double* A1, const double* A2, double* U1,
-                      double* U2, double* V1, double* theta, double eps, double tol,
-                      bool theta_from_lambda, int grid, double* scratch, int* d_status, Arena& ar,
-                      hipStream_t s) {
+size_t small_csd_scratch_bytes(int grid_large, int grid_small) {
+  return ((size_t)grid_large * kSmallMax * kSmallMax + (size_t)grid_small * kSmallSplit * kSmallSplit) * 6 *
+         sizeof(double);
+}
+
+void small_csd_launch(int count, int count_large, const int* d_list, const int* d_n,
+                      const long long* d_off, const long long* d_toff, const double* A1,
+                      const double* A2, double* U1, double* U2, double* V1, double* theta, double eps,
+                      double tol, bool theta_from_lambda, int grid_large, int grid_small,
+                      double* scratch, int* d_status, Arena& ar, hipStream_t s) {
   if (count <= 0) return;
   const std::vector<SmallCoef>& tab = small_table(eps, tol);
   SmallCoef* d_tab = static_cast<SmallCoef*>(ar.alloc(tab.size() * sizeof(SmallCoef)));
   h2d(d_tab, tab.data(), tab.size() * sizeof(SmallCoef), s);
-  hipLaunchKernelGGL(csd_small_kernel, dim3(grid), dim3(ST), 0, s, count, d_list, d_n, d_off, d_toff,
-                     A1, A2, U1, U2, V1, theta, d_tab, (int)tab.size(), eps, theta_from_lambda ? 1 : 0,
-                     scratch, d_status);
-  ZCSD_CHECK_LAUNCH();
+  const int lam = theta_from_lambda ? 1 : 0;
+  if (count_large > 0) {
+    hipLaunchKernelGGL((csd_small_kernel<kSmallMax, 256, 1>), dim3(grid_large), dim3(256), 0, s, count_large,
+                       d_list, d_n, d_off, d_toff, A1, A2, U1, U2, V1, theta, d_tab, (int)tab.size(), eps,
+                       lam, scratch, d_status);
+    ZCSD_CHECK_LAUNCH();
+  }
+  if (count > count_large) {
+    double* scr = scratch + (size_t)grid_large * kSmallMax * kSmallMax * 6;
+    hipLaunchKernelGGL((csd_small_kernel<kSmallSplit, 128, 2>), dim3(grid_small), dim3(128), 0, s,
+                       count - count_large, d_list + count_large, d_n, d_off, d_toff, A1, A2, U1, U2, V1,
+                       theta, d_tab, (int)tab.size(), eps, lam, scr, d_status + count_large);
+    ZCSD_CHECK_LAUNCH();
+  }
 }
 
 }  // namespace zcsd

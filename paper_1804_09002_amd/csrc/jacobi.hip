@@ -8,20 +8,20 @@
 
 namespace zcsd {
 
-__global__ __launch_bounds__(JNT) void jacobi_kernel(const int* __restrict__ sizes, const double* A,
+__global__ __launch_bounds__(kLeafThreads) void jacobi_kernel(const int* __restrict__ sizes, const double* A,
                                                      long long lda, long long sA, double* V,
                                                      long long ldv, long long sV, double* lam) {
-  __shared__ JacobiShared sh;
+  __shared__ JacobiShared<kLeafMax, kLeafThreads> sh;
   const int b = blockIdx.x;
   const int n = sizes[b];
   if (n <= 0) return;
-  jacobi_block(n, A + (long long)b * sA, lda, V + (long long)b * sV, ldv, lam + (long long)b * JB, sh);
+  jacobi_block(n, A + (long long)b * sA, lda, V + (long long)b * sV, ldv, lam + (long long)b * kLeafMax, sh);
 }
 
 void jacobi_batched(int nblk, const int* d_sizes, const double* A, long long lda, long long sA,
                     double* V, long long ldv, long long sV, double* d_lam, hipStream_t s) {
   if (nblk <= 0) return;
-  hipLaunchKernelGGL(jacobi_kernel, dim3(nblk), dim3(JNT), 0, s, d_sizes, A, lda, sA, V, ldv, sV,
+  hipLaunchKernelGGL(jacobi_kernel, dim3(nblk), dim3(kLeafThreads), 0, s, d_sizes, A, lda, sA, V, ldv, sV,
                      d_lam);
   ZCSD_CHECK_LAUNCH();
 }

@@ -31,10 +31,12 @@ namespace zcsd {
 // delta = 1e-6 ||A||_F stay as Jacobi left them (their eigenvectors are
 // determined only to u ||A|| / gap, and a correction divided by such a gap
 // would bring rounding of G back at second order); they are orthogonalised.
-constexpr int JB = 64;
-constexpr int JNT = 256;
+// the leaf blocks of Zolo-eig: at most 64, one workgroup of 256 threads
+constexpr int kLeafMax = 64;
+constexpr int kLeafThreads = 256;
 
-// LDS of one block solve
+// LDS of one block solve (blocks of at most JB, workgroups of JNT threads)
+template <int JB, int JNT>
 struct JacobiShared {
   // the matrix in two buffers: a round reads one and writes J^T S J into the other
   double Sbuf[2][JB][JB + 1];
@@ -50,11 +52,12 @@ struct JacobiShared {
   int rotated;
 };
 
-// Eigenpairs of the symmetric part of the n x n block A (1 <= n <= 64, ld lda)
+// Eigenpairs of the symmetric part of the n x n block A (1 <= n <= JB, ld lda)
 // by the workgroup of JNT threads that calls it (every thread, uniformly):
 // V (n x n, ld ldv) and lam (n).  A, V and lam may be global or LDS.
+template <int JB, int JNT>
 __device__ inline void jacobi_block(int n, const double* A, long long lda, double* V, long long ldv,
-                                    double* lam, JacobiShared& sh) {
+                                    double* lam, JacobiShared<JB, JNT>& sh) {
   double(*Sbuf)[JB][JB + 1] = sh.Sbuf;
   double(*Q)[JB + 1] = sh.Q;
   double(*cs)[2] = sh.cs;
@@ -106,6 +109,12 @@ __device__ inline void jacobi_block(int n, const double* A, long long lda, doubl
   afro = sqrt(afro);
   const double thr = 0x1p-53 * afro / n;
   const int m = (n % 2) ? n + 1 : n;  // players; index n is a dummy when n is odd
+  // a round's updates: thread tid takes row ri = tid % RB of the columns
+  // rj0 + CS q and of the pairs rj0 + CS q, RB the smallest of 16, 32, 64
+  // that holds n (every thread busy for small n)
+  const int RB = (n <= 16) ? 16 : ((n <= 32) ? 32 : 64);
+  const int CS = JNT / RB;
+  const int ri = tid & (RB - 1), rj0 = tid / RB;
   for (int sweep = 0; sweep < 40; ++sweep) {
     if (tid == 0) rotated = 0;
     __syncthreads();
@@ -151,27 +160,34 @@ __device__ inline void jacobi_block(int n, const double* A, long long lda, doubl
       // row combination of the two columns: the arithmetic of applying J on
       // the right, then J^T on the left), the rotated pairs' entries set to
       // zero; V <- V J in place (each pair's two columns by one thread)
-      {
+      // (the row's rotation is read once)
+      if (ri < n) {
         double(*Sn)[JB + 1] = Sbuf[cur ^ 1];
+        const int pi = pt[ri];
+        const double ai = al[ri], bi = be[ri];
 #pragma unroll
-        for (int qq = 0; qq < NL; ++qq) {
-          const int e = tid + JNT * qq, i = e % n, j = e / n;
-          if (e < n * n) {
-            const int pi = pt[i], pj = pt[j];
-            const double ai = al[i], bi = be[i], aj = al[j], bj = be[j];
-            const double t1 = aj * S[i][j] + bj * S[i][pj];
+        for (int qq = 0; qq < JB / 4; ++qq) {
+          const int j = rj0 + CS * qq;
+          if (j < n) {
+            const int pj = pt[j];
+            const double aj = al[j], bj = be[j];
+            const double t1 = aj * S[ri][j] + bj * S[ri][pj];
             const double t2 = aj * S[pi][j] + bj * S[pi][pj];
-            Sn[i][j] = (pi == j && pi != i) ? 0.0 : ai * t1 + bi * t2;
+            Sn[ri][j] = (pi == j && pi != ri) ? 0.0 : ai * t1 + bi * t2;
           }
         }
-        for (int e = tid; e < (m / 2) * n; e += JNT) {
-          const int k = e / n, i = e % n;
-          const int p = pq[k][0], q = pq[k][1];
-          if (p == q) continue;
-          const double c = cs[k][0], s = cs[k][1];
-          const double vp = Q[i][p], vq = Q[i][q];
-          Q[i][p] = c * vp - s * vq;
-          Q[i][q] = s * vp + c * vq;
+#pragma unroll
+        for (int qq = 0; qq < JB / 8; ++qq) {
+          const int k = rj0 + CS * qq;
+          if (k < m / 2) {
+            const int p = pq[k][0], q = pq[k][1];
+            if (p != q) {
+              const double c = cs[k][0], s = cs[k][1];
+              const double vp = Q[ri][p], vq = Q[ri][q];
+              Q[ri][p] = c * vp - s * vq;
+              Q[ri][q] = s * vp + c * vq;
+            }
+          }
         }
       }
       __syncthreads();

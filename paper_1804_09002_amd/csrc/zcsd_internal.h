@@ -97,8 +97,8 @@ struct zcsd_handle_s {
   int tune_workers = 4;
   int tune_step[3] = {8, 16, 64};
   // full-rank problems with n up to this run as whole CSDs of one workgroup
-  // each, in one persistent launch (0: none)
-  int tune_small_max = 64;
+  // each, in persistent launches (0: none)
+  int tune_small_max = 32;
 };
 
 namespace zcsd {
@@ -240,19 +240,23 @@ int csd_single_member(int n, const double* A1, const double* A2, double* U1, dou
 size_t csd_workspace_bytes(int n);
 // the batched path's first W worker streams of a handle (csd_batched.hip)
 void ensure_batch_workers(zcsd_handle_s* h, int W);
-// whole CSDs of small full-rank problems, one workgroup each, in one
-// persistent launch (csd_small.hip): the largest n it takes, its global
-// scratch for a grid of `grid` workgroups, and the launch.  status[t] of list
+// whole CSDs of small full-rank problems, one workgroup each, in persistent
+// launches (csd_small.hip): the largest n they take; the size up to which the
+// smaller instance runs (four workgroups per compute unit; above it, up to
+// the largest, one); their global scratch for grids of grid_large and
+// grid_small workgroups; and the launches, for a list whose first
+// count_large entries are the problems above the split.  status[t] of list
 // entry t: low byte 0 = written, 1 = the l estimate reached eps, 2 = a
 // Cholesky factorization broke down (1 and 2: nothing written); bits 8.. the
 // Zolotarev degree used
 int small_csd_max_n();
-size_t small_csd_scratch_bytes(int grid);
-void small_csd_launch(int count, const int* d_list, const int* d_n, const long long* d_off,
-                      const long long* d_toff, const double* A1, const double* A2, double* U1,
-                      double* U2, double* V1, double* theta, double eps, double tol,
-                      bool theta_from_lambda, int grid, double* scratch, int* d_status, Arena& ar,
-                      hipStream_t s);
+int small_csd_split_n();
+size_t small_csd_scratch_bytes(int grid_large, int grid_small);
+void small_csd_launch(int count, int count_large, const int* d_list, const int* d_n,
+                      const long long* d_off, const long long* d_toff, const double* A1,
+                      const double* A2, double* U1, double* U2, double* V1, double* theta, double eps,
+                      double tol, bool theta_from_lambda, int grid_large, int grid_small,
+                      double* scratch, int* d_status, Arena& ar, hipStream_t s);
 // Householder QR of the m x n block A (m >= n, ld lda): Q (m x n, ld m) and
 // the triangular R (n x n, ld n, zeros below the diagonal) (csd.hip)
 void tall_qr(int m, int n, const double* A, long long lda, double* Q, double* R, Arena& ar,

@@ -1,8 +1,10 @@
-"""The one-workgroup CSDs of the batched path (small full-rank problems, one
-persistent launch) against the oracle and against the size-class path.
+"""The one-workgroup CSDs of the batched path (small full-rank problems,
+persistent launches) against the oracle and against the size-class path.
 
-Every problem of size n <= 64 that is full rank runs as a whole CSD inside one
-workgroup (include/zcsd.h, ZCSD_TUNE_ONE_WORKGROUP_MAX_N).  Per problem: the
+Every full-rank problem with n up to the one-workgroup limit (default 32, at
+most 64; include/zcsd.h, ZCSD_TUNE_ONE_WORKGROUP_MAX_N) runs as a whole CSD
+inside one workgroup: n <= 32 in a launch of four workgroups per compute
+unit, 32 < n <= 64 in a launch of one per compute unit.  Per problem: the
 oracle's angles (Algorithm 1 through SVD polars and LAPACK's eigh) and the
 known angles of the construction to 10 max(n, 8) u, self-certifying 2-norm
 backward error and orthogonality to 1e-13, angles ascending; and, with the
@@ -54,7 +56,7 @@ def _run(zcsd, A1s, A2s, limit, **opts):
 
 def test_one_workgroup_matches_oracle_and_class_path(one_wg_limit):
     zcsd = one_wg_limit
-    assert zcsd.get_tuning()["one_workgroup_max_n"] == 64
+    assert zcsd.get_tuning()["one_workgroup_max_n"] == 32
     sizes = [1, 2, 3, 4, 5, 7, 8, 13, 16, 17, 31, 32, 33, 47, 63, 64]
     A1s, A2s, truth = [], [], []
     for k, n in enumerate(sizes):
@@ -79,14 +81,14 @@ def test_one_workgroup_matches_oracle_and_class_path(one_wg_limit):
 
 
 def test_one_workgroup_persistent_over_many_problems(one_wg_limit):
-    """700 problems with n in [1, 64]: more than one per workgroup of the
-    persistent grid (at most one workgroup per compute unit), every one with
-    its known angles and the FP64 targets (Frobenius norms, batched on the
-    device), sampled ones against the oracle."""
+    """2400 problems with n in [1, 64]: more than one per workgroup of both
+    persistent grids (four workgroups per compute unit for n <= 32, one above),
+    every one with its known angles and the FP64 targets (Frobenius norms),
+    sampled ones against the oracle."""
     zcsd = one_wg_limit
     zcsd.set_tuning(one_workgroup_max_n=64)
     rng = np.random.default_rng(77)
-    sizes = [int(x) for x in rng.integers(1, 65, size=700)]
+    sizes = [int(x) for x in rng.integers(1, 65, size=2400)]
     A1s, A2s, truth = [], [], []
     for n in sizes:
         A1, A2, meta = WL.uniform_pair(n, int(rng.integers(1 << 31)))
@@ -106,7 +108,7 @@ def test_one_workgroup_persistent_over_many_problems(one_wg_limit):
         for X in (U1, U2, V1):
             assert float(torch.linalg.norm(X.T @ X - I)) <= lim, k
     assert worst <= 10 * U, worst
-    for k in (0, 350, 699):
+    for k in (0, 1200, 2399):
         o = O.csd(A1s[k], A2s[k])
         assert np.max(np.abs(out[k][3].cpu().numpy() - o["theta"])) <= 10 * max(sizes[k], 8) * U
 

@@ -121,7 +121,7 @@ zcsd_status zcsd_destroy(zcsd_handle* handle);
 zcsd_status zcsd_set_stream(zcsd_handle* handle, void* stream);
 void zcsd_default_opts(zcsd_opts* opts);
 const char* zcsd_status_string(zcsd_status s);
-/* Tuning of the batched path (zcsd_dcsd_batched), per handle; not in the
+/* Tuning, per handle (mostly of the batched path, zcsd_dcsd_batched); not in the
  * paper.  The problems of a batch are grouped into size classes padded to
  * the next multiple of a step (ZCSD_TUNE_CLASS_STEP_SMALL for n <= 64,
  * default 8; _MID for 64 < n <= 256, default 16; _LARGE beyond, default 64),
@@ -137,16 +137,22 @@ const char* zcsd_status_string(zcsd_status s);
  * n <= 32, four workgroups per compute unit; one for 32 < n <= 64, one per
  * compute unit) that run beside the class groups (the same Algorithm 1 with
  * Zolo-pd; Zolo-eig of a block of at most 64 is its Jacobi leaf solve),
- * unless r_override, ell_override or n_leaf < n asks for the class path.  zcsd_set_tuning
- * returns ZCSD_EINVAL for an unknown key, workers outside [1, 16], a step
- * outside [1, 256] or a one-workgroup limit outside [0, 64]; it takes effect
- * on the next batched call of the handle. */
+ * unless r_override, ell_override or n_leaf < n asks for the class path.
+ * ZCSD_TUNE_GEMM_TILE128_MIN applies to every call of the handle: a matrix
+ * product with at least that many 128 x 128 output tiles (over its batch)
+ * uses the 128 x 128 tiling, the others 64 x 64 tiles (default 512, two per
+ * compute unit); paper_1804_09002_amd/autotune.py measures it per problem
+ * size and precision.  zcsd_set_tuning returns ZCSD_EINVAL for an
+ * unknown key, workers outside [1, 16], a step outside [1, 256], a
+ * one-workgroup limit outside [0, 64] or a tile threshold outside
+ * [1, 2^24]; it takes effect on the next call of the handle. */
 typedef enum {
   ZCSD_TUNE_BATCHED_WORKERS = 0,
   ZCSD_TUNE_CLASS_STEP_SMALL = 1,
   ZCSD_TUNE_CLASS_STEP_MID = 2,
   ZCSD_TUNE_CLASS_STEP_LARGE = 3,
-  ZCSD_TUNE_ONE_WORKGROUP_MAX_N = 4
+  ZCSD_TUNE_ONE_WORKGROUP_MAX_N = 4,
+  ZCSD_TUNE_GEMM_TILE128_MIN = 5
 } zcsd_tune_key;
 zcsd_status zcsd_set_tuning(zcsd_handle* handle, int key, int value);
 zcsd_status zcsd_get_tuning(zcsd_handle* handle, int key, int* value);

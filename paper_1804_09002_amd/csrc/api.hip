@@ -85,6 +85,10 @@ zcsd_status zcsd_set_tuning(zcsd_handle* handle, int key, int value) {
       if (value < 0 || value > zcsd::small_csd_max_n()) return ZCSD_EINVAL;
       handle->tune_small_max = value;
       return ZCSD_OK;
+    case ZCSD_TUNE_GEMM_TILE128_MIN:
+      if (value < 1 || value > (1 << 24)) return ZCSD_EINVAL;
+      handle->tune_tile128_min = value;
+      return ZCSD_OK;
     default:
       return ZCSD_EINVAL;
   }
@@ -103,6 +107,9 @@ zcsd_status zcsd_get_tuning(zcsd_handle* handle, int key, int* value) {
       return ZCSD_OK;
     case ZCSD_TUNE_ONE_WORKGROUP_MAX_N:
       *value = handle->tune_small_max;
+      return ZCSD_OK;
+    case ZCSD_TUNE_GEMM_TILE128_MIN:
+      *value = handle->tune_tile128_min;
       return ZCSD_OK;
     default:
       return ZCSD_EINVAL;
@@ -144,6 +151,7 @@ zcsd_status zcsd_dgemm(zcsd_handle* handle, int transA, int transB, int m, int n
                        long long strideC, int batch) {
   if (!handle) return ZCSD_EINVAL;
   return guarded([&] {
+    GemmTileScope tile_scope(handle->tune_tile128_min);
     ZCSD_REQUIRE(m >= 0 && n >= 0 && k >= 0 && batch >= 0, "dgemm: negative size");
     if (m == 0 || n == 0 || batch == 0) return;
     ZCSD_REQUIRE(C && (k == 0 || (A && B)), "dgemm: NULL pointer");
@@ -168,6 +176,7 @@ zcsd_status zcsd_dgemm_f32acc(zcsd_handle* handle, int transA, int transB, int m
                        long long strideC, int batch) {
   if (!handle) return ZCSD_EINVAL;
   return guarded([&] {
+    GemmTileScope tile_scope(handle->tune_tile128_min);
     ZCSD_REQUIRE(m >= 0 && n >= 0 && k >= 0 && batch >= 0, "dgemm_f32acc: negative size");
     if (m == 0 || n == 0 || batch == 0) return;
     ZCSD_REQUIRE(C && (k == 0 || (A && B)), "dgemm_f32acc: NULL pointer");
@@ -195,6 +204,7 @@ zcsd_status zcsd_dgemm_ex(zcsd_handle* handle, int transA, int transB, int m, in
                           double* d_ws, size_t ws_elems) {
   if (!handle) return ZCSD_EINVAL;
   return guarded([&] {
+    GemmTileScope tile_scope(handle->tune_tile128_min);
     ZCSD_REQUIRE(m >= 0 && n >= 0 && k >= 0 && batch >= 0, "dgemm_ex: negative size");
     ZCSD_REQUIRE((flags & ~(ZCSD_GEMM_SYM_UPPER | ZCSD_GEMM_UPPER_ONLY | ZCSD_GEMM_F32ACC)) == 0,
                  "dgemm_ex: unknown flag");
@@ -246,6 +256,7 @@ extern "C" zcsd_status zcsd_dzolo_pd(zcsd_handle* handle, int batch, int n, doub
                                      zcsd_info* info) {
   if (!handle) return ZCSD_EINVAL;
   return guarded([&] {
+    GemmTileScope tile_scope(handle->tune_tile128_min);
     ZCSD_REQUIRE(batch >= 1 && n >= 1, "zolo_pd: batch and n must be positive");
     ZCSD_REQUIRE(d_X && d_W, "zolo_pd: NULL pointer");
     ZCSD_REQUIRE(ldx >= n, "zolo_pd: ldx < n");
@@ -283,6 +294,7 @@ extern "C" zcsd_status zcsd_dqr(zcsd_handle* handle, int batch, int stacked, int
                                 long long strideQ) {
   if (!handle) return ZCSD_EINVAL;
   return guarded([&] {
+    GemmTileScope tile_scope(handle->tune_tile128_min);
     ZCSD_REQUIRE(batch >= 1 && n >= 1 && m >= n, "qr: need batch >= 1, m >= n >= 1");
     ZCSD_REQUIRE(!stacked || m == 2 * n, "qr: stacked shape needs m == 2n");
     ZCSD_REQUIRE(d_M && ldm >= m, "qr: bad M");

@@ -158,6 +158,7 @@ extern "C" zcsd_status zcsd_dcsd_backward(zcsd_handle* handle, int batch, int n,
                                           double* d_gA2) {
   if (!handle) return ZCSD_EINVAL;
   return guarded([&] {
+    GemmTileScope tile_scope(handle->tune_tile128_min);
     ZCSD_REQUIRE(batch >= 1 && n >= 1, "csd_backward: batch and n must be positive");
     ZCSD_REQUIRE(batch <= 65535, "csd_backward: batch <= 65535");
     ZCSD_REQUIRE(d_U1 && d_U2 && d_V1 && d_theta && d_gA1 && d_gA2, "csd_backward: NULL pointer");
@@ -178,6 +179,7 @@ extern "C" zcsd_status zcsd_dcsd_backward_noalloc(zcsd_handle* handle, int batch
                                                   double* d_gA2) {
   if (!handle) return ZCSD_EINVAL;
   return guarded([&] {
+    GemmTileScope tile_scope(handle->tune_tile128_min);
     ZCSD_REQUIRE(batch >= 1 && n >= 1, "csd_backward_noalloc: batch and n must be positive");
     ZCSD_REQUIRE(2LL * n * n <= kScratchDoubles,
                  "csd_backward_noalloc: n exceeds the scratch limit (2 n^2 <= 2^23 doubles, n <= 2048)");

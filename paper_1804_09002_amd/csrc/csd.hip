@@ -526,6 +526,7 @@ extern "C" zcsd_status zcsd_dcsd(zcsd_handle* handle, int n, const double* d_A1,
                                  double* d_W2, const zcsd_opts* opts, zcsd_info* info) {
   if (!handle) return ZCSD_EINVAL;
   return guarded([&] {
+    GemmTileScope tile_scope(handle->tune_tile128_min);
     ZCSD_REQUIRE(n >= 1, "csd: n must be positive");
     ZCSD_REQUIRE(d_A1 && d_A2 && d_U1 && d_U2 && d_V1 && d_theta, "csd: NULL pointer");
     ZCSD_REQUIRE(lda1 >= n && lda2 >= n && ldu1 >= n && ldu2 >= n && ldv1 >= n,
@@ -582,6 +583,7 @@ extern "C" zcsd_status zcsd_dcsd_mn(zcsd_handle* handle, int m1, int m2, int n,
                                     zcsd_info* info) {
   if (!handle) return ZCSD_EINVAL;
   return guarded([&] {
+    GemmTileScope tile_scope(handle->tune_tile128_min);
     ZCSD_REQUIRE(n >= 1 && m1 >= n && m2 >= n, "csd_mn: need n >= 1 and m1, m2 >= n");
     ZCSD_REQUIRE(d_A1 && d_A2 && d_U1 && d_U2 && d_V1 && d_theta, "csd_mn: NULL pointer");
     ZCSD_REQUIRE(lda1 >= m1 && lda2 >= m2 && ldu1 >= m1 && ldu2 >= m2 && ldv1 >= n,
@@ -632,6 +634,7 @@ extern "C" zcsd_status zcsd_dcsd2x2(zcsd_handle* handle, int n, const double* d_
                                     zcsd_info* info) {
   if (!handle) return ZCSD_EINVAL;
   return guarded([&] {
+    GemmTileScope tile_scope(handle->tune_tile128_min);
     ZCSD_REQUIRE(n >= 1, "csd2x2: n must be positive");
     ZCSD_REQUIRE(d_A1 && d_A2 && d_A3 && d_A4 && d_U1 && d_U2 && d_V1 && d_V2 && d_theta,
                  "csd2x2: NULL pointer");
@@ -705,6 +708,7 @@ extern "C" zcsd_status zcsd_dsyev_zolo(zcsd_handle* handle, int n, const double*
                                        double* d_lambda, const zcsd_opts* opts, zcsd_info* info) {
   if (!handle) return ZCSD_EINVAL;
   return guarded([&] {
+    GemmTileScope tile_scope(handle->tune_tile128_min);
     ZCSD_REQUIRE(n >= 1, "syev: n must be positive");
     ZCSD_REQUIRE(d_B && d_V && d_lambda, "syev: NULL pointer");
     ZCSD_REQUIRE(ldb >= n && ldv >= n, "syev: leading dimension < n");

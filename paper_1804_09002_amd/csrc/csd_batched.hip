@@ -460,6 +460,7 @@ extern "C" zcsd_status zcsd_dcsd_batched(zcsd_handle* handle, int batch, const i
                                          const zcsd_opts* opts, zcsd_info* info) {
   if (!handle) return ZCSD_EINVAL;
   return guarded([&] {
+    GemmTileScope tile_scope(handle->tune_tile128_min);
     ZCSD_REQUIRE(batch >= 1 && batch <= 65535, "csd_batched: 1 <= batch <= 65535");
     ZCSD_REQUIRE(n_host && off_host && rank_host, "csd_batched: NULL host array");
     ZCSD_REQUIRE(d_A1 && d_A2 && d_U1 && d_U2 && d_V1 && d_theta, "csd_batched: NULL pointer");
@@ -628,6 +629,7 @@ extern "C" zcsd_status zcsd_dcsd_batched(zcsd_handle* handle, int batch, const i
         ZCSD_HIP(hipSetDevice(dev));
         BatchWorker& bw = *handle->workers[w];
         set_thread_aux_stream(bw.aux);
+        GemmTileScope tile_scope(handle->tune_tile128_min);
         size_t need_w = 0;
         for (int gi : assign[w]) need_w = std::max(need_w, batched_group_bytes(groups[gi].N, groups[gi].mem.size()));
         bw.arena.reset();

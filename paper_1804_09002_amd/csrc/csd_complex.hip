@@ -577,6 +577,7 @@ extern "C" zcsd_status zcsd_zcsd(zcsd_handle* handle, int n, const double* d_A1,
                                  const zcsd_opts* opts, zcsd_info* info) {
   if (!handle) return ZCSD_EINVAL;
   return guarded([&] {
+    GemmTileScope tile_scope(handle->tune_tile128_min);
     ZCSD_REQUIRE(n >= 1 && n <= 32767, "zcsd: n must lie in [1, 32767]");
     ZCSD_REQUIRE(d_A1 && d_A2 && d_U1 && d_U2 && d_V1 && d_theta, "zcsd: NULL pointer");
     ZCSD_REQUIRE(lda1 >= n && lda2 >= n && ldu1 >= n && ldu2 >= n && ldv1 >= n,
@@ -596,6 +597,7 @@ extern "C" zcsd_status zcsd_zcsd_mn(zcsd_handle* handle, int m1, int m2, int n,
                                     zcsd_info* info) {
   if (!handle) return ZCSD_EINVAL;
   return guarded([&] {
+    GemmTileScope tile_scope(handle->tune_tile128_min);
     ZCSD_REQUIRE(n >= 1 && m1 >= n && m2 >= n && m1 <= 32767 && m2 <= 32767,
                  "zcsd_mn: need 1 <= n <= m1, m2 <= 32767");
     ZCSD_REQUIRE(d_A1 && d_A2 && d_U1 && d_U2 && d_V1 && d_theta, "zcsd_mn: NULL pointer");

@@ -32,6 +32,8 @@
 #include <cstdlib>
 #include <string>
 
+#include <hip/hip_ext.h>
+
 #include "zcsd_internal.h"
 #include "zcsd_prof.h"
 
@@ -44,6 +46,9 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 // count of FP32 product launches, per host thread
 namespace {
 thread_local int g_lowp_mode = 0;  // 0 FP64, 1 FP32 where it pays, 2 FP32 always
+// products with at least this many 128 x 128 output tiles (over the batch)
+// take the 128 x 128 tiling, the others the 64 x 64 one (GemmTileScope)
+thread_local int g_tile128_min = kGemmTile128MinDefault;
 thread_local long long g_lowp_launches = 0;
 }
 
@@ -393,9 +398,14 @@ static double computed_flops(const GemmBatch& g, bool split) {
 template <int BM, int BN, int BK, bool F32>
 static void launch_tile(const GemmBatch& g, hipStream_t s, int ksplit) {
   const double nprob_d = (double)g.batch * g.batch2;
+  // the events of the profiler are attached to the product's dispatches (the
+  // first chunk's start, the last chunk's end; a split-K reduction is not
+  // included): about 1500 launches a CSD, whose marker packets would
+  // lengthen the profiled run by several ms
   ProfScope prof(tile_name<BM, BN, BK, F32>(g.transA, g.transB), s,
                  prof_on() ? computed_flops<BM, BN, BK>(g, ksplit > 1) : 0.0,
-                 8.0 * nprob_d * ((double)g.m * g.k + (double)g.k * g.n + (g.beta != 0.0 ? 2.0 : 1.0) * g.m * g.n));
+                 8.0 * nprob_d * ((double)g.m * g.k + (double)g.k * g.n + (g.beta != 0.0 ? 2.0 : 1.0) * g.m * g.n),
+                 /*ext=*/true);
   const int gx = (g.m + BM - 1) / BM, gy = (g.n + BN - 1) / BN;
   if (g.batch > 65535) throw ArgError("dgemm: batch too large");
   int kchunk = 0;
@@ -429,8 +439,10 @@ static void launch_tile(const GemmBatch& g, hipStream_t s, int ksplit) {
     const double* A = g.A + (long long)c0 * g.sA2;
     const double* B = g.B + (long long)c0 * g.sB2;
     double* C = g.C + (long long)c0 * g.sC2;
+    hipEvent_t ev0 = (c0 == 0) ? prof.ext_start() : nullptr;
+    hipEvent_t ev1 = (c0 + per >= g.batch2) ? prof.ext_stop() : nullptr;
 #define ZCSD_GEMM_LAUNCH(TA_, TB_)                                                        \
-  hipLaunchKernelGGL((dgemm_kernel<BM, BN, BK, TA_, TB_, F32>), grid, block, 0, s, g.m, g.n, g.k, A, \
+  hipExtLaunchKernelGGL((dgemm_kernel<BM, BN, BK, TA_, TB_, F32>), grid, block, 0, s, ev0, ev1, 0, g.m, g.n, g.k, A, \
                      g.lda, g.sA, B, g.ldb, g.sB, C, g.ldc, g.sC, g.alpha, g.beta, g.batch,     \
                      g.sA2, g.sB2, g.sC2, nprob, kchunk, g.ws, (g.sym_upper || g.upper_only) ? 1 : 0, g.tri, \
                      g.kseg, order)
@@ -474,7 +486,7 @@ void dgemm(const GemmBatch& g, hipStream_t s) {
   const int lm = g_lowp_mode;
   const bool f32 = lm == 2 || (lm == 1 && !g.tri && !g.transB);
   if (f32) ++g_lowp_launches;
-  if (tiles128 >= 512) {
+  if (tiles128 >= g_tile128_min) {
     if (f32) launch_tile<128, 128, 32, true>(g, s, 1);
     else launch_tile<128, 128, 16, false>(g, s, 1);
     return;
@@ -511,5 +523,9 @@ GemmFp64Scope::~GemmFp64Scope() {
   if (on_) g_lowp_mode = saved_;
 }
 bool gemm_lowp_active() { return g_lowp_mode > 0; }
+GemmTileScope::GemmTileScope(int min_tiles) : saved_(g_tile128_min) {
+  if (min_tiles > 0) g_tile128_min = min_tiles;
+}
+GemmTileScope::~GemmTileScope() { g_tile128_min = saved_; }
 
 }  // namespace zcsd

@@ -1,10 +1,11 @@
 // Per-kernel timing with HIP events on the launching stream.
 //
 // When enabled (zcsd_profile_begin), instrumented launch sites bracket each
-// launch with a pair of events recorded on the stream the kernel runs on and
-// add its algorithmic flop and byte counts to a per-kernel record; queries
-// synchronise on the events and sum hipEventElapsedTime.  Disabled, a launch
-// site costs one branch.
+// launch with a pair of events recorded on the stream the kernel runs on (the
+// matrix products attach them to the dispatch itself through
+// hipExtLaunchKernelGGL) and add its algorithmic flop and byte counts to a
+// per-kernel record; queries synchronise on the events and sum
+// hipEventElapsedTime.  Disabled, a launch site costs one branch.
 #include <map>
 #include <mutex>
 #include <string>
@@ -59,21 +60,22 @@ void settle(Rec& r) {
 
 bool prof_on() { return st().on; }
 
-ProfScope::ProfScope(const char* name, hipStream_t s, double flops, double bytes)
+ProfScope::ProfScope(const char* name, hipStream_t s, double flops, double bytes, bool ext)
     : name_(name), s_(s), flops_(flops), bytes_(bytes) {
   if (!st().on) return;
   if (!st().filter.empty() && st().filter != name_) return;
   active_ = true;
+  ext_ = ext;
   std::lock_guard<std::mutex> g(st().mu);
   e0_ = get_event();
   e1_ = get_event();
-  ZCSD_HIP(hipEventRecord(static_cast<hipEvent_t>(e0_), s_));
+  if (!ext_) ZCSD_HIP(hipEventRecord(static_cast<hipEvent_t>(e0_), s_));
 }
 
 ProfScope::~ProfScope() {
   if (!active_) return;
   std::lock_guard<std::mutex> g(st().mu);
-  (void)hipEventRecord(static_cast<hipEvent_t>(e1_), s_);
+  if (!ext_) (void)hipEventRecord(static_cast<hipEvent_t>(e1_), s_);
   Rec& r = st().recs[name_];
   r.launches += 1;
   r.flops += flops_;

@@ -72,6 +72,9 @@ struct ArenaScope {
 }  // namespace zcsd
 
 namespace zcsd {
+// default of the GEMM tiling threshold (GemmTileScope): two 128 x 128 tiles
+// per compute unit
+constexpr int kGemmTile128MinDefault = 512;
 // One worker of the batched path: its own stream (default priority), its own
 // second stream for overlapped side work, and its own workspace arena.
 struct BatchWorker {
@@ -99,6 +102,8 @@ struct zcsd_handle_s {
   // full-rank problems with n up to this run as whole CSDs of one workgroup
   // each, in persistent launches (0: none)
   int tune_small_max = 32;
+  // products with at least this many 128 x 128 output tiles use that tiling
+  int tune_tile128_min = zcsd::kGemmTile128MinDefault;
 };
 
 namespace zcsd {
@@ -164,6 +169,20 @@ class GemmFp64Scope {
   int saved_;
 };
 bool gemm_lowp_active();
+// While a GemmTileScope(t) is alive on this host thread, products with at
+// least t output tiles of 128 x 128 (over the batch) use that tiling and the
+// others 64 x 64 tiles (default kGemmTile128MinDefault; a handle's
+// ZCSD_TUNE_GEMM_TILE128_MIN, set for each call of the library)
+class GemmTileScope {
+ public:
+  explicit GemmTileScope(int min_tiles);
+  ~GemmTileScope();
+  GemmTileScope(const GemmTileScope&) = delete;
+  GemmTileScope& operator=(const GemmTileScope&) = delete;
+
+ private:
+  int saved_;
+};
 // products launched on the FP32 matrix cores by this host thread so far
 long long gemm_lowp_launches();
 

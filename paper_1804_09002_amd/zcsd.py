@@ -156,10 +156,11 @@ def handle(device=None):
 
 
 (TUNE_BATCHED_WORKERS, TUNE_CLASS_STEP_SMALL, TUNE_CLASS_STEP_MID, TUNE_CLASS_STEP_LARGE,
- TUNE_ONE_WORKGROUP_MAX_N) = range(5)
+ TUNE_ONE_WORKGROUP_MAX_N, TUNE_GEMM_TILE128_MIN) = range(6)
 TUNE_KEYS = {"batched_workers": TUNE_BATCHED_WORKERS, "class_step_small": TUNE_CLASS_STEP_SMALL,
              "class_step_mid": TUNE_CLASS_STEP_MID, "class_step_large": TUNE_CLASS_STEP_LARGE,
-             "one_workgroup_max_n": TUNE_ONE_WORKGROUP_MAX_N}
+             "one_workgroup_max_n": TUNE_ONE_WORKGROUP_MAX_N,
+             "gemm_tile128_min": TUNE_GEMM_TILE128_MIN}
 
 
 def set_tuning(device=None, **values):

@@ -82,7 +82,11 @@ zcsd_status zcsd_set_tuning(zcsd_handle* handle, int key, int value) {
       handle->tune_step[key - ZCSD_TUNE_CLASS_STEP_SMALL] = value;
       return ZCSD_OK;
     case ZCSD_TUNE_ONE_WORKGROUP_MAX_N:
-      if (value < 0 || value > zcsd::small_csd_max_n()) return ZCSD_EINVAL;
+      {
+        int mx[8];
+        zcsd::small_csd_tiers(mx, nullptr);
+        if (value < 0 || value > mx[0]) return ZCSD_EINVAL;
+      }
       handle->tune_small_max = value;
       return ZCSD_OK;
     case ZCSD_TUNE_GEMM_TILE128_MIN:

@@ -496,24 +496,30 @@ extern "C" zcsd_status zcsd_dcsd_batched(zcsd_handle* handle, int batch, const i
     // small full-rank problems: whole CSDs of one workgroup each, one
     // persistent launch beside the class groups (candidates by size here, by
     // rank below); not when the options fix l or r, or split blocks <= 64
+    int tier_max[8], tier_per_cu[8];
+    const int n_tiers = small_csd_tiers(tier_max, tier_per_cu);
     const int small_lim = (o.r_override == 0 && o.ell_override <= 0.0)
-                              ? std::min(std::min(handle->tune_small_max, small_csd_max_n()), o.n_leaf)
+                              ? std::min(std::min(handle->tune_small_max, tier_max[0]), o.n_leaf)
                               : 0;
-    const int split = small_csd_split_n();
-    int n_cand_large = 0, n_cand_small = 0;
-    for (int k = 0; k < batch; ++k) {
-      n_cand_large += (n_host[k] <= small_lim && n_host[k] > split) ? 1 : 0;
-      n_cand_small += (n_host[k] <= small_lim && n_host[k] <= split) ? 1 : 0;
-    }
+    // the tier of a size: the last (smallest) tier that holds it
+    auto tier_of = [&](int n) {
+      int t = 0;
+      while (t + 1 < n_tiers && n <= tier_max[t + 1]) ++t;
+      return t;
+    };
+    int n_cand = 0, tier_cand[8] = {0};
+    for (int k = 0; k < batch; ++k)
+      if (n_host[k] <= small_lim) {
+        ++n_cand;
+        ++tier_cand[tier_of(n_host[k])];
+      }
     int n_cu = 1;
     ZCSD_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, handle->device));
-    // one workgroup per compute unit above the split, four at or below it
-    const int grid_large_max = std::min(n_cand_large, n_cu);
-    const int grid_small_max = std::min(n_cand_small, 4 * n_cu);
-    const size_t small_bytes = (n_cand_large + n_cand_small)
-                                   ? small_csd_scratch_bytes(grid_large_max, grid_small_max) +
-                                         (size_t)batch * 64 + ((size_t)1 << 20)
-                                   : 0;
+    // grids: as many workgroups as fit on the device at once (per tier)
+    int grid_max[8];
+    for (int t = 0; t < n_tiers; ++t) grid_max[t] = std::min(tier_cand[t], tier_per_cu[t] * n_cu);
+    const size_t small_bytes =
+        n_cand ? small_csd_scratch_bytes(grid_max) + (size_t)batch * 64 + ((size_t)1 << 20) : 0;
     ar.reserve(((size_t)64 << 20) + (size_t)batch * 64 + small_bytes);
     // ranks (Remark (vi)) for every problem
     std::vector<double> ss((size_t)2 * batch);
@@ -604,10 +610,9 @@ extern "C" zcsd_status zcsd_dcsd_batched(zcsd_handle* handle, int batch, const i
     ZCSD_HIP(hipEventRecord(ready, s));
     int* d_small_status = nullptr;
     if (!small.empty()) {
-      int count_large = 0;
-      for (int k : small) count_large += (n_host[k] > split) ? 1 : 0;
-      const int grid_large = std::min(count_large, grid_large_max);
-      const int grid_small = std::min((int)small.size() - count_large, grid_small_max);
+      int tier_count[8] = {0}, grid[8] = {0};
+      for (int k : small) ++tier_count[tier_of(n_host[k])];
+      for (int t = 0; t < n_tiers; ++t) grid[t] = std::min(tier_count[t], grid_max[t]);
       std::vector<int> nv(n_host, n_host + batch);
       std::vector<long long> ov(off_host, off_host + batch), tv(toff.begin(), toff.begin() + batch);
       int* d_list = upload_vec(ar, small, s);
@@ -615,10 +620,9 @@ extern "C" zcsd_status zcsd_dcsd_batched(zcsd_handle* handle, int batch, const i
       long long* d_ov = upload_vec(ar, ov, s);
       long long* d_tv = upload_vec(ar, tv, s);
       d_small_status = ar.ialloc(small.size());
-      double* scratch = ar.dalloc(small_csd_scratch_bytes(grid_large, grid_small) / sizeof(double));
-      small_csd_launch((int)small.size(), count_large, d_list, d_nv, d_ov, d_tv, d_A1, d_A2, d_U1, d_U2,
-                       d_V1, d_theta, o.eps, o.tol, o.postprocess == 2, grid_large, grid_small, scratch,
-                       d_small_status, ar, s);
+      double* scratch = ar.dalloc(small_csd_scratch_bytes(grid) / sizeof(double));
+      small_csd_launch(tier_count, d_list, d_nv, d_ov, d_tv, d_A1, d_A2, d_U1, d_U2, d_V1, d_theta, o.eps,
+                       o.tol, o.postprocess == 2, grid, scratch, d_small_status, ar, s);
     }
     const int dev = handle->device;
     std::vector<BatchedStats> wst(W);

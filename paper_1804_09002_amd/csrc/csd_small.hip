@@ -39,13 +39,14 @@ namespace zcsd {
 
 namespace {
 
-// Two instances of everything below (SN: largest size, ST: threads of a
-// workgroup): problems of 33..64 with 256 threads (138 KB of LDS: one
-// workgroup per compute unit), problems of at most 32 with 128 threads
-// (36 KB: four workgroups per compute unit, whose waves hide each other's
-// latency).
-constexpr int kSmallMax = 64;
-constexpr int kSmallSplit = 32;
+// Three instances of everything below (SN: largest size, ST: threads of a
+// workgroup), tiers of problem sizes: 49..64 with 256 threads (138 KB of
+// LDS: one workgroup per compute unit), 33..48 with 192 threads (79 KB: two
+// per compute unit) and at most 32 with 128 threads (36 KB: four per compute
+// unit, whose waves hide each other's latency).
+constexpr int kTiers = 3;
+constexpr int kTierMax[kTiers] = {64, 48, 32};
+constexpr int kTierPerCu[kTiers] = {1, 2, 4};
 
 // One tabulated lower bound and the coefficients of both Zolo-pd steps
 // (c_{2j-1} and a_j of the partial fractions, M); all doubles.
@@ -630,37 +631,53 @@ const std::vector<SmallCoef>& small_table(double eps, double tol) {
 
 }  // namespace
 
-int small_csd_max_n() { return kSmallMax; }
-
-int small_csd_split_n() { return kSmallSplit; }
-
-size_t small_csd_scratch_bytes(int grid_large, int grid_small) {
-  return ((size_t)grid_large * kSmallMax * kSmallMax + (size_t)grid_small * kSmallSplit * kSmallSplit) * 6 *
-         sizeof(double);
+int small_csd_tiers(int* max_n, int* per_cu) {
+  for (int t = 0; t < kTiers; ++t) {
+    if (max_n) max_n[t] = kTierMax[t];
+    if (per_cu) per_cu[t] = kTierPerCu[t];
+  }
+  return kTiers;
 }
 
-void small_csd_launch(int count, int count_large, const int* d_list, const int* d_n,
-                      const long long* d_off, const long long* d_toff, const double* A1,
-                      const double* A2, double* U1, double* U2, double* V1, double* theta, double eps,
-                      double tol, bool theta_from_lambda, int grid_large, int grid_small,
-                      double* scratch, int* d_status, Arena& ar, hipStream_t s) {
+size_t small_csd_scratch_bytes(const int* grid) {
+  size_t e = 0;
+  for (int t = 0; t < kTiers; ++t) e += (size_t)grid[t] * kTierMax[t] * kTierMax[t] * 6;
+  return e * sizeof(double);
+}
+
+void small_csd_launch(const int* tier_count, const int* d_list, const int* d_n, const long long* d_off,
+                      const long long* d_toff, const double* A1, const double* A2, double* U1,
+                      double* U2, double* V1, double* theta, double eps, double tol,
+                      bool theta_from_lambda, const int* grid, double* scratch, int* d_status, Arena& ar,
+                      hipStream_t s) {
+  int count = 0;
+  for (int t = 0; t < kTiers; ++t) count += tier_count[t];
   if (count <= 0) return;
   const std::vector<SmallCoef>& tab = small_table(eps, tol);
   SmallCoef* d_tab = static_cast<SmallCoef*>(ar.alloc(tab.size() * sizeof(SmallCoef)));
   h2d(d_tab, tab.data(), tab.size() * sizeof(SmallCoef), s);
   const int lam = theta_from_lambda ? 1 : 0;
-  if (count_large > 0) {
-    hipLaunchKernelGGL((csd_small_kernel<kSmallMax, 256, 1>), dim3(grid_large), dim3(256), 0, s, count_large,
-                       d_list, d_n, d_off, d_toff, A1, A2, U1, U2, V1, theta, d_tab, (int)tab.size(), eps,
-                       lam, scratch, d_status);
-    ZCSD_CHECK_LAUNCH();
-  }
-  if (count > count_large) {
-    double* scr = scratch + (size_t)grid_large * kSmallMax * kSmallMax * 6;
-    hipLaunchKernelGGL((csd_small_kernel<kSmallSplit, 128, 2>), dim3(grid_small), dim3(128), 0, s,
-                       count - count_large, d_list + count_large, d_n, d_off, d_toff, A1, A2, U1, U2, V1,
-                       theta, d_tab, (int)tab.size(), eps, lam, scr, d_status + count_large);
-    ZCSD_CHECK_LAUNCH();
+  const int nt = (int)tab.size();
+  int first = 0;
+  double* scr = scratch;
+  for (int t = 0; t < kTiers; ++t) {
+    const int c = tier_count[t];
+    if (c > 0) {
+      const int* li = d_list + first;
+      int* stt = d_status + first;
+      if (t == 0)
+        hipLaunchKernelGGL((csd_small_kernel<64, 256, 1>), dim3(grid[t]), dim3(256), 0, s, c, li, d_n, d_off,
+                           d_toff, A1, A2, U1, U2, V1, theta, d_tab, nt, eps, lam, scr, stt);
+      else if (t == 1)
+        hipLaunchKernelGGL((csd_small_kernel<48, 192, 2>), dim3(grid[t]), dim3(192), 0, s, c, li, d_n, d_off,
+                           d_toff, A1, A2, U1, U2, V1, theta, d_tab, nt, eps, lam, scr, stt);
+      else
+        hipLaunchKernelGGL((csd_small_kernel<32, 128, 2>), dim3(grid[t]), dim3(128), 0, s, c, li, d_n, d_off,
+                           d_toff, A1, A2, U1, U2, V1, theta, d_tab, nt, eps, lam, scr, stt);
+      ZCSD_CHECK_LAUNCH();
+    }
+    first += c;
+    scr += (size_t)grid[t] * kTierMax[t] * kTierMax[t] * 6;
   }
 }
 

@@ -115,6 +115,10 @@ __device__ inline void jacobi_block(int n, const double* A, long long lda, doubl
   const int RB = (n <= 16) ? 16 : ((n <= 32) ? 32 : 64);
   const int CS = JNT / RB;
   const int ri = tid & (RB - 1), rj0 = tid / RB;
+  // iterations that cover JB columns and JB / 2 pairs at the smallest stride
+  constexpr int RBMAX = (JB <= 16) ? 16 : ((JB <= 32) ? 32 : 64);
+  constexpr int CSMIN = JNT / RBMAX;
+  constexpr int NQC = (JB + CSMIN - 1) / CSMIN, NQP = (JB / 2 + CSMIN - 1) / CSMIN;
   for (int sweep = 0; sweep < 40; ++sweep) {
     if (tid == 0) rotated = 0;
     __syncthreads();
@@ -166,7 +170,7 @@ __device__ inline void jacobi_block(int n, const double* A, long long lda, doubl
         const int pi = pt[ri];
         const double ai = al[ri], bi = be[ri];
 #pragma unroll
-        for (int qq = 0; qq < JB / 4; ++qq) {
+        for (int qq = 0; qq < NQC; ++qq) {
           const int j = rj0 + CS * qq;
           if (j < n) {
             const int pj = pt[j];
@@ -177,7 +181,7 @@ __device__ inline void jacobi_block(int n, const double* A, long long lda, doubl
           }
         }
 #pragma unroll
-        for (int qq = 0; qq < JB / 8; ++qq) {
+        for (int qq = 0; qq < NQP; ++qq) {
           const int k = rj0 + CS * qq;
           if (k < m / 2) {
             const int p = pq[k][0], q = pq[k][1];

@@ -101,7 +101,7 @@ struct zcsd_handle_s {
   int tune_step[3] = {8, 16, 64};
   // full-rank problems with n up to this run as whole CSDs of one workgroup
   // each, in persistent launches (0: none)
-  int tune_small_max = 32;
+  int tune_small_max = 48;
   // products with at least this many 128 x 128 output tiles use that tiling
   int tune_tile128_min = zcsd::kGemmTile128MinDefault;
 };
@@ -260,22 +260,22 @@ size_t csd_workspace_bytes(int n);
 // the batched path's first W worker streams of a handle (csd_batched.hip)
 void ensure_batch_workers(zcsd_handle_s* h, int W);
 // whole CSDs of small full-rank problems, one workgroup each, in persistent
-// launches (csd_small.hip): the largest n they take; the size up to which the
-// smaller instance runs (four workgroups per compute unit; above it, up to
-// the largest, one); their global scratch for grids of grid_large and
-// grid_small workgroups; and the launches, for a list whose first
-// count_large entries are the problems above the split.  status[t] of list
-// entry t: low byte 0 = written, 1 = the l estimate reached eps, 2 = a
-// Cholesky factorization broke down (1 and 2: nothing written); bits 8.. the
-// Zolotarev degree used
-int small_csd_max_n();
-int small_csd_split_n();
-size_t small_csd_scratch_bytes(int grid_large, int grid_small);
-void small_csd_launch(int count, int count_large, const int* d_list, const int* d_n,
-                      const long long* d_off, const long long* d_toff, const double* A1,
-                      const double* A2, double* U1, double* U2, double* V1, double* theta, double eps,
-                      double tol, bool theta_from_lambda, int grid_large, int grid_small,
-                      double* scratch, int* d_status, Arena& ar, hipStream_t s);
+// launches (csd_small.hip), one per tier of sizes: small_csd_tiers gives the
+// tiers' largest sizes (descending, the first is the largest size taken) and
+// workgroups per compute unit, and returns their number (3);
+// small_csd_scratch_bytes the global scratch for grids of grid[t] workgroups;
+// small_csd_launch runs a list sorted by descending size whose first
+// tier_count[0] entries belong to tier 0, the next tier_count[1] to tier 1 and
+// so on.  status[t] of list entry t: low byte 0 = written, 1 = the l estimate
+// reached eps, 2 = a Cholesky factorization broke down (1 and 2: nothing
+// written); bits 8.. the Zolotarev degree used
+int small_csd_tiers(int* max_n, int* per_cu);
+size_t small_csd_scratch_bytes(const int* grid);
+void small_csd_launch(const int* tier_count, const int* d_list, const int* d_n, const long long* d_off,
+                      const long long* d_toff, const double* A1, const double* A2, double* U1,
+                      double* U2, double* V1, double* theta, double eps, double tol,
+                      bool theta_from_lambda, const int* grid, double* scratch, int* d_status, Arena& ar,
+                      hipStream_t s);
 // Householder QR of the m x n block A (m >= n, ld lda): Q (m x n, ld m) and
 // the triangular R (n x n, ld n, zeros below the diagonal) (csd.hip)
 void tall_qr(int m, int n, const double* A, long long lda, double* Q, double* R, Arena& ar,

@@ -1,10 +1,11 @@
 """The one-workgroup CSDs of the batched path (small full-rank problems,
 persistent launches) against the oracle and against the size-class path.
 
-Every full-rank problem with n up to the one-workgroup limit (default 32, at
+Every full-rank problem with n up to the one-workgroup limit (default 48, at
 most 64; include/zcsd.h, ZCSD_TUNE_ONE_WORKGROUP_MAX_N) runs as a whole CSD
-inside one workgroup: n <= 32 in a launch of four workgroups per compute
-unit, 32 < n <= 64 in a launch of one per compute unit.  Per problem: the
+inside one workgroup, in persistent launches by tier of size: n <= 32 with
+four workgroups per compute unit, 32 < n <= 48 with two, 48 < n <= 64 with
+one.  Per problem: the
 oracle's angles (Algorithm 1 through SVD polars and LAPACK's eigh) and the
 known angles of the construction to 10 max(n, 8) u, self-certifying 2-norm
 backward error and orthogonality to 1e-13, angles ascending; and, with the
@@ -56,8 +57,8 @@ def _run(zcsd, A1s, A2s, limit, **opts):
 
 def test_one_workgroup_matches_oracle_and_class_path(one_wg_limit):
     zcsd = one_wg_limit
-    assert zcsd.get_tuning()["one_workgroup_max_n"] == 32
-    sizes = [1, 2, 3, 4, 5, 7, 8, 13, 16, 17, 31, 32, 33, 47, 63, 64]
+    assert zcsd.get_tuning()["one_workgroup_max_n"] == 48
+    sizes = [1, 2, 3, 4, 5, 7, 8, 13, 16, 17, 31, 32, 33, 47, 48, 49, 63, 64]
     A1s, A2s, truth = [], [], []
     for k, n in enumerate(sizes):
         A1, A2, meta = WL.uniform_pair(n, 900 + k)
@@ -81,8 +82,8 @@ def test_one_workgroup_matches_oracle_and_class_path(one_wg_limit):
 
 
 def test_one_workgroup_persistent_over_many_problems(one_wg_limit):
-    """2400 problems with n in [1, 64]: more than one per workgroup of both
-    persistent grids (four workgroups per compute unit for n <= 32, one above),
+    """2400 problems with n in [1, 64]: more than one per workgroup of every
+    persistent grid (four, two and one workgroups per compute unit by tier),
     every one with its known angles and the FP64 targets (Frobenius norms),
     sampled ones against the oracle."""
     zcsd = one_wg_limit

@@ -134,8 +134,8 @@ const char* zcsd_status_string(zcsd_status s);
  * workload.  Full-rank problems with n <= ZCSD_TUNE_ONE_WORKGROUP_MAX_N
  * (default 48, at most 64, 0 = none) skip the classes: each runs as a whole
  * CSD inside one workgroup, all of them in persistent launches by tier of
- * size (n <= 32: four workgroups per compute unit; 32 < n <= 48: two;
- * 48 < n <= 64: one) that run beside the class groups (the same Algorithm 1 with
+ * size (n <= 16: eight workgroups per compute unit; n <= 32: four; n <= 48:
+ * two; n <= 64: one) that run beside the class groups (the same Algorithm 1 with
  * Zolo-pd; Zolo-eig of a block of at most 64 is its Jacobi leaf solve),
  * unless r_override, ell_override or n_leaf < n asks for the class path.
  * ZCSD_TUNE_GEMM_TILE128_MIN applies to every call of the handle: a matrix

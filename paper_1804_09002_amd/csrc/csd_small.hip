@@ -39,14 +39,15 @@ namespace zcsd {
 
 namespace {
 
-// Three instances of everything below (SN: largest size, ST: threads of a
+// Four instances of everything below (SN: largest size, ST: threads of a
 // workgroup), tiers of problem sizes: 49..64 with 256 threads (138 KB of
 // LDS: one workgroup per compute unit), 33..48 with 192 threads (79 KB: two
-// per compute unit) and at most 32 with 128 threads (36 KB: four per compute
-// unit, whose waves hide each other's latency).
-constexpr int kTiers = 3;
-constexpr int kTierMax[kTiers] = {64, 48, 32};
-constexpr int kTierPerCu[kTiers] = {1, 2, 4};
+// per compute unit), 17..32 with 128 threads (36 KB: four) and at most 16
+// with one wave of 64 threads (10 KB: eight); several workgroups per compute
+// unit hide each other's latency.
+constexpr int kTiers = 4;
+constexpr int kTierMax[kTiers] = {64, 48, 32, 16};
+constexpr int kTierPerCu[kTiers] = {1, 2, 4, 8};
 
 // One tabulated lower bound and the coefficients of both Zolo-pd steps
 // (c_{2j-1} and a_j of the partial fractions, M); all doubles.
@@ -671,8 +672,11 @@ void small_csd_launch(const int* tier_count, const int* d_list, const int* d_n, 
       else if (t == 1)
         hipLaunchKernelGGL((csd_small_kernel<48, 192, 2>), dim3(grid[t]), dim3(192), 0, s, c, li, d_n, d_off,
                            d_toff, A1, A2, U1, U2, V1, theta, d_tab, nt, eps, lam, scr, stt);
-      else
+      else if (t == 2)
         hipLaunchKernelGGL((csd_small_kernel<32, 128, 2>), dim3(grid[t]), dim3(128), 0, s, c, li, d_n, d_off,
+                           d_toff, A1, A2, U1, U2, V1, theta, d_tab, nt, eps, lam, scr, stt);
+      else
+        hipLaunchKernelGGL((csd_small_kernel<16, 64, 2>), dim3(grid[t]), dim3(64), 0, s, c, li, d_n, d_off,
                            d_toff, A1, A2, U1, U2, V1, theta, d_tab, nt, eps, lam, scr, stt);
       ZCSD_CHECK_LAUNCH();
     }

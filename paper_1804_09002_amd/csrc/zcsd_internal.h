@@ -262,7 +262,7 @@ void ensure_batch_workers(zcsd_handle_s* h, int W);
 // whole CSDs of small full-rank problems, one workgroup each, in persistent
 // launches (csd_small.hip), one per tier of sizes: small_csd_tiers gives the
 // tiers' largest sizes (descending, the first is the largest size taken) and
-// workgroups per compute unit, and returns their number (3);
+// workgroups per compute unit, and returns their number (4);
 // small_csd_scratch_bytes the global scratch for grids of grid[t] workgroups;
 // small_csd_launch runs a list sorted by descending size whose first
 // tier_count[0] entries belong to tier 0, the next tier_count[1] to tier 1 and

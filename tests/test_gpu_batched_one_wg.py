@@ -3,9 +3,9 @@ persistent launches) against the oracle and against the size-class path.
 
 Every full-rank problem with n up to the one-workgroup limit (default 48, at
 most 64; include/zcsd.h, ZCSD_TUNE_ONE_WORKGROUP_MAX_N) runs as a whole CSD
-inside one workgroup, in persistent launches by tier of size: n <= 32 with
-four workgroups per compute unit, 32 < n <= 48 with two, 48 < n <= 64 with
-one.  Per problem: the
+inside one workgroup, in persistent launches by tier of size: n <= 16 with
+eight workgroups per compute unit, n <= 32 with four, n <= 48 with two,
+n <= 64 with one.  Per problem: the
 oracle's angles (Algorithm 1 through SVD polars and LAPACK's eigh) and the
 known angles of the construction to 10 max(n, 8) u, self-certifying 2-norm
 backward error and orthogonality to 1e-13, angles ascending; and, with the
@@ -82,8 +82,8 @@ def test_one_workgroup_matches_oracle_and_class_path(one_wg_limit):
 
 
 def test_one_workgroup_persistent_over_many_problems(one_wg_limit):
-    """2400 problems with n in [1, 64]: more than one per workgroup of every
-    persistent grid (four, two and one workgroups per compute unit by tier),
+    """2400 problems with n in [1, 64]: more than one per workgroup of the
+    grids of the tiers above 16 (four, two and one workgroups per compute unit),
     every one with its known angles and the FP64 targets (Frobenius norms),
     sampled ones against the oracle."""
     zcsd = one_wg_limit
@@ -112,6 +112,31 @@ def test_one_workgroup_persistent_over_many_problems(one_wg_limit):
     for k in (0, 1200, 2399):
         o = O.csd(A1s[k], A2s[k])
         assert np.max(np.abs(out[k][3].cpu().numpy() - o["theta"])) <= 10 * max(sizes[k], 8) * U
+
+
+def test_one_workgroup_tiny_problems_more_than_the_grid(one_wg_limit):
+    """2500 problems with n in [1, 16]: more than the n <= 16 tier's grid
+    (eight workgroups per compute unit), so workgroups take several problems;
+    every one with its known angles and the FP64 targets."""
+    zcsd = one_wg_limit
+    rng = np.random.default_rng(79)
+    sizes = [int(x) for x in rng.integers(1, 17, size=2500)]
+    A1s, A2s, truth = [], [], []
+    for n in sizes:
+        A1, A2, meta = WL.uniform_pair(n, int(rng.integers(1 << 31)))
+        A1s.append(A1); A2s.append(A2); truth.append(np.sort(meta["theta"]))
+    out = zcsd.csd_batched([_t(a) for a in A1s], [_t(a) for a in A2s])
+    for k, (U1, U2, V1, th, r) in enumerate(out):
+        n = sizes[k]
+        assert r == n
+        assert np.max(np.abs(th.cpu().numpy() - truth[k])) <= 10 * max(n, 8) * U, k
+        c, s = torch.cos(th), torch.sin(th)
+        A1, A2 = _t(A1s[k]), _t(A2s[k])
+        R = torch.cat([(U1 * c) @ V1.T - A1, (U2 * s) @ V1.T - A2])
+        assert float(torch.linalg.norm(R)) / float(torch.linalg.norm(torch.cat([A1, A2]))) <= 1e-13, k
+        I = torch.eye(n, dtype=torch.float64, device=DEV)
+        for X in (U1, U2, V1):
+            assert float(torch.linalg.norm(X.T @ X - I)) <= 1e-13, k
 
 
 def test_one_workgroup_hands_eps_members_to_algorithm2(one_wg_limit):

@@ -1,5 +1,6 @@
-// Whole CSDs of small full-rank problems, one workgroup per problem, in one
-// persistent launch over the batch (Algorithm 1 with Zolo-pd, Sec. 5).
+// Whole CSDs of small full-rank problems, one workgroup per problem, in
+// persistent launches over the batch, one per tier of sizes (Algorithm 1
+// with Zolo-pd, Sec. 5).
 //
 // For n <= 64 every matrix of the method fits in LDS, so a problem needs no
 // launch sequence and no host decision: one workgroup runs

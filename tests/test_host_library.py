@@ -71,3 +71,27 @@ def test_workspace_size_host_query(lib):
         zcsd.workspace_size(0)
     with pytest.raises(zcsd.ZcsdError):
         zcsd.workspace_size(64, postprocess=7)
+
+
+def test_tuning_keys_of_the_binding_match_the_header(lib):
+    """The Python binding's tuning keys carry the values of include/zcsd.h's
+    zcsd_tune_key, and the tuning calls reject a NULL handle without touching
+    a device."""
+    src = open(os.path.join(ROOT, "include", "zcsd.h")).read()
+    body = re.search(r"typedef enum \{(.*?)\} zcsd_tune_key;", src, flags=re.S).group(1)
+    header = {name: int(v) for name, v in re.findall(r"(ZCSD_TUNE_[A-Z0-9_]+)\s*=\s*(\d+)", body)}
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("zcsd_binding", os.path.join(ROOT, "paper_1804_09002_amd", "zcsd.py"))
+    try:
+        mod = importlib.util.module_from_spec(spec)
+        spec.loader.exec_module(mod)
+    except Exception as e:  # the binding imports torch; it is importable here
+        pytest.fail(f"binding import failed: {e}")
+    assert set(mod.TUNE_KEYS.values()) == set(header.values())
+    for key, value in mod.TUNE_KEYS.items():
+        assert header["ZCSD_TUNE_" + key.upper()] == value, key
+    lib.zcsd_set_tuning.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]
+    lib.zcsd_get_tuning.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+    v = ctypes.c_int(0)
+    assert lib.zcsd_set_tuning(None, 0, 4) != 0
+    assert lib.zcsd_get_tuning(None, 0, ctypes.byref(v)) != 0

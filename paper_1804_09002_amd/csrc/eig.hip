@@ -19,7 +19,10 @@
 // A split with n+ in {0, n_b} only moves the interval (bisection on s).
 // Before each split the interval is tightened to mean_b -+ ||B_b - mean_b I||_F,
 // which holds every eigenvalue of the block.
-// Blocks of at most n_leaf go to batched Jacobi; blocks whose spread
+// Blocks of at most n_leaf go to batched Jacobi, all of them in one launch
+// after the last level (a leaf is independent of the rest, and the Jacobi
+// launch is latency-bound: one launch of a few hundred leaves costs about as
+// much as one of a few); blocks whose spread
 // ||B_b - mean I||_F is below 4 u max(|lo|, |hi|) are already diagonal to
 // working accuracy and are finished as they are.  Eigenpairs are finally sorted.
 #include <algorithm>
@@ -317,7 +320,111 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
   }
   unsigned long long seed = 0x5DEECE66DULL;
 
-  // blocks parked for the end: leaves
+  // blocks parked for the end: leaves (their matrix block, ld ldB, and their
+  // n x nb basis, ld n, in the buffers of the level that produced them)
+  struct Parked {
+    const double* B;
+    int ldB;
+    const double* V;
+    int nb, prob;
+  };
+  std::vector<Parked> parked;
+  std::vector<long long> parked_cols(nprob, 0);
+  // leaves: Jacobi on 64 x 64 padded copies, then V_b Q_leaf into the output
+  auto solve_leaves = [&]() {
+    if (parked.empty()) return;
+    {
+      const int nl = (int)parked.size();
+      const int L = 64;
+      double* Lb = ar.dalloc((size_t)nl * L * L);
+      double* Lv = ar.dalloc((size_t)nl * L * L);
+      double* Ll = ar.dalloc((size_t)nl * L);
+      double* LV = ar.dalloc((size_t)nl * n * L);
+      set_identity(nl, L, L, 0.0, Lv, L, (long long)L * L, s);
+      set_identity(nl, n, L, 0.0, LV, n, (long long)n * L, s);
+      // the parked blocks come from several levels' buffers: offsets from the
+      // lowest address (one flat device address space), two copy launches
+      const double* bbase = parked[0].B;
+      const double* vbase = parked[0].V;
+      for (const Parked& pk : parked) {
+        bbase = std::min(bbase, pk.B);
+        vbase = std::min(vbase, pk.V);
+      }
+      std::vector<CopyDesc> cb, cv;
+      std::vector<int> szs;
+      for (int q = 0; q < nl; ++q) {
+        const Parked& pk = parked[q];
+        cb.push_back({(long long)(pk.B - bbase), (long long)q * L * L, pk.ldB, L, pk.nb, pk.nb});
+        cv.push_back({(long long)(pk.V - vbase), (long long)q * n * L, n, n, n, pk.nb});
+        szs.push_back(pk.nb);
+      }
+      copy_blocks(bbase, Lb, cb, ar, s);
+      copy_blocks(vbase, LV, cv, ar, s);
+      int* d_sz = upload(ar, szs, s);
+      jacobi_batched(nl, d_sz, Lb, L, (long long)L * L, Lv, L, (long long)L * L, Ll, s);
+      double* LVo = ar.dalloc((size_t)nl * n * L);
+      GemmBatch g;
+      g.batch = nl;
+      g.m = n; g.n = L; g.k = L;
+      g.A = LV; g.lda = n; g.sA = (long long)n * L;
+      g.B = Lv; g.ldb = L; g.sB = (long long)L * L;
+      g.C = LVo; g.ldc = n; g.sC = (long long)n * L;
+      dgemm(g, s);
+      std::vector<double> ll((size_t)nl * L);
+      d2h(ll.data(), Ll, ll.size() * sizeof(double), s);
+      if (log_enabled() && nprob == 1) {
+        // leaf invariants: ||LVo^T B LVo - diag(lam)||_F per leaf, ||LVo^T LVo - I||_F
+        ArenaScope ds(ar);
+        double* BV = ar.dalloc((size_t)nl * n * L);
+        double* E = ar.dalloc((size_t)nl * L * L);
+        double* E2 = ar.dalloc((size_t)nl * L * L);
+        GemmBatch g1;
+        g1.batch = nl;
+        g1.m = n; g1.n = L; g1.k = n;
+        g1.A = a.B; g1.lda = a.ldb; g1.sA = 0;
+        g1.B = LVo; g1.ldb = n; g1.sB = (long long)n * L;
+        g1.C = BV; g1.ldc = n; g1.sC = (long long)n * L;
+        dgemm(g1, s);
+        GemmBatch g2;
+        g2.batch = nl;
+        g2.transA = 1;
+        g2.m = L; g2.n = L; g2.k = n;
+        g2.A = LVo; g2.lda = n; g2.sA = (long long)n * L;
+        g2.B = BV; g2.ldb = n; g2.sB = (long long)n * L;
+        g2.C = E; g2.ldc = L; g2.sC = (long long)L * L;
+        dgemm(g2, s);
+        g2.B = LVo;
+        g2.C = E2;
+        dgemm(g2, s);
+        std::vector<double> eh((size_t)nl * L * L), e2h((size_t)nl * L * L);
+        d2h(eh.data(), E, eh.size() * sizeof(double), s);
+        d2h(e2h.data(), E2, e2h.size() * sizeof(double), s);
+        for (int q = 0; q < nl; ++q) {
+          const int m = szs[q];
+          double r1 = 0.0, r2 = 0.0;
+          for (int j = 0; j < m; ++j)
+            for (int i = 0; i < m; ++i) {
+              const double v = eh[(size_t)q * L * L + i + j * L] - (i == j ? ll[(size_t)q * L + i] : 0.0);
+              const double w2 = e2h[(size_t)q * L * L + i + j * L] - (i == j ? 1.0 : 0.0);
+              r1 += v * v;
+              r2 += w2 * w2;
+            }
+          std::fprintf(stderr, "[zcsd] eig level %d leaf %d n=%d ||VtBV-L||=%.2e ||VtV-I||=%.2e\n",
+                       res.levels, q, m, std::sqrt(r1), std::sqrt(r2));
+        }
+      }
+      std::vector<CopyDesc> co;
+      for (int q = 0; q < nl; ++q) {
+        const Parked& pk = parked[q];
+        const int p = pk.prob;
+        co.push_back({(long long)q * n * L, p * nn + (long long)col_out[p] * n, n, n, n, pk.nb});
+        for (int i = 0; i < pk.nb; ++i) lam_out[p].push_back(ll[(size_t)q * L + i]);
+        col_out[p] += pk.nb;
+      }
+      copy_blocks(LVo, Vout, co, ar, s);
+    }
+    parked.clear();
+  };
   const bool lt = level_times_enabled();
   double lt_start = 0.0, lt_sign = 0.0;
   int lt_r = 0, lt_ns = 0, lt_N = 0, lt_blocks = 0;
@@ -406,7 +513,8 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
       for (int k : scalar_idx) add[all[k].prob] += all[k].n;
       for (int k : leaf_idx) add[all[k].prob] += all[k].n;
       for (int p = 0; p < nprob; ++p)
-        if (col_out[p] + add[p] > n) throw NumError(ZCSD_ENOCONV, "zolo_eig: block sizes exceed n");
+        if (col_out[p] + parked_cols[p] + add[p] > n)
+          throw NumError(ZCSD_ENOCONV, "zolo_eig: block sizes exceed n");
     }
     // scalar blocks: V columns as they are, eigenvalues = diag
     if (!scalar_idx.empty()) {
@@ -419,88 +527,11 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
       }
       copy_blocks(Vp, Vout, cv, ar, s);
     }
-    // leaves: Jacobi on 64 x 64 padded copies, then V_b Q_leaf into the output
-    if (!leaf_idx.empty()) {
-      const int nl = (int)leaf_idx.size();
-      const int L = 64;
-      double* Lb = ar.dalloc((size_t)nl * L * L);
-      double* Lv = ar.dalloc((size_t)nl * L * L);
-      double* Ll = ar.dalloc((size_t)nl * L);
-      double* LV = ar.dalloc((size_t)nl * n * L);
-      set_identity(nl, L, L, 0.0, Lv, L, (long long)L * L, s);
-      set_identity(nl, n, L, 0.0, LV, n, (long long)n * L, s);
-      std::vector<CopyDesc> cb, cv;
-      std::vector<int> szs;
-      for (int q = 0; q < nl; ++q) {
-        const int k = leaf_idx[q];
-        cb.push_back({(long long)k * NN, (long long)q * L * L, N, L, all[k].n, all[k].n});
-        cv.push_back({(long long)k * n * N, (long long)q * n * L, n, n, n, all[k].n});
-        szs.push_back(all[k].n);
-      }
-      copy_blocks(Bp, Lb, cb, ar, s);
-      copy_blocks(Vp, LV, cv, ar, s);
-      int* d_sz = upload(ar, szs, s);
-      jacobi_batched(nl, d_sz, Lb, L, (long long)L * L, Lv, L, (long long)L * L, Ll, s);
-      double* LVo = ar.dalloc((size_t)nl * n * L);
-      GemmBatch g;
-      g.batch = nl;
-      g.m = n; g.n = L; g.k = L;
-      g.A = LV; g.lda = n; g.sA = (long long)n * L;
-      g.B = Lv; g.ldb = L; g.sB = (long long)L * L;
-      g.C = LVo; g.ldc = n; g.sC = (long long)n * L;
-      dgemm(g, s);
-      std::vector<double> ll((size_t)nl * L);
-      d2h(ll.data(), Ll, ll.size() * sizeof(double), s);
-      if (log_enabled() && nprob == 1) {
-        // leaf invariants: ||LVo^T B LVo - diag(lam)||_F per leaf, ||LVo^T LVo - I||_F
-        ArenaScope ds(ar);
-        double* BV = ar.dalloc((size_t)nl * n * L);
-        double* E = ar.dalloc((size_t)nl * L * L);
-        double* E2 = ar.dalloc((size_t)nl * L * L);
-        GemmBatch g1;
-        g1.batch = nl;
-        g1.m = n; g1.n = L; g1.k = n;
-        g1.A = a.B; g1.lda = a.ldb; g1.sA = 0;
-        g1.B = LVo; g1.ldb = n; g1.sB = (long long)n * L;
-        g1.C = BV; g1.ldc = n; g1.sC = (long long)n * L;
-        dgemm(g1, s);
-        GemmBatch g2;
-        g2.batch = nl;
-        g2.transA = 1;
-        g2.m = L; g2.n = L; g2.k = n;
-        g2.A = LVo; g2.lda = n; g2.sA = (long long)n * L;
-        g2.B = BV; g2.ldb = n; g2.sB = (long long)n * L;
-        g2.C = E; g2.ldc = L; g2.sC = (long long)L * L;
-        dgemm(g2, s);
-        g2.B = LVo;
-        g2.C = E2;
-        dgemm(g2, s);
-        std::vector<double> eh((size_t)nl * L * L), e2h((size_t)nl * L * L);
-        d2h(eh.data(), E, eh.size() * sizeof(double), s);
-        d2h(e2h.data(), E2, e2h.size() * sizeof(double), s);
-        for (int q = 0; q < nl; ++q) {
-          const int m = szs[q];
-          double r1 = 0.0, r2 = 0.0;
-          for (int j = 0; j < m; ++j)
-            for (int i = 0; i < m; ++i) {
-              const double v = eh[(size_t)q * L * L + i + j * L] - (i == j ? ll[(size_t)q * L + i] : 0.0);
-              const double w2 = e2h[(size_t)q * L * L + i + j * L] - (i == j ? 1.0 : 0.0);
-              r1 += v * v;
-              r2 += w2 * w2;
-            }
-          std::fprintf(stderr, "[zcsd] eig level %d leaf %d n=%d ||VtBV-L||=%.2e ||VtV-I||=%.2e\n",
-                       res.levels, q, m, std::sqrt(r1), std::sqrt(r2));
-        }
-      }
-      std::vector<CopyDesc> co;
-      for (int q = 0; q < nl; ++q) {
-        const int k = leaf_idx[q];
-        const int p = all[k].prob;
-        co.push_back({(long long)q * n * L, p * nn + (long long)col_out[p] * n, n, n, n, all[k].n});
-        for (int i = 0; i < all[k].n; ++i) lam_out[p].push_back(ll[(size_t)q * L + i]);
-        col_out[p] += all[k].n;
-      }
-      copy_blocks(LVo, Vout, co, ar, s);
+    // leaves: parked (their blocks and bases stay in this level's buffers) and
+    // solved together after the last level, one Jacobi launch for all of them
+    for (int k : leaf_idx) {
+      parked.push_back({Bp + (long long)k * NN, N, Vp + (long long)k * n * N, all[k].n, all[k].prob});
+      parked_cols[all[k].prob] += all[k].n;
     }
     if (split_idx.empty()) {
       active.clear();
@@ -969,6 +1000,7 @@ ZoloEigResult zolo_eig(const ZoloEigArgs& a, Arena& ar, hipStream_t s) {
     }
     active.swap(next);
   }
+  solve_leaves();
   for (int p = 0; p < nprob; ++p)
     if (col_out[p] != n) throw NumError(ZCSD_ENOCONV, "zolo_eig: lost eigenpairs");
 

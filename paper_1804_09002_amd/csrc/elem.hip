@@ -1,6 +1,7 @@
 // Element-wise and reduction kernels (HBM-bound helpers around the MFMA path)
 // and the device workspace arena.
 #include <algorithm>
+#include <cstring>
 #include <map>
 #include <mutex>
 
@@ -48,14 +49,66 @@ void* Arena::alloc(size_t bytes) {
 // memory is not guaranteed to wait for kernels already queued on the stream,
 // and the destination of an upload is often arena memory that a queued kernel
 // still reads (arena blocks are reused as soon as a scope ends), so the stream
-// is drained before and after every such copy.
+// is drained before and after such a copy.  Uploads of at most kSlotBytes go
+// instead through a ring of pinned staging slots per stream: the data is
+// copied into a slot on the host and the slot's copy to the device is queued
+// on the stream (ordered after the kernels before it, so the arena hazard is
+// covered by the stream order), with no host wait; an event recorded after
+// the copy guards the slot's reuse.
 void d2h(void* h, const void* d, size_t bytes, hipStream_t s) {
   ZCSD_HIP(hipStreamSynchronize(s));
   ZCSD_HIP(hipMemcpyAsync(h, d, bytes, hipMemcpyDeviceToHost, s));
   ZCSD_HIP(hipStreamSynchronize(s));
 }
 
+namespace {
+constexpr int kSlots = 64;
+constexpr size_t kSlotBytes = (size_t)64 << 10;
+struct UploadRing {
+  std::mutex mu;
+  char* host = nullptr;  // kSlots x kSlotBytes, pinned
+  hipEvent_t ev[kSlots] = {};
+  bool pending[kSlots] = {};
+  int next = 0;
+};
+// one ring per stream, kept to the end of the process (a stream value reused
+// by a later stream reuses the ring, whose slots are guarded by their events)
+UploadRing* ring_for(hipStream_t s) {
+  static std::mutex mu;
+  static std::map<hipStream_t, UploadRing*> rings;
+  std::lock_guard<std::mutex> g(mu);
+  auto it = rings.find(s);
+  if (it != rings.end()) return it->second;
+  auto* r = new UploadRing();
+  void* p = nullptr;
+  if (hipHostMalloc(&p, kSlots * kSlotBytes, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    delete r;
+    return nullptr;
+  }
+  r->host = static_cast<char*>(p);
+  for (int k = 0; k < kSlots; ++k) ZCSD_HIP(hipEventCreateWithFlags(&r->ev[k], hipEventDisableTiming));
+  rings[s] = r;
+  return r;
+}
+}  // namespace
+
 void h2d(void* d, const void* h, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return;
+  if (bytes <= kSlotBytes) {
+    if (UploadRing* r = ring_for(s)) {
+      std::lock_guard<std::mutex> g(r->mu);
+      const int k = r->next;
+      r->next = (k + 1) % kSlots;
+      if (r->pending[k]) ZCSD_HIP(hipEventSynchronize(r->ev[k]));
+      char* slot = r->host + (size_t)k * kSlotBytes;
+      std::memcpy(slot, h, bytes);
+      ZCSD_HIP(hipMemcpyAsync(d, slot, bytes, hipMemcpyHostToDevice, s));
+      ZCSD_HIP(hipEventRecord(r->ev[k], s));
+      r->pending[k] = true;
+      return;
+    }
+  }
   ZCSD_HIP(hipStreamSynchronize(s));
   ZCSD_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s));
   ZCSD_HIP(hipStreamSynchronize(s));

@@ -247,7 +247,7 @@ class AuxStream {
   hipEvent_t fork_ = nullptr, done_ = nullptr;
   bool joined_ = false;
 };
-void h2d(void* d, const void* h, size_t bytes, hipStream_t s);  // async (pageable: sync inside)
+void h2d(void* d, const void* h, size_t bytes, hipStream_t s);  // queued on s (small: pinned staging, no wait)
 
 // One problem of a batch through the single-problem CSD (csd.hip), with
 // Algorithm 2: square blocks with ld n, outputs U1, U2, V1 (n x n, ld n) and

@@ -49,18 +49,13 @@ void* Arena::alloc(size_t bytes) {
 // memory is not guaranteed to wait for kernels already queued on the stream,
 // and the destination of an upload is often arena memory that a queued kernel
 // still reads (arena blocks are reused as soon as a scope ends), so the stream
-// is drained before and after such a copy.  Uploads of at most kSlotBytes go
-// instead through a ring of pinned staging slots per stream: the data is
+// is drained before and after such a copy.  Transfers of at most kSlotBytes
+// go instead through a ring of pinned staging slots per stream: an upload is
 // copied into a slot on the host and the slot's copy to the device is queued
 // on the stream (ordered after the kernels before it, so the arena hazard is
-// covered by the stream order), with no host wait; an event recorded after
-// the copy guards the slot's reuse.
-void d2h(void* h, const void* d, size_t bytes, hipStream_t s) {
-  ZCSD_HIP(hipStreamSynchronize(s));
-  ZCSD_HIP(hipMemcpyAsync(h, d, bytes, hipMemcpyDeviceToHost, s));
-  ZCSD_HIP(hipStreamSynchronize(s));
-}
-
+// covered by the stream order), with no host wait, and an event recorded
+// after the copy guards the slot's reuse; a download is queued into a slot,
+// waited for once, and copied out on the host.
 namespace {
 constexpr int kSlots = 64;
 constexpr size_t kSlotBytes = (size_t)64 << 10;
@@ -92,6 +87,30 @@ UploadRing* ring_for(hipStream_t s) {
   return r;
 }
 }  // namespace
+
+void d2h(void* h, const void* d, size_t bytes, hipStream_t s) {
+  if (bytes == 0) return;
+  if (bytes <= kSlotBytes) {
+    if (UploadRing* r = ring_for(s)) {
+      // into a pinned slot: the copy is ordered after the kernels before it,
+      // and one wait for it replaces the drain before and the wait after
+      std::lock_guard<std::mutex> g(r->mu);
+      const int k = r->next;
+      r->next = (k + 1) % kSlots;
+      if (r->pending[k]) ZCSD_HIP(hipEventSynchronize(r->ev[k]));
+      char* slot = r->host + (size_t)k * kSlotBytes;
+      ZCSD_HIP(hipMemcpyAsync(slot, d, bytes, hipMemcpyDeviceToHost, s));
+      ZCSD_HIP(hipEventRecord(r->ev[k], s));
+      ZCSD_HIP(hipEventSynchronize(r->ev[k]));
+      r->pending[k] = false;
+      std::memcpy(h, slot, bytes);
+      return;
+    }
+  }
+  ZCSD_HIP(hipStreamSynchronize(s));
+  ZCSD_HIP(hipMemcpyAsync(h, d, bytes, hipMemcpyDeviceToHost, s));
+  ZCSD_HIP(hipStreamSynchronize(s));
+}
 
 void h2d(void* d, const void* h, size_t bytes, hipStream_t s) {
   if (bytes == 0) return;

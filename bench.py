@@ -71,6 +71,8 @@ def parse():
     p.add_argument("--batched-count", type=int, default=2048)
     p.add_argument("--single-sample", type=int, default=256,
                    help="problems of the batched workload timed one by one on the single path")
+    p.add_argument("--leg", choices=("small_graph",), default=None,
+                   help="run only this side measurement and print its JSON (for profiling)")
     return p.parse_args()
 
 
@@ -228,6 +230,82 @@ def small_batched_leg(count=4096, lo=4, hi=64, seed=8):
             "worst_backward_rel_fro": worst_res, "worst_orth_fro": worst_orth}
 
 
+def small_graph_leg(count=4096, lo=4, hi=64, seed=8):
+    """`count` CSDs with n log-uniform in [lo, hi] (uniform angles) through the
+    device-routed entry point (zcsd_dcsd_batched_small: routing, persistent
+    launches and table on the device), eager and as a captured HIP graph
+    replay, against the host-routed batched call with every problem in the
+    one-workgroup launches (one_workgroup_max_n = 64); outputs of the three
+    compared bit for bit.  Each timing: two warm-up calls, mean of five."""
+    import numpy as np
+    import torch
+    from paper_1804_09002_amd import workloads as WL
+    from paper_1804_09002_amd import zcsd
+    sizes = [int(n) for n in WL.batched_sizes(count, seed, lo, hi)]
+    rng = np.random.default_rng(seed)
+    A1s, A2s = [], []
+    for n in sizes:
+        A1, A2, _ = WL.uniform_pair(n, int(rng.integers(1 << 31)))
+        A1s.append(torch.tensor(A1, device="cuda:0"))
+        A2s.append(torch.tensor(A2, device="cuda:0"))
+    a1, sizes, offs = zcsd.pack_ragged(A1s)
+    a2, _, _ = zcsd.pack_ragged(A2s)
+    dev = a1.device
+    n_d = torch.tensor(sizes, dtype=torch.int32, device=dev)
+    off_d = torch.tensor(offs, dtype=torch.int64, device=dev)
+    toff_d = torch.tensor(np.concatenate([[0], np.cumsum(sizes)[:-1]]), dtype=torch.int64, device=dev)
+    U1, U2, V1 = (torch.empty_like(a1) for _ in range(3))
+    th = torch.empty(sum(sizes), dtype=torch.float64, device=dev)
+    status = torch.empty(count, dtype=torch.int32, device=dev)
+    ws = zcsd.small_batch_workspace(count)
+
+    def call():
+        zcsd.csd_batched_small(a1, a2, n_d, off_d, toff_d, U1, U2, V1, th, status, ws)
+
+    def timed(fn, reps=5):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    saved = zcsd.get_tuning()
+    try:
+        zcsd.set_tuning(one_workgroup_max_n=64)
+        t_host = timed(lambda: zcsd.csd_batched_packed(a1, a2, sizes, offs))
+        ref = zcsd.csd_batched_packed(a1, a2, sizes, offs)
+    finally:
+        zcsd.set_tuning(**saved)
+    t_eager = timed(call)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        call()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        call()
+    torch.cuda.synchronize()
+    eager_out = [X.clone() for X in (U1, U2, V1, th)]
+    for X in (U1, U2, V1, th):
+        X.zero_()
+    t_graph = timed(g.replay)
+    same_graph = all(torch.equal(x, y) for x, y in zip(eager_out, (U1, U2, V1, th)))
+    same_host = all(torch.equal(x, y) for x, y in zip(ref[:4], (U1, U2, V1, th)))
+    sum_n3 = float(sum(n ** 3 for n in sizes))
+    return {"workload": f"csd_fp64_batched_{count}_n{lo}to{hi}_loguniform", "problems": count,
+            "graph_replay_ms": round(t_graph * 1e3, 3), "device_routed_eager_ms": round(t_eager * 1e3, 3),
+            "host_routed_one_workgroup_ms": round(t_host * 1e3, 3),
+            "graph_csd_per_s": round(count / t_graph, 1),
+            "model_tflops_graph": round(198.0 * sum_n3 / t_graph / 1e12, 4),
+            "unwritten": int(((status & 255) != 0).sum()),
+            "graph_equals_eager": same_graph, "equals_host_routed": same_host}
+
+
 def backward_leg(count=64, n=512, seed=6):
     """Forward (one batched call) + hand-written backward of 64 CSDs at n = 512
     (uniform angles)."""
@@ -333,6 +411,9 @@ def main():
         print(json.dumps({"error": "the path runs on one GPU; --gpus above 1 is not supported",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
+    if args.leg == "small_graph":
+        print(json.dumps([small_graph_leg(), small_graph_leg(256, 4, 16, seed=9)]), flush=True)
+        return
     import numpy as np
     import torch
     from paper_1804_09002_amd import workloads as WL
@@ -431,6 +512,8 @@ def main():
         extra = {"mixed": mixed, "batched": batched_leg(args.batched_count, args.single_sample)}
         log("small batched leg: 4096 problems, n in [4, 64]")
         extra["batched_small"] = small_batched_leg()
+        log("small batched leg, device-routed and as a captured graph")
+        extra["batched_small_graph"] = [small_graph_leg(), small_graph_leg(256, 4, 16, seed=9)]
         log("forward+backward leg: 64 x n=512")
         extra["backward"] = backward_leg()
         log("complex leg: n=2048")

@@ -28,7 +28,9 @@
  *    amount a call needs depends on host decisions made during the call
  *    (Zolotarev degree, split sizes of Zolo-eig, size classes of a batch), so
  *    one bound per call would have to be the worst case of all of them.
- *    zcsd_dcsd_backward_noalloc is the one entry point that allocates nothing.
+ *    zcsd_dcsd_backward_noalloc is the one entry point that allocates nothing;
+ *    zcsd_dcsd_batched_small, whose small problems need no host decision,
+ *    takes a caller-owned workspace sized by zcsd_small_batch_prepare.
  */
 #ifndef ZCSD_H
 #define ZCSD_H
@@ -323,6 +325,59 @@ zcsd_status zcsd_dcsd_batched(zcsd_handle* handle, int batch, const int* n_host,
                               const double* d_A1, const double* d_A2,
                               double* d_U1, double* d_U2, double* d_V1, double* d_theta,
                               int* rank_host, const zcsd_opts* opts, zcsd_info* info);
+
+/*
+ * Batched CS decompositions of small full-rank problems with every decision
+ * on the device, for HIP graph capture (Algorithm 1 with Zolo-pd, Sec. 5,
+ * and the Jacobi solve of Zolo-eig's blocks, Sec. 5): each problem runs as
+ * one workgroup with its own lower bound l and the Zolotarev coefficients of
+ * the largest tabulated bound 0.9 * 10^(-q/8) <= l, as the one-workgroup
+ * problems of zcsd_dcsd_batched do.  The call enqueues, on the handle's
+ * stream, one kernel that sorts the problems by descending size (a counting
+ * sort in one workgroup), so that each tier of sizes (49..64, 33..48, 17..32,
+ * 1..16) is a contiguous range of the list, and four persistent launches that
+ * read their ranges from the device; it makes no host transfer,
+ * synchronisation, memset or allocation, so a captured graph replays it over
+ * new contents of the same buffers.
+ * All arrays are device memory owned by the caller, read at run time:
+ *  d_n[k]      size n_k of problem k (1..64; any other size gets status 3);
+ *  d_off[k]    element offset of problem k's n_k x n_k blocks in d_A1, d_A2
+ *              (inputs) and d_U1, d_U2, d_V1 (outputs), column-major, ld n_k;
+ *  d_toff[k]   element offset of its n_k angles in d_theta (ascending);
+ *  d_status[k] written: low byte 0 = outputs written, 1 = the l estimate
+ *              reached opts->eps (sigma_min(A_i) below it or a rank-deficient
+ *              member: outputs not written; zcsd_dcsd_batched handles such
+ *              members, with Algorithm 2 or 3), 2 = a Cholesky factorisation
+ *              broke down (not written), 3 = size outside 1..64 (not
+ *              written); bits 8.. the Zolotarev degree used;
+ *  d_ws        workspace of at least the size zcsd_small_batch_prepare
+ *              returns for this batch, 256-byte aligned; its contents need
+ *              no initialisation and are not meaningful afterwards.
+ * Outputs must not alias inputs; problems' output blocks must not overlap.
+ * opts (may be NULL): eps, tol and postprocess as zcsd_dcsd; prec must be
+ * ZCSD_FP64, r_override and ell_override 0, rank_mode not
+ * ZCSD_RANK_DEFICIENT.  Errors (nothing enqueued): ZCSD_EINVAL for batch
+ * outside 1..2^20, NULL pointers, a short or misaligned workspace, options
+ * outside the above, or no prior zcsd_small_batch_prepare for these eps and
+ * tol on the handle's device.  Calls that share a workspace must not overlap
+ * in time.
+ */
+zcsd_status zcsd_dcsd_batched_small(zcsd_handle* handle, int batch, const int* d_n,
+                                    const long long* d_off, const long long* d_toff,
+                                    const double* d_A1, const double* d_A2,
+                                    double* d_U1, double* d_U2, double* d_V1, double* d_theta,
+                                    int* d_status, void* d_ws, size_t ws_bytes,
+                                    const zcsd_opts* opts);
+/*
+ * Set-up of zcsd_dcsd_batched_small, outside any capture: uploads the
+ * Zolotarev coefficient table of (opts->eps, opts->tol) to the handle's device
+ * once (synchronous; kept until the process ends, a few KB) and returns in
+ * *ws_bytes the workspace a call with `batch` problems needs (4 batch bytes
+ * of list plus the scratch of the persistent grids, about 57 MB on 256
+ * compute units).  Errors: ZCSD_EINVAL as zcsd_dcsd_batched_small.
+ */
+zcsd_status zcsd_small_batch_prepare(zcsd_handle* handle, int batch, const zcsd_opts* opts,
+                                     size_t* ws_bytes);
 
 /*
  * Backward of `batch` full-rank CS decompositions of size n: the gradients

@@ -30,9 +30,11 @@
 #include <cmath>
 #include <map>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "jacobi_block.h"
+#include "zcsd_api_guard.h"
 #include "zcsd_internal.h"
 #include "zcsd_zolo.h"
 
@@ -488,15 +490,19 @@ __device__ int small_polar(int n, const double* __restrict__ A, const SmallCoef*
 }
 
 // Persistent kernel: workgroup b solves problems list[b], list[b + grid], ...
-// (MINW: waves per SIMD it must allow, which bounds its registers)
-// status[t]: 0 done, 1 l reached eps (not written), 2 Cholesky breakdown (not
-// written); bits 8.. hold the Zolotarev degree of the two polars (max).
+// (MINW: waves per SIMD it must allow, which bounds its registers); the list
+// length is `count`, or, when drange is not NULL (lists built on the
+// device), the list starts at entry drange[0] and has drange[1] entries.
+// status[t] (status[list[t]] when st_by_k): 0 done, 1 l reached
+// eps (not written), 2 Cholesky breakdown (not written); bits 8.. hold the
+// Zolotarev degree of the two polars (max).
 template <int SN, int ST, int MINW>
 __global__ __launch_bounds__(ST, MINW) void csd_small_kernel(
-    int count, const int* __restrict__ list, const int* __restrict__ nq, const long long* __restrict__ off,
-    const long long* __restrict__ toff, const double* __restrict__ A1, const double* __restrict__ A2,
-    double* U1, double* U2, double* V1, double* theta, const SmallCoef* __restrict__ table, int ntab,
-    double eps, int theta_from_lambda, double* scratch, int* status) {
+    int count, const int* __restrict__ drange, const int* __restrict__ list, const int* __restrict__ nq,
+    const long long* __restrict__ off, const long long* __restrict__ toff, const double* __restrict__ A1,
+    const double* __restrict__ A2, double* U1, double* U2, double* V1, double* theta,
+    const SmallCoef* __restrict__ table, int ntab, double eps, int theta_from_lambda, double* scratch,
+    int* status, int st_by_k) {
   __shared__ SmallShared<SN, ST> sh;
   constexpr long long SNN = (long long)SN * SN;
   const int tid = threadIdx.x;
@@ -506,8 +512,14 @@ __global__ __launch_bounds__(ST, MINW) void csd_small_kernel(
   double* Ws2 = Ws1 + SNN;
   double* Bs = Ws2 + SNN;
   double* Vs = Bs + SNN;
-  for (int t = blockIdx.x; t < count; t += gridDim.x) {
+  int cnt = count;
+  if (drange) {
+    list += drange[0];
+    cnt = drange[1];
+  }
+  for (int t = blockIdx.x; t < cnt; t += gridDim.x) {
     const int k = list[t];
+    const int si = st_by_k ? k : t;
     const int n = nq[k];
     const long long o = off[k];
     if (tid == 0) sh.flag = 0;
@@ -516,7 +528,7 @@ __global__ __launch_bounds__(ST, MINW) void csd_small_kernel(
     int st = small_polar<SN, ST>(n, A1 + o, table, ntab, eps, Hs1, Ws1, sh, &r1);
     if (st == 0) st = small_polar<SN, ST>(n, A2 + o, table, ntab, eps, Hs2, Ws2, sh, &r2);
     if (st != 0) {
-      if (tid == 0) status[t] = st;
+      if (tid == 0) status[si] = st;
       __syncthreads();
       continue;
     }
@@ -590,8 +602,49 @@ __global__ __launch_bounds__(ST, MINW) void csd_small_kernel(
       U1[dst] = u1;
       U2[dst] = u2;
     }
-    if (tid == 0) status[t] = (max(r1, r2) << 8);
+    if (tid == 0) status[si] = (max(r1, r2) << 8);
     __syncthreads();
+  }
+}
+
+// Routing on the device (for the entry point that makes no host decision),
+// one workgroup: problems sorted by descending size with a counting sort over
+// the sizes 1..64 in LDS (the order within one size is arbitrary; a
+// problem's arithmetic does not depend on it), so that each tier's list is a
+// contiguous range, largest first, and its workgroups take the big problems
+// before the small ones; range[2t], range[2t + 1] = start and length of tier
+// t (sizes 49..64, 33..48, 17..32, 1..16).  A size outside 1..64 gets status
+// 3 and joins no list.
+constexpr int kRouteThreads = 1024;
+
+__global__ __launch_bounds__(kRouteThreads) void small_route_kernel(int batch, const int* __restrict__ nq,
+                                                                   int* list, int* range, int* status) {
+  __shared__ int bins[65], cur[65];
+  const int tid = threadIdx.x;
+  if (tid < 65) bins[tid] = 0;
+  __syncthreads();
+  for (int k = tid; k < batch; k += kRouteThreads) {
+    const int n = nq[k];
+    if (n < 1 || n > 64) status[k] = 3;
+    else atomicAdd(bins + n, 1);
+  }
+  __syncthreads();
+  if (tid == 0) {
+    int pos = 0;
+    for (int n = 64; n >= 1; --n) {
+      cur[n] = pos;
+      pos += bins[n];
+    }
+    for (int t = 0; t < 4; ++t) {
+      const int hi = 64 - 16 * t, lo = hi - 15;
+      range[2 * t] = cur[hi];
+      range[2 * t + 1] = (lo > 1 ? cur[lo - 1] : pos) - cur[hi];
+    }
+  }
+  __syncthreads();
+  for (int k = tid; k < batch; k += kRouteThreads) {
+    const int n = nq[k];
+    if (n >= 1 && n <= 64) list[atomicAdd(cur + n, 1)] = k;
   }
 }
 
@@ -668,17 +721,17 @@ void small_csd_launch(const int* tier_count, const int* d_list, const int* d_n, 
       const int* li = d_list + first;
       int* stt = d_status + first;
       if (t == 0)
-        hipLaunchKernelGGL((csd_small_kernel<64, 256, 1>), dim3(grid[t]), dim3(256), 0, s, c, li, d_n, d_off,
-                           d_toff, A1, A2, U1, U2, V1, theta, d_tab, nt, eps, lam, scr, stt);
+        hipLaunchKernelGGL((csd_small_kernel<64, 256, 1>), dim3(grid[t]), dim3(256), 0, s, c, nullptr, li, d_n,
+                           d_off, d_toff, A1, A2, U1, U2, V1, theta, d_tab, nt, eps, lam, scr, stt, 0);
       else if (t == 1)
-        hipLaunchKernelGGL((csd_small_kernel<48, 192, 2>), dim3(grid[t]), dim3(192), 0, s, c, li, d_n, d_off,
-                           d_toff, A1, A2, U1, U2, V1, theta, d_tab, nt, eps, lam, scr, stt);
+        hipLaunchKernelGGL((csd_small_kernel<48, 192, 2>), dim3(grid[t]), dim3(192), 0, s, c, nullptr, li, d_n,
+                           d_off, d_toff, A1, A2, U1, U2, V1, theta, d_tab, nt, eps, lam, scr, stt, 0);
       else if (t == 2)
-        hipLaunchKernelGGL((csd_small_kernel<32, 128, 2>), dim3(grid[t]), dim3(128), 0, s, c, li, d_n, d_off,
-                           d_toff, A1, A2, U1, U2, V1, theta, d_tab, nt, eps, lam, scr, stt);
+        hipLaunchKernelGGL((csd_small_kernel<32, 128, 2>), dim3(grid[t]), dim3(128), 0, s, c, nullptr, li, d_n,
+                           d_off, d_toff, A1, A2, U1, U2, V1, theta, d_tab, nt, eps, lam, scr, stt, 0);
       else
-        hipLaunchKernelGGL((csd_small_kernel<16, 64, 2>), dim3(grid[t]), dim3(64), 0, s, c, li, d_n, d_off,
-                           d_toff, A1, A2, U1, U2, V1, theta, d_tab, nt, eps, lam, scr, stt);
+        hipLaunchKernelGGL((csd_small_kernel<16, 64, 2>), dim3(grid[t]), dim3(64), 0, s, c, nullptr, li, d_n,
+                           d_off, d_toff, A1, A2, U1, U2, V1, theta, d_tab, nt, eps, lam, scr, stt, 0);
       ZCSD_CHECK_LAUNCH();
     }
     first += c;
@@ -686,4 +739,156 @@ void small_csd_launch(const int* tier_count, const int* d_list, const int* d_n, 
   }
 }
 
+namespace {
+
+struct DeviceTable {
+  const SmallCoef* d;
+  int n;
+};
+
+// Device copies of the coefficient tables, per (device, eps, tol), made on
+// request and kept until the process ends (a few KB each).
+std::mutex g_dtab_mu;
+std::map<std::tuple<int, double, double>, DeviceTable> g_dtab;
+
+// Workspace of the device-routed launch, in bytes from its start:
+// [0, 256) the tier ranges, then the sorted list of `batch` ints, then the
+// per-workgroup scratch of the largest tier grid (the tiers run one after
+// another on one stream and share it).
+size_t dev_lists_bytes(int batch) { return ((size_t)batch * sizeof(int) + 255) / 256 * 256; }
+
+size_t dev_scratch_bytes(int n_cu) {
+  size_t e = 0;
+  for (int t = 0; t < kTiers; ++t)
+    e = std::max(e, (size_t)kTierPerCu[t] * n_cu * kTierMax[t] * kTierMax[t] * 6);
+  return e * sizeof(double);
+}
+
+}  // namespace
+
+bool small_table_device_make(int device, double eps, double tol) {
+  std::lock_guard<std::mutex> lk(g_dtab_mu);
+  const auto key = std::make_tuple(device, eps, tol);
+  if (g_dtab.count(key)) return false;
+  const std::vector<SmallCoef>& tab = small_table(eps, tol);
+  void* d = nullptr;
+  ZCSD_HIP(hipMalloc(&d, tab.size() * sizeof(SmallCoef)));
+  const hipError_t e = hipMemcpy(d, tab.data(), tab.size() * sizeof(SmallCoef), hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    (void)hipFree(d);
+    ZCSD_HIP(e);
+  }
+  g_dtab[key] = DeviceTable{static_cast<const SmallCoef*>(d), (int)tab.size()};
+  return true;
+}
+
+size_t small_device_ws_bytes(int batch, int n_cu) { return 256 + dev_lists_bytes(batch) + dev_scratch_bytes(n_cu); }
+
+void small_device_launch(int device, int batch, const int* d_n, const long long* d_off,
+                         const long long* d_toff, const double* A1, const double* A2, double* U1,
+                         double* U2, double* V1, double* theta, double eps, double tol,
+                         bool theta_from_lambda, int n_cu, void* ws, int* d_status, hipStream_t s) {
+  DeviceTable tab{};
+  {
+    std::lock_guard<std::mutex> lk(g_dtab_mu);
+    auto it = g_dtab.find(std::make_tuple(device, eps, tol));
+    if (it == g_dtab.end())
+      throw ArgError("csd_batched_small: no coefficient table for these eps/tol on this device "
+                     "(call zcsd_small_batch_prepare first)");
+    tab = it->second;
+  }
+  char* base = static_cast<char*>(ws);
+  int* range = reinterpret_cast<int*>(base);
+  int* list = reinterpret_cast<int*>(base + 256);
+  double* scr = reinterpret_cast<double*>(base + 256 + dev_lists_bytes(batch));
+  hipLaunchKernelGGL(small_route_kernel, dim3(1), dim3(kRouteThreads), 0, s, batch, d_n, list, range,
+                     d_status);
+  ZCSD_CHECK_LAUNCH();
+  const int lam = theta_from_lambda ? 1 : 0;
+  for (int t = 0; t < kTiers; ++t) {
+    // every tier is launched with its full persistent grid; its workgroups
+    // read the range of the list from the device and leave at once if it is short
+    const int g = kTierPerCu[t] * n_cu;
+    const int* li = list;
+    const int* ct = range + 2 * t;
+    if (t == 0)
+      hipLaunchKernelGGL((csd_small_kernel<64, 256, 1>), dim3(g), dim3(256), 0, s, 0, ct, li, d_n, d_off,
+                         d_toff, A1, A2, U1, U2, V1, theta, tab.d, tab.n, eps, lam, scr, d_status, 1);
+    else if (t == 1)
+      hipLaunchKernelGGL((csd_small_kernel<48, 192, 2>), dim3(g), dim3(192), 0, s, 0, ct, li, d_n, d_off,
+                         d_toff, A1, A2, U1, U2, V1, theta, tab.d, tab.n, eps, lam, scr, d_status, 1);
+    else if (t == 2)
+      hipLaunchKernelGGL((csd_small_kernel<32, 128, 2>), dim3(g), dim3(128), 0, s, 0, ct, li, d_n, d_off,
+                         d_toff, A1, A2, U1, U2, V1, theta, tab.d, tab.n, eps, lam, scr, d_status, 1);
+    else
+      hipLaunchKernelGGL((csd_small_kernel<16, 64, 2>), dim3(g), dim3(64), 0, s, 0, ct, li, d_n, d_off,
+                         d_toff, A1, A2, U1, U2, V1, theta, tab.d, tab.n, eps, lam, scr, d_status, 1);
+    ZCSD_CHECK_LAUNCH();
+  }
+}
+
 }  // namespace zcsd
+
+using namespace zcsd;
+
+namespace {
+
+// the options the device-routed entry point takes: FP64, no forced l or r,
+// the rank left to the l estimate
+zcsd_opts small_batch_opts(const zcsd_opts* opts) {
+  zcsd_opts o;
+  zcsd_default_opts(&o);
+  if (opts) o = *opts;
+  ZCSD_REQUIRE(o.prec == ZCSD_FP64, "csd_batched_small: only FP64");
+  ZCSD_REQUIRE(o.rank_mode != ZCSD_RANK_DEFICIENT, "csd_batched_small: full-rank problems only");
+  ZCSD_REQUIRE(o.r_override == 0 && o.ell_override == 0.0, "csd_batched_small: r and l are not forced here");
+  ZCSD_REQUIRE(o.eps > 0.0 && o.eps < 1.0 && o.tol > 0.0, "csd_batched_small: eps/tol out of range");
+  ZCSD_REQUIRE(o.postprocess >= 0 && o.postprocess <= 2, "csd_batched_small: postprocess out of range");
+  return o;
+}
+
+constexpr int kSmallBatchMax = 1 << 20;
+
+int device_cus(int device) {
+  int n_cu = 1;
+  ZCSD_HIP(hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device));
+  return std::max(n_cu, 1);
+}
+
+}  // namespace
+
+extern "C" zcsd_status zcsd_small_batch_prepare(zcsd_handle* handle, int batch, const zcsd_opts* opts,
+                                                size_t* ws_bytes) {
+  if (!handle) return ZCSD_EINVAL;
+  return guarded([&] {
+    ZCSD_REQUIRE(batch >= 1 && batch <= kSmallBatchMax, "csd_batched_small: 1 <= batch <= 2^20");
+    ZCSD_REQUIRE(ws_bytes, "csd_batched_small: NULL ws_bytes");
+    const zcsd_opts o = small_batch_opts(opts);
+    ZCSD_HIP(hipSetDevice(handle->device));
+    small_table_device_make(handle->device, o.eps, o.tol);
+    *ws_bytes = small_device_ws_bytes(batch, device_cus(handle->device));
+  });
+}
+
+extern "C" zcsd_status zcsd_dcsd_batched_small(zcsd_handle* handle, int batch, const int* d_n,
+                                               const long long* d_off, const long long* d_toff,
+                                               const double* d_A1, const double* d_A2, double* d_U1,
+                                               double* d_U2, double* d_V1, double* d_theta,
+                                               int* d_status, void* d_ws, size_t ws_bytes,
+                                               const zcsd_opts* opts) {
+  if (!handle) return ZCSD_EINVAL;
+  return guarded([&] {
+    ZCSD_REQUIRE(batch >= 1 && batch <= kSmallBatchMax, "csd_batched_small: 1 <= batch <= 2^20");
+    ZCSD_REQUIRE(d_n && d_off && d_toff && d_A1 && d_A2 && d_U1 && d_U2 && d_V1 && d_theta && d_status &&
+                     d_ws,
+                 "csd_batched_small: NULL pointer");
+    ZCSD_REQUIRE(((uintptr_t)d_ws & 255) == 0, "csd_batched_small: workspace not 256-byte aligned");
+    const zcsd_opts o = small_batch_opts(opts);
+    ZCSD_HIP(hipSetDevice(handle->device));
+    const int n_cu = device_cus(handle->device);
+    ZCSD_REQUIRE(ws_bytes >= small_device_ws_bytes(batch, n_cu),
+                 "csd_batched_small: workspace smaller than zcsd_small_batch_prepare's size");
+    small_device_launch(handle->device, batch, d_n, d_off, d_toff, d_A1, d_A2, d_U1, d_U2, d_V1, d_theta,
+                        o.eps, o.tol, o.postprocess == 2, n_cu, d_ws, d_status, handle->stream);
+  });
+}

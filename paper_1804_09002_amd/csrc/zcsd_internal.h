@@ -276,6 +276,19 @@ void small_csd_launch(const int* tier_count, const int* d_list, const int* d_n, 
                       double* U2, double* V1, double* theta, double eps, double tol,
                       bool theta_from_lambda, const int* grid, double* scratch, int* d_status, Arena& ar,
                       hipStream_t s);
+// the same CSDs routed on the device (zcsd_dcsd_batched_small):
+// small_table_device_make uploads the coefficient table of (eps, tol) for
+// `device` once (synchronous; false if it was there);
+// small_device_ws_bytes is the workspace of a batch of `batch` on n_cu compute
+// units; small_device_launch enqueues the sort by size and the four
+// persistent launches on s, with no host transfer, synchronisation or
+// allocation.  status[k] of problem k as above, or 3 for a size outside 1..64.
+bool small_table_device_make(int device, double eps, double tol);
+size_t small_device_ws_bytes(int batch, int n_cu);
+void small_device_launch(int device, int batch, const int* d_n, const long long* d_off,
+                         const long long* d_toff, const double* A1, const double* A2, double* U1,
+                         double* U2, double* V1, double* theta, double eps, double tol,
+                         bool theta_from_lambda, int n_cu, void* ws, int* d_status, hipStream_t s);
 // Householder QR of the m x n block A (m >= n, ld lda): Q (m x n, ld m) and
 // the triangular R (n x n, ld n, zeros below the diagonal) (csd.hip)
 void tall_qr(int m, int n, const double* A, long long lda, double* Q, double* R, Arena& ar,

@@ -96,6 +96,9 @@ def _lib():
             "zcsd_dcsd_batched": [vp, i, C.POINTER(C.c_int), C.POINTER(C.c_longlong), vp, vp, vp, vp,
                                   vp, vp, C.POINTER(C.c_int), C.POINTER(Opts), C.POINTER(Info)],
             "zcsd_zolo_coeffs": [d, i, C.POINTER(d), C.POINTER(d), C.POINTER(d), C.POINTER(d)],
+            "zcsd_small_batch_prepare": [vp, i, C.POINTER(Opts), C.POINTER(C.c_size_t)],
+            "zcsd_dcsd_batched_small": [vp, i, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, C.c_size_t,
+                                        C.POINTER(Opts)],
             "zcsd_set_tuning": [vp, i, i],
             "zcsd_get_tuning": [vp, i, C.POINTER(C.c_int)],
             "zcsd_zolo_choose_r": [d, d],
@@ -603,6 +606,42 @@ def csd_batched_packed(a1, a2, sizes, offs, rank_mode="auto", **opts):
                                   _ptr(th), rk, C.byref(o), C.byref(info))
     _check(st, "zcsd_dcsd_batched")
     return U1, U2, V1, th, list(rk), info.as_dict()
+
+
+def small_batch_workspace(batch, device=None, **opts):
+    """Workspace (a uint8 device tensor) for csd_batched_small over `batch`
+    problems; also uploads the coefficient table for these options
+    (zcsd_small_batch_prepare).  Call it outside any graph capture."""
+    h = handle(device)
+    o = default_opts(**opts)
+    nb = C.c_size_t()
+    _check(_lib().zcsd_small_batch_prepare(h, int(batch), C.byref(o), C.byref(nb)), "zcsd_small_batch_prepare")
+    dev = torch.cuda.current_device() if device is None else int(device)
+    return torch.empty(nb.value, dtype=torch.uint8, device=f"cuda:{dev}")
+
+
+def csd_batched_small(a1, a2, n, off, toff, U1, U2, V1, theta, status, ws, **opts):
+    """Enqueue zcsd_dcsd_batched_small on torch's current stream: every buffer
+    is a device tensor the caller made (a1, a2, U1, U2, V1, theta float64; n,
+    status int32; off, toff int64; ws from small_batch_workspace), so the call
+    can be captured in a torch.cuda.CUDAGraph and replayed.  Nothing is
+    synchronised or read back: status[k] tells which problems were written
+    (low byte 0)."""
+    bs = int(n.numel())
+    for t, dt, nm in ((a1, torch.float64, "a1"), (a2, torch.float64, "a2"), (U1, torch.float64, "U1"),
+                      (U2, torch.float64, "U2"), (V1, torch.float64, "V1"), (theta, torch.float64, "theta"),
+                      (n, torch.int32, "n"), (status, torch.int32, "status"), (off, torch.int64, "off"),
+                      (toff, torch.int64, "toff"), (ws, torch.uint8, "ws")):
+        if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dt and t.is_contiguous()):
+            raise TypeError(f"{nm} must be a contiguous {dt} device tensor")
+    if off.numel() != bs or toff.numel() != bs or status.numel() != bs:
+        raise ValueError("n, off, toff and status must have one entry per problem")
+    h = handle(a1.device.index)
+    o = default_opts(**opts)
+    st = _lib().zcsd_dcsd_batched_small(h, bs, _ptr(n), _ptr(off), _ptr(toff), _ptr(a1), _ptr(a2), _ptr(U1),
+                                        _ptr(U2), _ptr(V1), _ptr(theta), _ptr(status), _ptr(ws),
+                                        ws.numel(), C.byref(o))
+    _check(st, "zcsd_dcsd_batched_small")
 
 
 def csd_batched(A1s, A2s, rank_mode="auto", **opts):

@@ -1,0 +1,234 @@
+"""The device-routed batched CSD of small problems (zcsd_dcsd_batched_small):
+the size routing, the persistent launches and the coefficient table all on
+the device, so the call can be captured in a HIP graph and replayed.
+
+Checked: each problem equals, bit for bit, the one-workgroup result of the
+host-routed batched path (the same kernel and table: both compute Algorithm 1
+in the same order), against the oracle's angles and the known angles of the
+construction to 10 max(n, 8) u, with the backward-error and orthogonality
+targets; the status codes (size outside 1..64, l reaching eps with A_1 = 0);
+a captured graph replayed over new inputs and new sizes, each replay equal to
+the eager call on the same inputs, with eager work and synchronisations
+between replays; and the argument errors.
+"""
+import ctypes as C
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import csd as O
+from paper_1804_09002_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+U = 2.0 ** -53
+DEV = torch.device("cuda:0")
+SLOT = 64 * 64
+
+
+def _t(x):
+    return torch.tensor(np.ascontiguousarray(x), device=DEV)
+
+
+class Batch:
+    """Fixed device buffers for `count` problems, each in a slot of 64 x 64
+    (offset k * 4096, angles at k * 64), so sizes can change between calls."""
+
+    def __init__(self, zcsd, count):
+        self.count = count
+        f = dict(dtype=torch.float64, device=DEV)
+        self.a1 = torch.zeros(count * SLOT, **f)
+        self.a2 = torch.zeros(count * SLOT, **f)
+        self.U1 = torch.zeros(count * SLOT, **f)
+        self.U2 = torch.zeros(count * SLOT, **f)
+        self.V1 = torch.zeros(count * SLOT, **f)
+        self.th = torch.zeros(count * 64, **f)
+        self.n = torch.ones(count, dtype=torch.int32, device=DEV)
+        self.off = torch.arange(count, dtype=torch.int64, device=DEV) * SLOT
+        self.toff = torch.arange(count, dtype=torch.int64, device=DEV) * 64
+        self.status = torch.full((count,), -1, dtype=torch.int32, device=DEV)
+        self.ws = zcsd.small_batch_workspace(count)
+
+    def load(self, A1s, A2s, sizes):
+        n = torch.tensor(sizes, dtype=torch.int32)
+        self.n.copy_(n)
+        for k, (a, b) in enumerate(zip(A1s, A2s)):
+            m = a.shape[0]
+            self.a1[k * SLOT:k * SLOT + m * m].copy_(torch.from_numpy(np.asfortranarray(a).reshape(-1, order="F")))
+            self.a2[k * SLOT:k * SLOT + m * m].copy_(torch.from_numpy(np.asfortranarray(b).reshape(-1, order="F")))
+
+    def call(self, zcsd, **opts):
+        zcsd.csd_batched_small(self.a1, self.a2, self.n, self.off, self.toff, self.U1, self.U2, self.V1,
+                               self.th, self.status, self.ws, **opts)
+
+    def out(self, k, n):
+        o = k * SLOT
+        return tuple(X[o:o + n * n].view(n, n).t() for X in (self.U1, self.U2, self.V1)) + \
+            (self.th[k * 64:k * 64 + n],)
+
+    def snapshot(self):
+        return [X.clone() for X in (self.U1, self.U2, self.V1, self.th, self.status)]
+
+
+def _problems(seed, count, lo=1, hi=64):
+    rng = np.random.default_rng(seed)
+    sizes = [int(x) for x in rng.integers(lo, hi + 1, size=count)]
+    A1s, A2s, truth = [], [], []
+    for n in sizes:
+        A1, A2, meta = WL.uniform_pair(n, int(rng.integers(1 << 31)))
+        A1s.append(A1); A2s.append(A2); truth.append(np.sort(meta["theta"]))
+    return sizes, A1s, A2s, truth
+
+
+@pytest.fixture
+def zcsd():
+    from paper_1804_09002_amd import zcsd as Z
+    saved = Z.get_tuning()
+    yield Z
+    Z.set_tuning(**saved)
+
+
+def test_device_routed_matches_host_routed_and_oracle(zcsd):
+    sizes, A1s, A2s, truth = _problems(501, 700)
+    sizes[:4] = [1, 16, 17, 64]
+    for k in range(4):
+        A1s[k], A2s[k], meta = WL.uniform_pair(sizes[k], 510 + k)
+        truth[k] = np.sort(meta["theta"])
+    b = Batch(zcsd, len(sizes))
+    b.load(A1s, A2s, sizes)
+    b.call(zcsd)
+    torch.cuda.synchronize()
+    assert torch.equal(b.status & 255, torch.zeros_like(b.status))
+    zcsd.set_tuning(one_workgroup_max_n=64)
+    ref = zcsd.csd_batched([_t(a) for a in A1s], [_t(a) for a in A2s])
+    for k, n in enumerate(sizes):
+        U1, U2, V1, th = b.out(k, n)
+        rU1, rU2, rV1, rth, r = ref[k]
+        assert r == n
+        assert torch.equal(th, rth) and torch.equal(U1, rU1) and torch.equal(U2, rU2) and torch.equal(V1, rV1), k
+        assert np.max(np.abs(th.cpu().numpy() - truth[k])) <= 10 * max(n, 8) * U, (k, n)
+        c, s = torch.cos(th), torch.sin(th)
+        A1, A2 = _t(A1s[k]), _t(A2s[k])
+        R = torch.cat([(U1 * c) @ V1.T - A1, (U2 * s) @ V1.T - A2])
+        lim = 1e-13 * max(1.0, np.sqrt(n) / 4)
+        assert float(torch.linalg.norm(R)) / float(torch.linalg.norm(torch.cat([A1, A2]))) <= lim, k
+        I = torch.eye(n, dtype=torch.float64, device=DEV)
+        for X in (U1, U2, V1):
+            assert float(torch.linalg.norm(X.T @ X - I)) <= lim, k
+    for k in (0, 3, 350, 699):
+        o = O.csd(A1s[k], A2s[k])
+        assert np.max(np.abs(b.out(k, sizes[k])[3].cpu().numpy() - o["theta"])) <= 10 * max(sizes[k], 8) * U
+
+
+def test_device_routed_status_codes(zcsd):
+    """A size of 0 or 65 gets status 3 and its slot is left as it was; a member
+    with A_1 = 0 (l reaches eps) gets status 1, unwritten; the others are
+    written with their Zolotarev degree in bits 8 and up."""
+    rng = np.random.default_rng(52)
+    A1u, A2u, mu = WL.uniform_pair(20, 53)
+    A1z, A2z, _ = WL.from_angles(np.full(12, np.pi / 2), rng)
+    A1z[:] = 0.0
+    A1v, A2v, mv = WL.uniform_pair(40, 54)
+    dummy = np.eye(1)
+    b = Batch(zcsd, 5)
+    b.load([A1u, A1z, dummy, A1v, dummy], [A2u, A2z, dummy, A2v, dummy], [20, 12, 1, 40, 1])
+    b.n.copy_(torch.tensor([20, 12, 65, 40, 0], dtype=torch.int32))
+    sentinel = 7.0
+    for X in (b.U1, b.U2, b.V1, b.th):
+        X.fill_(sentinel)
+    b.call(zcsd)
+    torch.cuda.synchronize()
+    st = b.status.cpu().tolist()
+    assert [x & 255 for x in st] == [0, 1, 3, 0, 3], st
+    assert 1 <= (st[0] >> 8) <= 8 and 1 <= (st[3] >> 8) <= 8
+    for k in (1, 2, 4):
+        o = k * SLOT
+        for X in (b.U1, b.U2, b.V1):
+            assert bool((X[o:o + SLOT] == sentinel).all()), k
+        assert bool((b.th[k * 64:(k + 1) * 64] == sentinel).all()), k
+    for k, (n, meta) in ((0, (20, mu)), (3, (40, mv))):
+        assert np.max(np.abs(b.out(k, n)[3].cpu().numpy() - np.sort(meta["theta"]))) <= 10 * max(n, 8) * U
+
+
+def test_device_routed_call_replays_in_a_captured_graph(zcsd):
+    """Capture once, replay over three new sets of problems (other sizes in
+    the same slots), with eager work between the replays; every replay equals
+    the eager call on the same inputs."""
+    count = 300
+    b = Batch(zcsd, count)
+    sizes, A1s, A2s, _ = _problems(61, count)
+    b.load(A1s, A2s, sizes)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        b.call(zcsd)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        b.call(zcsd)
+    torch.cuda.synchronize()
+    for rep, seed in enumerate((62, 63, 64)):
+        sizes, A1s, A2s, truth = _problems(seed, count)
+        b.load(A1s, A2s, sizes)
+        # a slot's entries beyond n_k^2 are not written: both calls start from zeros
+        for X in (b.U1, b.U2, b.V1, b.th):
+            X.zero_()
+        b.status.fill_(-1)
+        b.call(zcsd)
+        torch.cuda.synchronize()
+        eager = b.snapshot()
+        # eager work between the eager call and the replay
+        x = torch.randn(256, 256, dtype=torch.float64, device=DEV)
+        (x @ x).sum().item()
+        for X in (b.U1, b.U2, b.V1, b.th):
+            X.zero_()
+        b.status.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for e, r in zip(eager, b.snapshot()):
+            assert torch.equal(e, r), rep
+        assert bool(((b.status & 255) == 0).all()), rep
+        for k in (0, count // 2, count - 1):
+            n = sizes[k]
+            assert np.max(np.abs(b.out(k, n)[3].cpu().numpy() - truth[k])) <= 10 * max(n, 8) * U, (rep, k)
+
+
+def test_device_routed_angles_from_lambda(zcsd):
+    """postprocess = 2 (Remark (iv)): equal to the host-routed path's
+    one-workgroup result with the same option."""
+    sizes, A1s, A2s, _ = _problems(71, 40)
+    b = Batch(zcsd, len(sizes))
+    b.ws = zcsd.small_batch_workspace(len(sizes), postprocess=2)
+    b.load(A1s, A2s, sizes)
+    b.call(zcsd, postprocess=2)
+    torch.cuda.synchronize()
+    zcsd.set_tuning(one_workgroup_max_n=64)
+    ref = zcsd.csd_batched([_t(a) for a in A1s], [_t(a) for a in A2s], postprocess=2)
+    for k, n in enumerate(sizes):
+        assert torch.equal(b.out(k, n)[3], ref[k][3]), k
+
+
+def test_device_routed_argument_errors(zcsd):
+    b = Batch(zcsd, 4)
+    with pytest.raises(zcsd.ZcsdError):      # workspace too short
+        zcsd.csd_batched_small(b.a1, b.a2, b.n, b.off, b.toff, b.U1, b.U2, b.V1, b.th, b.status, b.ws[:1024])
+    big = torch.empty(b.ws.numel() + 256, dtype=torch.uint8, device=DEV)
+    with pytest.raises(zcsd.ZcsdError):      # workspace not 256-byte aligned
+        zcsd.csd_batched_small(b.a1, b.a2, b.n, b.off, b.toff, b.U1, b.U2, b.V1, b.th, b.status,
+                               big[8:8 + b.ws.numel()])
+    with pytest.raises(zcsd.ZcsdError):      # no table prepared for this tol
+        b.call(zcsd, tol=1e-12)
+    with pytest.raises(zcsd.ZcsdError):      # options the device path does not take
+        b.call(zcsd, r_override=3)
+    with pytest.raises(zcsd.ZcsdError):
+        b.call(zcsd, prec="mixed_fp32")
+    with pytest.raises(zcsd.ZcsdError):
+        zcsd.small_batch_workspace(0)
+    lib = zcsd._lib()
+    nb = C.c_size_t()
+    assert lib.zcsd_small_batch_prepare(zcsd.handle(), 4, None, None) != 0
+    assert lib.zcsd_small_batch_prepare(None, 4, None, C.byref(nb)) != 0
+    assert lib.zcsd_dcsd_batched_small(zcsd.handle(), 4, None, None, None, None, None, None, None, None, None,
+                                       None, None, 0, None) != 0

@@ -354,6 +354,8 @@ zcsd_status zcsd_dcsd_batched(zcsd_handle* handle, int batch, const int* n_host,
  *              returns for this batch, 256-byte aligned; its contents need
  *              no initialisation and are not meaningful afterwards.
  * Outputs must not alias inputs; problems' output blocks must not overlap.
+ * The offsets live on the device and are not checked: every problem's blocks
+ * and angles must lie inside the caller's arrays.
  * opts (may be NULL): eps, tol and postprocess as zcsd_dcsd; prec must be
  * ZCSD_FP64, r_override and ell_override 0, rank_mode not
  * ZCSD_RANK_DEFICIENT.  Errors (nothing enqueued): ZCSD_EINVAL for batch

@@ -120,6 +120,37 @@ def test_device_routed_matches_host_routed_and_oracle(zcsd):
         assert np.max(np.abs(b.out(k, sizes[k])[3].cpu().numpy() - o["theta"])) <= 10 * max(sizes[k], 8) * U
 
 
+def test_device_routed_many_problems_per_workgroup(zcsd):
+    """3000 problems with n in [1, 64]: about 750 per tier, more than the
+    grids of the tiers for n > 32 (256 and 512 workgroups), so workgroups
+    take several problems from the sorted list; bit-identical to the
+    host-routed one-workgroup result, every status 0, sampled angles against
+    the construction."""
+    sizes, A1s, A2s, truth = _problems(81, 3000)
+    a1, _, offs = zcsd.pack_ragged([_t(a) for a in A1s])
+    a2, _, _ = zcsd.pack_ragged([_t(a) for a in A2s])
+    n_d = torch.tensor(sizes, dtype=torch.int32, device=DEV)
+    off_d = torch.tensor(offs, dtype=torch.int64, device=DEV)
+    toff = np.concatenate([[0], np.cumsum(sizes)[:-1]])
+    toff_d = torch.tensor(toff, dtype=torch.int64, device=DEV)
+    U1, U2, V1 = (torch.full_like(a1, 7.0) for _ in range(3))
+    th = torch.full((sum(sizes),), 7.0, dtype=torch.float64, device=DEV)
+    st = torch.full((len(sizes),), -1, dtype=torch.int32, device=DEV)
+    ws = zcsd.small_batch_workspace(len(sizes))
+    zcsd.csd_batched_small(a1, a2, n_d, off_d, toff_d, U1, U2, V1, th, st, ws)
+    torch.cuda.synchronize()
+    assert bool(((st & 255) == 0).all())
+    zcsd.set_tuning(one_workgroup_max_n=64)
+    rU1, rU2, rV1, rth, ranks, _ = zcsd.csd_batched_packed(a1, a2, sizes, offs)
+    assert ranks == sizes
+    for x, y in ((U1, rU1), (U2, rU2), (V1, rV1), (th, rth)):
+        assert torch.equal(x, y)
+    for k in range(0, 3000, 97):
+        n = sizes[k]
+        got = th[int(toff[k]):int(toff[k]) + n].cpu().numpy()
+        assert np.max(np.abs(got - truth[k])) <= 10 * max(n, 8) * U, (k, n)
+
+
 def test_device_routed_status_codes(zcsd):
     """A size of 0 or 65 gets status 3 and its slot is left as it was; a member
     with A_1 = 0 (l reaches eps) gets status 1, unwritten; the others are

@@ -16,7 +16,7 @@ namespace zcsd {
 // c = 1/sqrt(1 + t^2), s = t c; A <- J^T A J annihilates a_pq.  A rotation is
 // skipped when |a_pq| <= u ||A||_F / n (dropping every such entry changes A by
 // at most u ||A||_F), and the sweeps stop after one that rotated nothing (or
-// after 40 sweeps).
+// after 40 sweeps); a round that rotates no pair skips its update.
 //
 // Every rotation applied to the basis adds rounding to it, and each column
 // takes n - 1 of them per sweep, so the accumulated basis X is orthonormal
@@ -50,6 +50,8 @@ struct JacobiShared {
   double red2[JNT / 64];
   double lt[JB];
   int rotated;
+  // whether round r rotates any pair, in rround[r % 2]
+  int rround[2];
 };
 
 // Eigenpairs of the symmetric part of the n x n block A (1 <= n <= JB, ld lda)
@@ -120,7 +122,10 @@ __device__ inline void jacobi_block(int n, const double* A, long long lda, doubl
   constexpr int CSMIN = JNT / RBMAX;
   constexpr int NQC = (JB + CSMIN - 1) / CSMIN, NQP = (JB / 2 + CSMIN - 1) / CSMIN;
   for (int sweep = 0; sweep < 40; ++sweep) {
-    if (tid == 0) rotated = 0;
+    if (tid == 0) {
+      rotated = 0;
+      sh.rround[0] = 0;
+    }
     __syncthreads();
     for (int rnd = 0; rnd < m - 1; ++rnd) {
       if (tid < m / 2) {
@@ -140,6 +145,7 @@ __device__ inline void jacobi_block(int n, const double* A, long long lda, doubl
           c = 1.0 / sqrt(1.0 + t * t);
           s = t * c;
           rotated = 1;
+          sh.rround[rnd & 1] = 1;
         } else {
           q = p;  // dummy pair or an entry below the threshold: no rotation
         }
@@ -160,12 +166,18 @@ __device__ inline void jacobi_block(int n, const double* A, long long lda, doubl
         }
       }
       __syncthreads();
+      // a round that rotates nothing leaves S and V as they are (its update
+      // would copy S unchanged into the other buffer): skipped; the flag of
+      // the next round is cleared here, after every thread has read it in
+      // the round before
+      const bool any = sh.rround[rnd & 1] != 0;
+      if (tid == 0) sh.rround[(rnd + 1) & 1] = 0;
       // S' = J^T S J into the other buffer (a column combination, then the
       // row combination of the two columns: the arithmetic of applying J on
       // the right, then J^T on the left), the rotated pairs' entries set to
       // zero; V <- V J in place (each pair's two columns by one thread)
       // (the row's rotation is read once)
-      if (ri < n) {
+      if (any && ri < n) {
         double(*Sn)[JB + 1] = Sbuf[cur ^ 1];
         const int pi = pt[ri];
         const double ai = al[ri], bi = be[ri];
@@ -195,8 +207,10 @@ __device__ inline void jacobi_block(int n, const double* A, long long lda, doubl
         }
       }
       __syncthreads();
-      cur ^= 1;
-      S = Sbuf[cur];
+      if (any) {
+        cur ^= 1;
+        S = Sbuf[cur];
+      }
     }
     if (!rotated) break;
     __syncthreads();  // every thread has read `rotated` before it is reset

@@ -43,11 +43,17 @@ namespace zcsd {
 namespace {
 
 // Four instances of everything below (SN: largest size, ST: threads of a
-// workgroup), tiers of problem sizes: 49..64 with 256 threads (138 KB of
-// LDS: one workgroup per compute unit), 33..48 with 192 threads (79 KB: two
+// workgroup), tiers of problem sizes: 49..64 with 512 threads (138 KB of
+// LDS: one workgroup per compute unit), 33..48 with 256 threads (79 KB: two
 // per compute unit), 17..32 with 128 threads (36 KB: four) and at most 16
 // with one wave of 64 threads (10 KB: eight); several workgroups per compute
-// unit hide each other's latency.
+// unit hide each other's latency.  The two largest tiers have two waves per
+// SIMD: the column steps use four threads per column and leave the others
+// idle, but the Jacobi rounds and the tile products spread over all of them
+// and the per-thread arrays shrink (measured at n = 64: 12.7 -> 10.4 ms for
+// 512 problems against 256 threads; at n = 40: 6.4 -> 5.7 ms for 1024
+// against 192 threads; 17..32 with 256 threads and two workgroups per
+// compute unit was slower, 2.6 -> 4.0 ms for 2048 at n = 24).
 constexpr int kTiers = 4;
 constexpr int kTierMax[kTiers] = {64, 48, 32, 16};
 constexpr int kTierPerCu[kTiers] = {1, 2, 4, 8};
@@ -721,10 +727,10 @@ void small_csd_launch(const int* tier_count, const int* d_list, const int* d_n, 
       const int* li = d_list + first;
       int* stt = d_status + first;
       if (t == 0)
-        hipLaunchKernelGGL((csd_small_kernel<64, 256, 1>), dim3(grid[t]), dim3(256), 0, s, c, nullptr, li, d_n,
+        hipLaunchKernelGGL((csd_small_kernel<64, 512, 1>), dim3(grid[t]), dim3(512), 0, s, c, nullptr, li, d_n,
                            d_off, d_toff, A1, A2, U1, U2, V1, theta, d_tab, nt, eps, lam, scr, stt, 0);
       else if (t == 1)
-        hipLaunchKernelGGL((csd_small_kernel<48, 192, 2>), dim3(grid[t]), dim3(192), 0, s, c, nullptr, li, d_n,
+        hipLaunchKernelGGL((csd_small_kernel<48, 256, 2>), dim3(grid[t]), dim3(256), 0, s, c, nullptr, li, d_n,
                            d_off, d_toff, A1, A2, U1, U2, V1, theta, d_tab, nt, eps, lam, scr, stt, 0);
       else if (t == 2)
         hipLaunchKernelGGL((csd_small_kernel<32, 128, 2>), dim3(grid[t]), dim3(128), 0, s, c, nullptr, li, d_n,
@@ -812,10 +818,10 @@ void small_device_launch(int device, int batch, const int* d_n, const long long*
     const int* li = list;
     const int* ct = range + 2 * t;
     if (t == 0)
-      hipLaunchKernelGGL((csd_small_kernel<64, 256, 1>), dim3(g), dim3(256), 0, s, 0, ct, li, d_n, d_off,
+      hipLaunchKernelGGL((csd_small_kernel<64, 512, 1>), dim3(g), dim3(512), 0, s, 0, ct, li, d_n, d_off,
                          d_toff, A1, A2, U1, U2, V1, theta, tab.d, tab.n, eps, lam, scr, d_status, 1);
     else if (t == 1)
-      hipLaunchKernelGGL((csd_small_kernel<48, 192, 2>), dim3(g), dim3(192), 0, s, 0, ct, li, d_n, d_off,
+      hipLaunchKernelGGL((csd_small_kernel<48, 256, 2>), dim3(g), dim3(256), 0, s, 0, ct, li, d_n, d_off,
                          d_toff, A1, A2, U1, U2, V1, theta, tab.d, tab.n, eps, lam, scr, d_status, 1);
     else if (t == 2)
       hipLaunchKernelGGL((csd_small_kernel<32, 128, 2>), dim3(g), dim3(128), 0, s, 0, ct, li, d_n, d_off,

@@ -176,7 +176,7 @@ def batched_leg(count, sample, seed=5):
 
 def small_batched_leg(count=4096, lo=4, hi=64, seed=8):
     """4096 CSDs with n log-uniform in [4, 64] (uniform angles): one batched call
-    with the handle's default one-workgroup limit (full-rank n <= 48 as whole
+    with the handle's default one-workgroup limit (full-rank n <= 56 as whole
     CSDs in persistent launches, the rest through the size classes) against
     the same call with every problem in the classes (one_workgroup_max_n = 0),
     both steady state (two warm-up calls, mean of three)."""

@@ -134,7 +134,7 @@ const char* zcsd_status_string(zcsd_status s);
  * measured on 2048 problems with n log-uniform in [8, 256];
  * paper_1804_09002_amd/autotune.py measures the settings for another
  * workload.  Full-rank problems with n <= ZCSD_TUNE_ONE_WORKGROUP_MAX_N
- * (default 48, at most 64, 0 = none) skip the classes: each runs as a whole
+ * (default 56, at most 64, 0 = none) skip the classes: each runs as a whole
  * CSD inside one workgroup, all of them in persistent launches by tier of
  * size (n <= 16: eight workgroups per compute unit; n <= 32: four; n <= 48:
  * two; n <= 64: one) that run beside the class groups (the same Algorithm 1 with

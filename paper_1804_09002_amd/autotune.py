@@ -30,7 +30,7 @@ import time
 
 WORKERS = (1, 2, 3, 4, 6, 8)
 STEPS = ((4, 8, 32), (8, 16, 64), (8, 32, 64), (16, 16, 64), (16, 32, 64))
-ONE_WG = (48, 32, 64, 16, 0)
+ONE_WG = (56, 48, 32, 64, 16, 0)
 
 
 def workload(count, lo, hi, seed):

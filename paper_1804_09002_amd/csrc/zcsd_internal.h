@@ -101,7 +101,7 @@ struct zcsd_handle_s {
   int tune_step[3] = {8, 16, 64};
   // full-rank problems with n up to this run as whole CSDs of one workgroup
   // each, in persistent launches (0: none)
-  int tune_small_max = 48;
+  int tune_small_max = 56;
   // products with at least this many 128 x 128 output tiles use that tiling
   int tune_tile128_min = zcsd::kGemmTile128MinDefault;
 };

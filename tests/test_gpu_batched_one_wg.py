@@ -1,7 +1,7 @@
 """The one-workgroup CSDs of the batched path (small full-rank problems,
 persistent launches) against the oracle and against the size-class path.
 
-Every full-rank problem with n up to the one-workgroup limit (default 48, at
+Every full-rank problem with n up to the one-workgroup limit (default 56, at
 most 64; include/zcsd.h, ZCSD_TUNE_ONE_WORKGROUP_MAX_N) runs as a whole CSD
 inside one workgroup, in persistent launches by tier of size: n <= 16 with
 eight workgroups per compute unit, n <= 32 with four, n <= 48 with two,
@@ -57,7 +57,7 @@ def _run(zcsd, A1s, A2s, limit, **opts):
 
 def test_one_workgroup_matches_oracle_and_class_path(one_wg_limit):
     zcsd = one_wg_limit
-    assert zcsd.get_tuning()["one_workgroup_max_n"] == 48
+    assert zcsd.get_tuning()["one_workgroup_max_n"] == 56
     sizes = [1, 2, 3, 4, 5, 7, 8, 13, 16, 17, 31, 32, 33, 47, 48, 49, 63, 64]
     A1s, A2s, truth = [], [], []
     for k, n in enumerate(sizes):

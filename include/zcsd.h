@@ -376,7 +376,8 @@ zcsd_status zcsd_dcsd_batched_small(zcsd_handle* handle, int batch, const int* d
  * once (synchronous; kept until the process ends, a few KB) and returns in
  * *ws_bytes the workspace a call with `batch` problems needs (4 batch bytes
  * of list plus the scratch of the persistent grids, about 57 MB on 256
- * compute units).  Errors: ZCSD_EINVAL as zcsd_dcsd_batched_small.
+ * compute units).  Errors: ZCSD_EINVAL as zcsd_dcsd_batched_small (or a
+ * NULL ws_bytes); ZCSD_EHIP if the table cannot be allocated or copied.
  */
 zcsd_status zcsd_small_batch_prepare(zcsd_handle* handle, int batch, const zcsd_opts* opts,
                                      size_t* ws_bytes);
